@@ -1,0 +1,307 @@
+"""FP64 CPU oracle for chunked test-time training (TTT) of a 2-layer fast MLP.
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test-suite, the smoke check
+and the benchmark's CPU-baseline leg may import this module.  It shares no
+code with the HIP path and never imports it.
+
+What is computed (per sequence and head, heads independent):
+
+* the fast network is ``f_W(x) = SiLU(x W1) W2`` with ``W1: [d][h]`` and
+  ``W2: [h][d]`` (row-vector convention of the per-head matrices in Supp. A);
+* the token stream is walked chunk by chunk; all tokens of a chunk form one
+  update unit (Sec. 4.2, chunk-wise update, Eq. 8);
+* the inner loss of chunk c is the mean over its M_c tokens of the squared
+  error ``||f_W(k_i) - v_i||^2`` (readings: mean over tokens, sum over the
+  feature axis, no 1/2 factor);
+* the step is ``W <- W - eta * grad_W L_c`` (TTT update, Sec. 3.2 Eq. 3);
+* after the step the chunk's queries are mapped, ``O_c = f_W(Q_c)`` (TTT
+  apply, Sec. 3.2 Eq. 4; "after the update" in Sec. 4.2).
+
+Q, K and V are L2-normalised per token and head, ``x / max(||x||, 1e-12)``,
+inside the differentiated function (an input-preparation reading; the paper
+does not mention it).
+
+The backward pass is the hand-derived reverse mode of the whole chain of inner
+updates, second-order terms through the inner gradient included, for the
+outer loss ``sum <O, dO>``.
+
+Every formula is plain numpy in float64; the loops follow the paper's order
+(chunks in sequence order).  Nothing here is blocked, fused or reordered.
+
+Parity pins (tests/test_oracle_*.py): central finite differences, torch
+float64 autograd, the identity-activation closed form, eta=0, first-step
+linearity in eta, loss decrease, token-shard additivity (Eq. 10),
+permutation within a chunk, head independence, split-call resume.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import expit
+
+NORM_EPS = 1e-12
+
+
+# --------------------------------------------------------------------------
+# activations: SiLU (the fast MLP's non-linearity) and identity (a pinning aid)
+# --------------------------------------------------------------------------
+
+def _silu_parts(z):
+    """Return (s(z), s'(z), s''(z)) for s(z) = z * sigmoid(z)."""
+    sg = expit(z)
+    s = z * sg
+    d1 = sg * (1.0 + z * (1.0 - sg))
+    d2 = sg * (1.0 - sg) * (2.0 + z * (1.0 - 2.0 * sg))
+    return s, d1, d2
+
+
+def _identity_parts(z):
+    return z.copy(), np.ones_like(z), np.zeros_like(z)
+
+
+ACTIVATIONS = {"silu": _silu_parts, "identity": _identity_parts}
+
+
+def activation(z, act="silu"):
+    return ACTIVATIONS[act](np.asarray(z, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# per-token L2 normalisation and its adjoint
+# --------------------------------------------------------------------------
+
+def l2norm_rows(x, eps=NORM_EPS):
+    """x / max(||x||_2, eps) along the last axis; returns (xhat, denom)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = np.sqrt(np.sum(x * x, axis=-1, keepdims=True))
+    den = np.maximum(n, eps)
+    return x / den, den
+
+
+def l2norm_rows_bwd(x, dxhat, eps=NORM_EPS):
+    """Adjoint of l2norm_rows: (dxhat - xhat (xhat . dxhat)) / ||x|| where
+    ||x|| > eps, and dxhat / eps where the floor is active."""
+    xhat, den = l2norm_rows(x, eps)
+    n = np.sqrt(np.sum(np.asarray(x, np.float64) ** 2, axis=-1, keepdims=True))
+    proj = np.sum(xhat * dxhat, axis=-1, keepdims=True)
+    above = (dxhat - xhat * proj) / den
+    floor = dxhat / eps
+    return np.where(n > eps, above, floor)
+
+
+# --------------------------------------------------------------------------
+# chunking
+# --------------------------------------------------------------------------
+
+def chunk_bounds(n_tokens, chunk_tokens):
+    """Non-overlapping token ranges [c*M, min((c+1)*M, N)); the last chunk may
+    be ragged.  N = 0 gives no chunks."""
+    if chunk_tokens < 1:
+        raise ValueError("chunk_tokens must be >= 1")
+    return [(s, min(s + chunk_tokens, n_tokens)) for s in range(0, n_tokens, chunk_tokens)]
+
+
+# --------------------------------------------------------------------------
+# the inner problem of one chunk (Eq. 8 with the MSE loss)
+# --------------------------------------------------------------------------
+
+def fast_forward(x, W1, W2, act="silu"):
+    """f_W(x) = s(x W1) W2 for rows x."""
+    s, _, _ = activation(x @ W1, act)
+    return s @ W2
+
+
+def inner_loss(k, v, W1, W2, act="silu"):
+    """L_c(W) = (1/M_c) * sum_i ||f_W(k_i) - v_i||^2."""
+    r = fast_forward(k, W1, W2, act) - v
+    return float(np.sum(r * r) / k.shape[0])
+
+
+def inner_grad(k, v, W1, W2, act="silu"):
+    """Hand-derived gradient of inner_loss with respect to (W1, W2).
+
+    Z = k W1, A = s(Z), R = A W2 - v, E = (2/M) R, P = E W2^T, D = P * s'(Z),
+    grad W1 = k^T D, grad W2 = A^T E.  Returns (G1, G2, loss, cache)."""
+    m = k.shape[0]
+    Z = k @ W1
+    A, S1, S2 = activation(Z, act)
+    R = A @ W2 - v
+    loss = float(np.sum(R * R) / m)
+    E = (2.0 / m) * R
+    P = E @ W2.T
+    D = P * S1
+    G1 = k.T @ D
+    G2 = A.T @ E
+    cache = dict(Z=Z, A=A, S1=S1, S2=S2, E=E, P=P, D=D)
+    return G1, G2, loss, cache
+
+
+# --------------------------------------------------------------------------
+# forward chain
+# --------------------------------------------------------------------------
+
+def _as_f64(*xs):
+    return [np.asarray(x, dtype=np.float64) for x in xs]
+
+
+def _prep(x, do_norm):
+    if do_norm:
+        return l2norm_rows(x)[0]
+    return np.asarray(x, dtype=np.float64)
+
+
+def ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm=(True, True, True), act="silu"):
+    """Chunked TTT forward for one sequence.
+
+    Q, K, V: [N][H][d] raw tokens; W1_0: [H][d][h]; W2_0: [H][h][d].
+    Returns dict with O [N][H][d], W1_T, W2_T (final fast weights),
+    ckpt1 [C][H][d][h], ckpt2 [C][H][h][d] (weights *before* chunk c) and
+    loss [H][C] (inner loss of chunk c at the weights before its step)."""
+    Q, K, V, W1_0, W2_0 = _as_f64(Q, K, V, W1_0, W2_0)
+    N, H, d = K.shape
+    h = W1_0.shape[-1]
+    bounds = chunk_bounds(N, chunk_tokens)
+    C = len(bounds)
+    O = np.zeros((N, H, d))
+    ckpt1 = np.zeros((C, H, d, h))
+    ckpt2 = np.zeros((C, H, h, d))
+    loss = np.zeros((H, C))
+    W1_T = W1_0.copy()
+    W2_T = W2_0.copy()
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        W1 = W1_0[hd].copy()
+        W2 = W2_0[hd].copy()
+        for c, (s, e) in enumerate(bounds):
+            ckpt1[c, hd] = W1
+            ckpt2[c, hd] = W2
+            G1, G2, l, _ = inner_grad(k[s:e], v[s:e], W1, W2, act)
+            loss[hd, c] = l
+            W1 = W1 - eta * G1
+            W2 = W2 - eta * G2
+            O[s:e, hd, :] = fast_forward(q[s:e], W1, W2, act)
+        W1_T[hd] = W1
+        W2_T[hd] = W2
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt1=ckpt1, ckpt2=ckpt2, loss=loss)
+
+
+def ttt_forward_batched(Q, K, V, cu_seqlens, W1_0, W2_0, eta, chunk_tokens,
+                        w0_per_seq=False, norm=(True, True, True), act="silu"):
+    """Many sequences packed along the token axis, [sum N_b][H][d], with
+    boundaries cu_seqlens [B+1].  Each sequence runs its own chain from its
+    initial weights (shared [H][..] or per sequence [B][H][..])."""
+    cu = [int(x) for x in cu_seqlens]
+    Q, K, V, W1_0, W2_0 = _as_f64(Q, K, V, W1_0, W2_0)
+    B = len(cu) - 1
+    O = np.zeros_like(Q)
+    W1_T = np.zeros((B,) + W1_0.shape[-3:])
+    W2_T = np.zeros((B,) + W2_0.shape[-3:])
+    for b in range(B):
+        s, e = cu[b], cu[b + 1]
+        w1 = W1_0[b] if w0_per_seq else W1_0
+        w2 = W2_0[b] if w0_per_seq else W2_0
+        r = ttt_forward(Q[s:e], K[s:e], V[s:e], w1, w2, eta, chunk_tokens, norm, act)
+        O[s:e] = r["O"]
+        W1_T[b] = r["W1_T"]
+        W2_T[b] = r["W2_T"]
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T)
+
+
+# --------------------------------------------------------------------------
+# backward through the whole chain (second-order terms included)
+# --------------------------------------------------------------------------
+
+def ttt_backward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True, True), act="silu"):
+    """Reverse mode of ttt_forward for the outer loss sum <O, dO>.
+
+    Walks chunks backwards carrying the adjoints (Wh1, Wh2) of the weights
+    *after* chunk c.  Per chunk, with W = W_c recomputed from the forward:
+
+    apply adjoint (O_c = s(q W1') W2' with W' = W_{c+1}):
+        Wh2 += Aq^T dO,  dZq = (dO W2'^T) * s'(Zq),  Wh1 += q^T dZq,
+        dq = dZq W1'^T
+    update adjoint (W' = W - eta * grad):
+        deta += -<k Wh1, D> - <A Wh2, E>
+        dD = -eta k Wh1,  dk = -eta D Wh1^T,  dA = -eta E Wh2^T,  dE = -eta A Wh2
+        dP = dD * s'(Z),  dZ = dD * P * s''(Z)
+        dE += dP W2,  dW2 = Wh2 + dP^T E
+        dY = (2/M) dE,  dv = -dY
+        dA += dY W2^T,  dW2 += A^T dY
+        dZ += dA * s'(Z),  dk += dZ W1^T,  dW1 = Wh1 + k^T dZ
+    then (Wh1, Wh2) <- (dW1, dW2).  Finally the L2-norm adjoint maps
+    dq, dk, dv to the raw inputs.
+
+    Returns dict dQ, dK, dV [N][H][d], dW1_0 [H][d][h], dW2_0 [H][h][d],
+    deta [H] (per head; the scalar eta's gradient is their sum)."""
+    Q, K, V, W1_0, W2_0, dO = _as_f64(Q, K, V, W1_0, W2_0, dO)
+    N, H, d = K.shape
+    bounds = chunk_bounds(N, chunk_tokens)
+    fwd = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)
+    dQ = np.zeros_like(Q)
+    dK = np.zeros_like(K)
+    dV = np.zeros_like(V)
+    dW1_0 = np.zeros_like(W1_0)
+    dW2_0 = np.zeros_like(W2_0)
+    deta = np.zeros(H)
+    C = len(bounds)
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        dq = np.zeros_like(q)
+        dk = np.zeros_like(k)
+        dv = np.zeros_like(v)
+        Wh1 = np.zeros_like(W1_0[hd])
+        Wh2 = np.zeros_like(W2_0[hd])
+        for c in range(C - 1, -1, -1):
+            s, e = bounds[c]
+            m = e - s
+            W1 = fwd["ckpt1"][c, hd]
+            W2 = fwd["ckpt2"][c, hd]
+            kc, vc, qc, dOc = k[s:e], v[s:e], q[s:e], dO[s:e, hd, :]
+            G1, G2, _, cc = inner_grad(kc, vc, W1, W2, act)
+            W1n = W1 - eta * G1
+            W2n = W2 - eta * G2
+            # apply adjoint
+            Zq = qc @ W1n
+            Aq, Sq1, _ = activation(Zq, act)
+            Wh2 = Wh2 + Aq.T @ dOc
+            dZq = (dOc @ W2n.T) * Sq1
+            Wh1 = Wh1 + qc.T @ dZq
+            dq[s:e] += dZq @ W1n.T
+            # update adjoint
+            A, S1, S2 = cc["A"], cc["S1"], cc["S2"]
+            E, P, D = cc["E"], cc["P"], cc["D"]
+            kWh1 = kc @ Wh1
+            AWh2 = A @ Wh2
+            deta[hd] += -np.sum(kWh1 * D) - np.sum(AWh2 * E)
+            dD = -eta * kWh1
+            dkc = -eta * (D @ Wh1.T)
+            dA = -eta * (E @ Wh2.T)
+            dE = -eta * AWh2
+            dP = dD * S1
+            dZ = dD * P * S2
+            dE = dE + dP @ W2
+            dW2 = Wh2 + dP.T @ E
+            dY = (2.0 / m) * dE
+            dv[s:e] += -dY
+            dA = dA + dY @ W2.T
+            dW2 = dW2 + A.T @ dY
+            dZ = dZ + dA * S1
+            dkc = dkc + dZ @ W1.T
+            dW1 = Wh1 + kc.T @ dZ
+            dk[s:e] += dkc
+            Wh1, Wh2 = dW1, dW2
+        dW1_0[hd] = Wh1
+        dW2_0[hd] = Wh2
+        dQ[:, hd, :] = l2norm_rows_bwd(Q[:, hd, :], dq) if norm[0] else dq
+        dK[:, hd, :] = l2norm_rows_bwd(K[:, hd, :], dk) if norm[1] else dk
+        dV[:, hd, :] = l2norm_rows_bwd(V[:, hd, :], dv) if norm[2] else dv
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1_0, dW2_0=dW2_0, deta=deta, fwd=fwd)
+
+
+def outer_objective(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True, True), act="silu"):
+    """sum <O, dO>: the scalar whose gradient ttt_backward returns."""
+    O = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)["O"]
+    return float(np.sum(O * np.asarray(dO, np.float64)))
