@@ -1,0 +1,172 @@
+"""Benchmark of the chunked TTT hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one whole forward (every chunk update and apply of every head) over
+the workload's synthetic token stream, inputs resident in HBM.  The default
+workload is 16 heads x 64, fast-MLP hidden 256, 64 frames x 1374 tokens,
+chunks of 8 frames, eta 0.05, FP32 (the plain path); the BF16-operand path on
+the same workload is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TTT fwd / fwd+bwd tokens/s, BF16 vs FP32 at stated error vs FP64 oracle"
+PEAK = {"f32": 157.3, "bf16": 2516.6}   # dense matrix-core TFLOP/s (MI355X)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="layer16_64f_chunk8f")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-heads", type=int, default=2)
+    return ap.parse_args()
+
+
+def alg_flops(w):
+    # forward: 10*d*h per token-head for the update chain + 4*d*h for the apply
+    return 14.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads
+
+
+def run_variant(w, dev_inputs, io, steps, warmup, lib):
+    import ctypes
+
+    import torch
+
+    from paper_2604_08542_amd import ops
+    dt = torch.float32 if io == "f32" else torch.bfloat16
+    Q, K, V = (dev_inputs[n].to(dt) for n in ("Q", "K", "V"))
+    W1, W2 = dev_inputs["W1"], dev_inputs["W2"]
+    cu = w.cu_seqlens()
+    O = torch.empty_like(Q)
+    prob = ops.problem(Q, w.d_hidden, 0, w.chunk_tokens, w.eta, ops._flags(True))
+    ws = ops.workspace(prob, len(cu) - 1, Q.device)
+
+    def step():
+        return ops.batched_fwd(Q, K, V, cu, W1, W2, w.eta, w.chunk_tokens, out=O, ws=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lib.ttt_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    lib.ttt_profile_read(4, ms, n)
+    lib.ttt_profile_enable(0)
+    ms_step = (t1 - t0) * 1e3 / steps
+    kern_ms_per_pass = ms[0] / steps
+    achieved = alg_flops(w) / (kern_ms_per_pass * 1e-3) / 1e12
+    return dict(
+        io=io, ms_per_step=ms_step, tokens_per_s=w.n_tokens / (ms_step * 1e-3),
+        step_kernel=dict(launches_per_pass=n[0] / steps, avg_launch_us=ms[0] / max(n[0], 1) * 1e3,
+                         ms_per_pass=kern_ms_per_pass),
+        update_kernel=dict(launches_per_pass=n[1] / steps, avg_launch_us=ms[1] / max(n[1], 1) * 1e3,
+                           ms_per_pass=ms[1] / steps),
+        roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[io], unit="TFLOP/s",
+                      frac=achieved / PEAK[io], traffic=None),
+        out=r,
+    )
+
+
+def cpu_baseline(w, host_inputs, gpu_out, n_heads):
+    """Time the FP64 oracle on the host for `n_heads` heads of the same
+    inputs (a bounded sample of the workload) and compare those heads."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+    sl = slice(0, n_heads)
+    x = {k: host_inputs[k][:, sl] for k in ("Q", "K", "V")}
+    W1, W2 = host_inputs["W1"][sl], host_inputs["W2"][sl]
+    cu = w.cu_seqlens()
+    t0 = time.perf_counter()
+    ref = oracle.ttt_forward_batched(x["Q"], x["K"], x["V"], cu, W1, W2, w.eta, w.chunk_tokens)
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    tok_s = w.n_tokens * (n_heads / w.n_heads) / dt
+    errs = {}
+    for io, out in gpu_out.items():
+        O = out["O"][:, sl].float().cpu().numpy().astype(np.float64)
+        errs[io] = float(np.linalg.norm(O - ref["O"]) / np.linalg.norm(ref["O"]))
+    return dict(value=tok_s, unit="tokens/s", cores=threads, kind="oracle",
+                sample=f"FP64 numpy oracle forward on {n_heads} of {w.n_heads} heads over all "
+                       f"{w.n_tokens} tokens ({dt:.1f} s), scaled to all heads",
+                seconds=dt), errs
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); chains shard over GPUs by "
+              f"(sequence, head) but no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2604_08542_amd as P
+    from workloads import WORKLOADS, make_inputs_torch
+    lib = P.load()
+    w = WORKLOADS[a.workload]
+    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=w.io_dtype)
+    variants = {}
+    for io in ("f32", "bf16"):
+        variants[io] = run_variant(w, dev, io, a.steps, a.warmup, lib)
+        print(f"# {io}: {variants[io]['ms_per_step']:.3f} ms/step, "
+              f"{variants[io]['tokens_per_s']:.4g} tokens/s, step-kernel "
+              f"{variants[io]['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    main_io = w.io_dtype
+    m = variants[main_io]
+    cpu = None
+    errs = {}
+    if not a.no_cpu_baseline:
+        host = {k: dev[k][:, : a.cpu_heads].float().cpu().numpy() for k in ("Q", "K", "V")}
+        host["W1"] = dev["W1"].cpu().numpy()
+        host["W2"] = dev["W2"].cpu().numpy()
+        cpu, errs = cpu_baseline(w, host, {io: variants[io]["out"] for io in variants}, a.cpu_heads)
+        if main_io == "f32":
+            # the BF16 variant's inputs were rounded from these FP32 values
+            errs["bf16_incl_input_rounding"] = errs.pop("bf16")
+    line = {
+        "metric": METRIC,
+        "value": m["tokens_per_s"],
+        "unit": "tokens/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_io,
+        "data": "synthetic",
+        "config": {"workload": w.name, "heads": w.n_heads, "d_head": w.d_head, "d_hidden": w.d_hidden,
+                   "frames": list(w.frames), "tokens": w.n_tokens, "chunk_tokens": w.chunk_tokens,
+                   "eta": w.eta, "pass": "forward"},
+        "roofline": m["roofline"],
+        "cpu_baseline": cpu,
+        "variants": {io: {k: v for k, v in var.items() if k != "out"} for io, var in variants.items()},
+        "speedup_bf16_over_f32": variants["f32"]["ms_per_step"] / variants["bf16"]["ms_per_step"],
+        "rel_err_vs_oracle_sampled_heads": errs,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * ttt.h - C ABI of the MI355X (gfx950) chunked test-time-training library.
+ *
+ * The operation (Scal3R, Sec. 3.2 Eq. 3-4 and Sec. 4.2 Eq. 8): per sequence
+ * and head there is a fast MLP f_W(x) = SiLU(x W1) W2 with W1: [d][h] and
+ * W2: [h][d] (the per-head matrices of Supp. A, row-vector convention).  The
+ * token stream is cut into chunks of `chunk_tokens` tokens (the last one may
+ * be shorter).  For chunk c with M_c tokens, in sequence order:
+ *
+ *     L_c(W)  = (1/M_c) * sum_i || f_W(k_i) - v_i ||^2      (inner loss)
+ *     W      <- W - eta * grad_W L_c(W)                      (update, Eq. 3/8)
+ *     O_c     = f_W(Q_c)   with the updated W                (apply, Eq. 4)
+ *
+ * Q, K, V are optionally L2-normalised per token and head first,
+ * x / max(||x||_2, 1e-12), inside the differentiated function.
+ *
+ * Conventions shared by every entry point
+ *   - Token tensors (Q, K, V, O, dO, dQ, dK, dV) are [N][H][d] with d
+ *     contiguous; element (t, h, j) lives at t*stride_tok + h*stride_head + j
+ *     (defaults stride_tok = H*d, stride_head = d).  Their element type is
+ *     io_dtype (float32 or bfloat16).
+ *   - Fast weights and everything derived from them (W1_0, W2_0, W1_T, W2_T,
+ *     checkpoints, dW1_0, dW2_0, deta, loss) are float32, dense, row-major:
+ *     W1 [H][d][h], W2 [H][h][d].
+ *   - All pointers except *_host ones are device pointers.  The caller owns
+ *     every buffer, including the workspace; the library allocates no device
+ *     memory and keeps no device state between calls.  Inputs are never
+ *     modified; outputs are fully overwritten (never accumulated into).
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = default
+ *     stream) and is asynchronous; the library never synchronises.
+ *   - Validation happens before anything is enqueued: on any error status
+ *     nothing has been launched.  Launch failures return TTT_EHIP.  No C++
+ *     exception crosses this boundary.  Calls from different host threads
+ *     are safe; calls that share a workspace must be stream-ordered.
+ *   - Supported shapes: d = 64, h in {128, 256}; other sizes return
+ *     TTT_ESHAPE.  n_tokens may be 0 (nothing is enqueued).
+ */
+#ifndef TTT_H_
+#define TTT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TTT_OK = 0,
+  TTT_EINVAL = 1,      /* null pointer, bad flag, non-monotone cu_seqlens, ... */
+  TTT_ESHAPE = 2,      /* unsupported d / h / strides */
+  TTT_EWORKSPACE = 3,  /* workspace missing or smaller than ttt_workspace_bytes */
+  TTT_EHIP = 4,        /* a HIP launch failed */
+  TTT_ENOTSUP = 5      /* valid request this build does not implement */
+} ttt_status_t;
+
+typedef enum { TTT_F32 = 0, TTT_BF16 = 1 } ttt_dtype_t;
+
+enum {
+  TTT_NORM_Q = 1u,     /* L2-normalise Q rows */
+  TTT_NORM_K = 2u,     /* L2-normalise K rows */
+  TTT_NORM_V = 4u,     /* L2-normalise V rows */
+  TTT_SAVE_CKPT = 8u,  /* write the weights before every chunk to `ckpt` */
+  TTT_EMIT_LOSS = 16u, /* write the inner loss of every chunk to `loss` */
+  TTT_MMA_BF16 = 32u   /* with io_dtype F32: round operands to bfloat16 for
+                          the matrix cores (always on for io_dtype BF16) */
+};
+
+typedef struct {
+  int32_t n_heads;      /* H >= 1 */
+  int32_t d_head;       /* d, must be 64 */
+  int32_t d_hidden;     /* h, 128 or 256 */
+  int64_t n_tokens;     /* N for single-sequence calls (ignored by ttt_batched_fwd) */
+  int64_t chunk_tokens; /* tokens per update chunk, >= 1 */
+  int64_t stride_tok;   /* elements between consecutive tokens; 0 = H*d */
+  int64_t stride_head;  /* elements between consecutive heads; 0 = d */
+  float eta;            /* inner step size (one scalar for all heads and chunks) */
+  uint32_t flags;       /* TTT_* bits */
+  ttt_dtype_t io_dtype; /* element type of the token tensors */
+} ttt_problem_t;
+
+/* Optional launch shape; pass NULL for the built-in heuristic or the tuned
+ * table.  wg_per_chain: work-groups that share one chunk of one chain
+ * (0 = automatic); target_wgs: total work-groups aimed for per chunk step
+ * (0 = automatic). */
+typedef struct {
+  int32_t wg_per_chain;
+  int32_t target_wgs;
+} ttt_tile_cfg_t;
+
+/* Bytes of device workspace needed by any call on `p` with `n_seqs`
+ * sequences (1 for the chunk calls).  Returns 0 for an invalid problem. */
+size_t ttt_workspace_bytes(const ttt_problem_t* p, int32_t n_seqs);
+
+/* Forward over one sequence (Sec. 4.2, Eq. 8 then Eq. 4 per chunk).
+ *   Q, K, V   [N][H][d] io_dtype, read only.
+ *   W1_0      [H][d][h] f32; W2_0 [H][h][d] f32: initial fast weights.
+ *   O         [N][H][d] io_dtype: O_c = f_{W_{c+1}}(Q_c).
+ *   W1_T,W2_T final fast weights (same shapes as W1_0/W2_0), nullable.
+ *   ckpt      [C][H][d*h + h*d] f32, required iff TTT_SAVE_CKPT: the weights
+ *             before chunk c (W1 block then W2 block per head).
+ *   loss      [H][C] f32, required iff TTT_EMIT_LOSS: L_c at the weights
+ *             before chunk c's step.
+ *   ws        device workspace of ws_bytes >= ttt_workspace_bytes(p, 1). */
+ttt_status_t ttt_chunk_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
+                           const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
+                           float* ckpt, float* loss, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Backward of ttt_chunk_fwd for the outer loss sum <O, dO>, second-order
+ * terms through every inner gradient included; recomputes each chunk from
+ * its checkpoint.
+ *   ckpt          the checkpoints written by ttt_chunk_fwd with TTT_SAVE_CKPT
+ *                 on the same inputs.
+ *   dO            [N][H][d] io_dtype.
+ *   dQ, dK, dV    [N][H][d] io_dtype, gradients w.r.t. the *raw* Q, K, V.
+ *   dW1_0, dW2_0  gradients w.r.t. the initial fast weights, f32.
+ *   deta          [H] f32, per-head contribution to d/d eta (sum = total). */
+ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
+                           const float* W1_0, const float* W2_0, const float* ckpt, const void* dO,
+                           void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta,
+                           void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Forward over B sequences packed along the token axis ([sum N_b][H][d]),
+ * each an independent chain.  cu_seqlens_host [B+1] is a HOST array of
+ * monotone token offsets with cu_seqlens_host[0] = 0.  w0_per_seq = 0: all
+ * sequences start from W1_0 [H][d][h] / W2_0 [H][h][d]; 1: per-sequence
+ * [B][H][..].  W1_T, W2_T are [B][H][..] (nullable).  tile_cfg nullable.
+ * Every chunk step of every sequence runs in the same stream-ordered
+ * schedule; a sequence's ragged last chunk is normalised by its own size. */
+ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host,
+                             const void* Q, const void* K, const void* V, const float* W1_0,
+                             const float* W2_0, int32_t w0_per_seq, void* O, float* W1_T, float* W2_T,
+                             const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Benchmark instrumentation.  While enabled, every launch the library
+ * enqueues is bracketed by a pair of HIP events on the launch stream (events
+ * come from a pool the library owns; enabling clears earlier records).
+ * ttt_profile_read waits for the recorded events and returns, per kernel
+ * kind (0 = chunk-step kernel, 1 = weight-update kernel, 2 = backward
+ * chunk-step kernel, 3 = backward reduction kernel), the summed elapsed
+ * milliseconds and the number of launches; arrays have n_kinds entries.
+ * Not meant for production calls: it adds event records to the stream. */
+ttt_status_t ttt_profile_enable(int32_t on);
+ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches);
+
+/* Human-readable name of a status code (static storage). */
+const char* ttt_status_string(ttt_status_t s);
+
+/* Library version as an integer (major*10000 + minor*100 + patch). */
+int32_t ttt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTT_H_ */

@@ -1,0 +1,317 @@
+// C ABI of the chunked TTT library: argument validation, workspace layout,
+// launch planning (work-groups per chain, active-sequence lists per chunk
+// step) and the stream-ordered launch sequence.  No device memory is
+// allocated here and the stream is never synchronised.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ttt.h"
+#include "ttt_internal.h"
+
+namespace {
+
+using namespace ttt;
+
+constexpr uint32_t KNOWN_FLAGS = TTT_NORM_Q | TTT_NORM_K | TTT_NORM_V | TTT_SAVE_CKPT | TTT_EMIT_LOSS | TTT_MMA_BF16;
+constexpr int64_t SLOT_CAP_MIN = 1024;  // shard-partial slots available per chunk step
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+struct Shape {
+  int H, d, h;
+  int64_t M, stride_tok, stride_head;
+  bool io_bf16, mma_bf16;
+  int64_t dh() const { return (int64_t)d * h; }
+};
+
+ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
+  if (!p) return TTT_EINVAL;
+  if (p->n_heads < 1 || p->chunk_tokens < 1 || p->n_tokens < 0) return TTT_EINVAL;
+  if (!std::isfinite(p->eta)) return TTT_EINVAL;
+  if (p->flags & ~KNOWN_FLAGS) return TTT_EINVAL;
+  if (p->io_dtype != TTT_F32 && p->io_dtype != TTT_BF16) return TTT_EINVAL;
+  if (p->d_head != 64) return TTT_ESHAPE;
+  if (p->d_hidden != 128 && p->d_hidden != 256) return TTT_ESHAPE;
+  const int64_t st = p->stride_tok ? p->stride_tok : (int64_t)p->n_heads * p->d_head;
+  const int64_t sh = p->stride_head ? p->stride_head : p->d_head;
+  if (st <= 0 || sh <= 0 || (st % 8) || (sh % 8)) return TTT_ESHAPE;
+  s->H = p->n_heads;
+  s->d = p->d_head;
+  s->h = p->d_hidden;
+  s->M = p->chunk_tokens;
+  s->stride_tok = st;
+  s->stride_head = sh;
+  s->io_bf16 = p->io_dtype == TTT_BF16;
+  s->mma_bf16 = s->io_bf16 || (p->flags & TTT_MMA_BF16);
+  return TTT_OK;
+}
+
+struct WsLayout {
+  size_t partial, partial_loss, pp, total;
+  int64_t slot_cap;
+};
+
+WsLayout ws_layout(const Shape& s, int64_t n_chains) {
+  WsLayout L{};
+  L.slot_cap = std::max<int64_t>(n_chains, SLOT_CAP_MIN);
+  size_t off = 0;
+  L.partial = off;
+  off = align_up(off + (size_t)L.slot_cap * 2 * s.dh() * sizeof(float));
+  L.partial_loss = off;
+  off = align_up(off + (size_t)L.slot_cap * sizeof(float));
+  L.pp = off;
+  off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+int default_target_wgs(const Shape& s) { return s.h == 256 ? 256 : 512; }
+
+// ---------------------------------------------------------------- profiling
+// Optional event pairs around launches (benchmark instrumentation only).
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;      // 2 events per record
+  std::vector<int> kinds;            // kind of record i
+  size_t used = 0;
+  int begin(int kind, hipStream_t st) {
+    std::lock_guard<std::mutex> g(mu);
+    if (!on) return -1;
+    if (2 * used + 2 > pool.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        pool.push_back(e);
+      }
+    }
+    const int idx = (int)used++;
+    if ((size_t)idx >= kinds.size()) kinds.resize(idx + 1);
+    kinds[idx] = kind;
+    (void)hipEventRecord(pool[2 * idx], st);
+    return idx;
+  }
+  void end(int idx, hipStream_t st) {
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> g(mu);
+    (void)hipEventRecord(pool[2 * idx + 1], st);
+  }
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+
+template <typename F>
+bool timed_launch(int kind, hipStream_t st, F&& f) {
+  const int idx = prof().begin(kind, st);
+  const bool ok = f() == hipSuccess;
+  prof().end(idx, st);
+  return ok;
+}
+
+template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+// The whole forward: for s = 0..C_max, one fwd-step launch (gradient of chunk
+// s, apply of chunk s-1) and, while any chunk s exists, one update launch.
+ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, const void* Q,
+                         const void* K, const void* V, const float* W1_0, const float* W2_0, int w0_per_seq,
+                         void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, const ttt_tile_cfg_t* cfg,
+                         void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t nch_total = (int64_t)B * S.H;
+  const WsLayout L = ws_layout(S, nch_total);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t M = S.M;
+  std::vector<int64_t> nb(B), cb(B);
+  int64_t cmax = 0, nmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nb[b] = cu[b + 1] - cu[b];
+    cb[b] = (nb[b] + M - 1) / M;
+    cmax = std::max(cmax, cb[b]);
+    nmax = std::max(nmax, nb[b]);
+  }
+  if (cmax == 0) return TTT_OK;
+  const int64_t dh = S.dh();
+  float* partial = at<float>(ws, L.partial);
+  float* partial_loss = at<float>(ws, L.partial_loss);
+  float* pp[2] = {at<float>(ws, L.pp), at<float>(ws, L.pp) + nch_total * 2 * dh};
+  const int64_t tiles_per_chunk = (std::min(M, nmax) + TT - 1) / TT;
+  const int target = (cfg && cfg->target_wgs > 0) ? cfg->target_wgs : default_target_wgs(S);
+  const int nbpc = (int)((2 * dh / 4 + 255) / 256);
+
+  for (int64_t s = 0; s <= cmax; ++s) {
+    std::vector<int> act;
+    for (int b = 0; b < B; ++b)
+      if (nb[b] > 0 && s <= cb[b]) act.push_back(b);
+    if (act.empty()) continue;
+    const int64_t n_chains = (int64_t)act.size() * S.H;
+    int64_t G = (cfg && cfg->wg_per_chain > 0) ? cfg->wg_per_chain : (target + n_chains - 1) / n_chains;
+    G = std::max<int64_t>(1, std::min<int64_t>({G, tiles_per_chunk, L.slot_cap / n_chains}));
+    bool any_grad = false;
+    for (size_t base = 0; base < act.size(); base += MAXS) {
+      const int na = (int)std::min<size_t>(MAXS, act.size() - base);
+      FwdStepArgs a{};
+      a.Q = Q; a.K = K; a.V = V; a.O = O;
+      a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+      if (s == 0) {
+        a.w1_src = W1_0; a.w2_src = W2_0; a.w_cstride = dh;
+        a.w_mod = w0_per_seq ? (int32_t)nch_total : S.H;
+      } else {
+        a.w1_src = pp[s % 2]; a.w2_src = pp[s % 2] + dh; a.w_cstride = 2 * dh;
+        a.w_mod = (int32_t)nch_total;
+      }
+      a.H = S.H; a.flags = p->flags; a.G = (int32_t)G;
+      const int64_t slot0 = (int64_t)base * S.H * G;
+      a.partial = partial + slot0 * 2 * dh;
+      a.partial_loss = partial_loss + slot0;
+      a.n_active = na;
+      UpdStepArgs u{};
+      bool grad_here = false;
+      for (int i = 0; i < na; ++i) {
+        const int b = act[base + i];
+        a.seq_id[i] = b;
+        a.grad_start[i] = cu[b] + s * M;
+        a.grad_len[i] = s < cb[b] ? (int32_t)std::min<int64_t>(M, nb[b] - s * M) : 0;
+        a.app_start[i] = cu[b] + (s - 1) * M;
+        a.app_len[i] = s >= 1 ? (int32_t)std::min<int64_t>(M, nb[b] - (s - 1) * M) : 0;
+        u.seq_id[i] = b;
+        u.grad_len[i] = a.grad_len[i];
+        u.is_last[i] = (s == cb[b] - 1);
+        grad_here |= a.grad_len[i] > 0;
+      }
+      const int n_blocks = (int)(na * S.H * G);
+      if (!timed_launch(0, st, [&] { return launch_fwd_step(a, n_blocks, S.h, S.io_bf16, S.mma_bf16, st); }))
+        return TTT_EHIP;
+      if (grad_here) {
+        any_grad = true;
+        u.w1_src = a.w1_src; u.w2_src = a.w2_src; u.w_cstride = a.w_cstride; u.w_mod = a.w_mod;
+        u.H = S.H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
+        u.partial = a.partial; u.partial_loss = a.partial_loss;
+        u.w_dst = pp[(s + 1) % 2];
+        u.ckpt = ckpt ? ckpt + s * S.H * 2 * dh : nullptr;
+        u.wT1 = W1_T; u.wT2 = W2_T;
+        u.loss = loss; u.loss_stride = (int32_t)cmax; u.chunk = (int32_t)s;
+        u.n_active = na;
+        if (!timed_launch(1, st, [&] { return launch_update(u, na * S.H * nbpc, st); })) return TTT_EHIP;
+      }
+    }
+    (void)any_grad;
+  }
+  return TTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ttt_workspace_bytes(const ttt_problem_t* p, int32_t n_seqs) {
+  Shape S{};
+  if (check_problem(p, &S) != TTT_OK || n_seqs < 1) return 0;
+  return ws_layout(S, (int64_t)n_seqs * S.H).total;
+}
+
+ttt_status_t ttt_chunk_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                           const float* W2_0, void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, void* ws,
+                           size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+    if (((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
+    if (((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
+    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
+                          (const void*)W2_T, (const void*)ckpt})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (p->n_tokens == 0) return TTT_OK;
+    const int64_t cu[2] = {0, p->n_tokens};
+    return run_forward(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, nullptr, ws, ws_bytes,
+                       static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host, const void* Q,
+                             const void* K, const void* V, const float* W1_0, const float* W2_0, int32_t w0_per_seq,
+                             void* O, float* W1_T, float* W2_T, const ttt_tile_cfg_t* tile_cfg, void* ws,
+                             size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (n_seqs < 1 || !cu_seqlens_host) return TTT_EINVAL;
+    if (w0_per_seq != 0 && w0_per_seq != 1) return TTT_EINVAL;
+    if (cu_seqlens_host[0] != 0) return TTT_EINVAL;
+    for (int b = 0; b < n_seqs; ++b)
+      if (cu_seqlens_host[b + 1] < cu_seqlens_host[b]) return TTT_EINVAL;
+    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+    if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
+    if (tile_cfg && (tile_cfg->wg_per_chain < 0 || tile_cfg->target_wgs < 0)) return TTT_EINVAL;
+    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
+                          (const void*)W2_T})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (cu_seqlens_host[n_seqs] == 0) return TTT_OK;
+    return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, nullptr,
+                       nullptr, tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                           const float* W2_0, const float* ckpt, const void* dO, void* dQ, void* dK, void* dV,
+                           float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes, void* hip_stream) {
+  (void)p; (void)Q; (void)K; (void)V; (void)W1_0; (void)W2_0; (void)ckpt; (void)dO; (void)dQ; (void)dK;
+  (void)dV; (void)dW1_0; (void)dW2_0; (void)deta; (void)ws; (void)ws_bytes; (void)hip_stream;
+  return TTT_ENOTSUP;
+}
+
+ttt_status_t ttt_profile_enable(int32_t on) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = on != 0;
+  P.used = 0;
+  return TTT_OK;
+}
+
+ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches) {
+  if (n_kinds < 0 || (n_kinds > 0 && (!ms || !launches))) return TTT_EINVAL;
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (int k = 0; k < n_kinds; ++k) { ms[k] = 0.0; launches[k] = 0; }
+  for (size_t i = 0; i < P.used; ++i) {
+    if (hipEventSynchronize(P.pool[2 * i + 1]) != hipSuccess) return TTT_EHIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, P.pool[2 * i], P.pool[2 * i + 1]) != hipSuccess) return TTT_EHIP;
+    const int k = P.kinds[i];
+    if (k < n_kinds) { ms[k] += t; launches[k] += 1; }
+  }
+  return TTT_OK;
+}
+
+const char* ttt_status_string(ttt_status_t s) {
+  switch (s) {
+    case TTT_OK: return "TTT_OK";
+    case TTT_EINVAL: return "TTT_EINVAL: invalid argument";
+    case TTT_ESHAPE: return "TTT_ESHAPE: unsupported shape or stride";
+    case TTT_EWORKSPACE: return "TTT_EWORKSPACE: workspace missing or too small";
+    case TTT_EHIP: return "TTT_EHIP: HIP launch failed";
+    case TTT_ENOTSUP: return "TTT_ENOTSUP: not supported";
+  }
+  return "unknown status";
+}
+
+int32_t ttt_version(void) { return 100; }
+
+}  // extern "C"

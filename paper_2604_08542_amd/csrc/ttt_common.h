@@ -1,0 +1,178 @@
+// Device-side building blocks shared by the forward and backward kernels:
+// vector types, matrix-core wrappers for gfx950, the SiLU family, token-row
+// loading with per-token L2 normalisation, and the launch-plan structs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace ttt {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int D = 64;   // head dimension (the only one supported)
+constexpr int TT = 32;  // tokens per tile
+constexpr int MAXS = 64;  // sequences per launch descriptor
+constexpr float NORM_EPS = 1e-12f;
+
+// ----------------------------------------------------------------- matrix cores
+// Lane layouts (verified on gfx950):
+//  32x32xK: A operand lane l holds A[l%32][kgrp(l/32)], B lane l holds
+//           B[kgrp(l/32)][l%32]; result register r of lane l holds
+//           C[8*(r/4) + 4*(l/32) + (r%4)][l%32].
+//  16x16xK: A lane l holds A[l%16][kgrp(l/16)], B lane l holds
+//           B[kgrp(l/16)][l%16]; result register r holds C[4*(l/16)+r][l%16].
+//  kgrp(g) is the g-th group of K/2 (32x32) or K/4 (16x16) contraction slots:
+//  8 consecutive slots for bf16, 1 slot for f32.
+__device__ __forceinline__ f32x16 mma32(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row index held by result register r of a 32x32 block in lane-half hf.
+__device__ __forceinline__ constexpr int c32_row(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
+
+// ----------------------------------------------------------------- SiLU family
+// sigma(z) from one exp2 and one reciprocal (both hardware transcendentals).
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+
+// ----------------------------------------------------------------- io helpers
+template <typename T> __device__ __forceinline__ float to_f(T x) { return (float)x; }
+template <typename T> __device__ __forceinline__ T from_f(float x) { return (T)x; }
+
+// Load n (4 or 8) consecutive io elements as floats.
+template <typename IOT, int N>
+__device__ __forceinline__ void load_vec(const IOT* p, float (&x)[N]) {
+  if constexpr (std::is_same_v<IOT, float>) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      f32x4 v = *reinterpret_cast<const f32x4*>(p + i);
+      x[i] = v[0]; x[i + 1] = v[1]; x[i + 2] = v[2]; x[i + 3] = v[3];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      bf16x4 v = *reinterpret_cast<const bf16x4*>(p + i);
+      x[i] = (float)v[0]; x[i + 1] = (float)v[1]; x[i + 2] = (float)v[2]; x[i + 3] = (float)v[3];
+    }
+  }
+}
+
+template <typename IOT, int N>
+__device__ __forceinline__ void store_vec(IOT* p, const float (&x)[N]) {
+  if constexpr (std::is_same_v<IOT, float>) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      f32x4 v = {x[i], x[i + 1], x[i + 2], x[i + 3]};
+      *reinterpret_cast<f32x4*>(p + i) = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      bf16x4 v = {(bf16)x[i], (bf16)x[i + 1], (bf16)x[i + 2], (bf16)x[i + 3]};
+      *reinterpret_cast<bf16x4*>(p + i) = v;
+    }
+  }
+}
+
+// One token row of D elements is spread over TPR = D/EPT consecutive lanes,
+// EPT elements each.  Loads the row (zeros for masked rows) and, when asked,
+// divides by max(||row||_2, eps); `inv` returns that divisor's reciprocal
+// (1 when not normalising) and `nrm` the raw row norm.
+template <typename IOT, int EPT>
+__device__ __forceinline__ void load_row_norm(const IOT* rowp, bool valid, bool do_norm, float (&x)[EPT],
+                                              float& inv) {
+  constexpr int TPR = D / EPT;
+  if (valid) {
+    load_vec<IOT, EPT>(rowp, x);
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) x[i] = 0.f;
+  }
+  inv = 1.f;
+  if (do_norm) {
+    float ss = 0.f;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
+#pragma unroll
+    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) x[i] *= inv;
+  }
+}
+
+// XCD-aware block order: work-groups are dealt round-robin over the 8 XCDs,
+// so consecutive logical blocks (the work-groups of one chain) are mapped to
+// one XCD to share its L2.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ int xcd_linear_block() {
+  const int nb = gridDim.x, bid = blockIdx.x;
+  return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+}
+
+// ----------------------------------------------------------------- launch plans
+// One chunk step of the forward for a list of active sequences: the gradient
+// partials of chunk s and the apply of chunk s-1 (both use the weights W_s).
+struct FwdStepArgs {
+  const void* Q;
+  const void* K;
+  const void* V;
+  void* O;
+  int64_t stride_tok, stride_head;
+  const float* w1_src;  // W1 of chain c at w1_src + (c % w_mod) * w_cstride, [D][h]
+  const float* w2_src;  // W2 likewise, [h][D]
+  int64_t w_cstride;
+  int32_t w_mod;
+  int32_t H;
+  uint32_t flags;
+  int32_t G;        // work-groups per chain
+  float* partial;   // [n_slots][2*D*h] gradient partials (slot = active chain * G + g)
+  float* partial_loss;  // [n_slots]
+  int32_t n_active;
+  int32_t seq_id[MAXS];
+  int64_t grad_start[MAXS];
+  int32_t grad_len[MAXS];  // 0: no gradient chunk this step
+  int64_t app_start[MAXS];
+  int32_t app_len[MAXS];   // 0: no apply chunk this step
+};
+
+// Reduction of the gradient partials and the fast-weight step W <- W - eta*g.
+struct UpdStepArgs {
+  const float* w1_src;
+  const float* w2_src;
+  int64_t w_cstride;
+  int32_t w_mod;
+  int32_t H, h;
+  float eta;
+  int32_t G;
+  const float* partial;
+  const float* partial_loss;
+  float* w_dst;      // [chains][2*D*h] next weights
+  float* ckpt;       // single sequence: weights before this chunk, [H][2*D*h]; nullable
+  float* wT1;        // [chains][D][h] final weights, nullable
+  float* wT2;        // [chains][h][D]
+  float* loss;       // single sequence: loss[head * loss_stride + chunk]; nullable
+  int32_t loss_stride, chunk;
+  int32_t n_active;
+  int32_t seq_id[MAXS];
+  int32_t grad_len[MAXS];
+  int32_t is_last[MAXS];
+};
+
+}  // namespace ttt

@@ -1,0 +1,376 @@
+// Forward kernels of the chunked TTT update/apply (Sec. 4.2 Eq. 8, Sec. 3.2
+// Eq. 3-4) for gfx950.
+//
+// One launch of ttt_fwd_step processes one chunk step for every active chain
+// (sequence x head): the gradient of chunk s over a token shard (Eq. 8; the
+// shards of a chunk are summed afterwards, Eq. 10) and the apply of chunk s-1
+// (Eq. 4), since both use the same weights W_s.  ttt_update then reduces the
+// shard partials in a fixed order and steps W_{s+1} = W_s - eta * grad.
+//
+// Work split inside a work-group: wave w owns hidden units [32w, 32w+32), so
+// its slices of W1 (columns) and W2 (rows) stay in registers for the whole
+// chunk, and it accumulates its slices of grad W1 / grad W2 in registers over
+// every token tile of its shard.  Per 32-token tile:
+//   P1  load K, V (or Q) rows, L2-normalise (FP32), stage in LDS
+//   P2  Z = K W1 (32x32 matrix-core block per wave), A = SiLU(Z), s'(Z);
+//       A is staged to LDS for the contraction over the hidden axis
+//   P3  Y = A W2 as 16x16 blocks over the full hidden axis, R = Y - V,
+//       E = (2/M) R, loss; (apply tiles: store O = Y)
+//   P4  P = E W2^T, D = P * s'(Z), grad W1 += K^T D, grad W2 += A^T E
+// Z/A/D keep the token index in registers (32x32 result layout), which is
+// exactly the contraction-slot layout the token-sum products need, so only A
+// goes through LDS to be contracted over the hidden axis.
+#include <hip/hip_runtime.h>
+
+#include "ttt_common.h"
+#include "ttt_internal.h"
+
+namespace ttt {
+
+template <typename IOT, bool BF, int NW>
+__global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
+  constexpr int HH = NW * 32;  // hidden size
+  constexpr int NT = NW * 64;
+  constexpr int EPT = D * TT / NT;  // row elements per thread in P1
+  constexpr int TPR = D / EPT;
+  using MT = std::conditional_t<BF, bf16, float>;
+  constexpr int XS_LD = D + (BF ? 8 : 4);
+  constexpr int XT_LD = TT + 8;
+  constexpr int VS_LD = D + 4;
+  constexpr int AS_LD = HH + (BF ? 8 : 4);
+  constexpr int W2T_LD = HH + (BF ? 8 : 4);
+  constexpr int DH = D * HH;
+
+  __shared__ __attribute__((aligned(16))) MT xs[TT * XS_LD];
+  __shared__ __attribute__((aligned(16))) bf16 xts[BF ? D * XT_LD : 8];
+  __shared__ __attribute__((aligned(16))) float vs[TT * VS_LD];
+  __shared__ __attribute__((aligned(16))) MT as_[TT * AS_LD];
+  __shared__ __attribute__((aligned(16))) MT es[TT * XS_LD];
+  __shared__ __attribute__((aligned(16))) bf16 ets[BF ? D * XT_LD : 8];
+  __shared__ __attribute__((aligned(16))) MT w2t[D * W2T_LD];
+  __shared__ float red[NW];
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, l32 = l & 31, hf = l >> 5, l16 = l & 15, g4 = l >> 4;
+  const int lin = xcd_linear_block();
+  const int G = p.G;
+  const int slot = lin / G, g = lin % G;
+  const int ai = slot / p.H, head = slot % p.H;
+  const int seq = p.seq_id[ai];
+  const int chain = seq * p.H + head;
+  const int hid = w * 32 + l32;
+
+  const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+
+  // W2^T in LDS (B operand of Y = A W2 over the full hidden axis).
+  for (int idx = tid; idx < DH; idx += NT) {
+    const int hh = idx / D, dd = idx % D;
+    w2t[dd * W2T_LD + hh] = (MT)W2[idx];
+  }
+  // Register-resident operand slices of this wave's hidden block.
+  bf16x8 w1b[4], w2b[4];
+  float w1f[BF ? 1 : 32], w2f[BF ? 1 : 32];
+  if constexpr (BF) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        w1b[m][e] = (bf16)W1[(16 * m + 8 * hf + e) * HH + hid];
+        w2b[m][e] = (bf16)W2[hid * D + 16 * m + 8 * hf + e];
+      }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      w1f[s] = W1[(32 * hf + s) * HH + hid];
+      w2f[s] = W2[hid * D + 32 * hf + s];
+    }
+  }
+
+  const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
+  const int row = tid / TPR, col0 = (tid % TPR) * EPT;
+  const int64_t hoff = (int64_t)head * p.stride_head;
+
+  // Z = X W1 for this wave's hidden block (X = staged K or Q rows); returns
+  // the 32x32 result block (rows = tokens in registers, cols = hidden).
+  auto z_block = [&]() {
+    f32x16 z = {};
+    if constexpr (BF) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&xs[l32 * XS_LD + 16 * m + 8 * hf]);
+        z = mma32(a, w1b[m], z);
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 8; ++s4) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&xs[l32 * XS_LD + 32 * hf + 4 * s4]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) z = mma32(a[e], w1f[4 * s4 + e], z);
+      }
+    }
+    return z;
+  };
+  // 16x16 block (token block tb, feature block db) of (staged A) W2.
+  auto y_block = [&](int tb, int db) {
+    f32x4 y = {};
+    const int arow = 16 * tb + l16, dcol = 16 * db + l16;
+    if constexpr (BF) {
+#pragma unroll
+      for (int u = 0; u < HH / 32; ++u) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&as_[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 8 * u]);
+        y = mma16(a, b, y);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < HH / 16; ++u) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&as_[arow * AS_LD + (HH / 4) * g4 + 4 * u]);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 4 * u]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y = mma16(a[e], b[e], y);
+      }
+    }
+    return y;
+  };
+
+  // ------------------------------------------------------------ gradient shard
+  const int gl = p.grad_len[ai];
+  if (gl > 0) {
+    const int64_t gs = p.grad_start[ai];
+    const int n_gt = (gl + TT - 1) / TT;
+    const float e_scale = 2.0f / (float)gl;
+    f32x16 gw1[2] = {}, gw2[2] = {};
+    float lacc = 0.f;
+    for (int t = g; t < n_gt; t += G) {
+      const int64_t t0 = gs + (int64_t)t * TT;
+      const int nv = min(TT, gl - t * TT);
+      {  // P1
+        float xk[EPT], xv[EPT], ik, iv;
+        const bool valid = row < nv;
+        const int64_t off = (t0 + row) * p.stride_tok + hoff + col0;
+        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.K) + (valid ? off : 0), valid, norm_k, xk, ik);
+        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.V) + (valid ? off : 0), valid, norm_v, xv, iv);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          xs[row * XS_LD + col0 + i] = (MT)xk[i];
+          vs[row * VS_LD + col0 + i] = xv[i];
+          if constexpr (BF) xts[(col0 + i) * XT_LD + row] = (bf16)xk[i];
+        }
+      }
+      __syncthreads();
+      // P2
+      f32x16 za = z_block();
+      float s1[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float zr = za[r];
+        const float sg = sigmoid(zr);
+        const float av = zr * sg;
+        s1[r] = fmaf(av, 1.0f - sg, sg);
+        za[r] = av;
+        as_[c32_row(r, hf) * AS_LD + hid] = (MT)av;
+      }
+      bf16x8 apk[2];
+      if constexpr (BF) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) apk[m][e] = (bf16)za[8 * m + e];
+      }
+      __syncthreads();
+      // P3
+#pragma unroll
+      for (int bi = 0; bi < 8 / NW; ++bi) {
+        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+        const f32x4 y = y_block(tb, db);
+        const int dcol = 16 * db + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int tok = 16 * tb + 4 * g4 + r;
+          const float R = y[r] - vs[tok * VS_LD + dcol];
+          lacc = fmaf(R, R, lacc);
+          const float E = e_scale * R;
+          es[tok * XS_LD + dcol] = (MT)E;
+          if constexpr (BF) ets[dcol * XT_LD + tok] = (bf16)E;
+        }
+      }
+      __syncthreads();
+      // P4
+      f32x16 pz = {};
+      if constexpr (BF) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
+          pz = mma32(a, w2b[m], pz);
+        }
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(&es[l32 * XS_LD + 32 * hf + 4 * s4]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pz = mma32(a[e], w2f[4 * s4 + e], pz);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) pz[r] *= s1[r];
+      if constexpr (BF) {
+        bf16x8 dpk[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dpk[m][e] = (bf16)pz[8 * m + e];
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const int dd = 32 * db + l32;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[dd * XT_LD + 16 * m + 4 * hf]);
+            const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[dd * XT_LD + 16 * m + 8 + 4 * hf]);
+            const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
+            gw1[db] = mma32(ka, dpk[m], gw1[db]);
+            const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
+            const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
+            const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
+            gw2[db] = mma32(apk[m], eb, gw2[db]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const int dd = 32 * db + l32;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const int tk = c32_row(s, hf);
+            gw1[db] = mma32(xs[tk * XS_LD + dd], pz[s], gw1[db]);
+            gw2[db] = mma32(za[s], es[tk * XS_LD + dd], gw2[db]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // Shard partials: grad W1 [D][h] then grad W2 [h][D].
+    float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = c32_row(r, hf);
+        part[(32 * db + rr) * HH + hid] = gw1[db][r];
+        part[DH + (32 * w + rr) * D + 32 * db + l32] = gw2[db][r];
+      }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) lacc += __shfl_xor(lacc, m, 64);
+    if (l == 0) red[w] = lacc;
+    __syncthreads();
+    if (tid == 0) {
+      float s = 0.f;
+      for (int i = 0; i < NW; ++i) s += red[i];
+      p.partial_loss[(int64_t)slot * G + g] = s;
+    }
+  }
+
+  // ------------------------------------------------------------ apply shard
+  const int al = p.app_len[ai];
+  if (al > 0) {
+    const int64_t as0 = p.app_start[ai];
+    const int n_at = (al + TT - 1) / TT;
+    IOT* O = static_cast<IOT*>(p.O);
+    for (int t = g; t < n_at; t += G) {
+      const int64_t t0 = as0 + (int64_t)t * TT;
+      const int nv = min(TT, al - t * TT);
+      {
+        float xq[EPT], iq;
+        const bool valid = row < nv;
+        const int64_t off = (t0 + row) * p.stride_tok + hoff + col0;
+        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.Q) + (valid ? off : 0), valid, norm_q, xq, iq);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) xs[row * XS_LD + col0 + i] = (MT)xq[i];
+      }
+      __syncthreads();
+      f32x16 za = z_block();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float zr = za[r];
+        as_[c32_row(r, hf) * AS_LD + hid] = (MT)(zr * sigmoid(zr));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int bi = 0; bi < 8 / NW; ++bi) {
+        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+        const f32x4 y = y_block(tb, db);
+        const int dcol = 16 * db + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int tok = 16 * tb + 4 * g4 + r;
+          if (tok < nv) O[(t0 + tok) * p.stride_tok + hoff + dcol] = from_f<IOT>(y[r]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Fixed-order reduction of the G shard partials of each active chain and the
+// step W_{s+1} = W_s - eta * grad.  Also writes the checkpoint W_s, the final
+// weights after a sequence's last chunk, and the chunk's inner loss.
+__global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
+  const int dh = D * p.h;
+  const int n4 = (2 * dh) / 4;
+  const int nbpc = (n4 + 255) / 256;
+  const int lin = xcd_linear_block();
+  const int slot = lin / nbpc, k = lin % nbpc;
+  const int ai = slot / p.H, head = slot % p.H;
+  const int gl = p.grad_len[ai];
+  if (gl <= 0) return;
+  const int chain = p.seq_id[ai] * p.H + head;
+  const int i4 = k * 256 + threadIdx.x;
+  if (i4 < n4) {
+    const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)slot * p.G * 2 * dh) + i4;
+    f32x4 s = part[0];
+    for (int gg = 1; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+    const int idx = 4 * i4;
+    const int64_t wc = (int64_t)(chain % p.w_mod) * p.w_cstride;
+    const f32x4 wv = idx < dh ? *reinterpret_cast<const f32x4*>(p.w1_src + wc + idx)
+                              : *reinterpret_cast<const f32x4*>(p.w2_src + wc + (idx - dh));
+    const f32x4 wn = wv - p.eta * s;
+    *reinterpret_cast<f32x4*>(p.w_dst + (int64_t)chain * 2 * dh + idx) = wn;
+    if (p.ckpt) *reinterpret_cast<f32x4*>(p.ckpt + (int64_t)head * 2 * dh + idx) = wv;
+    if (p.is_last[ai] && p.wT1) {
+      if (idx < dh)
+        *reinterpret_cast<f32x4*>(p.wT1 + (int64_t)chain * dh + idx) = wn;
+      else
+        *reinterpret_cast<f32x4*>(p.wT2 + (int64_t)chain * dh + (idx - dh)) = wn;
+    }
+  }
+  if (k == 0 && threadIdx.x == 0 && p.loss) {
+    float sl = 0.f;
+    for (int gg = 0; gg < p.G; ++gg) sl += p.partial_loss[(int64_t)slot * p.G + gg];
+    p.loss[(int64_t)head * p.loss_stride + p.chunk] = sl / (float)gl;
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+template <typename IOT, bool BF, int NW>
+static hipError_t launch_fwd_step_t(const FwdStepArgs& a, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL((ttt_fwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  if (h == 128) {
+    if (io_bf16) return launch_fwd_step_t<bf16, true, 4>(a, n_blocks, st);
+    return mma_bf16 ? launch_fwd_step_t<float, true, 4>(a, n_blocks, st)
+                    : launch_fwd_step_t<float, false, 4>(a, n_blocks, st);
+  }
+  if (io_bf16) return launch_fwd_step_t<bf16, true, 8>(a, n_blocks, st);
+  return mma_bf16 ? launch_fwd_step_t<float, true, 8>(a, n_blocks, st)
+                  : launch_fwd_step_t<float, false, 8>(a, n_blocks, st);
+}
+
+hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(ttt_update, dim3(n_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace ttt

@@ -1,0 +1,10 @@
+// Host-side declarations shared by the kernel translation units and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ttt_common.h"
+
+namespace ttt {
+hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
+hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st);
+}  // namespace ttt

@@ -1,0 +1,131 @@
+"""torch-facing wrappers of the C ABI (include/ttt.h).
+
+Only argument marshalling happens here: shapes and dtypes are checked, output
+and workspace tensors are allocated with torch (device memory plumbing), and
+the library call is enqueued on torch's current stream.  Every step of the
+computation runs in the HIP kernels of libttt_hip.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.TTT_F32, torch.bfloat16: L.TTT_BF16}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _flags(norm, save_ckpt=False, emit_loss=False, mma_bf16=False):
+    nq, nk, nv = (norm, norm, norm) if isinstance(norm, bool) else norm
+    f = (L.TTT_NORM_Q if nq else 0) | (L.TTT_NORM_K if nk else 0) | (L.TTT_NORM_V if nv else 0)
+    f |= (L.TTT_SAVE_CKPT if save_ckpt else 0) | (L.TTT_EMIT_LOSS if emit_loss else 0)
+    f |= L.TTT_MMA_BF16 if mma_bf16 else 0
+    return f
+
+
+def _check_tokens(Q, K, V):
+    for t in (Q, K, V):
+        if not t.is_cuda:
+            raise ValueError("token tensors must be on the GPU")
+        if t.dim() != 3 or t.stride(-1) != 1:
+            raise ValueError("token tensors must be [N][H][d] with d contiguous")
+        if t.dtype not in _DT:
+            raise ValueError(f"unsupported dtype {t.dtype}")
+    if not (Q.shape == K.shape == V.shape and Q.dtype == K.dtype == V.dtype):
+        raise ValueError("Q, K, V must share shape and dtype")
+    if not (Q.stride() == K.stride() == V.stride()):
+        raise ValueError("Q, K, V must share strides")
+
+
+def _check_w(W1, W2, H, lead=()):
+    if W1.dtype != torch.float32 or W2.dtype != torch.float32:
+        raise ValueError("fast weights are float32")
+    if not (W1.is_contiguous() and W2.is_contiguous()):
+        raise ValueError("fast weights must be contiguous")
+    d, h = W1.shape[-2], W1.shape[-1]
+    if tuple(W1.shape) != tuple(lead) + (H, d, h) or tuple(W2.shape) != tuple(lead) + (H, h, d):
+        raise ValueError(f"bad fast-weight shapes {tuple(W1.shape)} {tuple(W2.shape)}")
+    return d, h
+
+
+def problem(Q, h, n_tokens, chunk_tokens, eta, flags):
+    N, H, d = Q.shape
+    return L.Problem(n_heads=H, d_head=d, d_hidden=h, n_tokens=n_tokens, chunk_tokens=int(chunk_tokens),
+                     stride_tok=Q.stride(0), stride_head=Q.stride(1), eta=float(eta), flags=flags,
+                     io_dtype=_DT[Q.dtype])
+
+
+def workspace(prob, n_seqs, device):
+    lib = L.load()
+    nbytes = lib.ttt_workspace_bytes(ctypes.byref(prob), n_seqs)
+    if nbytes == 0:
+        raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def n_chunks(n_tokens: int, chunk_tokens: int) -> int:
+    return (n_tokens + chunk_tokens - 1) // chunk_tokens
+
+
+def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False, emit_loss=False,
+              mma_bf16=False, want_final=True, out=None, ws=None):
+    """Chunked TTT forward over one sequence.  Returns a dict with O and,
+    as requested, W1_T, W2_T, ckpt [C][H][2dh], loss [H][C]."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, save_ckpt, emit_loss, mma_bf16))
+    C = n_chunks(N, chunk_tokens)
+    dev = Q.device
+    O = out if out is not None else torch.empty_like(Q)
+    W1_T = torch.empty_like(W1) if want_final else None
+    W2_T = torch.empty_like(W2) if want_final else None
+    ckpt = torch.empty((C, H, 2 * d * h), dtype=torch.float32, device=dev) if save_ckpt else None
+    loss = torch.empty((H, C), dtype=torch.float32, device=dev) if emit_loss else None
+    if ws is None:
+        ws = workspace(prob, 1, dev)
+    st = lib.ttt_chunk_fwd(ctypes.byref(prob), _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), _ptr(O),
+                           _ptr(W1_T), _ptr(W2_T), _ptr(ckpt), _ptr(loss), _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_chunk_fwd")
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
+
+
+def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *, norm=True, w0_per_seq=False,
+                mma_bf16=False, want_final=True, tile_cfg=None, out=None, ws=None):
+    """Many sequences packed along the token axis ([sum N_b][H][d]) with host
+    offsets cu_seqlens [B+1]; one independent chain per sequence and head."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    cu = [int(x) for x in cu_seqlens]
+    B = len(cu) - 1
+    _, h = _check_w(W1, W2, H, (B,) if w0_per_seq else ())
+    if cu[-1] != N:
+        raise ValueError("cu_seqlens[-1] must equal the packed token count")
+    prob = problem(Q, h, 0, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    O = out if out is not None else torch.empty_like(Q)
+    W1_T = torch.empty((B, H, d, h), dtype=torch.float32, device=dev) if want_final else None
+    W2_T = torch.empty((B, H, h, d), dtype=torch.float32, device=dev) if want_final else None
+    cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
+    cfg = None
+    if tile_cfg is not None:
+        cfg = L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
+    if ws is None:
+        ws = workspace(prob, B, dev)
+    st = lib.ttt_batched_fwd(ctypes.byref(prob), B, cu_arr, _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2),
+                             1 if w0_per_seq else 0, _ptr(O), _ptr(W1_T), _ptr(W2_T),
+                             ctypes.byref(cfg) if cfg is not None else None, _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_batched_fwd")
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T)

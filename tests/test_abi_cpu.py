@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/ttt.h, sizes workspaces, and rejects invalid arguments
+before anything is enqueued (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_08542_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ttt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ttt_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert set(L.EXPORTED) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def prob(**kw):
+    base = dict(n_heads=16, d_head=64, d_hidden=256, n_tokens=87936, chunk_tokens=10992, stride_tok=0,
+                stride_head=0, eta=0.05, flags=7, io_dtype=L.TTT_F32)
+    base.update(kw)
+    return L.Problem(**base)
+
+
+def test_workspace_bytes(lib):
+    p = prob()
+    n1 = lib.ttt_workspace_bytes(ctypes.byref(p), 1)
+    n8 = lib.ttt_workspace_bytes(ctypes.byref(p), 8)
+    assert n1 > 0 and n8 >= n1
+    assert n1 >= 1024 * 2 * 64 * 256 * 4   # shard-partial slots
+    for bad in (dict(d_head=32), dict(d_hidden=192), dict(chunk_tokens=0), dict(n_heads=0),
+                dict(io_dtype=7), dict(flags=1 << 20), dict(stride_tok=3)):
+        assert lib.ttt_workspace_bytes(ctypes.byref(prob(**bad)), 1) == 0, bad
+    assert lib.ttt_workspace_bytes(ctypes.byref(p), 0) == 0
+    assert lib.ttt_workspace_bytes(None, 1) == 0
+
+
+FAKE = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+
+
+def fwd(lib, p, **ptrs):
+    a = dict(Q=FAKE, K=FAKE, V=FAKE, W1=FAKE, W2=FAKE, O=FAKE, W1T=None, W2T=None, ckpt=None, loss=None,
+             ws=FAKE, nws=1 << 40)
+    a.update(ptrs)
+    return lib.ttt_chunk_fwd(ctypes.byref(p), a["Q"], a["K"], a["V"], a["W1"], a["W2"], a["O"], a["W1T"],
+                             a["W2T"], a["ckpt"], a["loss"], a["ws"], a["nws"], None)
+
+
+def test_fwd_validation(lib):
+    assert fwd(lib, prob(d_head=32)) == L.TTT_ESHAPE
+    assert fwd(lib, prob(d_hidden=64)) == L.TTT_ESHAPE
+    assert fwd(lib, prob(chunk_tokens=0)) == L.TTT_EINVAL
+    assert fwd(lib, prob(eta=float("nan"))) == L.TTT_EINVAL
+    assert fwd(lib, prob(), Q=None) == L.TTT_EINVAL
+    assert fwd(lib, prob(), W1T=FAKE) == L.TTT_EINVAL             # W1_T without W2_T
+    assert fwd(lib, prob(flags=7 | L.TTT_SAVE_CKPT)) == L.TTT_EINVAL  # ckpt flag without buffer
+    assert fwd(lib, prob(flags=7), ckpt=FAKE) == L.TTT_EINVAL      # buffer without flag
+    assert fwd(lib, prob(flags=7 | L.TTT_EMIT_LOSS)) == L.TTT_EINVAL
+    assert fwd(lib, prob(), Q=ctypes.c_void_p((1 << 20) + 4)) == L.TTT_EINVAL  # misaligned
+    assert fwd(lib, prob(), ws=None) == L.TTT_EWORKSPACE
+    assert fwd(lib, prob(), nws=16) == L.TTT_EWORKSPACE
+    assert fwd(lib, prob(n_tokens=0)) == L.TTT_OK                  # nothing to do, nothing enqueued
+
+
+def test_batched_validation(lib):
+    p = prob(n_tokens=0)
+    cu = (ctypes.c_int64 * 4)(0, 10, 5, 20)  # non-monotone
+
+    def call(n, cu_arr, w0=0, cfg=None, **kw):
+        a = dict(Q=FAKE, ws=FAKE, nws=1 << 40)
+        a.update(kw)
+        return lib.ttt_batched_fwd(ctypes.byref(p), n, cu_arr, a["Q"], FAKE, FAKE, FAKE, FAKE, w0, FAKE, None,
+                                   None, cfg, a["ws"], a["nws"], None)
+    assert call(3, cu) == L.TTT_EINVAL
+    cu0 = (ctypes.c_int64 * 2)(5, 10)
+    assert call(1, cu0) == L.TTT_EINVAL                      # cu[0] != 0
+    ok = (ctypes.c_int64 * 3)(0, 0, 0)
+    assert call(0, ok) == L.TTT_EINVAL                       # no sequences
+    assert call(2, ok, w0=2) == L.TTT_EINVAL
+    assert call(2, ok) == L.TTT_OK                           # all empty: nothing enqueued
+    cfg = L.TileCfg(-1, 0)
+    good = (ctypes.c_int64 * 3)(0, 10, 30)
+    assert call(2, good, cfg=ctypes.byref(cfg)) == L.TTT_EINVAL
+    assert call(2, good, ws=None) == L.TTT_EWORKSPACE
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.ttt_status_string(s).startswith(b"TTT_")
+    assert lib.ttt_version() >= 100
