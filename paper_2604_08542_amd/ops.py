@@ -47,6 +47,16 @@ def _check_tokens(Q, K, V):
         raise ValueError("Q, K, V must share strides")
 
 
+def _like_tokens(Q, out):
+    """Output token tensor with exactly Q's strides (the ABI addresses every
+    token tensor with one (stride_tok, stride_head) pair)."""
+    if out is None:
+        return torch.empty_strided(Q.size(), Q.stride(), dtype=Q.dtype, device=Q.device)
+    if out.shape != Q.shape or out.stride() != Q.stride() or out.dtype != Q.dtype or out.device != Q.device:
+        raise ValueError("output token tensor must match Q's shape, strides, dtype and device")
+    return out
+
+
 def _check_w(W1, W2, H, lead=()):
     if W1.dtype != torch.float32 or W2.dtype != torch.float32:
         raise ValueError("fast weights are float32")
@@ -88,7 +98,7 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, save_ckpt, emit_loss, mma_bf16))
     C = n_chunks(N, chunk_tokens)
     dev = Q.device
-    O = out if out is not None else torch.empty_like(Q)
+    O = _like_tokens(Q, out)
     W1_T = torch.empty_like(W1) if want_final else None
     W2_T = torch.empty_like(W2) if want_final else None
     ckpt = torch.empty((C, H, 2 * d * h), dtype=torch.float32, device=dev) if save_ckpt else None
@@ -115,7 +125,7 @@ def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *
         raise ValueError("cu_seqlens[-1] must equal the packed token count")
     prob = problem(Q, h, 0, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
     dev = Q.device
-    O = out if out is not None else torch.empty_like(Q)
+    O = _like_tokens(Q, out)
     W1_T = torch.empty((B, H, d, h), dtype=torch.float32, device=dev) if want_final else None
     W2_T = torch.empty((B, H, h, d), dtype=torch.float32, device=dev) if want_final else None
     cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
