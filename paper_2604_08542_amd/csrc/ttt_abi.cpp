@@ -55,7 +55,7 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
 }
 
 struct WsLayout {
-  size_t partial, partial_loss, pp, total;
+  size_t partial, partial_loss, pp, adj, wlast, total;
   int64_t slot_cap;
 };
 
@@ -69,6 +69,11 @@ WsLayout ws_layout(const Shape& s, int64_t n_chains) {
   off = align_up(off + (size_t)L.slot_cap * sizeof(float));
   L.pp = off;
   off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
+  // backward only: two adjoint buffers and the recomputed last weights
+  L.adj = off;
+  off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
+  L.wlast = off;
+  off = align_up(off + (size_t)n_chains * 2 * s.dh() * sizeof(float));
   L.total = off;
   return L;
 }
@@ -208,6 +213,75 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
   return TTT_OK;
 }
 
+// Backward: recompute W_C from the last checkpoint, then walk s = C..0 with
+// one bwd-step launch (update adjoint of chunk s, apply adjoint of chunk s-1)
+// and one reduction launch each.
+ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K, const void* V,
+                          const float* ckpt, const void* dO, void* dQ, void* dK, void* dV, float* dW1_0,
+                          float* dW2_0, float* deta, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t H = S.H;
+  const WsLayout L = ws_layout(S, H);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  float* partial = at<float>(ws, L.partial);
+  float* pdeta = at<float>(ws, L.partial_loss);
+  float* adj[2] = {at<float>(ws, L.adj), at<float>(ws, L.adj) + H * 2 * dh};
+  float* wlast = at<float>(ws, L.wlast);
+  const int target = default_target_wgs(S);
+  const int nbpc = (int)((2 * dh / 4 + 255) / 256);
+  const int64_t tiles = (std::min(M, N) + TT - 1) / TT;
+  int64_t G = std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, std::max<int64_t>(tiles, 1),
+                                                      L.slot_cap / H}));
+  auto mlen = [&](int64_t c) { return (int32_t)std::min<int64_t>(M, N - c * M); };
+  if (C == 0) {
+    BwdReduceArgs r{};
+    r.dst1 = dW1_0; r.dst2 = dW2_0; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
+    r.deta_first = 1; r.G = 0; r.H = (int32_t)H; r.h = S.h;
+    return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
+  }
+  {  // W_C = W_{C-1} - eta * grad L_{C-1}(W_{C-1})
+    FwdStepArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = nullptr;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.w1_src = ckpt + (C - 1) * H * 2 * dh; a.w2_src = a.w1_src + dh; a.w_cstride = 2 * dh;
+    a.w_mod = (int32_t)H; a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G;
+    a.partial = partial; a.partial_loss = pdeta; a.n_active = 1;
+    a.seq_id[0] = 0; a.grad_start[0] = (C - 1) * M; a.grad_len[0] = mlen(C - 1);
+    a.app_start[0] = 0; a.app_len[0] = 0;
+    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+    UpdStepArgs u{};
+    u.w1_src = a.w1_src; u.w2_src = a.w2_src; u.w_cstride = a.w_cstride; u.w_mod = a.w_mod;
+    u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
+    u.partial = partial; u.partial_loss = pdeta; u.w_dst = wlast;
+    u.n_active = 1; u.seq_id[0] = 0; u.grad_len[0] = mlen(C - 1); u.is_last[0] = 0;
+    if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+  }
+  for (int64_t s = C; s >= 0; --s) {
+    BwdStepArgs b{};
+    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
+    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
+    b.w_src = s < C ? ckpt + s * H * 2 * dh : wlast;
+    b.wh_src = s < C ? adj[(s + 1) % 2] : nullptr;
+    b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta; b.G = (int32_t)G;
+    b.partial = partial; b.partial_deta = pdeta;
+    b.grad_start = s * M; b.grad_len = s < C ? mlen(s) : 0;
+    b.app_start = (s - 1) * M; b.app_len = s >= 1 ? mlen(s - 1) : 0;
+    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+    BwdReduceArgs r{};
+    r.wh_src = b.wh_src;
+    r.wh_dst = adj[s % 2];
+    r.dst1 = s == 0 ? dW1_0 : nullptr;
+    r.dst2 = s == 0 ? dW2_0 : nullptr;
+    r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
+    r.deta_first = s == C; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,9 +346,21 @@ ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64
 ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
                            const float* W2_0, const float* ckpt, const void* dO, void* dQ, void* dK, void* dV,
                            float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes, void* hip_stream) {
-  (void)p; (void)Q; (void)K; (void)V; (void)W1_0; (void)W2_0; (void)ckpt; (void)dO; (void)dQ; (void)dK;
-  (void)dV; (void)dW1_0; (void)dW2_0; (void)deta; (void)ws; (void)ws_bytes; (void)hip_stream;
-  return TTT_ENOTSUP;
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!Q || !K || !V || !ckpt || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
+    (void)W1_0; (void)W2_0;  // the checkpoint of chunk 0 holds W_0
+    for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
+                          (const void*)dW1_0, (const void*)dW2_0})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    return run_backward(p, S, Q, K, V, ckpt, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+                        static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
 }
 
 ttt_status_t ttt_profile_enable(int32_t on) {

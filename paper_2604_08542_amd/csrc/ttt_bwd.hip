@@ -1,0 +1,473 @@
+// Backward kernels of the chunked TTT chain: reverse mode through every
+// inner update, second-order terms through the inner gradient included, for
+// the outer loss sum <O, dO> (the forward is Sec. 4.2 Eq. 8 and Sec. 3.2
+// Eq. 3-4).
+//
+// Chunks are walked backwards.  With Wh the adjoint of W_{s+1} and W = W_s
+// recomputed from the checkpoint, one launch of ttt_bwd_step handles, per
+// token shard of every head:
+//   - the update adjoint of chunk s (recompute Z, A, E, P, D; then
+//       deta += -<K Wh1, D> - <A Wh2, E>,  dD = -eta K Wh1,
+//       dA = -eta E Wh2^T + dY W2^T,  dE = -eta A Wh2 + dP W2,
+//       dP = dD s'(Z),  dZ = dD P s''(Z) + dA s'(Z),  dY = (2/M) dE,
+//       dV = -dY,  dK = -eta D Wh1^T + dZ W1^T,
+//       token sums  dP^T E + A^T dY  and  K^T dZ),
+//   - the apply adjoint of chunk s-1, whose output used W_s
+//       (dZq = (dO W2^T) s'(Zq), token sums Aq^T dO and Q^T dZq,
+//        dQ = dZq W1^T),
+// and ttt_bwd_reduce adds the shard sums, in a fixed order, to Wh, giving the
+// adjoint of W_s.  The L2-normalisation adjoint maps dQ, dK, dV to the raw
+// inputs.
+//
+// Layout inside a work-group follows the forward kernel: wave w owns hidden
+// units [32w, 32w+32) for the products whose result has a hidden axis
+// (32x32 blocks with tokens in registers, which also feed the token-sum
+// products directly); products contracting the hidden axis read staged
+// [token][hidden] tiles from LDS as 16x16 blocks.  This first backward reads
+// its weight operands straight from memory (they are L2-resident per chain)
+// instead of keeping four weight matrices on chip.
+#include <hip/hip_runtime.h>
+
+#include "ttt_common.h"
+#include "ttt_internal.h"
+
+namespace ttt {
+
+// Hides a (wave-uniform) pointer's value from the optimiser so that loads
+// through it are not hoisted out of the token loop into registers.
+template <typename T>
+__device__ __forceinline__ T* opaque(T* ptr) {
+  asm volatile("" : "+v"(ptr));
+  return ptr;
+}
+
+template <typename IOT, bool BF, int NW>
+__global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
+  constexpr int HH = NW * 32;
+  constexpr int NT = NW * 64;
+  constexpr int EPT = D * TT / NT;
+  constexpr int TPR = D / EPT;
+  constexpr int DH = D * HH;
+  constexpr int LD = D + 4;  // f32 [token][d] tiles
+  using MT = std::conditional_t<BF, bf16, float>;
+  constexpr int AS_LD = HH + (BF ? 8 : 4);
+
+  __shared__ __attribute__((aligned(16))) float xs[TT * LD];    // K or Q rows (normalised)
+  __shared__ __attribute__((aligned(16))) float vs[TT * LD];    // V rows (normalised)
+  __shared__ __attribute__((aligned(16))) float es[TT * LD];    // E
+  __shared__ __attribute__((aligned(16))) float des[TT * LD];   // -eta A Wh2, then dE
+  __shared__ __attribute__((aligned(16))) float dys[TT * LD];   // dY, or dO rows for apply tiles
+  __shared__ __attribute__((aligned(16))) float dxs[TT * LD];   // dK or dQ before the norm adjoint
+  __shared__ __attribute__((aligned(16))) MT sta[TT * AS_LD];   // staged A, then D, or dZq
+  __shared__ __attribute__((aligned(16))) MT stb[TT * AS_LD];   // staged dP, then dZ
+  __shared__ float ninv[2][TT];   // 1 / max(||x||, eps) of the two staged row sets
+  __shared__ int nabove[2][TT];   // ||x|| > eps
+  __shared__ float red[NW];
+
+  // Lane-derived indices live in `li`, recomputed from an opaque thread id at
+  // the top of every tile iteration: the kernel's LDS exceeds the 64 KiB reach
+  // of LDS immediate offsets, and hoisting every per-lane address out of the
+  // token loop would otherwise exhaust the register file.
+  struct LaneIds {
+    int tid, w, l, l32, hf, l16, g4, hid, row, col0;
+  };
+  auto lane_ids = [](int t) {
+    LaneIds r;
+    r.tid = t; r.w = t >> 6; r.l = t & 63; r.l32 = t & 31; r.hf = (t & 63) >> 5; r.l16 = t & 15;
+    r.g4 = (t & 63) >> 4; r.hid = r.w * 32 + r.l32; r.row = t / TPR; r.col0 = (t % TPR) * EPT;
+    return r;
+  };
+  LaneIds li = lane_ids(threadIdx.x);
+  auto refresh = [&]() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    li = lane_ids(t);
+  };
+  const int lin = xcd_linear_block();
+  const int G = p.G;
+  const int head = lin / G, g = lin % G;
+  const float eta = p.eta;
+  const float* Wc0 = p.w_src + (int64_t)head * 2 * DH;                         // W1 [D][h], W2 [h][D]
+  const float* Wh0 = p.wh_src ? p.wh_src + (int64_t)head * 2 * DH : p.w_src;  // adjoint of W_{s+1}
+  const int64_t hoff = (int64_t)head * p.stride_head;
+  const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
+
+  // ---- operand helpers
+  auto w1 = [&](const float* W, int d, int hh) { return W[d * HH + hh]; };
+  auto w2 = [&](const float* W, int hh, int d) { return W[DH + hh * D + d]; };
+  // 32x32 block C[tok][li.hid] = X[tok][:] F, F(d, li.hid) given by fn.
+  auto th = [&](const float* X, auto fn) {
+    f32x16 c = {};
+    if constexpr (BF) {
+#pragma unroll 1
+      for (int m = 0; m < 4; ++m) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int d = 16 * m + 8 * li.hf + e;
+          a[e] = (bf16)X[li.l32 * LD + d];
+          b[e] = (bf16)fn(d, li.hid);
+        }
+        c = mma32(a, b, c);
+      }
+    } else {
+#pragma unroll 4
+      for (int s = 0; s < 32; ++s) {
+        const int d = 32 * li.hf + s;
+        c = mma32(X[li.l32 * LD + d], fn(d, li.hid), c);
+      }
+    }
+    return c;
+  };
+  // 16x16 block C[tok][d] (token block tb, feature block db) = S[tok][:] F,
+  // S staged [tok][hidden] in LDS, F(li.hid, d) given by fn.
+  auto td = [&](const MT* S, int tb, int db, auto fn) {
+    f32x4 c = {};
+    const int arow = 16 * tb + li.l16, dcol = 16 * db + li.l16;
+    if constexpr (BF) {
+#pragma unroll 1
+      for (int u = 0; u < HH / 32; ++u) {
+        const int k0 = (HH / 4) * li.g4 + 8 * u;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + k0]);
+        bf16x8 b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[e] = (bf16)fn(k0 + e, dcol);
+        c = mma16(a, b, c);
+      }
+    } else {
+#pragma unroll 2
+      for (int u = 0; u < HH / 16; ++u) {
+        const int k0 = (HH / 4) * li.g4 + 4 * u;
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + k0]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c = mma16(a[e], fn(k0 + e, dcol), c);
+      }
+    }
+    return c;
+  };
+  // gW1[db] (rows d, cols li.hid) += X[:, d]^T Yw ; gW2[db] (rows li.hid, cols d) += Yw^T X[:, d]
+  auto tok_sum_w1 = [&](f32x16 (&acc)[2], const float* X, const f32x16& Yw) {
+#pragma unroll
+    for (int db = 0; db < 2; ++db) {
+      const int dd = 32 * db + li.l32;
+      if constexpr (BF) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          bf16x8 a, b;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            a[e] = (bf16)X[c32_row(8 * m + e, li.hf) * LD + dd];
+            b[e] = (bf16)Yw[8 * m + e];
+          }
+          acc[db] = mma32(a, b, acc[db]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc[db] = mma32(X[c32_row(s, li.hf) * LD + dd], Yw[s], acc[db]);
+      }
+    }
+  };
+  auto tok_sum_w2 = [&](f32x16 (&acc)[2], const f32x16& Yw, const float* X) {
+#pragma unroll
+    for (int db = 0; db < 2; ++db) {
+      const int dd = 32 * db + li.l32;
+      if constexpr (BF) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          bf16x8 a, b;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            a[e] = (bf16)Yw[8 * m + e];
+            b[e] = (bf16)X[c32_row(8 * m + e, li.hf) * LD + dd];
+          }
+          acc[db] = mma32(a, b, acc[db]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc[db] = mma32(Yw[s], X[c32_row(s, li.hf) * LD + dd], acc[db]);
+      }
+    }
+  };
+  auto stage = [&](MT* S, const f32x16& Yw) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[c32_row(r, li.hf) * AS_LD + li.hid] = (MT)Yw[r];
+  };
+  // Load rows of a token tensor for tokens [t0, t0+nv) into an LDS tile,
+  // optionally L2-normalised (recording the norm data in set ns).
+  auto load_rows = [&](const void* base, int64_t t0, int nv, float* dst, bool do_norm, int ns) {
+    float x[EPT];
+    const bool valid = li.row < nv;
+    if (valid) {
+      load_vec<IOT, EPT>(static_cast<const IOT*>(base) + (t0 + li.row) * p.stride_tok + hoff + li.col0, x);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) x[i] = 0.f;
+    }
+    if (do_norm) {
+      float ss = 0.f;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
+#pragma unroll
+      for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+      const float nrm = sqrtf(ss);
+      const float inv = 1.0f / fmaxf(nrm, NORM_EPS);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) x[i] *= inv;
+      if (ns >= 0 && (li.tid % TPR) == 0) {
+        ninv[ns][li.row] = inv;
+        nabove[ns][li.row] = nrm > NORM_EPS;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) dst[li.row * LD + li.col0 + i] = x[i];
+  };
+  // Write dx~ = norm adjoint of dx (rows in LDS) for tokens [t0, t0+nv).
+  auto store_grad_rows = [&](void* base, int64_t t0, int nv, const float* dx, const float* xhat, bool did_norm,
+                             int ns, float sign) {
+    float v[EPT], xh[EPT];
+    float dot = 0.f;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      v[i] = sign * dx[li.row * LD + li.col0 + i];
+      xh[i] = xhat[li.row * LD + li.col0 + i];
+      dot = fmaf(v[i], xh[i], dot);
+    }
+    if (did_norm) {
+#pragma unroll
+      for (int m = 1; m < TPR; m <<= 1) dot += __shfl_xor(dot, m, 64);
+      const float inv = ninv[ns][li.row];
+      const bool above = nabove[ns][li.row];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) v[i] = above ? (v[i] - xh[i] * dot) * inv : v[i] * inv;
+    }
+    if (li.row < nv) store_vec<IOT, EPT>(static_cast<IOT*>(base) + (t0 + li.row) * p.stride_tok + hoff + li.col0, v);
+  };
+
+  f32x16 gw1[2] = {}, gw2[2] = {};
+  float deta_acc = 0.f;
+
+  // ------------------------------------------------ update adjoint of chunk s
+  const int gl = p.grad_len;
+  const int n_gt = (gl + TT - 1) / TT;
+  const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
+  for (int t = g; t < n_gt; t += G) {
+    const int64_t t0 = p.grad_start + (int64_t)t * TT;
+    const int nv = min(TT, gl - t * TT);
+    const float* Wc = opaque(Wc0);
+    const float* Wh = opaque(Wh0);
+    refresh();
+    load_rows(p.K, t0, nv, xs, norm_k, 0);
+    load_rows(p.V, t0, nv, vs, norm_v, 1);
+    __syncthreads();
+    // Z = K W1 is kept; A, s'(Z), s''(Z) are recomputed from it where needed.
+    const f32x16 Z = th(xs, [&](int d, int hh) { return w1(Wc, d, hh); });
+    {
+      f32x16 A;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) A[r] = Z[r] * sigmoid(Z[r]);
+      stage(sta, A);
+    }
+    __syncthreads();
+    // Y = A W2 -> E;  A Wh2 -> -eta A Wh2 and its deta term
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 y = td(sta, tb, db, [&](int hh, int d) { return w2(Wc, hh, d); });
+      const f32x4 aw = td(sta, tb, db, [&](int hh, int d) { return w2(Wh, hh, d); });
+      const int dcol = 16 * db + li.l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tok = 16 * tb + 4 * li.g4 + r;
+        const float E = e_scale * (y[r] - vs[tok * LD + dcol]);
+        es[tok * LD + dcol] = E;
+        des[tok * LD + dcol] = -eta * aw[r];
+        deta_acc -= aw[r] * E;
+      }
+    }
+    __syncthreads();
+    // P = E W2^T, D = P s'(Z) (staged), K Wh1 -> dD and its deta term,
+    // dP = dD s'(Z) (staged), dZ = dD P s''(Z)
+    f32x16 dP, dZ;
+    {
+      const f32x16 P = th(es, [&](int d, int hh) { return w2(Wc, hh, d); });
+      const f32x16 KW = th(xs, [&](int d, int hh) { return w1(Wh, d, hh); });
+      f32x16 Dm;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float z = Z[r];
+        const float sg = sigmoid(z);
+        const float a = z * sg;
+        const float s1 = fmaf(a, 1.0f - sg, sg);
+        const float s2 = sg * (1.0f - sg) * fmaf(z, 1.0f - 2.0f * sg, 2.0f);
+        Dm[r] = P[r] * s1;
+        deta_acc -= KW[r] * Dm[r];
+        const float dD = -eta * KW[r];
+        dP[r] = dD * s1;
+        dZ[r] = dD * P[r] * s2;
+      }
+      stage(sta, Dm);
+      stage(stb, dP);
+    }
+    __syncthreads();
+    // dE = -eta A Wh2 + dP W2 ; dY = (2/M) dE
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 de = td(stb, tb, db, [&](int hh, int d) { return w2(Wc, hh, d); });
+      const int dcol = 16 * db + li.l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tok = 16 * tb + 4 * li.g4 + r;
+        dys[tok * LD + dcol] = e_scale * (des[tok * LD + dcol] + de[r]);
+      }
+    }
+    __syncthreads();
+    // dA = -eta E Wh2^T + dY W2^T ; dZ += dA s'(Z) ; token sums
+    {
+      const f32x16 dA1 = th(es, [&](int d, int hh) { return w2(Wh, hh, d); });
+      const f32x16 dA2 = th(dys, [&](int d, int hh) { return w2(Wc, hh, d); });
+      f32x16 A;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float z = Z[r];
+        const float sg = sigmoid(z);
+        const float a = z * sg;
+        A[r] = a;
+        dZ[r] += (-eta * dA1[r] + dA2[r]) * fmaf(a, 1.0f - sg, sg);
+      }
+      tok_sum_w2(gw2, A, dys);
+    }
+    tok_sum_w2(gw2, dP, es);
+    tok_sum_w1(gw1, xs, dZ);
+    stage(stb, dZ);
+    __syncthreads();
+    // dK = -eta D Wh1^T + dZ W1^T
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 k1 = td(sta, tb, db, [&](int hh, int d) { return w1(Wh, d, hh); });
+      const f32x4 k2 = td(stb, tb, db, [&](int hh, int d) { return w1(Wc, d, hh); });
+      const int dcol = 16 * db + li.l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dxs[(16 * tb + 4 * li.g4 + r) * LD + dcol] = -eta * k1[r] + k2[r];
+    }
+    __syncthreads();
+    store_grad_rows(p.dK, t0, nv, dxs, xs, norm_k, 0, 1.0f);
+    store_grad_rows(p.dV, t0, nv, dys, vs, norm_v, 1, -1.0f);
+    __syncthreads();
+  }
+
+  // ------------------------------------------------ apply adjoint of chunk s-1
+  const int al = p.app_len;
+  const int n_at = (al + TT - 1) / TT;
+  for (int t = g; t < n_at; t += G) {
+    const int64_t t0 = p.app_start + (int64_t)t * TT;
+    const int nv = min(TT, al - t * TT);
+    const float* Wc = opaque(Wc0);
+    refresh();
+    load_rows(p.Q, t0, nv, xs, norm_q, 0);
+    load_rows(p.dO, t0, nv, dys, false, -1);
+    __syncthreads();
+    f32x16 Aq = th(xs, [&](int d, int hh) { return w1(Wc, d, hh); });
+    f32x16 dZq = th(dys, [&](int d, int hh) { return w2(Wc, hh, d); });
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float z = Aq[r];
+      const float sg = sigmoid(z);
+      const float a = z * sg;
+      dZq[r] *= fmaf(a, 1.0f - sg, sg);
+      Aq[r] = a;
+    }
+    tok_sum_w2(gw2, Aq, dys);
+    tok_sum_w1(gw1, xs, dZq);
+    stage(sta, dZq);
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 q1 = td(sta, tb, db, [&](int hh, int d) { return w1(Wc, d, hh); });
+      const int dcol = 16 * db + li.l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dxs[(16 * tb + 4 * li.g4 + r) * LD + dcol] = q1[r];
+    }
+    __syncthreads();
+    store_grad_rows(p.dQ, t0, nv, dxs, xs, norm_q, 0, 1.0f);
+    __syncthreads();
+  }
+
+  // ------------------------------------------------ shard partials
+  float* part = p.partial + ((int64_t)head * G + g) * (2 * DH);
+#pragma unroll
+  for (int db = 0; db < 2; ++db)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rr = c32_row(r, li.hf);
+      part[(32 * db + rr) * HH + li.hid] = gw1[db][r];
+      part[DH + (32 * li.w + rr) * D + 32 * db + li.l32] = gw2[db][r];
+    }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) deta_acc += __shfl_xor(deta_acc, m, 64);
+  if (li.l == 0) red[li.w] = deta_acc;
+  __syncthreads();
+  if (li.tid == 0) {
+    float s = 0.f;
+    for (int i = 0; i < NW; ++i) s += red[i];
+    p.partial_deta[(int64_t)head * G + g] = s;
+  }
+}
+
+// Wh_dst = Wh_src (0 if null) + sum of the G shard partials, in fixed order;
+// deta[head] (+)= sum of the dη partials.  dst may be split into W1 / W2
+// destinations (the final dW1_0 / dW2_0).
+__global__ __launch_bounds__(256) void ttt_bwd_reduce(BwdReduceArgs p) {
+  const int dh = D * p.h;
+  const int n4 = (2 * dh) / 4;
+  const int nbpc = (n4 + 255) / 256;
+  const int lin = xcd_linear_block();
+  const int head = lin / nbpc, k = lin % nbpc;
+  const int i4 = k * 256 + threadIdx.x;
+  if (i4 < n4) {
+    const int idx = 4 * i4;
+    f32x4 s = {0.f, 0.f, 0.f, 0.f};
+    if (p.wh_src) s = *reinterpret_cast<const f32x4*>(p.wh_src + (int64_t)head * 2 * dh + idx);
+    const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)head * p.G * 2 * dh) + i4;
+    for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+    if (p.dst1) {
+      if (idx < dh)
+        *reinterpret_cast<f32x4*>(p.dst1 + (int64_t)head * dh + idx) = s;
+      else
+        *reinterpret_cast<f32x4*>(p.dst2 + (int64_t)head * dh + (idx - dh)) = s;
+    } else {
+      *reinterpret_cast<f32x4*>(p.wh_dst + (int64_t)head * 2 * dh + idx) = s;
+    }
+  }
+  if (k == 0 && threadIdx.x == 0) {
+    float sd = p.deta_first ? 0.f : p.deta[head];
+    for (int gg = 0; gg < p.G; ++gg) sd += p.partial_deta[(int64_t)head * p.G + gg];
+    p.deta[head] = sd;
+  }
+}
+
+template <typename IOT, bool BF, int NW>
+static hipError_t launch_bwd_step_t(const BwdStepArgs& a, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL((ttt_bwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  if (h == 128) {
+    if (io_bf16) return launch_bwd_step_t<bf16, true, 4>(a, n_blocks, st);
+    return mma_bf16 ? launch_bwd_step_t<float, true, 4>(a, n_blocks, st)
+                    : launch_bwd_step_t<float, false, 4>(a, n_blocks, st);
+  }
+  if (io_bf16) return launch_bwd_step_t<bf16, true, 8>(a, n_blocks, st);
+  return mma_bf16 ? launch_bwd_step_t<float, true, 8>(a, n_blocks, st)
+                  : launch_bwd_step_t<float, false, 8>(a, n_blocks, st);
+}
+
+hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(ttt_bwd_reduce, dim3(n_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace ttt

@@ -175,4 +175,41 @@ struct UpdStepArgs {
   int32_t is_last[MAXS];
 };
 
+// One reverse chunk step of the backward for every head of one sequence:
+// the update adjoint of chunk s and the apply adjoint of chunk s-1.
+struct BwdStepArgs {
+  const void* Q;
+  const void* K;
+  const void* V;
+  const void* dO;
+  void* dQ;
+  void* dK;
+  void* dV;
+  int64_t stride_tok, stride_head;
+  const float* w_src;   // W_s per head: [W1 (D*h) | W2 (h*D)], head stride 2*D*h
+  const float* wh_src;  // adjoint of W_{s+1}, same layout (null when no update tile)
+  int32_t H;
+  uint32_t flags;
+  float eta;
+  int32_t G;
+  float* partial;       // [H*G][2*D*h]
+  float* partial_deta;  // [H*G]
+  int64_t grad_start;
+  int32_t grad_len;     // chunk s tokens (0: none)
+  int64_t app_start;
+  int32_t app_len;      // chunk s-1 tokens (0: none)
+};
+
+struct BwdReduceArgs {
+  const float* wh_src;  // previous adjoint (null = 0)
+  float* wh_dst;        // next adjoint [H][2*D*h] (unused when dst1 is set)
+  float* dst1;          // final split destinations dW1_0 [H][D][h], dW2_0 [H][h][D]; nullable
+  float* dst2;
+  const float* partial;
+  const float* partial_deta;
+  float* deta;          // [H]
+  int32_t deta_first;
+  int32_t G, H, h;
+};
+
 }  // namespace ttt

@@ -31,9 +31,15 @@ template <typename IOT, bool BF, int NW>
 __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   constexpr int HH = NW * 32;  // hidden size
   constexpr int NT = NW * 64;
-  constexpr int EPT = D * TT / NT;  // row elements per thread in P1
+  constexpr int EPT = D * TT / NT;  // row elements per thread when loading
   constexpr int TPR = D / EPT;
   using MT = std::conditional_t<BF, bf16, float>;
+  // BF16 operands: the gradient tile and the apply tile of one iteration are
+  // processed together, token rows are prefetched one iteration ahead and
+  // double-buffered in LDS (3 barriers per iteration).  FP32 operands need
+  // twice the LDS per staged tile, so gradient and apply tiles run in two
+  // loops with single-buffered LDS (4 barriers per tile), still prefetched.
+  constexpr int NB = BF ? 2 : 1;
   constexpr int XS_LD = D + (BF ? 8 : 4);
   constexpr int XT_LD = TT + 8;
   constexpr int VS_LD = D + 4;
@@ -41,13 +47,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   constexpr int W2T_LD = HH + (BF ? 8 : 4);
   constexpr int DH = D * HH;
 
-  __shared__ __attribute__((aligned(16))) MT xs[TT * XS_LD];
-  __shared__ __attribute__((aligned(16))) bf16 xts[BF ? D * XT_LD : 8];
-  __shared__ __attribute__((aligned(16))) float vs[TT * VS_LD];
-  __shared__ __attribute__((aligned(16))) MT as_[TT * AS_LD];
-  __shared__ __attribute__((aligned(16))) MT es[TT * XS_LD];
-  __shared__ __attribute__((aligned(16))) bf16 ets[BF ? D * XT_LD : 8];
-  __shared__ __attribute__((aligned(16))) MT w2t[D * W2T_LD];
+  __shared__ __attribute__((aligned(16))) MT xs[NB][TT * XS_LD];     // K rows (normalised)
+  __shared__ __attribute__((aligned(16))) bf16 xts[NB][BF ? D * XT_LD : 8];  // K^T (bf16 only)
+  __shared__ __attribute__((aligned(16))) float vs[NB][TT * VS_LD];  // V rows (normalised, f32)
+  __shared__ __attribute__((aligned(16))) MT qs[BF ? NB : 1][BF ? TT * XS_LD : 8];  // Q rows (bf16 path)
+  __shared__ __attribute__((aligned(16))) MT as_[TT * AS_LD];        // A = SiLU(K W1)
+  __shared__ __attribute__((aligned(16))) MT aqs[BF ? TT * AS_LD : 8];  // SiLU(Q W1) (bf16 path)
+  __shared__ __attribute__((aligned(16))) MT es[TT * XS_LD];         // E
+  __shared__ __attribute__((aligned(16))) bf16 ets[BF ? D * XT_LD : 8];  // E^T (bf16 only)
+  __shared__ __attribute__((aligned(16))) MT w2t[D * W2T_LD];        // W2^T
   __shared__ float red[NW];
 
   const int tid = threadIdx.x;
@@ -90,42 +98,70 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
   const int row = tid / TPR, col0 = (tid % TPR) * EPT;
   const int64_t hoff = (int64_t)head * p.stride_head;
+  const int gl = p.grad_len[ai], al = p.app_len[ai];
+  const int64_t gs = p.grad_start[ai], as0 = p.app_start[ai];
+  const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
+  const int my_g = n_gt > g ? (n_gt - g + G - 1) / G : 0;  // tiles of this work-group
+  const int my_a = n_at > g ? (n_at - g + G - 1) / G : 0;
+  const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
 
-  // Z = X W1 for this wave's hidden block (X = staged K or Q rows); returns
-  // the 32x32 result block (rows = tokens in registers, cols = hidden).
-  auto z_block = [&]() {
+  // ---- phase helpers
+  // raw row fetch (registers) for tile `it` of this work-group; zeros when
+  // the row is past the chunk end or the tile does not exist.
+  auto fetch_row = [&](const void* base, int64_t start, int len, int it, float (&x)[EPT]) {
+    const int tr = (g + it * G) * TT + row;  // token index within the chunk
+    if (tr < len) {
+      load_vec<IOT, EPT>(static_cast<const IOT*>(base) + (start + tr) * p.stride_tok + hoff + col0, x);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) x[i] = 0.f;
+    }
+  };
+  auto normalise = [&](float (&x)[EPT], bool do_norm) {
+    if (!do_norm) return;
+    float ss = 0.f;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
+#pragma unroll
+    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    const float inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) x[i] *= inv;
+  };
+  // Z = X W1 for this wave's hidden block: 32x32 result, rows = tokens.
+  auto z_block = [&](const MT* X) {
     f32x16 z = {};
     if constexpr (BF) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&xs[l32 * XS_LD + 16 * m + 8 * hf]);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
         z = mma32(a, w1b[m], z);
       }
     } else {
 #pragma unroll
       for (int s4 = 0; s4 < 8; ++s4) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&xs[l32 * XS_LD + 32 * hf + 4 * s4]);
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&X[l32 * XS_LD + 32 * hf + 4 * s4]);
 #pragma unroll
         for (int e = 0; e < 4; ++e) z = mma32(a[e], w1f[4 * s4 + e], z);
       }
     }
     return z;
   };
-  // 16x16 block (token block tb, feature block db) of (staged A) W2.
-  auto y_block = [&](int tb, int db) {
+  // 16x16 block (token block tb, feature block db) of S W2, S staged [tok][h].
+  auto y_block = [&](const MT* S, int tb, int db) {
     f32x4 y = {};
     const int arow = 16 * tb + l16, dcol = 16 * db + l16;
     if constexpr (BF) {
 #pragma unroll
       for (int u = 0; u < HH / 32; ++u) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&as_[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
         const bf16x8 b = *reinterpret_cast<const bf16x8*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 8 * u]);
         y = mma16(a, b, y);
       }
     } else {
 #pragma unroll
       for (int u = 0; u < HH / 16; ++u) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&as_[arow * AS_LD + (HH / 4) * g4 + 4 * u]);
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + (HH / 4) * g4 + 4 * u]);
         const f32x4 b = *reinterpret_cast<const f32x4*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 4 * u]);
 #pragma unroll
         for (int e = 0; e < 4; ++e) y = mma16(a[e], b[e], y);
@@ -133,122 +169,204 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     }
     return y;
   };
+  // A = SiLU(Z) staged to S; keeps s'(Z) and A (in za) for the gradient.
+  auto silu_stage = [&](f32x16& za, float (&s1)[16], MT* S) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float zr = za[r];
+      const float sg = sigmoid(zr);
+      const float av = zr * sg;
+      s1[r] = fmaf(av, 1.0f - sg, sg);
+      za[r] = av;
+      S[c32_row(r, hf) * AS_LD + hid] = (MT)av;
+    }
+  };
+  auto silu_stage_apply = [&](const f32x16& za, MT* S) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float zr = za[r];
+      S[c32_row(r, hf) * AS_LD + hid] = (MT)(zr * sigmoid(zr));
+    }
+  };
+  // Residual, loss and E for this wave's Y blocks (E staged for phase 4).
+  auto residual = [&](int b_vs, float& lacc) {
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 y = y_block(as_, tb, db);
+      const int dcol = 16 * db + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tok = 16 * tb + 4 * g4 + r;
+        const float R = y[r] - vs[b_vs][tok * VS_LD + dcol];
+        lacc = fmaf(R, R, lacc);
+        const float E = e_scale * R;
+        es[tok * XS_LD + dcol] = (MT)E;
+        if constexpr (BF) ets[dcol * XT_LD + tok] = (bf16)E;
+      }
+    }
+  };
+  auto apply_out = [&](const MT* S, int it) {
+    IOT* O = static_cast<IOT*>(p.O);
+    const int t_base = (g + it * G) * TT;
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+      const f32x4 y = y_block(S, tb, db);
+      const int dcol = 16 * db + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tok = 16 * tb + 4 * g4 + r;
+        if (t_base + tok < al) O[(as0 + t_base + tok) * p.stride_tok + hoff + dcol] = from_f<IOT>(y[r]);
+      }
+    }
+  };
+  // P = E W2^T, D = P * s'(Z), grad W1 += K^T D, grad W2 += A^T E.
+  auto grad_update = [&](int bx, const f32x16& za, const float (&s1)[16], f32x16 (&gw1)[2], f32x16 (&gw2)[2]) {
+    f32x16 pz = {};
+    if constexpr (BF) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
+        pz = mma32(a, w2b[m], pz);
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 8; ++s4) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&es[l32 * XS_LD + 32 * hf + 4 * s4]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pz = mma32(a[e], w2f[4 * s4 + e], pz);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) pz[r] *= s1[r];
+    if constexpr (BF) {
+      bf16x8 dpk[2], apk[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          dpk[m][e] = (bf16)pz[8 * m + e];
+          apk[m][e] = (bf16)za[8 * m + e];
+        }
+#pragma unroll
+      for (int db = 0; db < 2; ++db) {
+        const int dd = 32 * db + l32;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[bx][dd * XT_LD + 16 * m + 4 * hf]);
+          const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[bx][dd * XT_LD + 16 * m + 8 + 4 * hf]);
+          const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
+          gw1[db] = mma32(ka, dpk[m], gw1[db]);
+          const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
+          const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
+          const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
+          gw2[db] = mma32(apk[m], eb, gw2[db]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int db = 0; db < 2; ++db) {
+        const int dd = 32 * db + l32;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int tk = c32_row(s, hf);
+          gw1[db] = mma32(xs[bx][tk * XS_LD + dd], pz[s], gw1[db]);
+          gw2[db] = mma32(za[s], es[tk * XS_LD + dd], gw2[db]);
+        }
+      }
+    }
+  };
+  auto stage_kv = [&](int bx, float (&xk)[EPT], float (&xv)[EPT]) {
+    normalise(xk, norm_k);
+    normalise(xv, norm_v);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      xs[bx][row * XS_LD + col0 + i] = (MT)xk[i];
+      vs[bx][row * VS_LD + col0 + i] = xv[i];
+      if constexpr (BF) xts[bx][(col0 + i) * XT_LD + row] = (bf16)xk[i];
+    }
+  };
 
-  // ------------------------------------------------------------ gradient shard
-  const int gl = p.grad_len[ai];
-  if (gl > 0) {
-    const int64_t gs = p.grad_start[ai];
-    const int n_gt = (gl + TT - 1) / TT;
-    const float e_scale = 2.0f / (float)gl;
-    f32x16 gw1[2] = {}, gw2[2] = {};
-    float lacc = 0.f;
-    for (int t = g; t < n_gt; t += G) {
-      const int64_t t0 = gs + (int64_t)t * TT;
-      const int nv = min(TT, gl - t * TT);
-      {  // P1
-        float xk[EPT], xv[EPT], ik, iv;
-        const bool valid = row < nv;
-        const int64_t off = (t0 + row) * p.stride_tok + hoff + col0;
-        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.K) + (valid ? off : 0), valid, norm_k, xk, ik);
-        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.V) + (valid ? off : 0), valid, norm_v, xv, iv);
+  f32x16 gw1[2] = {}, gw2[2] = {};
+  float lacc = 0.f;
+  float rk[EPT], rv[EPT], rq[EPT];
+
+  if constexpr (BF) {
+    const int iters = max(my_g, my_a);
+    if (iters > 0) {
+      fetch_row(p.K, gs, my_g > 0 ? gl : 0, 0, rk);
+      fetch_row(p.V, gs, my_g > 0 ? gl : 0, 0, rv);
+      fetch_row(p.Q, as0, my_a > 0 ? al : 0, 0, rq);
+    }
+    for (int it = 0; it < iters; ++it) {
+      const int bx = it & 1;
+      const bool hg = it < my_g, ha = it < my_a;
+      // P1: normalise the prefetched rows into LDS buffer bx, prefetch next.
+      stage_kv(bx, rk, rv);
+      normalise(rq, norm_q);
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-          xs[row * XS_LD + col0 + i] = (MT)xk[i];
-          vs[row * VS_LD + col0 + i] = xv[i];
-          if constexpr (BF) xts[(col0 + i) * XT_LD + row] = (bf16)xk[i];
-        }
+      for (int i = 0; i < EPT; ++i) qs[bx][row * XS_LD + col0 + i] = (MT)rq[i];
+      if (it + 1 < iters) {
+        fetch_row(p.K, gs, it + 1 < my_g ? gl : 0, it + 1, rk);
+        fetch_row(p.V, gs, it + 1 < my_g ? gl : 0, it + 1, rv);
+        fetch_row(p.Q, as0, it + 1 < my_a ? al : 0, it + 1, rq);
       }
       __syncthreads();
-      // P2
-      f32x16 za = z_block();
+      // P2: Z = K W1 and Zq = Q W1, SiLU, stage both activations.
+      f32x16 za = {};
       float s1[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float zr = za[r];
-        const float sg = sigmoid(zr);
-        const float av = zr * sg;
-        s1[r] = fmaf(av, 1.0f - sg, sg);
-        za[r] = av;
-        as_[c32_row(r, hf) * AS_LD + hid] = (MT)av;
+      if (hg) {
+        za = z_block(xs[bx]);
+        silu_stage(za, s1, as_);
       }
-      bf16x8 apk[2];
-      if constexpr (BF) {
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) apk[m][e] = (bf16)za[8 * m + e];
+      if (ha) silu_stage_apply(z_block(qs[bx]), aqs);
+      __syncthreads();
+      // P3: Y -> residual -> E (gradient tile); O = SiLU(Q W1) W2 (apply tile).
+      if (hg) residual(bx, lacc);
+      if (ha) apply_out(aqs, it);
+      __syncthreads();
+      // P4: gradient outer products.
+      if (hg) grad_update(bx, za, s1, gw1, gw2);
+    }
+  } else {
+    // gradient tiles
+    if (my_g > 0) {
+      fetch_row(p.K, gs, gl, 0, rk);
+      fetch_row(p.V, gs, gl, 0, rv);
+    }
+    for (int it = 0; it < my_g; ++it) {
+      stage_kv(0, rk, rv);
+      if (it + 1 < my_g) {
+        fetch_row(p.K, gs, gl, it + 1, rk);
+        fetch_row(p.V, gs, gl, it + 1, rv);
       }
       __syncthreads();
-      // P3
-#pragma unroll
-      for (int bi = 0; bi < 8 / NW; ++bi) {
-        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-        const f32x4 y = y_block(tb, db);
-        const int dcol = 16 * db + l16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tok = 16 * tb + 4 * g4 + r;
-          const float R = y[r] - vs[tok * VS_LD + dcol];
-          lacc = fmaf(R, R, lacc);
-          const float E = e_scale * R;
-          es[tok * XS_LD + dcol] = (MT)E;
-          if constexpr (BF) ets[dcol * XT_LD + tok] = (bf16)E;
-        }
-      }
+      f32x16 za = z_block(xs[0]);
+      float s1[16];
+      silu_stage(za, s1, as_);
       __syncthreads();
-      // P4
-      f32x16 pz = {};
-      if constexpr (BF) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
-          pz = mma32(a, w2b[m], pz);
-        }
-      } else {
-#pragma unroll
-        for (int s4 = 0; s4 < 8; ++s4) {
-          const f32x4 a = *reinterpret_cast<const f32x4*>(&es[l32 * XS_LD + 32 * hf + 4 * s4]);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) pz = mma32(a[e], w2f[4 * s4 + e], pz);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) pz[r] *= s1[r];
-      if constexpr (BF) {
-        bf16x8 dpk[2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) dpk[m][e] = (bf16)pz[8 * m + e];
-#pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const int dd = 32 * db + l32;
-#pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[dd * XT_LD + 16 * m + 4 * hf]);
-            const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[dd * XT_LD + 16 * m + 8 + 4 * hf]);
-            const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
-            gw1[db] = mma32(ka, dpk[m], gw1[db]);
-            const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
-            const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
-            const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
-            gw2[db] = mma32(apk[m], eb, gw2[db]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const int dd = 32 * db + l32;
-#pragma unroll
-          for (int s = 0; s < 16; ++s) {
-            const int tk = c32_row(s, hf);
-            gw1[db] = mma32(xs[tk * XS_LD + dd], pz[s], gw1[db]);
-            gw2[db] = mma32(za[s], es[tk * XS_LD + dd], gw2[db]);
-          }
-        }
-      }
+      residual(0, lacc);
+      __syncthreads();
+      grad_update(0, za, s1, gw1, gw2);
       __syncthreads();
     }
+    // apply tiles
+    if (my_a > 0) fetch_row(p.Q, as0, al, 0, rq);
+    for (int it = 0; it < my_a; ++it) {
+      normalise(rq, norm_q);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) xs[0][row * XS_LD + col0 + i] = (MT)rq[i];
+      if (it + 1 < my_a) fetch_row(p.Q, as0, al, it + 1, rq);
+      __syncthreads();
+      silu_stage_apply(z_block(xs[0]), as_);
+      __syncthreads();
+      apply_out(as_, it);
+      __syncthreads();
+    }
+  }
+
+  if (gl > 0) {
     // Shard partials: grad W1 [D][h] then grad W2 [h][D].
     float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
 #pragma unroll
@@ -267,46 +385,6 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
       float s = 0.f;
       for (int i = 0; i < NW; ++i) s += red[i];
       p.partial_loss[(int64_t)slot * G + g] = s;
-    }
-  }
-
-  // ------------------------------------------------------------ apply shard
-  const int al = p.app_len[ai];
-  if (al > 0) {
-    const int64_t as0 = p.app_start[ai];
-    const int n_at = (al + TT - 1) / TT;
-    IOT* O = static_cast<IOT*>(p.O);
-    for (int t = g; t < n_at; t += G) {
-      const int64_t t0 = as0 + (int64_t)t * TT;
-      const int nv = min(TT, al - t * TT);
-      {
-        float xq[EPT], iq;
-        const bool valid = row < nv;
-        const int64_t off = (t0 + row) * p.stride_tok + hoff + col0;
-        load_row_norm<IOT, EPT>(static_cast<const IOT*>(p.Q) + (valid ? off : 0), valid, norm_q, xq, iq);
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) xs[row * XS_LD + col0 + i] = (MT)xq[i];
-      }
-      __syncthreads();
-      f32x16 za = z_block();
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float zr = za[r];
-        as_[c32_row(r, hf) * AS_LD + hid] = (MT)(zr * sigmoid(zr));
-      }
-      __syncthreads();
-#pragma unroll
-      for (int bi = 0; bi < 8 / NW; ++bi) {
-        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-        const f32x4 y = y_block(tb, db);
-        const int dcol = 16 * db + l16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tok = 16 * tb + 4 * g4 + r;
-          if (tok < nv) O[(t0 + tok) * p.stride_tok + hoff + dcol] = from_f<IOT>(y[r]);
-        }
-      }
-      __syncthreads();
     }
   }
 }

@@ -7,4 +7,6 @@
 namespace ttt {
 hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st);
+hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
+hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st);
 }  // namespace ttt

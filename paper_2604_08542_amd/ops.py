@@ -139,3 +139,64 @@ def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *
                              ctypes.byref(cfg) if cfg is not None else None, _ptr(ws), ws.numel(), _stream(dev))
     L.check(st, "ttt_batched_fwd")
     return dict(O=O, W1_T=W1_T, W2_T=W2_T)
+
+
+def chunk_bwd(Q, K, V, W1, W2, eta, chunk_tokens, ckpt, dO, *, norm=True, mma_bf16=False, ws=None):
+    """Backward of chunk_fwd for the outer loss sum <O, dO>.  `ckpt` is the
+    [C][H][2dh] checkpoint tensor of the forward (save_ckpt=True).  Returns
+    dQ, dK, dV (raw-input gradients, io dtype), dW1_0, dW2_0 and deta [H]."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    _check_tokens(Q, dO, dO)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    if dO.stride() != Q.stride():
+        raise ValueError("dO must share Q's strides")
+    prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    dQ, dK, dV = (_like_tokens(Q, None) for _ in range(3))
+    dW1 = torch.empty_like(W1)
+    dW2 = torch.empty_like(W2)
+    deta = torch.empty((H,), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(prob, 1, dev)
+    st = lib.ttt_chunk_bwd(ctypes.byref(prob), _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), _ptr(ckpt), _ptr(dO),
+                           _ptr(dQ), _ptr(dK), _ptr(dV), _ptr(dW1), _ptr(dW2), _ptr(deta), _ptr(ws), ws.numel(),
+                           _stream(dev))
+    L.check(st, "ttt_chunk_bwd")
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1, dW2_0=dW2, deta=deta)
+
+
+class TTTChunk(torch.autograd.Function):
+    """O = chunked TTT forward over one sequence, differentiable in
+    (Q, K, V, W1_0, W2_0, eta).  The forward saves the per-chunk weight
+    checkpoints; the backward recomputes each chunk from them in the HIP
+    backward kernels."""
+
+    @staticmethod
+    def forward(ctx, Q, K, V, W1, W2, eta, chunk_tokens, norm=True, mma_bf16=False):
+        eta_f = float(eta)
+        need = any(ctx.needs_input_grad[:6])
+        r = chunk_fwd(Q, K, V, W1, W2, eta_f, chunk_tokens, norm=norm, save_ckpt=need, mma_bf16=mma_bf16,
+                      want_final=False)
+        ctx.chunk_tokens, ctx.norm, ctx.mma_bf16, ctx.eta = chunk_tokens, norm, mma_bf16, eta_f
+        ctx.eta_is_tensor = isinstance(eta, torch.Tensor)
+        if need:
+            ctx.save_for_backward(Q, K, V, W1, W2, r["ckpt"])
+        return r["O"]
+
+    @staticmethod
+    def backward(ctx, dO):
+        Q, K, V, W1, W2, ckpt = ctx.saved_tensors
+        dO = dO.contiguous() if dO.stride() != Q.stride() else dO
+        if dO.stride() != Q.stride():
+            dO = torch.empty_strided(Q.size(), Q.stride(), dtype=Q.dtype, device=Q.device).copy_(dO)
+        g = chunk_bwd(Q, K, V, W1, W2, ctx.eta, ctx.chunk_tokens, ckpt, dO.to(Q.dtype), norm=ctx.norm,
+                      mma_bf16=ctx.mma_bf16)
+        deta = g["deta"].sum() if ctx.eta_is_tensor else None
+        return g["dQ"], g["dK"], g["dV"], g["dW1_0"], g["dW2_0"], deta, None, None, None
+
+
+def ttt_chunk(Q, K, V, W1, W2, eta, chunk_tokens, norm=True, mma_bf16=False):
+    """Differentiable chunked TTT forward (see TTTChunk)."""
+    return TTTChunk.apply(Q, K, V, W1, W2, eta, chunk_tokens, norm, mma_bf16)
