@@ -132,6 +132,27 @@ ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64
                              const float* W2_0, int32_t w0_per_seq, void* O, float* W1_T, float* W2_T,
                              const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes, void* hip_stream);
 
+/* Global Context Synchronization form over one sequence (Sec. 4.2, Eq. 10):
+ * every chunk's gradient is taken at the same initial weights W0 (chunk c
+ * normalised by its own M_c), the gradients are summed over chunks, one step
+ * W* = W0 - eta * sum_c grad L_c(W0) is applied, and every token's query is
+ * mapped with W*: O = f_{W*}(Q).  Equal to ttt_chunk_fwd when there is one
+ * chunk.  Buffers as in ttt_chunk_fwd; W1_T/W2_T receive W* (nullable);
+ * loss [H][C] (iff TTT_EMIT_LOSS) holds each chunk's loss at W0.
+ * TTT_SAVE_CKPT is not used (the only weights are W0 and W*). */
+ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
+                         const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
+                         float* loss, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Backward of ttt_gcs_fwd for sum <O, dO>: the adjoint of W* collects the
+ * apply adjoint of every token, each chunk's update adjoint is taken at W0
+ * against it, and dW0 = adjoint of W* + the sum of the chunks' terms.
+ * Outputs as in ttt_chunk_bwd; W* is recomputed, no checkpoint is needed. */
+ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
+                         const float* W1_0, const float* W2_0, const void* dO, void* dQ, void* dK,
+                         void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes,
+                         void* hip_stream);
+
 /* Benchmark instrumentation.  While enabled, every launch the library
  * enqueues is bracketed by a pair of HIP events on the launch stream (events
  * come from a pool the library owns; enabling clears earlier records).

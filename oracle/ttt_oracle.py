@@ -305,3 +305,103 @@ def outer_objective(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True
     """sum <O, dO>: the scalar whose gradient ttt_backward returns."""
     O = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)["O"]
     return float(np.sum(O * np.asarray(dO, np.float64)))
+
+
+# --------------------------------------------------------------------------
+# Global Context Synchronization form (Sec. 4.2, Eq. 10)
+# --------------------------------------------------------------------------
+
+def ttt_forward_gcs(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm=(True, True, True), act="silu"):
+    """GCS semantics for one sequence: every chunk's gradient is taken at the
+    same initial weights, the gradients are summed over chunks (Eq. 10: the
+    synchronised gradient is the sum of the per-chunk gradients), one step
+    W* = W0 - eta * g is applied, and every chunk's queries are mapped with
+    W*.  With one chunk this is the chain form.  Returns O, W1_T, W2_T (= W*)
+    and loss [H][C] (each chunk's loss at W0)."""
+    Q, K, V, W1_0, W2_0 = _as_f64(Q, K, V, W1_0, W2_0)
+    N, H, d = K.shape
+    bounds = chunk_bounds(N, chunk_tokens)
+    O = np.zeros((N, H, d))
+    W1_T = W1_0.copy()
+    W2_T = W2_0.copy()
+    loss = np.zeros((H, len(bounds)))
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        g1 = np.zeros_like(W1_0[hd])
+        g2 = np.zeros_like(W2_0[hd])
+        for c, (s, e) in enumerate(bounds):
+            G1, G2, l, _ = inner_grad(k[s:e], v[s:e], W1_0[hd], W2_0[hd], act)
+            g1 += G1
+            g2 += G2
+            loss[hd, c] = l
+        W1_T[hd] = W1_0[hd] - eta * g1
+        W2_T[hd] = W2_0[hd] - eta * g2
+        O[:, hd, :] = fast_forward(q, W1_T[hd], W2_T[hd], act)
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, loss=loss)
+
+
+def ttt_backward_gcs(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True, True), act="silu"):
+    """Reverse mode of ttt_forward_gcs for sum <O, dO>.  The adjoint of W*
+    collects the apply adjoint of every token; each chunk's update adjoint is
+    then taken at W0 with that same adjoint (the per-chunk formulas of
+    ttt_backward with W = W0), and dW0 = adjoint of W* + the sum over chunks
+    of their token sums."""
+    Q, K, V, W1_0, W2_0, dO = _as_f64(Q, K, V, W1_0, W2_0, dO)
+    N, H, d = K.shape
+    bounds = chunk_bounds(N, chunk_tokens)
+    fwd = ttt_forward_gcs(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)
+    dQ = np.zeros_like(Q)
+    dK = np.zeros_like(K)
+    dV = np.zeros_like(V)
+    dW1_0 = np.zeros_like(W1_0)
+    dW2_0 = np.zeros_like(W2_0)
+    deta = np.zeros(H)
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        W1, W2 = W1_0[hd], W2_0[hd]
+        W1s, W2s = fwd["W1_T"][hd], fwd["W2_T"][hd]
+        # apply adjoint over all tokens (O = s(q W1*) W2*)
+        Zq = q @ W1s
+        Aq, Sq1, _ = activation(Zq, act)
+        Wh2 = Aq.T @ dO[:, hd, :]
+        dZq = (dO[:, hd, :] @ W2s.T) * Sq1
+        Wh1 = q.T @ dZq
+        dq = dZq @ W1s.T
+        dk = np.zeros_like(k)
+        dv = np.zeros_like(v)
+        tot1, tot2 = Wh1.copy(), Wh2.copy()
+        for (s, e) in bounds:
+            m = e - s
+            kc, vc = k[s:e], v[s:e]
+            _, _, _, cc = inner_grad(kc, vc, W1, W2, act)
+            A, S1, S2 = cc["A"], cc["S1"], cc["S2"]
+            E, P, D = cc["E"], cc["P"], cc["D"]
+            kWh1 = kc @ Wh1
+            AWh2 = A @ Wh2
+            deta[hd] += -np.sum(kWh1 * D) - np.sum(AWh2 * E)
+            dD = -eta * kWh1
+            dkc = -eta * (D @ Wh1.T)
+            dA = -eta * (E @ Wh2.T)
+            dE = -eta * AWh2
+            dP = dD * S1
+            dZ = dD * P * S2
+            dE = dE + dP @ W2
+            tot2 = tot2 + dP.T @ E
+            dY = (2.0 / m) * dE
+            dv[s:e] += -dY
+            dA = dA + dY @ W2.T
+            tot2 = tot2 + A.T @ dY
+            dZ = dZ + dA * S1
+            dkc = dkc + dZ @ W1.T
+            tot1 = tot1 + kc.T @ dZ
+            dk[s:e] += dkc
+        dW1_0[hd] = tot1
+        dW2_0[hd] = tot2
+        dQ[:, hd, :] = l2norm_rows_bwd(Q[:, hd, :], dq) if norm[0] else dq
+        dK[:, hd, :] = l2norm_rows_bwd(K[:, hd, :], dk) if norm[1] else dk
+        dV[:, hd, :] = l2norm_rows_bwd(V[:, hd, :], dv) if norm[2] else dv
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1_0, dW2_0=dW2_0, deta=deta, fwd=fwd)

@@ -12,7 +12,7 @@ TTT_F32, TTT_BF16 = 0, 1
 TTT_NORM_Q, TTT_NORM_K, TTT_NORM_V = 1, 2, 4
 TTT_SAVE_CKPT, TTT_EMIT_LOSS, TTT_MMA_BF16 = 8, 16, 32
 
-EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd",
+EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd", "ttt_gcs_fwd", "ttt_gcs_bwd",
             "ttt_profile_enable", "ttt_profile_read", "ttt_status_string", "ttt_version")
 
 
@@ -67,6 +67,10 @@ def load(path: str = LIB_PATH):
     lib.ttt_batched_fwd.restype = st
     lib.ttt_status_string.argtypes = [st]
     lib.ttt_status_string.restype = ctypes.c_char_p
+    lib.ttt_gcs_fwd.argtypes = [P, vp, vp, vp, fp, fp, vp, fp, fp, fp, vp, sz, vp]
+    lib.ttt_gcs_fwd.restype = st
+    lib.ttt_gcs_bwd.argtypes = [P, vp, vp, vp, fp, fp, vp, vp, vp, vp, fp, fp, fp, vp, sz, vp]
+    lib.ttt_gcs_bwd.restype = st
     lib.ttt_profile_enable.argtypes = [ctypes.c_int32]
     lib.ttt_profile_enable.restype = st
     lib.ttt_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]

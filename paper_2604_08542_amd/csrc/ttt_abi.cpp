@@ -282,6 +282,154 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q,
   return TTT_OK;
 }
 
+// GCS forward: gradient launches over all chunks at W0 (entries = chunks),
+// one summing update into W*, one apply launch over all tokens.
+ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K, const void* V,
+                             const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T, float* loss,
+                             void* ws, size_t ws_bytes, hipStream_t st, float* wstar_out) {
+  const int64_t H = S.H;
+  const WsLayout L = ws_layout(S, H);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  float* partial = at<float>(ws, L.partial);
+  float* partial_loss = at<float>(ws, L.partial_loss);
+  float* wstar = wstar_out ? wstar_out : at<float>(ws, L.pp);
+  const int nbpc = (int)((2 * dh / 4 + 255) / 256);
+  const int64_t n_chains = C * H;
+  if (n_chains > L.slot_cap) return TTT_ENOTSUP;  // more chunks x heads than partial slots
+  const int64_t tiles = (std::min(M, N) + TT - 1) / TT;
+  int64_t G = (default_target_wgs(S) + n_chains - 1) / n_chains;
+  G = std::max<int64_t>(1, std::min<int64_t>({G, tiles, L.slot_cap / n_chains}));
+  for (int64_t base = 0; base < C; base += MAXS) {
+    const int na = (int)std::min<int64_t>(MAXS, C - base);
+    FwdStepArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = O;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.w1_src = W1_0; a.w2_src = W2_0; a.w_cstride = dh; a.w_mod = (int32_t)H;
+    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G;
+    const int64_t slot0 = base * H * G;
+    a.partial = partial + slot0 * 2 * dh;
+    a.partial_loss = partial_loss + slot0;
+    a.n_active = na;
+    for (int i = 0; i < na; ++i) {
+      const int64_t c = base + i;
+      a.seq_id[i] = 0;
+      a.grad_start[i] = c * M;
+      a.grad_len[i] = (int32_t)std::min<int64_t>(M, N - c * M);
+      a.app_start[i] = 0;
+      a.app_len[i] = 0;
+    }
+    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(na * H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+  }
+  UpdStepArgs u{};
+  u.w1_src = W1_0; u.w2_src = W2_0; u.w_cstride = dh; u.w_mod = (int32_t)H;
+  u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
+  u.partial = partial; u.partial_loss = partial_loss; u.w_dst = wstar;
+  u.wT1 = W1_T; u.wT2 = W2_T; u.loss = loss; u.loss_stride = (int32_t)C; u.chunk = 0;
+  u.gcs_chunks = (int32_t)C; u.gcs_M = (int32_t)M; u.gcs_last_len = (int32_t)(N - (C - 1) * M);
+  if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+  if (O) {
+    FwdStepArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = O;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.w1_src = wstar; a.w2_src = wstar + dh; a.w_cstride = 2 * dh; a.w_mod = (int32_t)H;
+    a.H = (int32_t)H; a.flags = p->flags;
+    const int64_t atiles = (N + TT - 1) / TT;
+    int64_t Ga = std::max<int64_t>(1, std::min<int64_t>((default_target_wgs(S) + H - 1) / H, atiles));
+    a.G = (int32_t)Ga;
+    a.partial = partial; a.partial_loss = partial_loss;
+    a.n_active = 1; a.seq_id[0] = 0;
+    a.grad_start[0] = 0; a.grad_len[0] = 0; a.app_start[0] = 0; a.app_len[0] = (int32_t)N;
+    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(H * Ga), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
+// GCS backward: W* recomputed; apply adjoint over all tokens at W* -> Wh;
+// then per chunk the update adjoint at W0 against the fixed Wh, accumulated.
+ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K, const void* V,
+                              const float* W1_0, const float* W2_0, const void* dO, void* dQ, void* dK, void* dV,
+                              float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t H = S.H;
+  const WsLayout L = ws_layout(S, H);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  float* partial = at<float>(ws, L.partial);
+  float* pdeta = at<float>(ws, L.partial_loss);
+  float* wstar = at<float>(ws, L.wlast);
+  float* wh = at<float>(ws, L.adj);                      // adjoint of W* (fixed)
+  float* acc[2] = {at<float>(ws, L.pp), at<float>(ws, L.pp) + H * 2 * dh};  // running dW0
+  float* w0 = at<float>(ws, L.adj) + H * 2 * dh;         // W0 packed [W1 | W2] per head
+  const int nbpc = (int)((2 * dh / 4 + 255) / 256);
+  if (C == 0) {  // no tokens: zero gradients
+    BwdReduceArgs r{};
+    r.dst1 = dW1_0; r.dst2 = dW2_0; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
+    r.deta_first = 1; r.G = 0; r.H = (int32_t)H; r.h = S.h;
+    return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
+  }
+  // W* (no outputs)
+  ttt_status_t e = run_gcs_forward(p, S, Q, K, V, W1_0, W2_0, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, st,
+                                   wstar);
+  if (e != TTT_OK) return e;
+  // W0 packed like a checkpoint: an update with zero partials copies it
+  {
+    UpdStepArgs u{};
+    u.w1_src = W1_0; u.w2_src = W2_0; u.w_cstride = dh; u.w_mod = (int32_t)H;
+    u.H = (int32_t)H; u.h = S.h; u.eta = 0.f; u.G = 0;
+    u.partial = partial; u.partial_loss = pdeta; u.w_dst = w0;
+    u.gcs_chunks = 1; u.gcs_M = 1; u.gcs_last_len = 1;
+    if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+  }
+  const int target = default_target_wgs(S);
+  auto grid_g = [&](int64_t len) {
+    const int64_t tiles = (len + TT - 1) / TT;
+    return std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, std::max<int64_t>(tiles, 1),
+                                                   L.slot_cap / H}));
+  };
+  // apply adjoint of all tokens at W*  ->  Wh (and dQ), deta starts at 0
+  {
+    BwdStepArgs b{};
+    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
+    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
+    b.w_src = wstar; b.wh_src = nullptr; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    const int64_t G = grid_g(N);
+    b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
+    b.grad_start = 0; b.grad_len = 0; b.app_start = 0; b.app_len = (int32_t)N;
+    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+    BwdReduceArgs r{};
+    r.wh_src = nullptr; r.wh_dst = wh; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
+    r.deta_first = 1; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+  }
+  // update adjoint of each chunk at W0 against Wh, accumulated on top of Wh
+  const float* prev = wh;
+  for (int64_t c = 0; c < C; ++c) {
+    const int32_t len = (int32_t)std::min<int64_t>(M, N - c * M);
+    BwdStepArgs b{};
+    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
+    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
+    b.w_src = w0; b.wh_src = wh; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    const int64_t G = grid_g(len);
+    b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
+    b.grad_start = c * M; b.grad_len = len; b.app_start = 0; b.app_len = 0;
+    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+    BwdReduceArgs r{};
+    r.wh_src = prev; r.wh_dst = acc[c % 2];
+    r.dst1 = c == C - 1 ? dW1_0 : nullptr; r.dst2 = c == C - 1 ? dW2_0 : nullptr;
+    r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
+    r.deta_first = 0; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+    prev = acc[c % 2];
+  }
+  return TTT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -358,6 +506,48 @@ ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K,
       if (q && !aligned16(q)) return TTT_EINVAL;
     return run_backward(p, S, Q, K, V, ckpt, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
                         static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                         const float* W2_0, void* O, float* W1_T, float* W2_T, float* loss, void* ws, size_t ws_bytes,
+                         void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+    if (p->flags & TTT_SAVE_CKPT) return TTT_EINVAL;
+    if (((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
+    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
+                          (const void*)W2_T})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (p->n_tokens == 0) return TTT_OK;
+    return run_gcs_forward(p, S, Q, K, V, W1_0, W2_0, O, W1_T, W2_T, loss, ws, ws_bytes,
+                           static_cast<hipStream_t>(hip_stream), nullptr);
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                         const float* W2_0, const void* dO, void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0,
+                         float* deta, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (!W1_0 || !W2_0 || !dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!Q || !K || !V || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
+    if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_EINVAL;
+    for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)W1_0,
+                          (const void*)W2_0, (const void*)dW1_0, (const void*)dW2_0})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    return run_gcs_backward(p, S, Q, K, V, W1_0, W2_0, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+                            static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;
   }

@@ -173,6 +173,11 @@ struct UpdStepArgs {
   int32_t seq_id[MAXS];
   int32_t grad_len[MAXS];
   int32_t is_last[MAXS];
+  // Global Context Synchronization: when gcs_chunks > 0 the grid covers the
+  // H heads of one sequence and each head sums the partials of all
+  // gcs_chunks chunk entries (entry e, slot (e*H + head)*G + g); chunk e has
+  // gcs_M tokens except the last (gcs_last_len).
+  int32_t gcs_chunks, gcs_M, gcs_last_len;
 };
 
 // One reverse chunk step of the backward for every head of one sequence:

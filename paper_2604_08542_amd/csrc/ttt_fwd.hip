@@ -398,15 +398,29 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
   const int nbpc = (n4 + 255) / 256;
   const int lin = xcd_linear_block();
   const int slot = lin / nbpc, k = lin % nbpc;
-  const int ai = slot / p.H, head = slot % p.H;
-  const int gl = p.grad_len[ai];
+  const bool gcs = p.gcs_chunks > 0;
+  const int ai = gcs ? 0 : slot / p.H, head = gcs ? slot : slot % p.H;
+  const int gl = gcs ? 1 : p.grad_len[ai];
   if (gl <= 0) return;
-  const int chain = p.seq_id[ai] * p.H + head;
+  const int chain = gcs ? head : p.seq_id[ai] * p.H + head;
+  const int n_ent = gcs ? p.gcs_chunks : 1;
   const int i4 = k * 256 + threadIdx.x;
   if (i4 < n4) {
-    const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)slot * p.G * 2 * dh) + i4;
-    f32x4 s = part[0];
-    for (int gg = 1; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+    // fixed order: entries, then shards; four independent partial sums
+    f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0, s3 = s0;
+    for (int e = 0; e < n_ent; ++e) {
+      const int64_t sl = gcs ? (int64_t)e * p.H + head : slot;
+      const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + sl * p.G * 2 * dh) + i4;
+      int gg = 0;
+      for (; gg + 4 <= p.G; gg += 4) {
+        s0 += part[(int64_t)gg * n4];
+        s1 += part[(int64_t)(gg + 1) * n4];
+        s2 += part[(int64_t)(gg + 2) * n4];
+        s3 += part[(int64_t)(gg + 3) * n4];
+      }
+      for (; gg < p.G; ++gg) s0 += part[(int64_t)gg * n4];
+    }
+    const f32x4 s = (s0 + s1) + (s2 + s3);
     const int idx = 4 * i4;
     const int64_t wc = (int64_t)(chain % p.w_mod) * p.w_cstride;
     const f32x4 wv = idx < dh ? *reinterpret_cast<const f32x4*>(p.w1_src + wc + idx)
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
     const f32x4 wn = wv - p.eta * s;
     *reinterpret_cast<f32x4*>(p.w_dst + (int64_t)chain * 2 * dh + idx) = wn;
     if (p.ckpt) *reinterpret_cast<f32x4*>(p.ckpt + (int64_t)head * 2 * dh + idx) = wv;
-    if (p.is_last[ai] && p.wT1) {
+    if ((gcs || p.is_last[ai]) && p.wT1) {
       if (idx < dh)
         *reinterpret_cast<f32x4*>(p.wT1 + (int64_t)chain * dh + idx) = wn;
       else
@@ -422,9 +436,13 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
     }
   }
   if (k == 0 && threadIdx.x == 0 && p.loss) {
-    float sl = 0.f;
-    for (int gg = 0; gg < p.G; ++gg) sl += p.partial_loss[(int64_t)slot * p.G + gg];
-    p.loss[(int64_t)head * p.loss_stride + p.chunk] = sl / (float)gl;
+    for (int e = 0; e < n_ent; ++e) {
+      const int64_t sl = gcs ? (int64_t)e * p.H + head : slot;
+      const int len = gcs ? (e + 1 < n_ent ? p.gcs_M : p.gcs_last_len) : gl;
+      float sum = 0.f;
+      for (int gg = 0; gg < p.G; ++gg) sum += p.partial_loss[sl * p.G + gg];
+      p.loss[(int64_t)head * p.loss_stride + (gcs ? e : p.chunk)] = sum / (float)len;
+    }
   }
 }
 

@@ -130,6 +130,9 @@ def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *
     W2_T = torch.empty((B, H, h, d), dtype=torch.float32, device=dev) if want_final else None
     cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
     cfg = None
+    if tile_cfg is None:
+        from .tune import lookup
+        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), B * H)
     if tile_cfg is not None:
         cfg = L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
     if ws is None:
@@ -200,3 +203,48 @@ class TTTChunk(torch.autograd.Function):
 def ttt_chunk(Q, K, V, W1, W2, eta, chunk_tokens, norm=True, mma_bf16=False):
     """Differentiable chunked TTT forward (see TTTChunk)."""
     return TTTChunk.apply(Q, K, V, W1, W2, eta, chunk_tokens, norm, mma_bf16)
+
+
+def gcs_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, emit_loss=False, mma_bf16=False, want_final=True,
+            out=None, ws=None):
+    """Global Context Synchronization forward over one sequence: the chunks'
+    gradients at W0 are summed, one step gives W*, O = f_{W*}(Q)."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, emit_loss=emit_loss, mma_bf16=mma_bf16))
+    dev = Q.device
+    O = _like_tokens(Q, out)
+    W1_T = torch.empty_like(W1) if want_final else None
+    W2_T = torch.empty_like(W2) if want_final else None
+    loss = torch.empty((H, n_chunks(N, chunk_tokens)), dtype=torch.float32, device=dev) if emit_loss else None
+    if ws is None:
+        ws = workspace(prob, 1, dev)
+    st = lib.ttt_gcs_fwd(ctypes.byref(prob), _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), _ptr(O), _ptr(W1_T),
+                         _ptr(W2_T), _ptr(loss), _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_gcs_fwd")
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, loss=loss)
+
+
+def gcs_bwd(Q, K, V, W1, W2, eta, chunk_tokens, dO, *, norm=True, mma_bf16=False, ws=None):
+    """Backward of gcs_fwd for sum <O, dO>."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    _check_tokens(Q, dO, dO)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    if dO.stride() != Q.stride():
+        raise ValueError("dO must share Q's strides")
+    prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    dQ, dK, dV = (_like_tokens(Q, None) for _ in range(3))
+    dW1 = torch.empty_like(W1)
+    dW2 = torch.empty_like(W2)
+    deta = torch.empty((H,), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(prob, 1, dev)
+    st = lib.ttt_gcs_bwd(ctypes.byref(prob), _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), _ptr(dO), _ptr(dQ),
+                         _ptr(dK), _ptr(dV), _ptr(dW1), _ptr(dW2), _ptr(deta), _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_gcs_bwd")
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1, dW2_0=dW2, deta=deta)

@@ -1,0 +1,49 @@
+"""GPU parity of the Global Context Synchronization form (Sec. 4.2, Eq. 10)
+against the FP64 oracle, forward and backward, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from gpu_util import TOL, host, inputs, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def ops():
+    from paper_2604_08542_amd import ops
+    return ops
+
+
+@pytest.mark.parametrize("N,H,h,M,eta,io", [(2500, 2, 256, 600, 0.05, "f32"), (1374 * 4, 1, 128, 1374, 0.1, "f32"),
+                                            (2000, 2, 256, 700, 0.05, "bf16")])
+def test_gcs_forward(gpu, N, H, h, M, eta, io):
+    x, d = inputs(N, H, h, seed=200 + N, io=io)
+    r = ops().gcs_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, emit_loss=True)
+    torch.cuda.synchronize()
+    ref = orc.ttt_forward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M)
+    errs = dict(O=rel(host(r["O"]), ref["O"]), W1_T=rel(host(r["W1_T"]), ref["W1_T"]),
+                dW2=rel(host(r["W2_T"]) - x["W2"], ref["W2_T"] - x["W2"]), loss=rel(host(r["loss"]), ref["loss"]))
+    print(f"gcs fwd N={N} H={H} h={h} M={M} {io}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL[io], (k, v)
+
+
+def test_gcs_one_chunk_equals_chain(gpu):
+    x, d = inputs(900, 2, 128, seed=5, io="f32")
+    a = ops().gcs_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], 0.1, 900)
+    b = ops().chunk_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], 0.1, 900)
+    assert rel(host(a["O"]), host(b["O"])) <= 1e-6
+
+
+@pytest.mark.parametrize("N,H,h,M,eta,io", [(1300, 2, 256, 500, 0.05, "f32"), (700, 2, 128, 300, 0.2, "f32"),
+                                            (1000, 2, 256, 400, 0.05, "bf16")])
+def test_gcs_backward(gpu, N, H, h, M, eta, io):
+    x, d = inputs(N, H, h, seed=300 + N, io=io, with_dO=True)
+    g = ops().gcs_bwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, d["dO"])
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M, x["dO"])
+    errs = {k: rel(host(g[k]), ref[k]) for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0", "deta")}
+    print(f"gcs bwd N={N} H={H} h={h} M={M} {io}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL[io], (k, v)
