@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-heads", type=int, default=16)
     ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
+    ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -88,6 +89,89 @@ def run_variant(w, dev_inputs, io, steps, warmup, lib):
     )
 
 
+def time_fn(fn, steps, warmup, lib):
+    """Wall time per call (synchronised) and per-kind kernel times from the
+    library's event instrumentation over the timed calls."""
+    import ctypes
+
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    lib.ttt_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    lib.ttt_profile_read(4, ms, n)
+    lib.ttt_profile_enable(0)
+    kinds = ["fwd_step", "update", "bwd_step", "bwd_reduce"]
+    per = {k: dict(ms_per_call=ms[i] / steps, launches_per_call=n[i] / steps,
+                   avg_launch_us=ms[i] / max(n[i], 1) * 1e3) for i, k in enumerate(kinds) if n[i]}
+    return (t1 - t0) * 1e3 / steps, per, out
+
+
+def extra_variants(steps, warmup, lib):
+    """The other forms on their own workloads: GCS forward (same layer
+    workload), forward+backward (differentiation workload), batched forward
+    (8 uneven sequences)."""
+    import torch
+
+    from paper_2604_08542_amd import ops
+    from workloads import WORKLOADS, make_inputs_torch
+    res = {}
+    # GCS forward on the layer workload, BF16 and FP32 operands
+    w = WORKLOADS["layer16_64f_chunk8f"]
+    for io in ("bf16", "f32"):
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
+        ms, per, _ = time_fn(lambda: ops.gcs_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta,
+                                                 w.chunk_tokens), steps, warmup, lib)
+        kms = per["fwd_step"]["ms_per_call"]
+        ach = alg_flops(w) / (kms * 1e-3) / 1e12
+        res[f"gcs_fwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                    kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
+                                                               unit="TFLOP/s", frac=ach / PEAK[io]))
+        del dev
+    # forward + backward on the differentiation workload
+    w = WORKLOADS["layer16_32f_chunk4f_bwd"]
+    for io in ("bf16", "f32"):
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io, with_dO=True)
+
+        def fb():
+            f = ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                              save_ckpt=True, want_final=False)
+            return ops.chunk_bwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                 f["ckpt"], dev["dO"])
+        ms, per, _ = time_fn(fb, max(2, steps // 2), 1, lib)
+        # algorithmic: forward 14 d h + backward 28 d h per token-head
+        fl = 42.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads
+        bms = per["bwd_step"]["ms_per_call"]
+        bach = 28.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (bms * 1e-3) / 1e12
+        res[f"fwd_bwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                    alg_tflops_per_s=fl / (ms * 1e-3) / 1e12, kernels=per,
+                                    bwd_step_roofline=dict(bound="mfma", achieved=bach, peak=PEAK[io],
+                                                           unit="TFLOP/s", frac=bach / PEAK[io]))
+        del dev
+    # batched forward: 8 uneven sequences, BF16
+    w = WORKLOADS["batch8_uneven_chunk8f_bf16"]
+    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16")
+    cu = w.cu_seqlens()
+    O = torch.empty_like(dev["Q"])
+    ms, per, _ = time_fn(lambda: ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta,
+                                                 w.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
+    kms = per["fwd_step"]["ms_per_call"]
+    ach = alg_flops(w) / (kms * 1e-3) / 1e12
+    res["batched_fwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                   kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                                              unit="TFLOP/s", frac=ach / PEAK["bf16"]))
+    del dev, O
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(w, host_inputs, gpu_out, n_heads):
     """Time the FP64 oracle on the host for `n_heads` heads of the same
     inputs (a bounded sample of the workload) and compare those heads."""
@@ -134,6 +218,12 @@ def main():
         print(f"# {io}: {variants[io]['ms_per_step']:.3f} ms/step, "
               f"{variants[io]['tokens_per_s']:.4g} tokens/s, step-kernel "
               f"{variants[io]['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    extra = {}
+    if not a.no_extra:
+        extra = extra_variants(a.steps, a.warmup, lib)
+        for k, v in extra.items():
+            print(f"# {k}: {v['ms_per_step']:.3f} ms/step, {v['tokens_per_s']:.4g} tokens/s", file=sys.stderr,
+                  flush=True)
     if a.copy_calib:
         src = torch.empty(128 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -175,6 +265,7 @@ def main():
         "speedup_bf16_over_f32": (variants["f32"]["ms_per_step"] / variants["bf16"]["ms_per_step"]
                                   if "f32" in variants and "bf16" in variants else None),
         "rel_err_vs_oracle_sampled_heads": errs,
+        "other_forms": extra,
     }
     print(json.dumps(line))
 

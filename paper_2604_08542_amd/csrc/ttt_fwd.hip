@@ -55,7 +55,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   __shared__ __attribute__((aligned(16))) MT aqs[BF ? TT * AS_LD : 8];  // SiLU(Q W1) (bf16 path)
   __shared__ __attribute__((aligned(16))) MT es[TT * XS_LD];         // E
   __shared__ __attribute__((aligned(16))) bf16 ets[BF ? D * XT_LD : 8];  // E^T (bf16 only)
-  __shared__ __attribute__((aligned(16))) MT w2t[D * W2T_LD];        // W2^T
+  __shared__ __attribute__((aligned(16))) MT w2t[BF ? 8 : D * W2T_LD];  // W2^T (FP32 path)
   __shared__ float red[NW];
 
   const int tid = threadIdx.x;
@@ -71,10 +71,25 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
   const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
 
-  // W2^T in LDS (B operand of Y = A W2 over the full hidden axis).
-  for (int idx = tid; idx < DH; idx += NT) {
-    const int hh = idx / D, dd = idx % D;
-    w2t[dd * W2T_LD + hh] = (MT)W2[idx];
+  // B operand of Y = A W2 over the full hidden axis: FP32 path from LDS
+  // (W2^T), BF16 path from registers (each wave keeps the W2 columns of the
+  // 16-wide feature blocks it produces).
+  if constexpr (!BF) {
+    for (int idx = tid; idx < DH; idx += NT) {
+      const int hh = idx / D, dd = idx % D;
+      w2t[dd * W2T_LD + hh] = (MT)W2[idx];
+    }
+  }
+  bf16x8 w2y[BF ? 8 / NW : 1][BF ? HH / 32 : 1];
+  if constexpr (BF) {
+#pragma unroll
+    for (int bi = 0; bi < 8 / NW; ++bi) {
+      const int dcol = 16 * ((w + NW * bi) >> 1) + l16;
+#pragma unroll
+      for (int u = 0; u < HH / 32; ++u)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w2y[bi][u][e] = (bf16)W2[((HH / 4) * g4 + 8 * u + e) * D + dcol];
+    }
   }
   // Register-resident operand slices of this wave's hidden block.
   bf16x8 w1b[4], w2b[4];
@@ -147,16 +162,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     }
     return z;
   };
-  // 16x16 block (token block tb, feature block db) of S W2, S staged [tok][h].
-  auto y_block = [&](const MT* S, int tb, int db) {
+  // 16x16 block (token block tb, feature block db = the wave's bi-th) of
+  // S W2, S staged [tok][h].
+  auto y_block = [&](const MT* S, int tb, int db, int bi) {
     f32x4 y = {};
     const int arow = 16 * tb + l16, dcol = 16 * db + l16;
     if constexpr (BF) {
 #pragma unroll
       for (int u = 0; u < HH / 32; ++u) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 8 * u]);
-        y = mma16(a, b, y);
+        y = mma16(a, w2y[bi][u], y);
       }
     } else {
 #pragma unroll
@@ -193,7 +208,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 y = y_block(as_, tb, db);
+      const f32x4 y = y_block(as_, tb, db, bi);
       const int dcol = 16 * db + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 y = y_block(S, tb, db);
+      const f32x4 y = y_block(S, tb, db, bi);
       const int dcol = 16 * db + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
