@@ -405,3 +405,75 @@ def ttt_backward_gcs(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, Tru
         dK[:, hd, :] = l2norm_rows_bwd(K[:, hd, :], dk) if norm[1] else dk
         dV[:, hd, :] = l2norm_rows_bwd(V[:, hd, :], dv) if norm[2] else dv
     return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1_0, dW2_0=dW2_0, deta=deta, fwd=fwd)
+
+
+# --------------------------------------------------------------------------
+# The paper's own adaptive memory unit: SwiGLU fast network (Supp. A),
+# dot-product inner loss (Sec. 4.2, Eq. 9), token-wise step sizes (Eq. 8)
+# --------------------------------------------------------------------------
+
+def swiglu_forward(x, W1, W2, W3):
+    """f_W(x) = (SiLU(x W1) * (x W3)) W2 for rows x (W1, W3: [d][h], W2: [h][d])."""
+    s, _, _ = activation(x @ W1)
+    return (s * (x @ W3)) @ W2
+
+
+def swiglu_dot_loss(k, v, eta_tok, W1, W2, W3):
+    """sum_i eta_i * ( - f_W(k_i)^T v_i ): the chunk's weighted dot-product
+    loss whose gradient is the update of Eq. 8 (the step size lives inside)."""
+    y = swiglu_forward(k, W1, W2, W3)
+    return float(-np.sum(eta_tok[:, None] * y * v))
+
+
+def swiglu_dot_grad(k, v, eta_tok, W1, W2, W3):
+    """Hand-derived gradient of swiglu_dot_loss w.r.t. (W1, W2, W3).
+
+    Z1 = k W1, Z3 = k W3, S = SiLU(Z1), Hd = S * Z3, E = -eta_i v_i (does not
+    depend on W), grad W2 = Hd^T E, dHd = E W2^T, dZ3 = dHd * S,
+    dZ1 = dHd * Z3 * s'(Z1), grad W1 = k^T dZ1, grad W3 = k^T dZ3."""
+    Z1 = k @ W1
+    Z3 = k @ W3
+    S, S1, _ = activation(Z1)
+    Hd = S * Z3
+    E = -eta_tok[:, None] * v
+    G2 = Hd.T @ E
+    dH = E @ W2.T
+    G3 = k.T @ (dH * S)
+    G1 = k.T @ (dH * Z3 * S1)
+    return G1, G2, G3
+
+
+def ttt_forward_swiglu(Q, K, V, W1_0, W2_0, W3_0, eta_tok, chunk_tokens, sync="chain", norm=(True, True, True)):
+    """The paper's AMU over one sequence.  eta_tok [N][H] are the token-wise
+    step sizes (predicted from the tokens in the paper; an input here).
+    sync="chain": each chunk updates W then maps its queries (Eq. 8 then
+    Eq. 4, chunks in sequence order); sync="gcs": all chunks' gradients at W0
+    are summed, one update, all queries mapped with the result (Eq. 10).
+    Returns O, W1_T, W2_T, W3_T."""
+    Q, K, V, W1_0, W2_0, W3_0, eta_tok = _as_f64(Q, K, V, W1_0, W2_0, W3_0, eta_tok)
+    N, H, d = K.shape
+    bounds = chunk_bounds(N, chunk_tokens)
+    O = np.zeros((N, H, d))
+    WT = [W1_0.copy(), W2_0.copy(), W3_0.copy()]
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        W = [W1_0[hd].copy(), W2_0[hd].copy(), W3_0[hd].copy()]
+        if sync == "chain":
+            for (s, e) in bounds:
+                G = swiglu_dot_grad(k[s:e], v[s:e], eta_tok[s:e, hd], *W)
+                W = [W[i] - G[i] for i in range(3)]
+                O[s:e, hd, :] = swiglu_forward(q[s:e], *W)
+        elif sync == "gcs":
+            tot = [np.zeros_like(x) for x in W]
+            for (s, e) in bounds:
+                G = swiglu_dot_grad(k[s:e], v[s:e], eta_tok[s:e, hd], *W)
+                tot = [tot[i] + G[i] for i in range(3)]
+            W = [W[i] - tot[i] for i in range(3)]
+            O[:, hd, :] = swiglu_forward(q, *W)
+        else:
+            raise ValueError(sync)
+        for i in range(3):
+            WT[i][hd] = W[i]
+    return dict(O=O, W1_T=WT[0], W2_T=WT[1], W3_T=WT[2])
