@@ -404,6 +404,326 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   }
 }
 
+// BF16-operand chunk step, software-pipelined over token tiles.  Iteration
+// i holds, between two barriers each,
+//   phase A: Y_i = A_i W2 -> residual -> E_i (staged), O_i = Aq_i W2 (stored),
+//            Z_{i+1} = K_{i+1} W1 -> SiLU -> A_{i+1} (staged), Zq_{i+1} = Q_{i+1} W1
+//   phase B: P_i = E_i W2^T, D_i = P_i s'(Z_i), grad W1 += K_i^T D_i,
+//            grad W2 += A_i^T E_i, SiLU(Zq_{i+1}) -> Aq_{i+1} (staged),
+//            rows of tile i+2 normalised into LDS, rows of tile i+3 prefetched
+// so that every phase mixes matrix-core products with the transcendental-heavy
+// activations of the neighbouring tile.  -log2(e) is folded into the W1
+// operand (the exponent comes straight out of the product) and -ln(2) into
+// the W2 operand of Y and O; the A-side gradient is rescaled once at the end.
+// Per-tile register state (packed A, s'(Z) in f16, packed Zq) is held for two
+// tiles, so the loop is unrolled by two to keep register indices static.
+template <typename IOT, int NW>
+__global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
+  constexpr int HH = NW * 32;
+  constexpr int NT = NW * 64;
+  constexpr int EPT = D * TT / NT;
+  constexpr int TPR = D / EPT;
+  constexpr int XS_LD = D + 8;
+  constexpr int XT_LD = TT + 8;
+  constexpr int VS_LD = D + 4;
+  constexpr int AS_LD = HH + 8;
+  constexpr int DH = D * HH;
+  constexpr float LOG2E = 1.4426950408889634f;
+  constexpr float LN2 = 0.6931471805599453f;
+  typedef _Float16 h16;
+  typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
+  __shared__ __attribute__((aligned(16))) bf16 xs[3][TT * XS_LD];    // K rows
+  __shared__ __attribute__((aligned(16))) bf16 xts[3][D * XT_LD];    // K^T
+  __shared__ __attribute__((aligned(16))) float vs[2][TT * VS_LD];   // V rows (f32)
+  __shared__ __attribute__((aligned(16))) bf16 qs[2][TT * XS_LD];    // Q rows
+  __shared__ __attribute__((aligned(16))) bf16 as_[2][TT * AS_LD];   // A' = -log2(e) SiLU(K W1)
+  __shared__ __attribute__((aligned(16))) bf16 aqs[2][TT * AS_LD];   // -log2(e) SiLU(Q W1)
+  __shared__ __attribute__((aligned(16))) bf16 es[2][TT * XS_LD];    // E
+  __shared__ __attribute__((aligned(16))) bf16 ets[2][D * XT_LD];    // E^T
+  __shared__ float red[NW];
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, l32 = l & 31, hf = l >> 5, l16 = l & 15, g4 = l >> 4;
+  const int lin = xcd_linear_block();
+  const int G = p.G;
+  const int slot = lin / G, g = lin % G;
+  const int ai = slot / p.H, head = slot % p.H;
+  const int chain = p.seq_id[ai] * p.H + head;
+  const int hid = w * 32 + l32;
+  const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+
+  bf16x8 w1b[4], w2b[4], w2y[8 / NW][HH / 32];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      w1b[m][e] = (bf16)(-LOG2E * W1[(16 * m + 8 * hf + e) * HH + hid]);
+      w2b[m][e] = (bf16)W2[hid * D + 16 * m + 8 * hf + e];
+    }
+#pragma unroll
+  for (int bi = 0; bi < 8 / NW; ++bi) {
+    const int dcol = 16 * ((w + NW * bi) >> 1) + l16;
+#pragma unroll
+    for (int u = 0; u < HH / 32; ++u)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w2y[bi][u][e] = (bf16)(-LN2 * W2[((HH / 4) * g4 + 8 * u + e) * D + dcol]);
+  }
+
+  const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
+  const int row = tid / TPR, col0 = (tid % TPR) * EPT;
+  const int64_t hoff = (int64_t)head * p.stride_head;
+  const int gl = p.grad_len[ai], al = p.app_len[ai];
+  const int64_t gs = p.grad_start[ai], as0 = p.app_start[ai];
+  const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
+  const int my_g = n_gt > g ? (n_gt - g + G - 1) / G : 0;
+  const int my_a = n_at > g ? (n_at - g + G - 1) / G : 0;
+  const int iters = max(my_g, my_a);
+  const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
+
+  // prefetched raw rows kept in the io type (4 or 8 elements per thread)
+  typedef IOT iovec __attribute__((ext_vector_type(EPT)));
+  iovec rk, rv, rq;
+  auto fetch = [&](int it) {
+    const int tr = (g + it * G) * TT + row;
+    const bool kv = it < my_g && tr < gl, qv = it < my_a && tr < al;
+    const iovec zero = {};
+    rk = zero;
+    rv = zero;
+    rq = zero;
+    if (kv) {
+      rk = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.K) + (gs + tr) * p.stride_tok + hoff + col0);
+      rv = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.V) + (gs + tr) * p.stride_tok + hoff + col0);
+    }
+    if (qv) rq = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.Q) + (as0 + tr) * p.stride_tok + hoff + col0);
+  };
+  auto normalise = [&](float (&x)[EPT], bool do_norm) {
+    if (!do_norm) return;
+    float ss = 0.f;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
+#pragma unroll
+    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    const float inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) x[i] *= inv;
+  };
+  // normalise the fetched rows of tile `it` into LDS buffers
+  auto stage_rows = [&](int it) {
+    const int b3 = it % 3, b2 = it & 1;
+    float fk[EPT], fv[EPT], fq[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      fk[i] = (float)rk[i];
+      fv[i] = (float)rv[i];
+      fq[i] = (float)rq[i];
+    }
+    normalise(fk, norm_k);
+    normalise(fv, norm_v);
+    normalise(fq, norm_q);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      xs[b3][row * XS_LD + col0 + i] = (bf16)fk[i];
+      xts[b3][(col0 + i) * XT_LD + row] = (bf16)fk[i];
+      vs[b2][row * VS_LD + col0 + i] = fv[i];
+      qs[b2][row * XS_LD + col0 + i] = (bf16)fq[i];
+    }
+  };
+  auto z_block = [&](const bf16* X) {
+    f32x16 z = {};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
+      z = mma32(a, w1b[m], z);
+    }
+    return z;
+  };
+  auto y_block = [&](const bf16* S, int tb, int bi) {
+    f32x4 y = {};
+    const int arow = 16 * tb + l16;
+#pragma unroll
+    for (int u = 0; u < HH / 32; ++u) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
+      y = mma16(a, w2y[bi][u], y);
+    }
+    return y;
+  };
+  // z' = -log2(e) z:  sigma = 1/(1+2^z'),  A' = z' sigma = -log2(e) SiLU(z),
+  // s'(z) = sigma + A (1 - sigma) = sigma + A' ln2 (sigma - 1)
+  auto act_grad = [&](const f32x16& z, bf16x8 (&apk)[2], h16x2 (&s1h)[8], bf16* S) {
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+      float av[2], sv[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float zz = z[r + j];
+        const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zz));
+        av[j] = zz * sg;
+        sv[j] = fmaf(av[j], fmaf(sg, LN2, -LN2), sg);
+      }
+      apk[r >> 3][(r & 7)] = (bf16)av[0];
+      apk[r >> 3][(r & 7) + 1] = (bf16)av[1];
+      s1h[r >> 1] = h16x2{(h16)sv[0], (h16)sv[1]};
+      S[c32_row(r, hf) * AS_LD + hid] = apk[r >> 3][(r & 7)];
+      S[c32_row(r + 1, hf) * AS_LD + hid] = apk[r >> 3][(r & 7) + 1];
+    }
+  };
+  auto act_apply = [&](const bf16x8 (&zq)[2], bf16* S) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float zz = (float)zq[r >> 3][r & 7];
+      const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zz));
+      S[c32_row(r, hf) * AS_LD + hid] = (bf16)(zz * sg);
+    }
+  };
+
+  f32x16 gw1[2] = {}, gw2[2] = {};
+  float lacc = 0.f;
+  bf16x8 apk[2][2];       // per tile parity: packed A' (token-contraction operand)
+  h16x2 s1h[2][8];        // per tile parity: s'(Z) in f16 pairs
+  bf16x8 zqp[2];          // Zq' of the next tile, packed
+
+  // phase A of iteration `it` (tile parity P = it & 1)
+  auto phase_a = [&](int it, auto PC) {
+    constexpr int P = decltype(PC)::value;
+    if (it < my_g) {
+#pragma unroll
+      for (int bi = 0; bi < 8 / NW; ++bi) {
+        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+        const f32x4 y = y_block(as_[P], tb, bi);
+        const int dcol = 16 * db + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int tok = 16 * tb + 4 * g4 + r;
+          const float R = y[r] - vs[P][tok * VS_LD + dcol];
+          lacc = fmaf(R, R, lacc);
+          const bf16 E = (bf16)(e_scale * R);
+          es[P][tok * XS_LD + dcol] = E;
+          ets[P][dcol * XT_LD + tok] = E;
+        }
+      }
+    }
+    if (it < my_a) {
+      IOT* O = static_cast<IOT*>(p.O);
+      const int t_base = (g + it * G) * TT;
+#pragma unroll
+      for (int bi = 0; bi < 8 / NW; ++bi) {
+        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+        const f32x4 y = y_block(aqs[P], tb, bi);
+        const int dcol = 16 * db + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int tok = 16 * tb + 4 * g4 + r;
+          if (t_base + tok < al) O[(as0 + t_base + tok) * p.stride_tok + hoff + dcol] = from_f<IOT>(y[r]);
+        }
+      }
+    }
+    if (it + 1 < iters) {
+      const int nb3 = (it + 1) % 3;
+      if (it + 1 < my_g) act_grad(z_block(xs[nb3]), apk[P ^ 1], s1h[P ^ 1], as_[P ^ 1]);
+      if (it + 1 < my_a) {
+        const f32x16 zq = z_block(qs[P ^ 1]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) zqp[r >> 3][r & 7] = (bf16)zq[r];
+      }
+    }
+  };
+  // phase B of iteration `it`
+  auto phase_b = [&](int it, auto PC) {
+    constexpr int P = decltype(PC)::value;
+    if (it < my_g) {
+      const int b3 = it % 3;
+      f32x16 pz = {};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[P][l32 * XS_LD + 16 * m + 8 * hf]);
+        pz = mma32(a, w2b[m], pz);
+      }
+      bf16x8 dpk[2];
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const h16x2 sv = s1h[P][r >> 1];
+        dpk[r >> 3][r & 7] = (bf16)(pz[r] * (float)sv[0]);
+        dpk[r >> 3][(r & 7) + 1] = (bf16)(pz[r + 1] * (float)sv[1]);
+      }
+#pragma unroll
+      for (int db = 0; db < 2; ++db) {
+        const int dd = 32 * db + l32;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 4 * hf]);
+          const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 8 + 4 * hf]);
+          const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
+          gw1[db] = mma32(ka, dpk[m], gw1[db]);
+          const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 4 * hf]);
+          const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 8 + 4 * hf]);
+          const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
+          gw2[db] = mma32(apk[P][m], eb, gw2[db]);
+        }
+      }
+    }
+    if (it + 1 < my_a) act_apply(zqp, aqs[P ^ 1]);
+    if (it + 2 < iters) {
+      stage_rows(it + 2);
+      if (it + 3 < iters) fetch(it + 3);
+    }
+  };
+
+  if (iters > 0) {
+    // prologue: rows of tiles 0 and 1 staged, activations of tile 0 staged
+    fetch(0);
+    stage_rows(0);
+    if (iters > 1) fetch(1);
+    __syncthreads();
+    if (my_g > 0) act_grad(z_block(xs[0]), apk[0], s1h[0], as_[0]);
+    if (my_a > 0) {
+      const f32x16 zq = z_block(qs[0]);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) zqp[r >> 3][r & 7] = (bf16)zq[r];
+      act_apply(zqp, aqs[0]);
+    }
+    if (iters > 1) {
+      stage_rows(1);
+      if (iters > 2) fetch(2);
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; it += 2) {
+      phase_a(it, std::integral_constant<int, 0>{});
+      __syncthreads();
+      phase_b(it, std::integral_constant<int, 0>{});
+      __syncthreads();
+      if (it + 1 < iters) {
+        phase_a(it + 1, std::integral_constant<int, 1>{});
+        __syncthreads();
+        phase_b(it + 1, std::integral_constant<int, 1>{});
+        __syncthreads();
+      }
+    }
+  }
+
+  if (gl > 0) {
+    float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = c32_row(r, hf);
+        part[(32 * db + rr) * HH + hid] = gw1[db][r];
+        part[DH + (32 * w + rr) * D + 32 * db + l32] = -LN2 * gw2[db][r];
+      }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) lacc += __shfl_xor(lacc, m, 64);
+    if (l == 0) red[w] = lacc;
+    __syncthreads();
+    if (tid == 0) {
+      float s = 0.f;
+      for (int i = 0; i < NW; ++i) s += red[i];
+      p.partial_loss[(int64_t)slot * G + g] = s;
+    }
+  }
+}
+
 // Fixed-order reduction of the G shard partials of each active chain and the
 // step W_{s+1} = W_s - eta * grad.  Also writes the checkpoint W_s, the final
 // weights after a sequence's last chunk, and the chunk's inner loss.
@@ -464,7 +784,10 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
 // ----------------------------------------------------------------- launchers
 template <typename IOT, bool BF, int NW>
 static hipError_t launch_fwd_step_t(const FwdStepArgs& a, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL((ttt_fwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  if constexpr (BF)
+    hipLaunchKernelGGL((ttt_fwd_step_bf<IOT, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  else
+    hipLaunchKernelGGL((ttt_fwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
