@@ -43,6 +43,16 @@ __device__ __forceinline__ f32x4 mma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Two floats to a bf16 pair (one v_cvt_pk_bf16_f32, round to nearest even).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2_t));
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(bf16x8, (u32x4){a, b, c, d});
+}
+
 // Row index held by result register r of a 32x32 block in lane-half hf.
 __device__ __forceinline__ constexpr int c32_row(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
 

@@ -424,7 +424,10 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   constexpr int EPT = D * TT / NT;
   constexpr int TPR = D / EPT;
   constexpr int XS_LD = D + 8;
-  constexpr int XT_LD = TT + 8;
+  // 36: transposed [d][token] tiles are written by 16 lanes at stride 4 rows
+  // and read as 8-byte runs by 32 lanes; an 18-dword row pitch makes both
+  // patterns bank-conflict free and keeps 8-byte alignment.
+  constexpr int XT_LD = TT + 4;
   constexpr int VS_LD = D + 4;
   constexpr int AS_LD = HH + 8;
   constexpr int DH = D * HH;
@@ -454,21 +457,43 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
   const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
 
+  // Register-resident operands, packed once; the empty asm pins each packed
+  // word so that the compiler keeps it instead of re-deriving it from the
+  // source floats inside the token loop.
   bf16x8 w1b[4], w2b[4], w2y[8 / NW][HH / 32];
+  auto pin8 = [](bf16x8& v) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    asm volatile("" : "+v"(u));
+    v = __builtin_bit_cast(bf16x8, u);
+  };
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m) {
+    uint32_t a[4], b[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      w1b[m][e] = (bf16)(-LOG2E * W1[(16 * m + 8 * hf + e) * HH + hid]);
-      w2b[m][e] = (bf16)W2[hid * D + 16 * m + 8 * hf + e];
+    for (int e = 0; e < 8; e += 2) {
+      a[e / 2] = pack_bf16x2(-LOG2E * W1[(16 * m + 8 * hf + e) * HH + hid],
+                             -LOG2E * W1[(16 * m + 8 * hf + e + 1) * HH + hid]);
+      b[e / 2] = pack_bf16x2(W2[hid * D + 16 * m + 8 * hf + e], W2[hid * D + 16 * m + 8 * hf + e + 1]);
     }
+    w1b[m] = as_bf16x8(a[0], a[1], a[2], a[3]);
+    w2b[m] = as_bf16x8(b[0], b[1], b[2], b[3]);
+    pin8(w1b[m]);
+    pin8(w2b[m]);
+  }
 #pragma unroll
   for (int bi = 0; bi < 8 / NW; ++bi) {
     const int dcol = 16 * ((w + NW * bi) >> 1) + l16;
 #pragma unroll
-    for (int u = 0; u < HH / 32; ++u)
+    for (int u = 0; u < HH / 32; ++u) {
+      uint32_t c[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) w2y[bi][u][e] = (bf16)(-LN2 * W2[((HH / 4) * g4 + 8 * u + e) * D + dcol]);
+      for (int e = 0; e < 8; e += 2)
+        c[e / 2] = pack_bf16x2(-LN2 * W2[((HH / 4) * g4 + 8 * u + e) * D + dcol],
+                               -LN2 * W2[((HH / 4) * g4 + 8 * u + e + 1) * D + dcol]);
+      w2y[bi][u] = as_bf16x8(c[0], c[1], c[2], c[3]);
+      pin8(w2y[bi][u]);
+    }
   }
 
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
@@ -482,22 +507,35 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   const int iters = max(my_g, my_a);
   const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
 
-  // prefetched raw rows kept in the io type (4 or 8 elements per thread)
+  // prefetched raw rows kept in the io type (4 or 8 elements per thread);
+  // running row pointers advance by one tile stride per fetch.
   typedef IOT iovec __attribute__((ext_vector_type(EPT)));
   iovec rk, rv, rq;
-  auto fetch = [&](int it) {
-    const int tr = (g + it * G) * TT + row;
-    const bool kv = it < my_g && tr < gl, qv = it < my_a && tr < al;
+  const int64_t tile_step = (int64_t)G * TT * p.stride_tok;
+  const int64_t row0 = (int64_t)(g * TT + row) * p.stride_tok + hoff + col0;
+  const IOT* kp = static_cast<const IOT*>(p.K) + gs * p.stride_tok + row0;
+  const IOT* vp = static_cast<const IOT*>(p.V) + gs * p.stride_tok + row0;
+  const IOT* qp = static_cast<const IOT*>(p.Q) + as0 * p.stride_tok + row0;
+  int tr_next = g * TT + row;  // token index (in the chunk) of the next fetch
+  int it_next = 0;
+  auto fetch = [&]() {
+    const bool kv = it_next < my_g && tr_next < gl, qv = it_next < my_a && tr_next < al;
     const iovec zero = {};
     rk = zero;
     rv = zero;
     rq = zero;
     if (kv) {
-      rk = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.K) + (gs + tr) * p.stride_tok + hoff + col0);
-      rv = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.V) + (gs + tr) * p.stride_tok + hoff + col0);
+      rk = *reinterpret_cast<const iovec*>(kp);
+      rv = *reinterpret_cast<const iovec*>(vp);
     }
-    if (qv) rq = *reinterpret_cast<const iovec*>(static_cast<const IOT*>(p.Q) + (as0 + tr) * p.stride_tok + hoff + col0);
+    if (qv) rq = *reinterpret_cast<const iovec*>(qp);
+    kp += tile_step;
+    vp += tile_step;
+    qp += tile_step;
+    tr_next += G * TT;
+    ++it_next;
   };
+  // 1 / max(||x||, eps) = rsq(max(||x||^2, eps^2))
   auto normalise = [&](float (&x)[EPT], bool do_norm) {
     if (!do_norm) return;
     float ss = 0.f;
@@ -505,7 +543,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
 #pragma unroll
     for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
-    const float inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
+    const float inv = __builtin_amdgcn_rsqf(fmaxf(ss, NORM_EPS * NORM_EPS));
 #pragma unroll
     for (int i = 0; i < EPT; ++i) x[i] *= inv;
   };
@@ -522,12 +560,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     normalise(fk, norm_k);
     normalise(fv, norm_v);
     normalise(fq, norm_q);
+    uint16_t* xt16 = reinterpret_cast<uint16_t*>(xts[b3]);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      xs[b3][row * XS_LD + col0 + i] = (bf16)fk[i];
-      xts[b3][(col0 + i) * XT_LD + row] = (bf16)fk[i];
+    for (int i = 0; i < EPT; i += 2) {
+      const uint32_t kp = pack_bf16x2(fk[i], fk[i + 1]);
+      *reinterpret_cast<uint32_t*>(&xs[b3][row * XS_LD + col0 + i]) = kp;
+      *reinterpret_cast<uint32_t*>(&qs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fq[i], fq[i + 1]);
+      xt16[(col0 + i) * XT_LD + row] = (uint16_t)kp;
+      xt16[(col0 + i + 1) * XT_LD + row] = (uint16_t)(kp >> 16);
       vs[b2][row * VS_LD + col0 + i] = fv[i];
-      qs[b2][row * XS_LD + col0 + i] = (bf16)fq[i];
+      vs[b2][row * VS_LD + col0 + i + 1] = fv[i + 1];
     }
   };
   auto z_block = [&](const bf16* X) {
@@ -550,39 +592,43 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     return y;
   };
   // z' = -log2(e) z:  sigma = 1/(1+2^z'),  A' = z' sigma = -log2(e) SiLU(z),
-  // s'(z) = sigma + A (1 - sigma) = sigma + A' ln2 (sigma - 1)
-  auto act_grad = [&](const f32x16& z, bf16x8 (&apk)[2], h16x2 (&s1h)[8], bf16* S) {
+  // s'(z) = sigma + A (1 - sigma) = sigma + A' ln2 (sigma - 1).  Results are
+  // packed in pairs: A' as bf16 (token-contraction operand and the staged
+  // copy), s'(z) as f16.
+  auto act_grad = [&](const f32x16& z, uint32_t (&apk)[8], h16x2 (&s1h)[8], bf16* S) {
+    uint16_t* S16 = reinterpret_cast<uint16_t*>(S);
 #pragma unroll
     for (int r = 0; r < 16; r += 2) {
-      float av[2], sv[2];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float zz = z[r + j];
-        const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zz));
-        av[j] = zz * sg;
-        sv[j] = fmaf(av[j], fmaf(sg, LN2, -LN2), sg);
-      }
-      apk[r >> 3][(r & 7)] = (bf16)av[0];
-      apk[r >> 3][(r & 7) + 1] = (bf16)av[1];
-      s1h[r >> 1] = h16x2{(h16)sv[0], (h16)sv[1]};
-      S[c32_row(r, hf) * AS_LD + hid] = apk[r >> 3][(r & 7)];
-      S[c32_row(r + 1, hf) * AS_LD + hid] = apk[r >> 3][(r & 7) + 1];
+      const float z0 = z[r], z1 = z[r + 1];
+      const float g0 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z0));
+      const float g1 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z1));
+      const float a0 = z0 * g0, a1 = z1 * g1;
+      const float s0 = fmaf(a0, fmaf(g0, LN2, -LN2), g0);
+      const float s1 = fmaf(a1, fmaf(g1, LN2, -LN2), g1);
+      const uint32_t pa = pack_bf16x2(a0, a1);
+      apk[r >> 1] = pa;
+      s1h[r >> 1] = __builtin_convertvector((f32x2){s0, s1}, h16x2);
+      S16[c32_row(r, hf) * AS_LD + hid] = (uint16_t)pa;
+      S16[c32_row(r + 1, hf) * AS_LD + hid] = (uint16_t)(pa >> 16);
     }
   };
-  auto act_apply = [&](const bf16x8 (&zq)[2], bf16* S) {
+  auto act_apply = [&](const f32x16& z, bf16* S) {
+    uint16_t* S16 = reinterpret_cast<uint16_t*>(S);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float zz = (float)zq[r >> 3][r & 7];
-      const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(zz));
-      S[c32_row(r, hf) * AS_LD + hid] = (bf16)(zz * sg);
+    for (int r = 0; r < 16; r += 2) {
+      const float z0 = z[r], z1 = z[r + 1];
+      const float g0 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z0));
+      const float g1 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z1));
+      const uint32_t pa = pack_bf16x2(z0 * g0, z1 * g1);
+      S16[c32_row(r, hf) * AS_LD + hid] = (uint16_t)pa;
+      S16[c32_row(r + 1, hf) * AS_LD + hid] = (uint16_t)(pa >> 16);
     }
   };
 
   f32x16 gw1[2] = {}, gw2[2] = {};
   float lacc = 0.f;
-  bf16x8 apk[2][2];       // per tile parity: packed A' (token-contraction operand)
+  uint32_t apk[2][8];     // per tile parity: A' packed in bf16 pairs (token-contraction operand)
   h16x2 s1h[2][8];        // per tile parity: s'(Z) in f16 pairs
-  bf16x8 zqp[2];          // Zq' of the next tile, packed
 
   // phase A of iteration `it` (tile parity P = it & 1)
   auto phase_a = [&](int it, auto PC) {
@@ -593,19 +639,26 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         const int b = w + NW * bi, tb = b & 1, db = b >> 1;
         const f32x4 y = y_block(as_[P], tb, bi);
         const int dcol = 16 * db + l16;
+        float ev[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int tok = 16 * tb + 4 * g4 + r;
           const float R = y[r] - vs[P][tok * VS_LD + dcol];
           lacc = fmaf(R, R, lacc);
-          const bf16 E = (bf16)(e_scale * R);
-          es[P][tok * XS_LD + dcol] = E;
-          ets[P][dcol * XT_LD + tok] = E;
+          ev[r] = e_scale * R;
         }
+        const uint32_t e01 = pack_bf16x2(ev[0], ev[1]), e23 = pack_bf16x2(ev[2], ev[3]);
+        const int tok0 = 16 * tb + 4 * g4;
+        *reinterpret_cast<uint64_t*>(&ets[P][dcol * XT_LD + tok0]) = ((uint64_t)e23 << 32) | e01;
+        uint16_t* es16 = reinterpret_cast<uint16_t*>(es[P]);
+        es16[(tok0 + 0) * XS_LD + dcol] = (uint16_t)e01;
+        es16[(tok0 + 1) * XS_LD + dcol] = (uint16_t)(e01 >> 16);
+        es16[(tok0 + 2) * XS_LD + dcol] = (uint16_t)e23;
+        es16[(tok0 + 3) * XS_LD + dcol] = (uint16_t)(e23 >> 16);
       }
     }
     if (it < my_a) {
-      IOT* O = static_cast<IOT*>(p.O);
+      IOT* O = static_cast<IOT*>(p.O) + (as0 + (int64_t)(g + it * G) * TT) * p.stride_tok + hoff;
       const int t_base = (g + it * G) * TT;
 #pragma unroll
       for (int bi = 0; bi < 8 / NW; ++bi) {
@@ -615,18 +668,14 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int tok = 16 * tb + 4 * g4 + r;
-          if (t_base + tok < al) O[(as0 + t_base + tok) * p.stride_tok + hoff + dcol] = from_f<IOT>(y[r]);
+          if (t_base + tok < al) O[(int64_t)tok * p.stride_tok + dcol] = from_f<IOT>(y[r]);
         }
       }
     }
     if (it + 1 < iters) {
       const int nb3 = (it + 1) % 3;
       if (it + 1 < my_g) act_grad(z_block(xs[nb3]), apk[P ^ 1], s1h[P ^ 1], as_[P ^ 1]);
-      if (it + 1 < my_a) {
-        const f32x16 zq = z_block(qs[P ^ 1]);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) zqp[r >> 3][r & 7] = (bf16)zq[r];
-      }
+      if (it + 1 < my_a) act_apply(z_block(qs[P ^ 1]), aqs[P ^ 1]);
     }
   };
   // phase B of iteration `it`
@@ -640,13 +689,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[P][l32 * XS_LD + 16 * m + 8 * hf]);
         pz = mma32(a, w2b[m], pz);
       }
-      bf16x8 dpk[2];
+      uint32_t dw[8];
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
         const h16x2 sv = s1h[P][r >> 1];
-        dpk[r >> 3][r & 7] = (bf16)(pz[r] * (float)sv[0]);
-        dpk[r >> 3][(r & 7) + 1] = (bf16)(pz[r + 1] * (float)sv[1]);
+        dw[r >> 1] = pack_bf16x2(fmaf(pz[r], (float)sv[0], 0.0f), fmaf(pz[r + 1], (float)sv[1], 0.0f));
       }
+      const bf16x8 dpk[2] = {as_bf16x8(dw[0], dw[1], dw[2], dw[3]), as_bf16x8(dw[4], dw[5], dw[6], dw[7])};
+      const bf16x8 apv[2] = {as_bf16x8(apk[P][0], apk[P][1], apk[P][2], apk[P][3]),
+                             as_bf16x8(apk[P][4], apk[P][5], apk[P][6], apk[P][7])};
 #pragma unroll
       for (int db = 0; db < 2; ++db) {
         const int dd = 32 * db + l32;
@@ -659,33 +710,27 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
           const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 4 * hf]);
           const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 8 + 4 * hf]);
           const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
-          gw2[db] = mma32(apk[P][m], eb, gw2[db]);
+          gw2[db] = mma32(apv[m], eb, gw2[db]);
         }
       }
     }
-    if (it + 1 < my_a) act_apply(zqp, aqs[P ^ 1]);
     if (it + 2 < iters) {
       stage_rows(it + 2);
-      if (it + 3 < iters) fetch(it + 3);
+      if (it + 3 < iters) fetch();
     }
   };
 
   if (iters > 0) {
     // prologue: rows of tiles 0 and 1 staged, activations of tile 0 staged
-    fetch(0);
+    fetch();
     stage_rows(0);
-    if (iters > 1) fetch(1);
+    if (iters > 1) fetch();
     __syncthreads();
     if (my_g > 0) act_grad(z_block(xs[0]), apk[0], s1h[0], as_[0]);
-    if (my_a > 0) {
-      const f32x16 zq = z_block(qs[0]);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) zqp[r >> 3][r & 7] = (bf16)zq[r];
-      act_apply(zqp, aqs[0]);
-    }
+    if (my_a > 0) act_apply(z_block(qs[0]), aqs[0]);
     if (iters > 1) {
       stage_rows(1);
-      if (iters > 2) fetch(2);
+      if (iters > 2) fetch();
     }
     __syncthreads();
     for (int it = 0; it < iters; it += 2) {
