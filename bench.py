@@ -104,11 +104,11 @@ def time_fn(fn, steps, warmup, lib):
         out = fn()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
-    lib.ttt_profile_read(4, ms, n)
+    ms = (ctypes.c_double * 5)()
+    n = (ctypes.c_int64 * 5)()
+    lib.ttt_profile_read(5, ms, n)
     lib.ttt_profile_enable(0)
-    kinds = ["fwd_step", "update", "bwd_step", "bwd_reduce"]
+    kinds = ["fwd_step", "update", "bwd_step", "bwd_reduce", "bwd_prep"]
     per = {k: dict(ms_per_call=ms[i] / steps, launches_per_call=n[i] / steps,
                    avg_launch_us=ms[i] / max(n[i], 1) * 1e3) for i, k in enumerate(kinds) if n[i]}
     return (t1 - t0) * 1e3 / steps, per, out

@@ -158,7 +158,8 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
  * come from a pool the library owns; enabling clears earlier records).
  * ttt_profile_read waits for the recorded events and returns, per kernel
  * kind (0 = chunk-step kernel, 1 = weight-update kernel, 2 = backward
- * chunk-step kernel, 3 = backward reduction kernel), the summed elapsed
+ * chunk-step kernel, 3 = backward reduction kernel, 4 = backward operand
+ * preparation kernel), the summed elapsed
  * milliseconds and the number of launches; arrays have n_kinds entries.
  * Not meant for production calls: it adds event records to the stream. */
 ttt_status_t ttt_profile_enable(int32_t on);

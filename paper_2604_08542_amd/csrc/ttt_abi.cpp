@@ -55,7 +55,7 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
 }
 
 struct WsLayout {
-  size_t partial, partial_loss, pp, adj, wlast, total;
+  size_t partial, partial_loss, pp, adj, wlast, prep, total;
   int64_t slot_cap;
 };
 
@@ -74,6 +74,8 @@ WsLayout ws_layout(const Shape& s, int64_t n_chains) {
   off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
   L.wlast = off;
   off = align_up(off + (size_t)n_chains * 2 * s.dh() * sizeof(float));
+  L.prep = off;  // backward operand copies: 8 matrices per head (float-sized slots)
+  off = align_up(off + (size_t)s.H * 8 * s.dh() * sizeof(float));
   L.total = off;
   return L;
 }
@@ -228,6 +230,7 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q,
   float* pdeta = at<float>(ws, L.partial_loss);
   float* adj[2] = {at<float>(ws, L.adj), at<float>(ws, L.adj) + H * 2 * dh};
   float* wlast = at<float>(ws, L.wlast);
+  void* prep = at<char>(ws, L.prep);
   const int target = default_target_wgs(S);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
   const int64_t tiles = (std::min(M, N) + TT - 1) / TT;
@@ -259,11 +262,14 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q,
     if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   for (int64_t s = C; s >= 0; --s) {
+    const float* w_s = s < C ? ckpt + s * H * 2 * dh : wlast;
+    const float* wh_s = s < C ? adj[(s + 1) % 2] : nullptr;
+    if (!timed_launch(4, st, [&] { return launch_bwd_prep(w_s, wh_s, prep, (int)H, S.h, S.mma_bf16, st); }))
+      return TTT_EHIP;
     BwdStepArgs b{};
     b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
     b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.w_src = s < C ? ckpt + s * H * 2 * dh : wlast;
-    b.wh_src = s < C ? adj[(s + 1) % 2] : nullptr;
+    b.prep = prep;
     b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta; b.G = (int32_t)G;
     b.partial = partial; b.partial_deta = pdeta;
     b.grad_start = s * M; b.grad_len = s < C ? mlen(s) : 0;
@@ -271,7 +277,7 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q,
     if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
     BwdReduceArgs r{};
-    r.wh_src = b.wh_src;
+    r.wh_src = wh_s;
     r.wh_dst = adj[s % 2];
     r.dst1 = s == 0 ? dW1_0 : nullptr;
     r.dst2 = s == 0 ? dW2_0 : nullptr;
@@ -364,6 +370,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   float* wh = at<float>(ws, L.adj);                      // adjoint of W* (fixed)
   float* acc[2] = {at<float>(ws, L.pp), at<float>(ws, L.pp) + H * 2 * dh};  // running dW0
   float* w0 = at<float>(ws, L.adj) + H * 2 * dh;         // W0 packed [W1 | W2] per head
+  void* prep = at<char>(ws, L.prep);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
   if (C == 0) {  // no tokens: zero gradients
     BwdReduceArgs r{};
@@ -392,10 +399,12 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   };
   // apply adjoint of all tokens at W*  ->  Wh (and dQ), deta starts at 0
   {
+    if (!timed_launch(4, st, [&] { return launch_bwd_prep(wstar, nullptr, prep, (int)H, S.h, S.mma_bf16, st); }))
+      return TTT_EHIP;
     BwdStepArgs b{};
     b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
     b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.w_src = wstar; b.wh_src = nullptr; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    b.prep = prep; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
     const int64_t G = grid_g(N);
     b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
     b.grad_start = 0; b.grad_len = 0; b.app_start = 0; b.app_len = (int32_t)N;
@@ -407,13 +416,15 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
     if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   // update adjoint of each chunk at W0 against Wh, accumulated on top of Wh
+  if (!timed_launch(4, st, [&] { return launch_bwd_prep(w0, wh, prep, (int)H, S.h, S.mma_bf16, st); }))
+    return TTT_EHIP;
   const float* prev = wh;
   for (int64_t c = 0; c < C; ++c) {
     const int32_t len = (int32_t)std::min<int64_t>(M, N - c * M);
     BwdStepArgs b{};
     b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
     b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.w_src = w0; b.wh_src = wh; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    b.prep = prep; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
     const int64_t G = grid_g(len);
     b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
     b.grad_start = c * M; b.grad_len = len; b.app_start = 0; b.app_len = 0;

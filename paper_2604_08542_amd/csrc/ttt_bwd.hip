@@ -41,9 +41,9 @@ __device__ __forceinline__ T* opaque(T* ptr) {
   return ptr;
 }
 
-template <typename IOT, bool BF, int NW>
+template <typename IOT, bool BF, int NW, int NB>
 __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
-  constexpr int HH = NW * 32;
+  constexpr int HH = NW * 32 * NB;  // hidden size: NW waves x NB 32-wide blocks each
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;
   constexpr int TPR = D / EPT;
@@ -69,12 +69,12 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   // of LDS immediate offsets, and hoisting every per-lane address out of the
   // token loop would otherwise exhaust the register file.
   struct LaneIds {
-    int tid, w, l, l32, hf, l16, g4, hid, row, col0;
+    int tid, w, l, l32, hf, l16, g4, hid0, row, col0;
   };
   auto lane_ids = [](int t) {
     LaneIds r;
     r.tid = t; r.w = t >> 6; r.l = t & 63; r.l32 = t & 31; r.hf = (t & 63) >> 5; r.l16 = t & 15;
-    r.g4 = (t & 63) >> 4; r.hid = r.w * 32 + r.l32; r.row = t / TPR; r.col0 = (t % TPR) * EPT;
+    r.g4 = (t & 63) >> 4; r.hid0 = r.w * 32 * NB + r.l32; r.row = t / TPR; r.col0 = (t % TPR) * EPT;
     return r;
   };
   LaneIds li = lane_ids(threadIdx.x);
@@ -87,51 +87,55 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   const int G = p.G;
   const int head = lin / G, g = lin % G;
   const float eta = p.eta;
-  const float* Wc0 = p.w_src + (int64_t)head * 2 * DH;                         // W1 [D][h], W2 [h][D]
-  const float* Wh0 = p.wh_src ? p.wh_src + (int64_t)head * 2 * DH : p.w_src;  // adjoint of W_{s+1}
+  // prepared operand block of this head: 8 matrices of D*h elements
+  const MT* prep0 = static_cast<const MT*>(p.prep) + (int64_t)head * 8 * DH;
   const int64_t hoff = (int64_t)head * p.stride_head;
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
 
   // ---- operand helpers
-  auto w1 = [&](const float* W, int d, int hh) { return W[d * HH + hh]; };
-  auto w2 = [&](const float* W, int hh, int d) { return W[DH + hh * D + d]; };
-  // 32x32 block C[tok][li.hid] = X[tok][:] F, F(d, li.hid) given by fn.
-  auto th = [&](const float* X, auto fn) {
+  // The prepared operand copies of W_s and of the carried adjoint (see
+  // ttt_bwd_prep) are [hid][d] or [d][hid] matrices in the operand type.
+  // 32x32 block C[tok][hid] (hidden block j of this wave) = X[tok][:] F with
+  // F(d, hid) = M[hid][d].
+  auto th = [&](const float* X, const MT* M, int j) {
     f32x16 c = {};
+    const MT* mrow = M + (li.hid0 + 32 * j) * D;
     if constexpr (BF) {
-#pragma unroll 1
+#pragma unroll 2
       for (int m = 0; m < 4; ++m) {
-        bf16x8 a, b;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int d = 16 * m + 8 * li.hf + e;
-          a[e] = (bf16)X[li.l32 * LD + d];
-          b[e] = (bf16)fn(d, li.hid);
-        }
+        const int d0 = 16 * m + 8 * li.hf;
+        const f32x4 x0 = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
+        const f32x4 x1 = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0 + 4]);
+        const bf16x8 a = as_bf16x8(pack_bf16x2(x0[0], x0[1]), pack_bf16x2(x0[2], x0[3]),
+                                   pack_bf16x2(x1[0], x1[1]), pack_bf16x2(x1[2], x1[3]));
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(mrow + d0);
         c = mma32(a, b, c);
       }
     } else {
-#pragma unroll 4
-      for (int s = 0; s < 32; ++s) {
-        const int d = 32 * li.hf + s;
-        c = mma32(X[li.l32 * LD + d], fn(d, li.hid), c);
+#pragma unroll 2
+      for (int s4 = 0; s4 < 8; ++s4) {
+        const int d0 = 32 * li.hf + 4 * s4;
+        const f32x4 x = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(mrow + d0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c = mma32(x[e], b[e], c);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
     return c;
   };
   // 16x16 block C[tok][d] (token block tb, feature block db) = S[tok][:] F,
-  // S staged [tok][hidden] in LDS, F(li.hid, d) given by fn.
-  auto td = [&](const MT* S, int tb, int db, auto fn) {
+  // S staged [tok][hidden] in LDS, F(hid, d) = M[d][hid].
+  auto td = [&](const MT* S, int tb, int db, const MT* M) {
     f32x4 c = {};
     const int arow = 16 * tb + li.l16, dcol = 16 * db + li.l16;
+    const MT* mrow = M + dcol * HH;
     if constexpr (BF) {
-#pragma unroll 1
+#pragma unroll 2
       for (int u = 0; u < HH / 32; ++u) {
         const int k0 = (HH / 4) * li.g4 + 8 * u;
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + k0]);
-        bf16x8 b;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) b[e] = (bf16)fn(k0 + e, dcol);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(mrow + k0);
         c = mma16(a, b, c);
       }
     } else {
@@ -139,13 +143,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       for (int u = 0; u < HH / 16; ++u) {
         const int k0 = (HH / 4) * li.g4 + 4 * u;
         const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + k0]);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(mrow + k0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) c = mma16(a[e], fn(k0 + e, dcol), c);
+        for (int e = 0; e < 4; ++e) c = mma16(a[e], b[e], c);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
     return c;
   };
-  // gW1[db] (rows d, cols li.hid) += X[:, d]^T Yw ; gW2[db] (rows li.hid, cols d) += Yw^T X[:, d]
+  // gW1[j][db] (rows d, cols hidden block j) += X[:, d]^T Yw ;
+  // gW2[j][db] (rows hidden block j, cols d) += Yw^T X[:, d]
   auto tok_sum_w1 = [&](f32x16 (&acc)[2], const float* X, const f32x16& Yw) {
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
@@ -153,13 +160,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       if constexpr (BF) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-          bf16x8 a, b;
+          uint32_t aw[4], bw[4];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            a[e] = (bf16)X[c32_row(8 * m + e, li.hf) * LD + dd];
-            b[e] = (bf16)Yw[8 * m + e];
+          for (int e = 0; e < 8; e += 2) {
+            aw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, li.hf) * LD + dd], X[c32_row(8 * m + e + 1, li.hf) * LD + dd]);
+            bw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
           }
-          acc[db] = mma32(a, b, acc[db]);
+          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
         }
       } else {
 #pragma unroll
@@ -174,13 +181,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       if constexpr (BF) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-          bf16x8 a, b;
+          uint32_t aw[4], bw[4];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            a[e] = (bf16)Yw[8 * m + e];
-            b[e] = (bf16)X[c32_row(8 * m + e, li.hf) * LD + dd];
+          for (int e = 0; e < 8; e += 2) {
+            aw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
+            bw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, li.hf) * LD + dd], X[c32_row(8 * m + e + 1, li.hf) * LD + dd]);
           }
-          acc[db] = mma32(a, b, acc[db]);
+          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
         }
       } else {
 #pragma unroll
@@ -188,9 +195,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       }
     }
   };
-  auto stage = [&](MT* S, const f32x16& Yw) {
+  auto stage = [&](MT* S, const f32x16& Yw, int j) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) S[c32_row(r, li.hf) * AS_LD + li.hid] = (MT)Yw[r];
+    for (int r = 0; r < 16; ++r) S[c32_row(r, li.hf) * AS_LD + li.hid0 + 32 * j] = (MT)Yw[r];
   };
   // Load rows of a token tensor for tokens [t0, t0+nv) into an LDS tile,
   // optionally L2-normalised (recording the norm data in set ns).
@@ -243,7 +250,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
     if (li.row < nv) store_vec<IOT, EPT>(static_cast<IOT*>(base) + (t0 + li.row) * p.stride_tok + hoff + li.col0, v);
   };
 
-  f32x16 gw1[2] = {}, gw2[2] = {};
+  f32x16 gw1[NB][2] = {}, gw2[NB][2] = {};
   float deta_acc = 0.f;
 
   // ------------------------------------------------ update adjoint of chunk s
@@ -253,27 +260,36 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   for (int t = g; t < n_gt; t += G) {
     const int64_t t0 = p.grad_start + (int64_t)t * TT;
     const int nv = min(TT, gl - t * TT);
-    const float* Wc = opaque(Wc0);
-    const float* Wh = opaque(Wh0);
+    const MT* pr = opaque(prep0);
+    const MT* W1t = pr + 0 * DH;   // [hid][d] of W1
+    const MT* W2n = pr + 1 * DH;   // [hid][d] of W2
+    const MT* H1t = pr + 2 * DH;   // [hid][d] of Wh1
+    const MT* H2n = pr + 3 * DH;   // [hid][d] of Wh2
+    const MT* W1n = pr + 4 * DH;   // [d][hid] of W1
+    const MT* W2t = pr + 5 * DH;   // [d][hid] of W2
+    const MT* H1n = pr + 6 * DH;   // [d][hid] of Wh1
+    const MT* H2t = pr + 7 * DH;   // [d][hid] of Wh2
     refresh();
     load_rows(p.K, t0, nv, xs, norm_k, 0);
     load_rows(p.V, t0, nv, vs, norm_v, 1);
     __syncthreads();
     // Z = K W1 is kept; A, s'(Z), s''(Z) are recomputed from it where needed.
-    const f32x16 Z = th(xs, [&](int d, int hh) { return w1(Wc, d, hh); });
-    {
+    f32x16 Z[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      Z[j] = th(xs, W1t, j);
       f32x16 A;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) A[r] = Z[r] * sigmoid(Z[r]);
-      stage(sta, A);
+      for (int r = 0; r < 16; ++r) A[r] = Z[j][r] * sigmoid(Z[j][r]);
+      stage(sta, A, j);
     }
     __syncthreads();
     // Y = A W2 -> E;  A Wh2 -> -eta A Wh2 and its deta term
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 y = td(sta, tb, db, [&](int hh, int d) { return w2(Wc, hh, d); });
-      const f32x4 aw = td(sta, tb, db, [&](int hh, int d) { return w2(Wh, hh, d); });
+      const f32x4 y = td(sta, tb, db, W2t);
+      const f32x4 aw = td(sta, tb, db, H2t);
       const int dcol = 16 * db + li.l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -287,14 +303,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
     __syncthreads();
     // P = E W2^T, D = P s'(Z) (staged), K Wh1 -> dD and its deta term,
     // dP = dD s'(Z) (staged), dZ = dD P s''(Z)
-    f32x16 dP, dZ;
-    {
-      const f32x16 P = th(es, [&](int d, int hh) { return w2(Wc, hh, d); });
-      const f32x16 KW = th(xs, [&](int d, int hh) { return w1(Wh, d, hh); });
+    f32x16 dP[NB], dZ[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const f32x16 P = th(es, W2n, j);
+      const f32x16 KW = th(xs, H1t, j);
       f32x16 Dm;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float z = Z[r];
+        const float z = Z[j][r];
         const float sg = sigmoid(z);
         const float a = z * sg;
         const float s1 = fmaf(a, 1.0f - sg, sg);
@@ -302,18 +319,18 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
         Dm[r] = P[r] * s1;
         deta_acc -= KW[r] * Dm[r];
         const float dD = -eta * KW[r];
-        dP[r] = dD * s1;
-        dZ[r] = dD * P[r] * s2;
+        dP[j][r] = dD * s1;
+        dZ[j][r] = dD * P[r] * s2;
       }
-      stage(sta, Dm);
-      stage(stb, dP);
+      stage(sta, Dm, j);
+      stage(stb, dP[j], j);
     }
     __syncthreads();
     // dE = -eta A Wh2 + dP W2 ; dY = (2/M) dE
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 de = td(stb, tb, db, [&](int hh, int d) { return w2(Wc, hh, d); });
+      const f32x4 de = td(stb, tb, db, W2t);
       const int dcol = 16 * db + li.l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -323,30 +340,31 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
     }
     __syncthreads();
     // dA = -eta E Wh2^T + dY W2^T ; dZ += dA s'(Z) ; token sums
-    {
-      const f32x16 dA1 = th(es, [&](int d, int hh) { return w2(Wh, hh, d); });
-      const f32x16 dA2 = th(dys, [&](int d, int hh) { return w2(Wc, hh, d); });
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const f32x16 dA1 = th(es, H2n, j);
+      const f32x16 dA2 = th(dys, W2n, j);
       f32x16 A;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float z = Z[r];
+        const float z = Z[j][r];
         const float sg = sigmoid(z);
         const float a = z * sg;
         A[r] = a;
-        dZ[r] += (-eta * dA1[r] + dA2[r]) * fmaf(a, 1.0f - sg, sg);
+        dZ[j][r] += (-eta * dA1[r] + dA2[r]) * fmaf(a, 1.0f - sg, sg);
       }
-      tok_sum_w2(gw2, A, dys);
+      tok_sum_w2(gw2[j], A, dys);
+      tok_sum_w2(gw2[j], dP[j], es);
+      tok_sum_w1(gw1[j], xs, dZ[j]);
+      stage(stb, dZ[j], j);
     }
-    tok_sum_w2(gw2, dP, es);
-    tok_sum_w1(gw1, xs, dZ);
-    stage(stb, dZ);
     __syncthreads();
     // dK = -eta D Wh1^T + dZ W1^T
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 k1 = td(sta, tb, db, [&](int hh, int d) { return w1(Wh, d, hh); });
-      const f32x4 k2 = td(stb, tb, db, [&](int hh, int d) { return w1(Wc, d, hh); });
+      const f32x4 k1 = td(sta, tb, db, H1n);
+      const f32x4 k2 = td(stb, tb, db, W1n);
       const int dcol = 16 * db + li.l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) dxs[(16 * tb + 4 * li.g4 + r) * LD + dcol] = -eta * k1[r] + k2[r];
@@ -363,29 +381,35 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   for (int t = g; t < n_at; t += G) {
     const int64_t t0 = p.app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
-    const float* Wc = opaque(Wc0);
+    const MT* pr = opaque(prep0);
+    const MT* W1t = pr + 0 * DH;
+    const MT* W2n = pr + 1 * DH;
+    const MT* W1n = pr + 4 * DH;
     refresh();
     load_rows(p.Q, t0, nv, xs, norm_q, 0);
     load_rows(p.dO, t0, nv, dys, false, -1);
     __syncthreads();
-    f32x16 Aq = th(xs, [&](int d, int hh) { return w1(Wc, d, hh); });
-    f32x16 dZq = th(dys, [&](int d, int hh) { return w2(Wc, hh, d); });
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float z = Aq[r];
-      const float sg = sigmoid(z);
-      const float a = z * sg;
-      dZq[r] *= fmaf(a, 1.0f - sg, sg);
-      Aq[r] = a;
+    for (int j = 0; j < NB; ++j) {
+      f32x16 Aq = th(xs, W1t, j);
+      f32x16 dZq = th(dys, W2n, j);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float z = Aq[r];
+        const float sg = sigmoid(z);
+        const float a = z * sg;
+        dZq[r] *= fmaf(a, 1.0f - sg, sg);
+        Aq[r] = a;
+      }
+      tok_sum_w2(gw2[j], Aq, dys);
+      tok_sum_w1(gw1[j], xs, dZq);
+      stage(sta, dZq, j);
     }
-    tok_sum_w2(gw2, Aq, dys);
-    tok_sum_w1(gw1, xs, dZq);
-    stage(sta, dZq);
     __syncthreads();
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = li.w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 q1 = td(sta, tb, db, [&](int hh, int d) { return w1(Wc, d, hh); });
+      const f32x4 q1 = td(sta, tb, db, W1n);
       const int dcol = 16 * db + li.l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) dxs[(16 * tb + 4 * li.g4 + r) * LD + dcol] = q1[r];
@@ -398,13 +422,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   // ------------------------------------------------ shard partials
   float* part = p.partial + ((int64_t)head * G + g) * (2 * DH);
 #pragma unroll
-  for (int db = 0; db < 2; ++db)
+  for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int rr = c32_row(r, li.hf);
-      part[(32 * db + rr) * HH + li.hid] = gw1[db][r];
-      part[DH + (32 * li.w + rr) * D + 32 * db + li.l32] = gw2[db][r];
-    }
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = c32_row(r, li.hf);
+        part[(32 * db + rr) * HH + li.hid0 + 32 * j] = gw1[j][db][r];
+        part[DH + ((li.w * NB + j) * 32 + rr) * D + 32 * db + li.l32] = gw2[j][db][r];
+      }
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) deta_acc += __shfl_xor(deta_acc, m, 64);
   if (li.l == 0) red[li.w] = deta_acc;
@@ -414,6 +440,43 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
     for (int i = 0; i < NW; ++i) s += red[i];
     p.partial_deta[(int64_t)head * G + g] = s;
   }
+}
+
+// Operand copies for one backward step, per head: W_s and the carried
+// adjoint Wh (zeros when absent), each of W1 [d][h] and W2 [h][d] written in
+// both orientations ([hid][d] and [d][hid]) in the matrix-core operand type,
+// so that every operand fragment is one contiguous vector load.
+template <typename MT>
+__global__ __launch_bounds__(256) void ttt_bwd_prep(const float* w_src, const float* wh_src, MT* prep, int h) {
+  const int dh = D * h;
+  const int head = blockIdx.y;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= dh) return;
+  const float* W = w_src + (int64_t)head * 2 * dh;
+  const float* Wh = wh_src ? wh_src + (int64_t)head * 2 * dh : nullptr;
+  MT* o = prep + (int64_t)head * 8 * dh;
+  const int d = idx / h, hh = idx % h;    // idx = d*h + hh: W1 element (d, hh)
+  const int hh2 = idx / D, d2 = idx % D;  // idx = hh2*D + d2: W2 element (hh2, d2)
+  const float w1 = W[idx], h1 = Wh ? Wh[idx] : 0.f;
+  const float w2 = W[dh + idx], h2 = Wh ? Wh[dh + idx] : 0.f;
+  o[0 * dh + hh * D + d] = (MT)w1;     // W1 as [hid][d]
+  o[1 * dh + idx] = (MT)w2;            // W2 as [hid][d]
+  o[2 * dh + hh * D + d] = (MT)h1;
+  o[3 * dh + idx] = (MT)h2;
+  o[4 * dh + idx] = (MT)w1;            // W1 as [d][hid]
+  o[5 * dh + d2 * h + hh2] = (MT)w2;   // W2 as [d][hid]
+  o[6 * dh + idx] = (MT)h1;
+  o[7 * dh + d2 * h + hh2] = (MT)h2;
+}
+
+hipError_t launch_bwd_prep(const float* w_src, const float* wh_src, void* prep, int H, int h, bool mma_bf16,
+                           hipStream_t st) {
+  const dim3 grid((D * h + 255) / 256, H);
+  if (mma_bf16)
+    hipLaunchKernelGGL(ttt_bwd_prep<bf16>, grid, dim3(256), 0, st, w_src, wh_src, static_cast<bf16*>(prep), h);
+  else
+    hipLaunchKernelGGL(ttt_bwd_prep<float>, grid, dim3(256), 0, st, w_src, wh_src, static_cast<float*>(prep), h);
+  return hipGetLastError();
 }
 
 // Wh_dst = Wh_src (0 if null) + sum of the G shard partials, in fixed order;
@@ -448,21 +511,22 @@ __global__ __launch_bounds__(256) void ttt_bwd_reduce(BwdReduceArgs p) {
   }
 }
 
-template <typename IOT, bool BF, int NW>
+// One wave per 32-wide hidden block: 4 waves at h=128, 8 at h=256.
+template <typename IOT, bool BF, int NW, int NB>
 static hipError_t launch_bwd_step_t(const BwdStepArgs& a, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL((ttt_bwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  hipLaunchKernelGGL((ttt_bwd_step<IOT, BF, NW, NB>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st) {
   if (h == 128) {
-    if (io_bf16) return launch_bwd_step_t<bf16, true, 4>(a, n_blocks, st);
-    return mma_bf16 ? launch_bwd_step_t<float, true, 4>(a, n_blocks, st)
-                    : launch_bwd_step_t<float, false, 4>(a, n_blocks, st);
+    if (io_bf16) return launch_bwd_step_t<bf16, true, 4, 1>(a, n_blocks, st);
+    return mma_bf16 ? launch_bwd_step_t<float, true, 4, 1>(a, n_blocks, st)
+                    : launch_bwd_step_t<float, false, 4, 1>(a, n_blocks, st);
   }
-  if (io_bf16) return launch_bwd_step_t<bf16, true, 8>(a, n_blocks, st);
-  return mma_bf16 ? launch_bwd_step_t<float, true, 8>(a, n_blocks, st)
-                  : launch_bwd_step_t<float, false, 8>(a, n_blocks, st);
+  if (io_bf16) return launch_bwd_step_t<bf16, true, 8, 1>(a, n_blocks, st);
+  return mma_bf16 ? launch_bwd_step_t<float, true, 8, 1>(a, n_blocks, st)
+                  : launch_bwd_step_t<float, false, 8, 1>(a, n_blocks, st);
 }
 
 hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st) {

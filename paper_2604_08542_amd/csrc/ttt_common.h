@@ -201,8 +201,7 @@ struct BwdStepArgs {
   void* dK;
   void* dV;
   int64_t stride_tok, stride_head;
-  const float* w_src;   // W_s per head: [W1 (D*h) | W2 (h*D)], head stride 2*D*h
-  const float* wh_src;  // adjoint of W_{s+1}, same layout (null when no update tile)
+  const void* prep;     // per head 8 operand matrices of D*h (see ttt_bwd_prep)
   int32_t H;
   uint32_t flags;
   float eta;
