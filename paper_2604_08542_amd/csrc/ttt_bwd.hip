@@ -519,6 +519,7 @@ static hipError_t launch_bwd_step_t(const BwdStepArgs& a, int n_blocks, hipStrea
 }
 
 hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  if (mma_bf16) return launch_bwd_step_bf(a, n_blocks, h, io_bf16, st);
   if (h == 128) {
     if (io_bf16) return launch_bwd_step_t<bf16, true, 4, 1>(a, n_blocks, st);
     return mma_bf16 ? launch_bwd_step_t<float, true, 4, 1>(a, n_blocks, st)

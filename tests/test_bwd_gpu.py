@@ -24,6 +24,8 @@ CASES = [
     (96, 1, 128, 40, 0.5, "f32", False),      # tiny chunks, ragged tiles
     (1000, 2, 256, 333, 0.05, "bf16", True),
     (800, 2, 128, 300, 0.1, "f32", True),
+    (700, 2, 128, 256, 0.3, "bf16", True),    # ragged, h=128, bf16 io
+    (96, 1, 256, 40, 0.5, "bf16", True),      # tiny chunks, ragged tiles, h=256
 ]
 
 
