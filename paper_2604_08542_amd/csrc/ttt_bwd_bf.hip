@@ -82,13 +82,13 @@ struct RawRow<bf16> {
 // Rows are always loaded (masked rows of a ragged tile read the tile's last
 // valid row) and zeroed when unpacked, so the loads need no branch.
 template <typename IOT>
-__device__ __forceinline__ void fetch_row(const void* base, int64_t elem, RawRow<IOT>& r) {
+__device__ __forceinline__ void fetch_row(const IOT* base, uint32_t elem, RawRow<IOT>& r) {
   if constexpr (std::is_same_v<IOT, float>) {
-    const f32x4* s = reinterpret_cast<const f32x4*>(static_cast<const float*>(base) + elem);
+    const f32x4* s = reinterpret_cast<const f32x4*>(base + elem);
     r.a = s[0];
     r.b = s[1];
   } else {
-    r.a = *reinterpret_cast<const u32x4*>(static_cast<const bf16*>(base) + elem);
+    r.a = *reinterpret_cast<const u32x4*>(base + elem);
   }
 }
 
@@ -141,23 +141,50 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) a[m] = *reinterpret_cast<const bf16x8*>(lds(off + (l32 * XB + 16 * m + 8 * hf) * 2));
   };
-  // 32x32 block C[token][hid] of hidden block hb: X[token][:] M[hid][:]^T.
-  auto th = [&](const bf16x8 (&a)[4], const bf16* M, int hb) {
-    const bf16* mrow = M + (32 * hb + l32) * D + 8 * hf;
-    bf16x8 b[4];
+  // Weight fragments are loaded one LDS phase before the phase that uses
+  // them (the barrier between phases does not wait for global loads), so
+  // their L2 latency overlaps the elementwise epilogue of the current phase.
+  // Prepared operand k: 0..3 = W1, W2, Wh1, Wh2 as [hid][d]; 4..7 = the same
+  // as [d][hid].
+  struct ThW {  // B fragments of the 32x32 products for this wave's NB hidden blocks
+    bf16x8 f[NB][4];
+  };
+  struct TdW {  // B fragments of the 16x16 products for this wave's 16 feature columns
+    bf16x8 f[NU];
+  };
+  // Buffer loads: one descriptor for this head's 8 prepared operands, a
+  // per-lane byte offset shared by every matrix of a kind, and the matrix /
+  // fragment offset in a scalar register (no per-matrix address registers).
+  const __amdgpu_buffer_rsrc_t prsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16*>(prep), (short)0, 8 * DH * 2, 0x00020000);
+  const int th_off = ((32 * NB * w + l32) * D + 8 * hf) * 2;
+  const int td_off = ((16 * w + l16) * HH + (HH / 4) * g4) * 2;
+  auto bload = [&](int voff, int soff) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(prsrc, voff, soff, 0));
+  };
+  auto load_th = [&](int k) {
+    ThW r;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) b[m] = *reinterpret_cast<const bf16x8*>(mrow + 16 * m);
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) r.f[j][m] = bload(th_off, k * DH * 2 + j * 32 * D * 2 + 32 * m);
+    return r;
+  };
+  auto load_td = [&](int k) {
+    TdW r;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) r.f[u] = bload(td_off, k * DH * 2 + 16 * u);
+    return r;
+  };
+  // 32x32 block C[token][hid] of hidden block j: X[token][:] M[hid][:]^T.
+  auto th = [&](const bf16x8 (&a)[4], const ThW& wt, int j) {
     f32x16 c = {};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) c = mma32(a[m], b[m], c);
+    for (int m = 0; m < 4; ++m) c = mma32(a[m], wt.f[j][m], c);
     return c;
   };
-  // B fragments of a [d][hid] weight for this wave's 16 feature columns.
-  auto wfrag = [&](const bf16* M, bf16x8 (&b)[NU]) {
-    const bf16* mrow = M + (16 * w + l16) * HH + (HH / 4) * g4;
-#pragma unroll
-    for (int u = 0; u < NU; ++u) b[u] = *reinterpret_cast<const bf16x8*>(mrow + 8 * u);
-  };
+  // Keeps the scheduler from hoisting a prefetch above the products before it.
+  auto fence_sched = [] { __builtin_amdgcn_sched_barrier(0); };
   // A fragment u of the staged [token][hid] tile for token half tb.
   auto sfrag = [&](int soff, int tb, int u) {
     return *reinterpret_cast<const bf16x8*>(lds(soff + ((16 * tb + l16) * SL + (HH / 4) * g4 + 8 * u) * 2));
@@ -257,7 +284,8 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = ab ? (v[i] - xh[i] * dot) * inv : v[i] * inv;
     }
-    if (row < nv) store_vec<IOT, 8>(static_cast<IOT*>(base) + (t0 + row) * p.stride_tok + hoff + col0, v);
+    IOT* tile = static_cast<IOT*>(base) + t0 * p.stride_tok + hoff;  // wave-uniform
+    if (row < nv) store_vec<IOT, 8>(tile + (uint32_t)(row * (uint32_t)p.stride_tok + col0), v);
   };
 
   f32x16 gw1[NB][2] = {}, gw2[NB][2] = {};
@@ -267,22 +295,25 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
   const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
   RawRow<IOT> ra, rb;
+  // Row loads: a wave-uniform tile base plus a 32-bit per-lane offset.
   auto fetch_upd = [&](int t) {
-    const int64_t t0 = p.grad_start + (int64_t)t * TT;
-    const int64_t e = (t0 + min(row, gl - t * TT - 1)) * p.stride_tok + hoff + col0;
-    fetch_row<IOT>(p.K, e, ra);
-    fetch_row<IOT>(p.V, e, rb);
+    const int64_t tb0 = (p.grad_start + (int64_t)t * TT) * p.stride_tok + hoff;
+    const uint32_t e = (uint32_t)(min(row, gl - t * TT - 1) * (uint32_t)p.stride_tok + col0);
+    fetch_row<IOT>(static_cast<const IOT*>(p.K) + tb0, e, ra);
+    fetch_row<IOT>(static_cast<const IOT*>(p.V) + tb0, e, rb);
   };
   auto fetch_app = [&](int t) {
-    const int64_t t0 = p.app_start + (int64_t)t * TT;
-    const int64_t e = (t0 + min(row, al - t * TT - 1)) * p.stride_tok + hoff + col0;
-    fetch_row<IOT>(p.Q, e, ra);
-    fetch_row<IOT>(p.dO, e, rb);
+    const int64_t tb0 = (p.app_start + (int64_t)t * TT) * p.stride_tok + hoff;
+    const uint32_t e = (uint32_t)(min(row, al - t * TT - 1) * (uint32_t)p.stride_tok + col0);
+    fetch_row<IOT>(static_cast<const IOT*>(p.Q) + tb0, e, ra);
+    fetch_row<IOT>(static_cast<const IOT*>(p.dO) + tb0, e, rb);
   };
   if (g < n_gt)
     fetch_upd(g);
   else if (g < n_at)
     fetch_app(g);
+
+  ThW wA = load_th(0);  // W1 for the first Z (or Zq) products
 
   // ------------------------------------------------ update adjoint of chunk s
   for (int t = g; t < n_gt; t += G) {
@@ -299,12 +330,18 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     // phase 1: Z = K W1, sigma(Z), A = s(Z) (staged)
     f32x16 Z[NB], Sg[NB];
     uint32_t Apk[NB][8];
+    TdW b2, bh;
     {
       bf16x8 xa[4];
       xfrag(L::xb, xa);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        Z[j] = th(xa, prep + 0 * DH, NB * w + j);
+        Z[j] = th(xa, wA, j);
+        if (j == NB - 1) {
+          fence_sched();
+          b2 = load_td(5);
+          bh = load_td(7);
+        }
         f32x16 A;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -318,19 +355,20 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     __syncthreads();
     // phase 2: Y = A W2 -> E;  A Wh2 -> -eta A Wh2 (kept) and its d(eta) term
     f32x4 des[2];
+    ThW wP, wK;
     {
-      bf16x8 b2[NU], bh[NU];
-      wfrag(prep + 5 * DH, b2);
-      wfrag(prep + 7 * DH, bh);
       f32x4 y[2] = {}, aw[2] = {};
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb) {
           const bf16x8 a = sfrag(L::s0, tb, u);
-          y[tb] = mma16(a, b2[u], y[tb]);
-          aw[tb] = mma16(a, bh[u], aw[tb]);
+          y[tb] = mma16(a, b2.f[u], y[tb]);
+          aw[tb] = mma16(a, bh.f[u], aw[tb]);
         }
+      fence_sched();
+      wP = load_th(1);
+      wK = load_th(2);
       const float* vf = reinterpret_cast<const float*>(lds(L::vf));
       const int d = 16 * w + l16;
 #pragma unroll
@@ -350,14 +388,19 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     // (staged), dZ = dD P s''(Z) with dD = -eta K Wh1
     f32x16 S1[NB], dZ[NB];
     uint32_t dPpk[NB][8];
+    TdW b2b;
     {
       bf16x8 ea[4], xa[4];
       xfrag(L::eb, ea);
       xfrag(L::xb, xa);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const f32x16 P = th(ea, prep + 1 * DH, NB * w + j);
-        const f32x16 KW = th(xa, prep + 2 * DH, NB * w + j);
+        const f32x16 P = th(ea, wP, j);
+        const f32x16 KW = th(xa, wK, j);
+        if (j == NB - 1) {
+          fence_sched();
+          b2b = load_td(5);
+        }
         f32x16 Dm, dP;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -381,14 +424,16 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     }
     __syncthreads();
     // phase 4: dE = -eta A Wh2 + dP W2;  dY = (2/M) dE
+    ThW wH, wW;
     {
-      bf16x8 b2[NU];
-      wfrag(prep + 5 * DH, b2);
       f32x4 de[2] = {};
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb) de[tb] = mma16(sfrag(L::s0, tb, u), b2[u], de[tb]);
+        for (int tb = 0; tb < 2; ++tb) de[tb] = mma16(sfrag(L::s0, tb, u), b2b.f[u], de[tb]);
+      fence_sched();
+      wH = load_th(3);
+      wW = load_th(1);
       float* yf = reinterpret_cast<float*>(lds(L::yf));
       const int d = 16 * w + l16;
 #pragma unroll
@@ -405,14 +450,20 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     __syncthreads();
     // phase 5: dA = -eta E Wh2^T + dY W2^T;  dZ += dA s'(Z);  token sums
     //          dP^T E + A^T dY (W2) and K^T dZ (W1);  stage dZ
+    TdW b1, bh1;
     {
       bf16x8 ea[4], ya[4];
       xfrag(L::eb, ea);
       xfrag(L::yb, ya);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const f32x16 dA1 = th(ea, prep + 3 * DH, NB * w + j);
-        const f32x16 dA2 = th(ya, prep + 1 * DH, NB * w + j);
+        const f32x16 dA1 = th(ea, wH, j);
+        const f32x16 dA2 = th(ya, wW, j);
+        if (j == NB - 1) {
+          fence_sched();
+          b1 = load_td(4);
+          bh1 = load_td(6);
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) dZ[j][r] += (-eta * dA1[r] + dA2[r]) * S1[j][r];
         uint32_t dZpk[8];
@@ -431,17 +482,16 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     __syncthreads();
     // phase 6: dK = -eta D Wh1^T + dZ W1^T
     {
-      bf16x8 b1[NU], bh[NU];
-      wfrag(prep + 4 * DH, b1);
-      wfrag(prep + 6 * DH, bh);
       f32x4 k1[2] = {}, k2[2] = {};
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int tb = 0; tb < 2; ++tb) {
-          k1[tb] = mma16(sfrag(L::s1, tb, u), bh[u], k1[tb]);
-          k2[tb] = mma16(sfrag(L::s0, tb, u), b1[u], k2[tb]);
+          k1[tb] = mma16(sfrag(L::s1, tb, u), bh1.f[u], k1[tb]);
+          k2[tb] = mma16(sfrag(L::s0, tb, u), b1.f[u], k2[tb]);
         }
+      fence_sched();
+      wA = load_th(0);
       float* df = reinterpret_cast<float*>(lds(L::df));
       const int d = 16 * w + l16;
 #pragma unroll
@@ -457,6 +507,8 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   }
 
   // ------------------------------------------------ apply adjoint of chunk s-1
+  ThW wB;
+  if (g < n_at) wB = load_th(1);  // W2 for the dO W2^T products
   for (int t = g; t < n_at; t += G) {
     const int64_t t0 = p.app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
@@ -465,14 +517,19 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     if (t + G < n_at) fetch_app(t + G);
     __syncthreads();
     // Zq = Q W1, dZq = (dO W2^T) s'(Zq); token sums Aq^T dO and Q^T dZq
+    TdW b1;
     {
       bf16x8 xa[4], ya[4];
       xfrag(L::xb, xa);
       xfrag(L::yb, ya);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const f32x16 Zq = th(xa, prep + 0 * DH, NB * w + j);
-        const f32x16 Gq = th(ya, prep + 1 * DH, NB * w + j);
+        const f32x16 Zq = th(xa, wA, j);
+        const f32x16 Gq = th(ya, wB, j);
+        if (j == NB - 1) {
+          fence_sched();
+          b1 = load_td(4);
+        }
         f32x16 Aq, dZq;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -498,13 +555,16 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
     __syncthreads();
     // dQ = dZq W1^T
     {
-      bf16x8 b1[NU];
-      wfrag(prep + 4 * DH, b1);
       f32x4 q1[2] = {};
 #pragma unroll
       for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int tb = 0; tb < 2; ++tb) q1[tb] = mma16(sfrag(L::s0, tb, u), b1[u], q1[tb]);
+        for (int tb = 0; tb < 2; ++tb) q1[tb] = mma16(sfrag(L::s0, tb, u), b1.f[u], q1[tb]);
+      if (t + G < n_at) {
+        fence_sched();
+        wA = load_th(0);
+        wB = load_th(1);
+      }
       float* df = reinterpret_cast<float*>(lds(L::df));
       const int d = 16 * w + l16;
 #pragma unroll
