@@ -131,6 +131,34 @@ ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64
                              const void* Q, const void* K, const void* V, const float* W1_0,
                              const float* W2_0, int32_t w0_per_seq, void* O, float* W1_T, float* W2_T,
                              const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes, void* hip_stream);
+/* ttt_batched_fwd that also writes the per-chunk checkpoints needed by
+ * ttt_batched_bwd (TTT_SAVE_CKPT must be set, and only here: ttt_batched_fwd
+ * rejects it with TTT_EINVAL; TTT_EMIT_LOSS is TTT_ENOTSUP for batches).
+ *   ckpt  [sum_b C_b][H][d*h + h*d] f32, C_b = ceil(N_b / chunk_tokens):
+ *         sequence b's rows follow those of sequences 0..b-1; row j of
+ *         sequence b holds the weights before its chunk j. */
+ttt_status_t ttt_batched_fwd_ckpt(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host,
+                                  const void* Q, const void* K, const void* V, const float* W1_0,
+                                  const float* W2_0, int32_t w0_per_seq, void* O, float* W1_T, float* W2_T,
+                                  float* ckpt, const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes,
+                                  void* hip_stream);
+/* Backward of ttt_batched_fwd_ckpt for the outer loss sum <O, dO> over all
+ * sequences (each sequence's chain differentiated as in ttt_chunk_bwd).
+ * The reverse chunk walks of all sequences run in one stream-ordered
+ * schedule, aligned at each sequence's last chunk.
+ *   ckpt          checkpoints of ttt_batched_fwd_ckpt on the same inputs.
+ *   dO            [sum N_b][H][d] io_dtype; dQ, dK, dV likewise (raw inputs).
+ *   dW1_0, dW2_0  w0_per_seq = 1: per-sequence gradients [B][H][..];
+ *                 w0_per_seq = 0: gradient of the shared W_0, [H][..]
+ *                 (the sum over sequences, in sequence order).
+ *   deta          [H] f32: per-head d/d eta summed over sequences.
+ *   tile_cfg      as in ttt_batched_fwd (nullable).
+ *   ws            ws_bytes >= ttt_workspace_bytes(p, n_seqs). */
+ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host,
+                             const void* Q, const void* K, const void* V, const float* W1_0,
+                             const float* W2_0, int32_t w0_per_seq, const float* ckpt, const void* dO,
+                             void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta,
+                             const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes, void* hip_stream);
 
 /* Global Context Synchronization form over one sequence (Sec. 4.2, Eq. 10):
  * every chunk's gradient is taken at the same initial weights W0 (chunk c

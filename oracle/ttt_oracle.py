@@ -301,6 +301,36 @@ def ttt_backward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True, T
     return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1_0, dW2_0=dW2_0, deta=deta, fwd=fwd)
 
 
+def ttt_backward_batched(Q, K, V, cu_seqlens, W1_0, W2_0, eta, chunk_tokens, dO,
+                         w0_per_seq=False, norm=(True, True, True), act="silu"):
+    """Reverse mode of ttt_forward_batched for sum <O, dO> over all
+    sequences.  Sequences are independent chains, so each one is ttt_backward
+    on its own token range; a shared W0 (and the shared eta) receives the sum
+    of the sequences' gradients."""
+    cu = [int(x) for x in cu_seqlens]
+    Q, K, V, W1_0, W2_0, dO = _as_f64(Q, K, V, W1_0, W2_0, dO)
+    B = len(cu) - 1
+    dQ, dK, dV = np.zeros_like(Q), np.zeros_like(K), np.zeros_like(V)
+    dW1 = np.zeros_like(W1_0)
+    dW2 = np.zeros_like(W2_0)
+    deta = np.zeros(Q.shape[1])
+    for b in range(B):
+        s, e = cu[b], cu[b + 1]
+        w1 = W1_0[b] if w0_per_seq else W1_0
+        w2 = W2_0[b] if w0_per_seq else W2_0
+        if e == s:
+            continue
+        r = ttt_backward(Q[s:e], K[s:e], V[s:e], w1, w2, eta, chunk_tokens, dO[s:e], norm, act)
+        dQ[s:e], dK[s:e], dV[s:e] = r["dQ"], r["dK"], r["dV"]
+        if w0_per_seq:
+            dW1[b], dW2[b] = r["dW1_0"], r["dW2_0"]
+        else:
+            dW1 += r["dW1_0"]
+            dW2 += r["dW2_0"]
+        deta += r["deta"]
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1, dW2_0=dW2, deta=deta)
+
+
 def outer_objective(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm=(True, True, True), act="silu"):
     """sum <O, dO>: the scalar whose gradient ttt_backward returns."""
     O = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)["O"]

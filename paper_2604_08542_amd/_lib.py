@@ -12,8 +12,9 @@ TTT_F32, TTT_BF16 = 0, 1
 TTT_NORM_Q, TTT_NORM_K, TTT_NORM_V = 1, 2, 4
 TTT_SAVE_CKPT, TTT_EMIT_LOSS, TTT_MMA_BF16 = 8, 16, 32
 
-EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd", "ttt_gcs_fwd", "ttt_gcs_bwd",
-            "ttt_profile_enable", "ttt_profile_read", "ttt_status_string", "ttt_version")
+EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd", "ttt_batched_fwd_ckpt",
+            "ttt_batched_bwd", "ttt_gcs_fwd", "ttt_gcs_bwd", "ttt_profile_enable", "ttt_profile_read",
+            "ttt_status_string", "ttt_version")
 
 
 class Problem(ctypes.Structure):
@@ -65,6 +66,13 @@ def load(path: str = LIB_PATH):
     lib.ttt_batched_fwd.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, fp, fp,
                                     ctypes.c_int32, vp, fp, fp, ctypes.POINTER(TileCfg), vp, sz, vp]
     lib.ttt_batched_fwd.restype = st
+    lib.ttt_batched_fwd_ckpt.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, fp, fp,
+                                         ctypes.c_int32, vp, fp, fp, fp, ctypes.POINTER(TileCfg), vp, sz, vp]
+    lib.ttt_batched_fwd_ckpt.restype = st
+    lib.ttt_batched_bwd.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, fp, fp,
+                                    ctypes.c_int32, fp, vp, vp, vp, vp, fp, fp, fp, ctypes.POINTER(TileCfg), vp, sz,
+                                    vp]
+    lib.ttt_batched_bwd.restype = st
     lib.ttt_status_string.argtypes = [st]
     lib.ttt_status_string.restype = ctypes.c_char_p
     lib.ttt_gcs_fwd.argtypes = [P, vp, vp, vp, fp, fp, vp, fp, fp, fp, vp, sz, vp]

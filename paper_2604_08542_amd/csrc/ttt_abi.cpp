@@ -55,27 +55,35 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
 }
 
 struct WsLayout {
-  size_t partial, partial_loss, pp, adj, wlast, prep, total;
+  size_t partial, partial_loss, pp, adj, wlast, prep, fin, deta_seq, total;
   int64_t slot_cap;
 };
 
+// n_chains = sequences x heads of the call.
 WsLayout ws_layout(const Shape& s, int64_t n_chains) {
   WsLayout L{};
   L.slot_cap = std::max<int64_t>(n_chains, SLOT_CAP_MIN);
+  const size_t wbytes = (size_t)2 * s.dh() * sizeof(float);  // one chain's [W1 | W2]
   size_t off = 0;
   L.partial = off;
-  off = align_up(off + (size_t)L.slot_cap * 2 * s.dh() * sizeof(float));
+  off = align_up(off + (size_t)L.slot_cap * wbytes);
   L.partial_loss = off;
   off = align_up(off + (size_t)L.slot_cap * sizeof(float));
-  L.pp = off;
-  off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
-  // backward only: two adjoint buffers and the recomputed last weights
+  L.pp = off;  // forward: ping-pong weights per chain
+  off = align_up(off + 2 * (size_t)n_chains * wbytes);
+  // backward: two adjoint buffers per chain, the recomputed last weights,
+  // operand copies (8 matrices per chain of one launch, float-sized slots),
+  // per-sequence final adjoints and d(eta) sums (shared initial weights)
   L.adj = off;
-  off = align_up(off + (size_t)2 * n_chains * 2 * s.dh() * sizeof(float));
+  off = align_up(off + 2 * (size_t)n_chains * wbytes);
   L.wlast = off;
-  off = align_up(off + (size_t)n_chains * 2 * s.dh() * sizeof(float));
-  L.prep = off;  // backward operand copies: 8 matrices per head (float-sized slots)
-  off = align_up(off + (size_t)s.H * 8 * s.dh() * sizeof(float));
+  off = align_up(off + (size_t)n_chains * wbytes);
+  L.prep = off;
+  off = align_up(off + (size_t)std::min<int64_t>(n_chains, (int64_t)MAXS * s.H) * 8 * s.dh() * sizeof(float));
+  L.fin = off;
+  off = align_up(off + (size_t)n_chains * wbytes);
+  L.deta_seq = off;
+  off = align_up(off + (size_t)n_chains * sizeof(float));
   L.total = off;
   return L;
 }
@@ -147,6 +155,8 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
   }
   if (cmax == 0) return TTT_OK;
   const int64_t dh = S.dh();
+  std::vector<int64_t> ckoff(B, 0);  // checkpoint row of each sequence's chunk 0
+  for (int b = 1; b < B; ++b) ckoff[b] = ckoff[b - 1] + cb[b - 1];
   float* partial = at<float>(ws, L.partial);
   float* partial_loss = at<float>(ws, L.partial_loss);
   float* pp[2] = {at<float>(ws, L.pp), at<float>(ws, L.pp) + nch_total * 2 * dh};
@@ -190,6 +200,7 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
         a.app_start[i] = cu[b] + (s - 1) * M;
         a.app_len[i] = s >= 1 ? (int32_t)std::min<int64_t>(M, nb[b] - (s - 1) * M) : 0;
         u.seq_id[i] = b;
+        u.ckpt_off[i] = (ckoff[b] + s) * S.H * 2 * dh;
         u.grad_len[i] = a.grad_len[i];
         u.is_last[i] = (s == cb[b] - 1);
         grad_here |= a.grad_len[i] > 0;
@@ -203,7 +214,7 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
         u.H = S.H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
         u.partial = a.partial; u.partial_loss = a.partial_loss;
         u.w_dst = pp[(s + 1) % 2];
-        u.ckpt = ckpt ? ckpt + s * S.H * 2 * dh : nullptr;
+        u.ckpt = ckpt;
         u.wT1 = W1_T; u.wT2 = W2_T;
         u.loss = loss; u.loss_stride = (int32_t)cmax; u.chunk = (int32_t)s;
         u.n_active = na;
@@ -215,75 +226,116 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
   return TTT_OK;
 }
 
-// Backward: recompute W_C from the last checkpoint, then walk s = C..0 with
-// one bwd-step launch (update adjoint of chunk s, apply adjoint of chunk s-1)
-// and one reduction launch each.
-ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K, const void* V,
-                          const float* ckpt, const void* dO, void* dQ, void* dK, void* dV, float* dW1_0,
-                          float* dW2_0, float* deta, void* ws, size_t ws_bytes, hipStream_t st) {
+// Backward over B sequences (B = 1 for ttt_chunk_bwd).  Every sequence's
+// W_C is recomputed from its last checkpoint; then reverse step r = 0..C_max
+// handles, for every sequence b with C_b >= r, its chunk s = C_b - r: one
+// operand-preparation launch, one bwd-step launch (update adjoint of chunk
+// s, apply adjoint of chunk s-1) and one reduction launch for all of them.
+// Sequences are aligned at their last chunk, so a sequence's gradient is
+// final (s = 0) at step C_b.
+ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, int w0_per_seq,
+                          const float* ckpt, const void* Q, const void* K, const void* V, const void* dO, void* dQ,
+                          void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta, const ttt_tile_cfg_t* cfg,
+                          void* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t H = S.H;
-  const WsLayout L = ws_layout(S, H);
+  const WsLayout L = ws_layout(S, (int64_t)B * H);
   if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
-  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
-  const int64_t C = (N + M - 1) / M;
+  const int64_t M = S.M, dh = S.dh(), wsz = 2 * dh;
+  std::vector<int64_t> nb(B), cb(B), ckoff(B, 0);
+  int64_t cmax = 0, nmax = 0;
+  for (int b = 0; b < B; ++b) {
+    nb[b] = cu[b + 1] - cu[b];
+    cb[b] = (nb[b] + M - 1) / M;
+    if (b > 0) ckoff[b] = ckoff[b - 1] + cb[b - 1];
+    cmax = std::max(cmax, cb[b]);
+    nmax = std::max(nmax, nb[b]);
+  }
   float* partial = at<float>(ws, L.partial);
   float* pdeta = at<float>(ws, L.partial_loss);
-  float* adj[2] = {at<float>(ws, L.adj), at<float>(ws, L.adj) + H * 2 * dh};
+  float* adj[2] = {at<float>(ws, L.adj), at<float>(ws, L.adj) + B * H * wsz};
   float* wlast = at<float>(ws, L.wlast);
   void* prep = at<char>(ws, L.prep);
-  const int target = default_target_wgs(S);
+  float* fin = at<float>(ws, L.fin);
+  float* deta_seq = B == 1 ? deta : at<float>(ws, L.deta_seq);
+  const bool shared_w0 = B > 1 && !w0_per_seq;
+  const int target = (cfg && cfg->target_wgs > 0) ? cfg->target_wgs : default_target_wgs(S);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
-  const int64_t tiles = (std::min(M, N) + TT - 1) / TT;
-  int64_t G = std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, std::max<int64_t>(tiles, 1),
-                                                      L.slot_cap / H}));
-  auto mlen = [&](int64_t c) { return (int32_t)std::min<int64_t>(M, N - c * M); };
-  if (C == 0) {
-    BwdReduceArgs r{};
-    r.dst1 = dW1_0; r.dst2 = dW2_0; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
-    r.deta_first = 1; r.G = 0; r.H = (int32_t)H; r.h = S.h;
-    return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
-  }
-  {  // W_C = W_{C-1} - eta * grad L_{C-1}(W_{C-1})
+  const int64_t tiles = std::max<int64_t>((std::min(M, nmax) + TT - 1) / TT, 1);
+  auto mlen = [&](int b, int64_t c) { return (int32_t)std::min<int64_t>(M, nb[b] - c * M); };
+
+  // W_{C_b} = W_{C_b - 1} - eta * grad L_{C_b - 1}(W_{C_b - 1}) per sequence
+  for (int b = 0; b < B; ++b) {
+    if (cb[b] == 0) continue;
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, tiles, L.slot_cap / H}));
     FwdStepArgs a{};
     a.Q = Q; a.K = K; a.V = V; a.O = nullptr;
     a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
-    a.w1_src = ckpt + (C - 1) * H * 2 * dh; a.w2_src = a.w1_src + dh; a.w_cstride = 2 * dh;
+    a.w1_src = ckpt + (ckoff[b] + cb[b] - 1) * H * wsz; a.w2_src = a.w1_src + dh; a.w_cstride = wsz;
     a.w_mod = (int32_t)H; a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G;
     a.partial = partial; a.partial_loss = pdeta; a.n_active = 1;
-    a.seq_id[0] = 0; a.grad_start[0] = (C - 1) * M; a.grad_len[0] = mlen(C - 1);
+    a.seq_id[0] = 0; a.grad_start[0] = cu[b] + (cb[b] - 1) * M; a.grad_len[0] = mlen(b, cb[b] - 1);
     a.app_start[0] = 0; a.app_len[0] = 0;
     if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
     UpdStepArgs u{};
     u.w1_src = a.w1_src; u.w2_src = a.w2_src; u.w_cstride = a.w_cstride; u.w_mod = a.w_mod;
     u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
-    u.partial = partial; u.partial_loss = pdeta; u.w_dst = wlast;
-    u.n_active = 1; u.seq_id[0] = 0; u.grad_len[0] = mlen(C - 1); u.is_last[0] = 0;
+    u.partial = partial; u.partial_loss = pdeta; u.w_dst = wlast + b * H * wsz;
+    u.n_active = 1; u.seq_id[0] = 0; u.grad_len[0] = a.grad_len[0]; u.is_last[0] = 0;
     if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
-  for (int64_t s = C; s >= 0; --s) {
-    const float* w_s = s < C ? ckpt + s * H * 2 * dh : wlast;
-    const float* wh_s = s < C ? adj[(s + 1) % 2] : nullptr;
-    if (!timed_launch(4, st, [&] { return launch_bwd_prep(w_s, wh_s, prep, (int)H, S.h, S.mma_bf16, st); }))
-      return TTT_EHIP;
-    BwdStepArgs b{};
-    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
-    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.prep = prep;
-    b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta; b.G = (int32_t)G;
-    b.partial = partial; b.partial_deta = pdeta;
-    b.grad_start = s * M; b.grad_len = s < C ? mlen(s) : 0;
-    b.app_start = (s - 1) * M; b.app_len = s >= 1 ? mlen(s - 1) : 0;
-    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
-      return TTT_EHIP;
-    BwdReduceArgs r{};
-    r.wh_src = wh_s;
-    r.wh_dst = adj[s % 2];
-    r.dst1 = s == 0 ? dW1_0 : nullptr;
-    r.dst2 = s == 0 ? dW2_0 : nullptr;
-    r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
-    r.deta_first = s == C; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
-    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+
+  for (int64_t r = 0; r <= cmax; ++r) {
+    std::vector<int> act;
+    for (int b = 0; b < B; ++b)
+      if (r <= cb[b]) act.push_back(b);
+    for (size_t base = 0; base < act.size(); base += MAXS) {
+      const int na = (int)std::min<size_t>(MAXS, act.size() - base);
+      const int64_t n_chains = (int64_t)na * H;
+      int64_t G = (cfg && cfg->wg_per_chain > 0) ? cfg->wg_per_chain : (target + n_chains - 1) / n_chains;
+      G = std::max<int64_t>(1, std::min<int64_t>({G, tiles, L.slot_cap / n_chains}));
+      BwdPrepArgs pa{};
+      pa.prep = prep; pa.H = (int32_t)H; pa.h = S.h;
+      BwdStepArgs bs{};
+      bs.Q = Q; bs.K = K; bs.V = V; bs.dO = dO; bs.dQ = dQ; bs.dK = dK; bs.dV = dV;
+      bs.stride_tok = S.stride_tok; bs.stride_head = S.stride_head;
+      bs.prep = prep; bs.H = (int32_t)H; bs.flags = p->flags; bs.eta = p->eta; bs.G = (int32_t)G;
+      bs.partial = partial; bs.partial_deta = pdeta; bs.n_active = na;
+      BwdReduceArgs rd{};
+      rd.partial = partial; rd.partial_deta = pdeta; rd.n_active = na; rd.G = (int32_t)G;
+      rd.H = (int32_t)H; rd.h = S.h;
+      for (int i = 0; i < na; ++i) {
+        const int b = act[base + i];
+        const int64_t s = cb[b] - r;
+        const float* whs = r == 0 ? nullptr : adj[(r + 1) % 2] + b * H * wsz;
+        pa.w_src[i] = s < cb[b] ? ckpt + (ckoff[b] + s) * H * wsz : wlast + b * H * wsz;
+        pa.wh_src[i] = whs;
+        bs.grad_start[i] = cu[b] + s * M;
+        bs.grad_len[i] = s < cb[b] ? mlen(b, s) : 0;
+        bs.app_start[i] = cu[b] + (s - 1) * M;
+        bs.app_len[i] = s >= 1 ? mlen(b, s - 1) : 0;
+        rd.wh_src[i] = whs;
+        rd.wh_dst[i] = adj[r % 2] + b * H * wsz;
+        if (s == 0 && shared_w0) rd.wh_dst[i] = fin + b * H * wsz;
+        if (s == 0 && !shared_w0) {
+          rd.dst1[i] = dW1_0 + (w0_per_seq ? b * H * dh : 0);
+          rd.dst2[i] = dW2_0 + (w0_per_seq ? b * H * dh : 0);
+        }
+        rd.deta[i] = deta_seq + (B == 1 ? 0 : b * H);
+        rd.deta_first[i] = r == 0;
+      }
+      if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, na, S.mma_bf16, st); })) return TTT_EHIP;
+      if (!timed_launch(2, st, [&] { return launch_bwd_step(bs, (int)(n_chains * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+        return TTT_EHIP;
+      if (!timed_launch(3, st, [&] { return launch_bwd_reduce(rd, (int)(n_chains * nbpc), st); })) return TTT_EHIP;
+    }
+  }
+  if (B > 1) {  // d(eta) over sequences, and the shared initial weights' gradient
+    BwdSumArgs sm{};
+    sm.src = shared_w0 ? fin : nullptr;
+    sm.deta_src = deta_seq; sm.dW1 = dW1_0; sm.dW2 = dW2_0; sm.deta = deta;
+    sm.B = B; sm.H = (int32_t)H; sm.h = S.h;
+    if (!timed_launch(3, st, [&] { return launch_bwd_sum(sm, st); })) return TTT_EHIP;
   }
   return TTT_OK;
 }
@@ -372,10 +424,29 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   float* w0 = at<float>(ws, L.adj) + H * 2 * dh;         // W0 packed [W1 | W2] per head
   void* prep = at<char>(ws, L.prep);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
-  if (C == 0) {  // no tokens: zero gradients
+  auto reduce_args = [&](const float* src, float* dst, float* d1, float* d2, int first, int64_t G) {
     BwdReduceArgs r{};
-    r.dst1 = dW1_0; r.dst2 = dW2_0; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
-    r.deta_first = 1; r.G = 0; r.H = (int32_t)H; r.h = S.h;
+    r.wh_src[0] = src; r.wh_dst[0] = dst; r.dst1[0] = d1; r.dst2[0] = d2;
+    r.deta[0] = deta; r.deta_first[0] = first;
+    r.partial = partial; r.partial_deta = pdeta; r.n_active = 1; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    return r;
+  };
+  auto prep_args = [&](const float* w, const float* whs) {
+    BwdPrepArgs a{};
+    a.w_src[0] = w; a.wh_src[0] = whs; a.prep = prep; a.H = (int32_t)H; a.h = S.h;
+    return a;
+  };
+  auto step_args = [&](int64_t G, int64_t gs, int32_t gl, int64_t as, int32_t al) {
+    BwdStepArgs b{};
+    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
+    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
+    b.prep = prep; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta; b.n_active = 1;
+    b.grad_start[0] = gs; b.grad_len[0] = gl; b.app_start[0] = as; b.app_len[0] = al;
+    return b;
+  };
+  if (C == 0) {  // no tokens: zero gradients
+    const BwdReduceArgs r = reduce_args(nullptr, nullptr, dW1_0, dW2_0, 1, 0);
     return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
   }
   // W* (no outputs)
@@ -399,48 +470,66 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   };
   // apply adjoint of all tokens at W*  ->  Wh (and dQ), deta starts at 0
   {
-    if (!timed_launch(4, st, [&] { return launch_bwd_prep(wstar, nullptr, prep, (int)H, S.h, S.mma_bf16, st); }))
-      return TTT_EHIP;
-    BwdStepArgs b{};
-    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
-    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.prep = prep; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
+    const BwdPrepArgs pa = prep_args(wstar, nullptr);
+    if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
     const int64_t G = grid_g(N);
-    b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
-    b.grad_start = 0; b.grad_len = 0; b.app_start = 0; b.app_len = (int32_t)N;
+    const BwdStepArgs b = step_args(G, 0, 0, 0, (int32_t)N);
     if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
-    BwdReduceArgs r{};
-    r.wh_src = nullptr; r.wh_dst = wh; r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
-    r.deta_first = 1; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    const BwdReduceArgs r = reduce_args(nullptr, wh, nullptr, nullptr, 1, G);
     if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   // update adjoint of each chunk at W0 against Wh, accumulated on top of Wh
-  if (!timed_launch(4, st, [&] { return launch_bwd_prep(w0, wh, prep, (int)H, S.h, S.mma_bf16, st); }))
-    return TTT_EHIP;
+  {
+    const BwdPrepArgs pa = prep_args(w0, wh);
+    if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
+  }
   const float* prev = wh;
   for (int64_t c = 0; c < C; ++c) {
     const int32_t len = (int32_t)std::min<int64_t>(M, N - c * M);
-    BwdStepArgs b{};
-    b.Q = Q; b.K = K; b.V = V; b.dO = dO; b.dQ = dQ; b.dK = dK; b.dV = dV;
-    b.stride_tok = S.stride_tok; b.stride_head = S.stride_head;
-    b.prep = prep; b.H = (int32_t)H; b.flags = p->flags; b.eta = p->eta;
     const int64_t G = grid_g(len);
-    b.G = (int32_t)G; b.partial = partial; b.partial_deta = pdeta;
-    b.grad_start = c * M; b.grad_len = len; b.app_start = 0; b.app_len = 0;
+    const BwdStepArgs b = step_args(G, c * M, len, 0, 0);
     if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
-    BwdReduceArgs r{};
-    r.wh_src = prev; r.wh_dst = acc[c % 2];
-    r.dst1 = c == C - 1 ? dW1_0 : nullptr; r.dst2 = c == C - 1 ? dW2_0 : nullptr;
-    r.partial = partial; r.partial_deta = pdeta; r.deta = deta;
-    r.deta_first = 0; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    const BwdReduceArgs r = reduce_args(prev, acc[c % 2], c == C - 1 ? dW1_0 : nullptr, c == C - 1 ? dW2_0 : nullptr,
+                                        0, G);
     if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
     prev = acc[c % 2];
   }
   return TTT_OK;
 }
 
+ttt_status_t check_batch(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu, int32_t w0_per_seq,
+                         const ttt_tile_cfg_t* tile_cfg) {
+  if (n_seqs < 1 || !cu) return TTT_EINVAL;
+  if (w0_per_seq != 0 && w0_per_seq != 1) return TTT_EINVAL;
+  if (cu[0] != 0) return TTT_EINVAL;
+  for (int b = 0; b < n_seqs; ++b)
+    if (cu[b + 1] < cu[b]) return TTT_EINVAL;
+  if (tile_cfg && (tile_cfg->wg_per_chain < 0 || tile_cfg->target_wgs < 0)) return TTT_EINVAL;
+  (void)p;
+  return TTT_OK;
+}
+
+ttt_status_t batched_fwd_impl(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host, const void* Q,
+                              const void* K, const void* V, const float* W1_0, const float* W2_0, int32_t w0_per_seq,
+                              void* O, float* W1_T, float* W2_T, float* ckpt, const ttt_tile_cfg_t* tile_cfg,
+                              void* ws, size_t ws_bytes, void* hip_stream) {
+  Shape S{};
+  ttt_status_t e = check_problem(p, &S);
+  if (e != TTT_OK) return e;
+  if ((e = check_batch(p, n_seqs, cu_seqlens_host, w0_per_seq, tile_cfg)) != TTT_OK) return e;
+  if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+  if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+  if (((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
+  if (p->flags & TTT_EMIT_LOSS) return TTT_ENOTSUP;
+  for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
+                        (const void*)W2_T, (const void*)ckpt})
+    if (q && !aligned16(q)) return TTT_EINVAL;
+  if (cu_seqlens_host[n_seqs] == 0) return TTT_OK;
+  return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt, nullptr,
+                     tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+}
 }  // namespace
 
 extern "C" {
@@ -479,24 +568,45 @@ ttt_status_t ttt_batched_fwd(const ttt_problem_t* p, int32_t n_seqs, const int64
                              void* O, float* W1_T, float* W2_T, const ttt_tile_cfg_t* tile_cfg, void* ws,
                              size_t ws_bytes, void* hip_stream) {
   try {
+    if (p && (p->flags & TTT_SAVE_CKPT)) return TTT_EINVAL;  // checkpoints: ttt_batched_fwd_ckpt
+    return batched_fwd_impl(p, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, nullptr,
+                            tile_cfg, ws, ws_bytes, hip_stream);
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_batched_fwd_ckpt(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host,
+                                  const void* Q, const void* K, const void* V, const float* W1_0, const float* W2_0,
+                                  int32_t w0_per_seq, void* O, float* W1_T, float* W2_T, float* ckpt,
+                                  const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    return batched_fwd_impl(p, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt,
+                            tile_cfg, ws, ws_bytes, hip_stream);
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host, const void* Q,
+                             const void* K, const void* V, const float* W1_0, const float* W2_0, int32_t w0_per_seq,
+                             const float* ckpt, const void* dO, void* dQ, void* dK, void* dV, float* dW1_0,
+                             float* dW2_0, float* deta, const ttt_tile_cfg_t* tile_cfg, void* ws, size_t ws_bytes,
+                             void* hip_stream) {
+  try {
     Shape S{};
-    const ttt_status_t e = check_problem(p, &S);
+    ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (n_seqs < 1 || !cu_seqlens_host) return TTT_EINVAL;
-    if (w0_per_seq != 0 && w0_per_seq != 1) return TTT_EINVAL;
-    if (cu_seqlens_host[0] != 0) return TTT_EINVAL;
-    for (int b = 0; b < n_seqs; ++b)
-      if (cu_seqlens_host[b + 1] < cu_seqlens_host[b]) return TTT_EINVAL;
-    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
-    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
-    if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
-    if (tile_cfg && (tile_cfg->wg_per_chain < 0 || tile_cfg->target_wgs < 0)) return TTT_EINVAL;
-    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
-                          (const void*)W2_T})
+    if ((e = check_batch(p, n_seqs, cu_seqlens_host, w0_per_seq, tile_cfg)) != TTT_OK) return e;
+    if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
+    const bool any = cu_seqlens_host[n_seqs] > 0;
+    if (any && (!Q || !K || !V || !ckpt || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
+    (void)W1_0; (void)W2_0;  // each sequence's chunk-0 checkpoint holds its W_0
+    for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
+                          (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
-    if (cu_seqlens_host[n_seqs] == 0) return TTT_OK;
-    return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, nullptr,
-                       nullptr, tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+    return run_backward(p, S, n_seqs, cu_seqlens_host, w0_per_seq, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0,
+                        deta, tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;
   }
@@ -515,7 +625,8 @@ ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K,
     for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
                           (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
-    return run_backward(p, S, Q, K, V, ckpt, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+    const int64_t cu[2] = {0, p->n_tokens};
+    return run_backward(p, S, 1, cu, 0, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, nullptr, ws, ws_bytes,
                         static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;

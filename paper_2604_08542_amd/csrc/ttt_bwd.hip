@@ -85,10 +85,11 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   };
   const int lin = xcd_linear_block();
   const int G = p.G;
-  const int head = lin / G, g = lin % G;
+  const int slot = lin / G, g = lin % G;  // slot = active sequence * H + head
+  const int ai = slot / p.H, head = slot % p.H;
   const float eta = p.eta;
   // prepared operand block of this head: 8 matrices of D*h elements
-  const MT* prep0 = static_cast<const MT*>(p.prep) + (int64_t)head * 8 * DH;
+  const MT* prep0 = static_cast<const MT*>(p.prep) + (int64_t)slot * 8 * DH;
   const int64_t hoff = (int64_t)head * p.stride_head;
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
 
@@ -254,11 +255,12 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   float deta_acc = 0.f;
 
   // ------------------------------------------------ update adjoint of chunk s
-  const int gl = p.grad_len;
+  const int gl = p.grad_len[ai];
+  const int64_t grad_start = p.grad_start[ai];
   const int n_gt = (gl + TT - 1) / TT;
   const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
   for (int t = g; t < n_gt; t += G) {
-    const int64_t t0 = p.grad_start + (int64_t)t * TT;
+    const int64_t t0 = grad_start + (int64_t)t * TT;
     const int nv = min(TT, gl - t * TT);
     const MT* pr = opaque(prep0);
     const MT* W1t = pr + 0 * DH;   // [hid][d] of W1
@@ -376,10 +378,11 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   }
 
   // ------------------------------------------------ apply adjoint of chunk s-1
-  const int al = p.app_len;
+  const int al = p.app_len[ai];
+  const int64_t app_start = p.app_start[ai];
   const int n_at = (al + TT - 1) / TT;
   for (int t = g; t < n_at; t += G) {
-    const int64_t t0 = p.app_start + (int64_t)t * TT;
+    const int64_t t0 = app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
     const MT* pr = opaque(prep0);
     const MT* W1t = pr + 0 * DH;
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   }
 
   // ------------------------------------------------ shard partials
-  float* part = p.partial + ((int64_t)head * G + g) * (2 * DH);
+  float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
 #pragma unroll
   for (int j = 0; j < NB; ++j)
 #pragma unroll
@@ -438,23 +441,25 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   if (li.tid == 0) {
     float s = 0.f;
     for (int i = 0; i < NW; ++i) s += red[i];
-    p.partial_deta[(int64_t)head * G + g] = s;
+    p.partial_deta[(int64_t)slot * G + g] = s;
   }
 }
 
-// Operand copies for one backward step, per head: W_s and the carried
-// adjoint Wh (zeros when absent), each of W1 [d][h] and W2 [h][d] written in
-// both orientations ([hid][d] and [d][hid]) in the matrix-core operand type,
-// so that every operand fragment is one contiguous vector load.
+// Operand copies for one backward step, per (active sequence, head): W_s and
+// the carried adjoint Wh (zeros when absent), each of W1 [d][h] and W2 [h][d]
+// written in both orientations ([hid][d] and [d][hid]) in the matrix-core
+// operand type, so that every operand fragment is one contiguous vector load.
 template <typename MT>
-__global__ __launch_bounds__(256) void ttt_bwd_prep(const float* w_src, const float* wh_src, MT* prep, int h) {
-  const int dh = D * h;
-  const int head = blockIdx.y;
+__global__ __launch_bounds__(256) void ttt_bwd_prep(BwdPrepArgs p) {
+  const int dh = D * p.h;
+  const int chain = blockIdx.y;  // active sequence * H + head
+  const int ai = chain / p.H, head = chain % p.H;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= dh) return;
-  const float* W = w_src + (int64_t)head * 2 * dh;
-  const float* Wh = wh_src ? wh_src + (int64_t)head * 2 * dh : nullptr;
-  MT* o = prep + (int64_t)head * 8 * dh;
+  const float* W = p.w_src[ai] + (int64_t)head * 2 * dh;
+  const float* Wh = p.wh_src[ai] ? p.wh_src[ai] + (int64_t)head * 2 * dh : nullptr;
+  MT* o = static_cast<MT*>(p.prep) + (int64_t)chain * 8 * dh;
+  const int h = p.h;
   const int d = idx / h, hh = idx % h;    // idx = d*h + hh: W1 element (d, hh)
   const int hh2 = idx / D, d2 = idx % D;  // idx = hh2*D + d2: W2 element (hh2, d2)
   const float w1 = W[idx], h1 = Wh ? Wh[idx] : 0.f;
@@ -469,46 +474,77 @@ __global__ __launch_bounds__(256) void ttt_bwd_prep(const float* w_src, const fl
   o[7 * dh + d2 * h + hh2] = (MT)h2;
 }
 
-hipError_t launch_bwd_prep(const float* w_src, const float* wh_src, void* prep, int H, int h, bool mma_bf16,
-                           hipStream_t st) {
-  const dim3 grid((D * h + 255) / 256, H);
+hipError_t launch_bwd_prep(const BwdPrepArgs& a, int n_active, bool mma_bf16, hipStream_t st) {
+  const dim3 grid((D * a.h + 255) / 256, n_active * a.H);
   if (mma_bf16)
-    hipLaunchKernelGGL(ttt_bwd_prep<bf16>, grid, dim3(256), 0, st, w_src, wh_src, static_cast<bf16*>(prep), h);
+    hipLaunchKernelGGL(ttt_bwd_prep<bf16>, grid, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(ttt_bwd_prep<float>, grid, dim3(256), 0, st, w_src, wh_src, static_cast<float*>(prep), h);
+    hipLaunchKernelGGL(ttt_bwd_prep<float>, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-// Wh_dst = Wh_src (0 if null) + sum of the G shard partials, in fixed order;
-// deta[head] (+)= sum of the dη partials.  dst may be split into W1 / W2
-// destinations (the final dW1_0 / dW2_0).
+// Per (active sequence, head): Wh_dst = Wh_src (0 if null) + the sum of the
+// G shard partials, in fixed order; deta[head] (+)= the sum of the dη
+// partials.  dst may be split into W1 / W2 destinations (the final dW1_0 /
+// dW2_0 of that sequence).
 __global__ __launch_bounds__(256) void ttt_bwd_reduce(BwdReduceArgs p) {
   const int dh = D * p.h;
   const int n4 = (2 * dh) / 4;
   const int nbpc = (n4 + 255) / 256;
   const int lin = xcd_linear_block();
-  const int head = lin / nbpc, k = lin % nbpc;
+  const int chain = lin / nbpc, k = lin % nbpc;
+  const int ai = chain / p.H, head = chain % p.H;
   const int i4 = k * 256 + threadIdx.x;
   if (i4 < n4) {
     const int idx = 4 * i4;
     f32x4 s = {0.f, 0.f, 0.f, 0.f};
-    if (p.wh_src) s = *reinterpret_cast<const f32x4*>(p.wh_src + (int64_t)head * 2 * dh + idx);
-    const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)head * p.G * 2 * dh) + i4;
+    if (p.wh_src[ai]) s = *reinterpret_cast<const f32x4*>(p.wh_src[ai] + (int64_t)head * 2 * dh + idx);
+    const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)chain * p.G * 2 * dh) + i4;
     for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
-    if (p.dst1) {
+    if (p.dst1[ai]) {
       if (idx < dh)
-        *reinterpret_cast<f32x4*>(p.dst1 + (int64_t)head * dh + idx) = s;
+        *reinterpret_cast<f32x4*>(p.dst1[ai] + (int64_t)head * dh + idx) = s;
       else
-        *reinterpret_cast<f32x4*>(p.dst2 + (int64_t)head * dh + (idx - dh)) = s;
+        *reinterpret_cast<f32x4*>(p.dst2[ai] + (int64_t)head * dh + (idx - dh)) = s;
     } else {
-      *reinterpret_cast<f32x4*>(p.wh_dst + (int64_t)head * 2 * dh + idx) = s;
+      *reinterpret_cast<f32x4*>(p.wh_dst[ai] + (int64_t)head * 2 * dh + idx) = s;
     }
   }
   if (k == 0 && threadIdx.x == 0) {
-    float sd = p.deta_first ? 0.f : p.deta[head];
-    for (int gg = 0; gg < p.G; ++gg) sd += p.partial_deta[(int64_t)head * p.G + gg];
+    float sd = p.deta_first[ai] ? 0.f : p.deta[ai][head];
+    for (int gg = 0; gg < p.G; ++gg) sd += p.partial_deta[(int64_t)chain * p.G + gg];
+    p.deta[ai][head] = sd;
+  }
+}
+
+// Shared initial weights: sum the per-sequence gradients in sequence order
+// (src may be null: d(eta) only).
+__global__ __launch_bounds__(256) void ttt_bwd_sum(BwdSumArgs p) {
+  const int dh = D * p.h;
+  const int n4 = (2 * dh) / 4;
+  const int i4 = blockIdx.x * 256 + threadIdx.x;
+  const int head = blockIdx.y;
+  if (p.src && i4 < n4) {
+    const int idx = 4 * i4;
+    f32x4 s = {0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < p.B; ++b)
+      s += *reinterpret_cast<const f32x4*>(p.src + ((int64_t)b * p.H + head) * 2 * dh + idx);
+    if (idx < dh)
+      *reinterpret_cast<f32x4*>(p.dW1 + (int64_t)head * dh + idx) = s;
+    else
+      *reinterpret_cast<f32x4*>(p.dW2 + (int64_t)head * dh + (idx - dh)) = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float sd = 0.f;
+    for (int b = 0; b < p.B; ++b) sd += p.deta_src[(int64_t)b * p.H + head];
     p.deta[head] = sd;
   }
+}
+
+hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st) {
+  const dim3 grid(((2 * D * a.h) / 4 + 255) / 256, a.H);
+  hipLaunchKernelGGL(ttt_bwd_sum, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // One wave per 32-wide hidden block: 4 waves at h=128, 8 at h=256.

@@ -127,9 +127,10 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   const int row = tid >> 3, col0 = (tid & 7) * 8;  // row mapping: 8 threads x 8 elements per token
   const int lin = xcd_linear_block();
   const int G = p.G;
-  const int head = lin / G, g = lin % G;
+  const int slot = lin / G, g = lin % G;  // slot = active sequence * H + head
+  const int ai = slot / p.H, head = slot % p.H;
   const float eta = p.eta;
-  const bf16* prep = static_cast<const bf16*>(p.prep) + (int64_t)head * 8 * DH;
+  const bf16* prep = static_cast<const bf16*>(p.prep) + (int64_t)slot * 8 * DH;
   const int64_t hoff = (int64_t)head * p.stride_head;
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
   float* ninv = reinterpret_cast<float*>(lds(L::ninv));
@@ -291,19 +292,20 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   f32x16 gw1[NB][2] = {}, gw2[NB][2] = {};
   float deta_acc = 0.f;
 
-  const int gl = p.grad_len, al = p.app_len;
+  const int gl = p.grad_len[ai], al = p.app_len[ai];
+  const int64_t grad_start = p.grad_start[ai], app_start = p.app_start[ai];
   const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
   const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
   RawRow<IOT> ra, rb;
   // Row loads: a wave-uniform tile base plus a 32-bit per-lane offset.
   auto fetch_upd = [&](int t) {
-    const int64_t tb0 = (p.grad_start + (int64_t)t * TT) * p.stride_tok + hoff;
+    const int64_t tb0 = (grad_start + (int64_t)t * TT) * p.stride_tok + hoff;
     const uint32_t e = (uint32_t)(min(row, gl - t * TT - 1) * (uint32_t)p.stride_tok + col0);
     fetch_row<IOT>(static_cast<const IOT*>(p.K) + tb0, e, ra);
     fetch_row<IOT>(static_cast<const IOT*>(p.V) + tb0, e, rb);
   };
   auto fetch_app = [&](int t) {
-    const int64_t tb0 = (p.app_start + (int64_t)t * TT) * p.stride_tok + hoff;
+    const int64_t tb0 = (app_start + (int64_t)t * TT) * p.stride_tok + hoff;
     const uint32_t e = (uint32_t)(min(row, al - t * TT - 1) * (uint32_t)p.stride_tok + col0);
     fetch_row<IOT>(static_cast<const IOT*>(p.Q) + tb0, e, ra);
     fetch_row<IOT>(static_cast<const IOT*>(p.dO) + tb0, e, rb);
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
 
   // ------------------------------------------------ update adjoint of chunk s
   for (int t = g; t < n_gt; t += G) {
-    const int64_t t0 = p.grad_start + (int64_t)t * TT;
+    const int64_t t0 = grad_start + (int64_t)t * TT;
     const int nv = min(TT, gl - t * TT);
     // phase 0: rows of K and V
     put_row(ra, row < nv, norm_k, 0, L::xf, L::xb, L::xt);
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   ThW wB;
   if (g < n_at) wB = load_th(1);  // W2 for the dO W2^T products
   for (int t = g; t < n_at; t += G) {
-    const int64_t t0 = p.app_start + (int64_t)t * TT;
+    const int64_t t0 = app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
     put_row(ra, row < nv, norm_q, 0, L::xf, L::xb, L::xt);
     put_row(rb, row < nv, false, 1, -1, L::yb, L::yt);
@@ -577,7 +579,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   }
 
   // ------------------------------------------------ shard partials
-  float* part = p.partial + ((int64_t)head * G + g) * (2 * DH);
+  float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int hb = NB * w + j;
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
   __syncthreads();
   if ((tid & 63) == 0) red[w] = deta_acc;
   __syncthreads();
-  if (tid == 0) p.partial_deta[(int64_t)head * G + g] = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) p.partial_deta[(int64_t)slot * G + g] = red[0] + red[1] + red[2] + red[3];
 }
 
 template <typename IOT, int NB>

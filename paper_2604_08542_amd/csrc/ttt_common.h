@@ -174,7 +174,8 @@ struct UpdStepArgs {
   const float* partial;
   const float* partial_loss;
   float* w_dst;      // [chains][2*D*h] next weights
-  float* ckpt;       // single sequence: weights before this chunk, [H][2*D*h]; nullable
+  float* ckpt;       // checkpoint rows: weights before this chunk; nullable
+  int64_t ckpt_off[MAXS];  // float offset of active sequence i's row [H][2*D*h] in ckpt
   float* wT1;        // [chains][D][h] final weights, nullable
   float* wT2;        // [chains][h][D]
   float* loss;       // single sequence: loss[head * loss_stride + chunk]; nullable
@@ -190,8 +191,10 @@ struct UpdStepArgs {
   int32_t gcs_chunks, gcs_M, gcs_last_len;
 };
 
-// One reverse chunk step of the backward for every head of one sequence:
-// the update adjoint of chunk s and the apply adjoint of chunk s-1.
+// One reverse chunk step of the backward for every head of the active
+// sequences: per sequence, the update adjoint of its chunk s and the apply
+// adjoint of its chunk s-1.  Work-group slot = (active sequence * H + head)
+// * G + shard.
 struct BwdStepArgs {
   const void* Q;
   const void* K;
@@ -201,29 +204,52 @@ struct BwdStepArgs {
   void* dK;
   void* dV;
   int64_t stride_tok, stride_head;
-  const void* prep;     // per head 8 operand matrices of D*h (see ttt_bwd_prep)
+  const void* prep;     // per (active sequence, head) 8 operand matrices of D*h (see ttt_bwd_prep)
   int32_t H;
   uint32_t flags;
   float eta;
   int32_t G;
-  float* partial;       // [H*G][2*D*h]
-  float* partial_deta;  // [H*G]
-  int64_t grad_start;
-  int32_t grad_len;     // chunk s tokens (0: none)
-  int64_t app_start;
-  int32_t app_len;      // chunk s-1 tokens (0: none)
+  float* partial;       // [n_active*H*G][2*D*h]
+  float* partial_deta;  // [n_active*H*G]
+  int32_t n_active;
+  int64_t grad_start[MAXS];
+  int32_t grad_len[MAXS];  // chunk s tokens (0: none)
+  int64_t app_start[MAXS];
+  int32_t app_len[MAXS];   // chunk s-1 tokens (0: none)
 };
 
+// Operand preparation for the active sequences of one backward step.
+struct BwdPrepArgs {
+  const float* w_src[MAXS];   // W_s of active sequence i, [H][2*D*h]
+  const float* wh_src[MAXS];  // carried adjoint, [H][2*D*h]; null = 0
+  void* prep;                 // [n_active][H][8][D*h] operand type
+  int32_t H, h;
+};
+
+// Per active sequence: wh_dst = wh_src (0 if null) + the sum of its G shard
+// partials in fixed order; deta[head] (+)= the sum of its dη partials.
 struct BwdReduceArgs {
-  const float* wh_src;  // previous adjoint (null = 0)
-  float* wh_dst;        // next adjoint [H][2*D*h] (unused when dst1 is set)
-  float* dst1;          // final split destinations dW1_0 [H][D][h], dW2_0 [H][h][D]; nullable
-  float* dst2;
+  const float* wh_src[MAXS];  // previous adjoint (null = 0)
+  float* wh_dst[MAXS];        // next adjoint [H][2*D*h] (unused when dst1 is set)
+  float* dst1[MAXS];          // split destinations dW1 [H][D][h], dW2 [H][h][D]; nullable
+  float* dst2[MAXS];
+  float* deta[MAXS];          // [H]
+  int32_t deta_first[MAXS];
   const float* partial;
   const float* partial_deta;
-  float* deta;          // [H]
-  int32_t deta_first;
-  int32_t G, H, h;
+  int32_t n_active, G, H, h;
+};
+
+// Shared initial weights over B sequences: dW1/dW2 = sum over b of the
+// per-sequence gradients src[b] ([H][2*D*h]), deta[head] = sum over b of
+// deta_src[b][head], in sequence order.
+struct BwdSumArgs {
+  const float* src;
+  const float* deta_src;
+  float* dW1;
+  float* dW2;
+  float* deta;
+  int32_t B, H, h;
 };
 
 }  // namespace ttt

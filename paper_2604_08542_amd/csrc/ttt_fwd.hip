@@ -807,7 +807,7 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
                               : *reinterpret_cast<const f32x4*>(p.w2_src + wc + (idx - dh));
     const f32x4 wn = wv - p.eta * s;
     *reinterpret_cast<f32x4*>(p.w_dst + (int64_t)chain * 2 * dh + idx) = wn;
-    if (p.ckpt) *reinterpret_cast<f32x4*>(p.ckpt + (int64_t)head * 2 * dh + idx) = wv;
+    if (p.ckpt) *reinterpret_cast<f32x4*>(p.ckpt + p.ckpt_off[ai] + (int64_t)head * 2 * dh + idx) = wv;
     if ((gcs || p.is_last[ai]) && p.wT1) {
       if (idx < dh)
         *reinterpret_cast<f32x4*>(p.wT1 + (int64_t)chain * dh + idx) = wn;

@@ -10,6 +10,6 @@ hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_bwd_step_bf(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, hipStream_t st);
 hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st);
-hipError_t launch_bwd_prep(const float* w_src, const float* wh_src, void* prep, int H, int h, bool mma_bf16,
-                           hipStream_t st);
+hipError_t launch_bwd_prep(const BwdPrepArgs& a, int n_active, bool mma_bf16, hipStream_t st);
+hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st);
 }  // namespace ttt

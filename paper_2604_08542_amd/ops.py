@@ -111,10 +111,31 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
 
 
+def _tile_cfg(tile_cfg, Q, h, chunk_tokens, n_chains):
+    if tile_cfg is None:
+        from .tune import lookup
+        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), n_chains)
+    if tile_cfg is None:
+        return None
+    return L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
+
+
+def batch_chunks(cu_seqlens: Sequence[int], chunk_tokens: int):
+    """Chunks per sequence and the first checkpoint row of each sequence."""
+    cu = [int(x) for x in cu_seqlens]
+    cb = [n_chunks(cu[b + 1] - cu[b], chunk_tokens) for b in range(len(cu) - 1)]
+    rows = [0]
+    for c in cb:
+        rows.append(rows[-1] + c)
+    return cb, rows
+
+
 def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *, norm=True, w0_per_seq=False,
-                mma_bf16=False, want_final=True, tile_cfg=None, out=None, ws=None):
+                mma_bf16=False, want_final=True, save_ckpt=False, tile_cfg=None, out=None, ws=None):
     """Many sequences packed along the token axis ([sum N_b][H][d]) with host
-    offsets cu_seqlens [B+1]; one independent chain per sequence and head."""
+    offsets cu_seqlens [B+1]; one independent chain per sequence and head.
+    With save_ckpt, also returns ckpt [sum_b C_b][H][2dh] (sequence b's rows
+    start at batch_chunks(cu_seqlens, chunk_tokens)[1][b])."""
     lib = L.load()
     _check_tokens(Q, K, V)
     N, H, d = Q.shape
@@ -123,25 +144,65 @@ def batched_fwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, *
     _, h = _check_w(W1, W2, H, (B,) if w0_per_seq else ())
     if cu[-1] != N:
         raise ValueError("cu_seqlens[-1] must equal the packed token count")
-    prob = problem(Q, h, 0, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
+    prob = problem(Q, h, 0, chunk_tokens, eta, _flags(norm, save_ckpt=save_ckpt, mma_bf16=mma_bf16))
     dev = Q.device
     O = _like_tokens(Q, out)
     W1_T = torch.empty((B, H, d, h), dtype=torch.float32, device=dev) if want_final else None
     W2_T = torch.empty((B, H, h, d), dtype=torch.float32, device=dev) if want_final else None
     cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
-    cfg = None
-    if tile_cfg is None:
-        from .tune import lookup
-        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), B * H)
-    if tile_cfg is not None:
-        cfg = L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
+    cfg = _tile_cfg(tile_cfg, Q, h, chunk_tokens, B * H)
     if ws is None:
         ws = workspace(prob, B, dev)
-    st = lib.ttt_batched_fwd(ctypes.byref(prob), B, cu_arr, _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2),
-                             1 if w0_per_seq else 0, _ptr(O), _ptr(W1_T), _ptr(W2_T),
-                             ctypes.byref(cfg) if cfg is not None else None, _ptr(ws), ws.numel(), _stream(dev))
-    L.check(st, "ttt_batched_fwd")
-    return dict(O=O, W1_T=W1_T, W2_T=W2_T)
+    args = [ctypes.byref(prob), B, cu_arr, _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), 1 if w0_per_seq else 0,
+            _ptr(O), _ptr(W1_T), _ptr(W2_T)]
+    tail = [ctypes.byref(cfg) if cfg is not None else None, _ptr(ws), ws.numel(), _stream(dev)]
+    ckpt = None
+    if save_ckpt:
+        rows = batch_chunks(cu, chunk_tokens)[1][-1]
+        ckpt = torch.empty((rows, H, 2 * d * h), dtype=torch.float32, device=dev)
+        st = lib.ttt_batched_fwd_ckpt(*args, _ptr(ckpt), *tail)
+        L.check(st, "ttt_batched_fwd_ckpt")
+    else:
+        st = lib.ttt_batched_fwd(*args, *tail)
+        L.check(st, "ttt_batched_fwd")
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt)
+
+
+def batched_bwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, ckpt, dO, *, norm=True,
+                w0_per_seq=False, mma_bf16=False, tile_cfg=None, ws=None):
+    """Backward of batched_fwd(save_ckpt=True) for sum <O, dO>.  dW1_0/dW2_0
+    are per sequence [B][H][..] with w0_per_seq, else the shared W0's
+    gradient [H][..]; deta [H] is summed over sequences."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    _check_tokens(Q, dO, dO)
+    N, H, d = Q.shape
+    cu = [int(x) for x in cu_seqlens]
+    B = len(cu) - 1
+    _, h = _check_w(W1, W2, H, (B,) if w0_per_seq else ())
+    if cu[-1] != N:
+        raise ValueError("cu_seqlens[-1] must equal the packed token count")
+    if dO.stride() != Q.stride():
+        raise ValueError("dO must share Q's strides")
+    prob = problem(Q, h, 0, chunk_tokens, eta, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    dQ, dK, dV = (_like_tokens(Q, None) for _ in range(3))
+    dW1 = torch.empty_like(W1)
+    dW2 = torch.empty_like(W2)
+    deta = torch.empty((H,), dtype=torch.float32, device=dev)
+    cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
+    # the tuned table holds forward launch shapes; the backward takes an
+    # explicit shape or the library's heuristic
+    cfg = None if tile_cfg is None else L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)),
+                                                  int(tile_cfg.get("target_wgs", 0)))
+    if ws is None:
+        ws = workspace(prob, B, dev)
+    st = lib.ttt_batched_bwd(ctypes.byref(prob), B, cu_arr, _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2),
+                             1 if w0_per_seq else 0, _ptr(ckpt), _ptr(dO), _ptr(dQ), _ptr(dK), _ptr(dV), _ptr(dW1),
+                             _ptr(dW2), _ptr(deta), ctypes.byref(cfg) if cfg is not None else None, _ptr(ws),
+                             ws.numel(), _stream(dev))
+    L.check(st, "ttt_batched_bwd")
+    return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1, dW2_0=dW2, deta=deta)
 
 
 def chunk_bwd(Q, K, V, W1, W2, eta, chunk_tokens, ckpt, dO, *, norm=True, mma_bf16=False, ws=None):

@@ -99,6 +99,40 @@ def test_batched_validation(lib):
     assert call(2, good, ws=None) == L.TTT_EWORKSPACE
 
 
+def test_batched_ckpt_and_bwd_validation(lib):
+    good = (ctypes.c_int64 * 3)(0, 10, 30)
+    bad = (ctypes.c_int64 * 3)(0, 10, 5)
+
+    def fwdc(p, cu, ckpt=FAKE, n=2):
+        return lib.ttt_batched_fwd_ckpt(ctypes.byref(p), n, cu, FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, None, None,
+                                        ckpt, None, FAKE, 1 << 40, None)
+    ck = prob(n_tokens=0, flags=7 | L.TTT_SAVE_CKPT)
+    assert fwdc(ck, bad) == L.TTT_EINVAL
+    assert fwdc(ck, good, ckpt=None) == L.TTT_EINVAL                  # flag without buffer
+    assert fwdc(prob(n_tokens=0), good) == L.TTT_EINVAL               # buffer without flag
+    assert fwdc(prob(n_tokens=0, flags=7 | L.TTT_SAVE_CKPT | L.TTT_EMIT_LOSS), good) == L.TTT_ENOTSUP
+    # plain batched forward rejects the checkpoint flag (no buffer to write)
+    assert lib.ttt_batched_fwd(ctypes.byref(ck), 2, good, FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, None, None,
+                               None, FAKE, 1 << 40, None) == L.TTT_EINVAL
+
+    def bwd(cu, n=2, w0=0, **kw):
+        a = dict(ckpt=FAKE, dO=FAKE, dW1=FAKE, deta=FAKE, ws=FAKE, nws=1 << 40, Q=FAKE)
+        a.update(kw)
+        p = prob(n_tokens=0)
+        return lib.ttt_batched_bwd(ctypes.byref(p), n, cu, a["Q"], FAKE, FAKE, FAKE, FAKE, w0, a["ckpt"], a["dO"],
+                                   FAKE, FAKE, FAKE, a["dW1"], FAKE, a["deta"], None, a["ws"], a["nws"], None)
+    assert bwd(bad) == L.TTT_EINVAL
+    assert bwd(good, n=0) == L.TTT_EINVAL
+    assert bwd(good, w0=3) == L.TTT_EINVAL
+    assert bwd(good, ckpt=None) == L.TTT_EINVAL
+    assert bwd(good, dO=None) == L.TTT_EINVAL
+    assert bwd(good, dW1=None) == L.TTT_EINVAL
+    assert bwd(good, deta=None) == L.TTT_EINVAL
+    assert bwd(good, Q=ctypes.c_void_p((1 << 20) + 8)) == L.TTT_EINVAL  # misaligned
+    assert bwd(good, ws=None) == L.TTT_EWORKSPACE
+    assert bwd(good, nws=64) == L.TTT_EWORKSPACE
+
+
 def test_status_strings(lib):
     for s in range(6):
         assert lib.ttt_status_string(s).startswith(b"TTT_")
