@@ -43,6 +43,30 @@ def alg_flops(w):
     return 14.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttt_fwd_step_layer16_64f_hbm_counters.md")
+
+
+def measured_traffic(io, workload):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration),
+    or None when that summary is for other kernel sources or another
+    workload."""
+    import hashlib
+    if workload != "layer16_64f_chunk8f" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in ("ttt_fwd.hip", "ttt_common.h"):
+        with open(os.path.join(ROOT, "paper_2604_08542_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    text = open(TRAFFIC_PROFILE).read()
+    if f"ttt_fwd.hip+ttt_common.h: {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"traffic_per_launch_bytes {io} = "):
+            return float(line.split("=")[1])
+    return None
+
+
 def run_variant(w, dev_inputs, io, steps, warmup, lib):
     import ctypes
 
@@ -84,7 +108,8 @@ def run_variant(w, dev_inputs, io, steps, warmup, lib):
         update_kernel=dict(launches_per_pass=n[1] / steps, avg_launch_us=ms[1] / max(n[1], 1) * 1e3,
                            ms_per_pass=ms[1] / steps),
         roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[io], unit="TFLOP/s",
-                      frac=achieved / PEAK[io], traffic=None),
+                      frac=achieved / PEAK[io], traffic=measured_traffic(io, w.name),
+                      traffic_unit="HBM bytes per step-kernel launch"),
         out=r,
     )
 
@@ -168,6 +193,22 @@ def extra_variants(steps, warmup, lib):
                                    kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
                                                               unit="TFLOP/s", frac=ach / PEAK["bf16"]))
     del dev, O
+    # batched forward (with checkpoints) + batched backward: 8 uneven sequences, BF16
+    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16", with_dO=True)
+
+    def bfb():
+        f = ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                            save_ckpt=True, want_final=False)
+        return ops.batched_bwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                               f["ckpt"], dev["dO"])
+    ms, per, _ = time_fn(bfb, max(2, steps // 4), 1, lib)
+    bms = per["bwd_step"]["ms_per_call"]
+    bach = 28.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (bms * 1e-3) / 1e12
+    res["batched_fwd_bwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                       kernels=per,
+                                       bwd_step_roofline=dict(bound="mfma", achieved=bach, peak=PEAK["bf16"],
+                                                              unit="TFLOP/s", frac=bach / PEAK["bf16"]))
+    del dev
     torch.cuda.empty_cache()
     return res
 
