@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--cpu-heads", type=int, default=16)
     ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
     ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
+    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd",
+                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -139,7 +141,7 @@ def time_fn(fn, steps, warmup, lib):
     return (t1 - t0) * 1e3 / steps, per, out
 
 
-def extra_variants(steps, warmup, lib):
+def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd")):
     """The other forms on their own workloads: GCS forward (same layer
     workload), forward+backward (differentiation workload), batched forward
     (8 uneven sequences)."""
@@ -150,7 +152,7 @@ def extra_variants(steps, warmup, lib):
     res = {}
     # GCS forward on the layer workload, BF16 and FP32 operands
     w = WORKLOADS["layer16_64f_chunk8f"]
-    for io in ("bf16", "f32"):
+    for io in (("bf16", "f32") if "gcs" in forms else ()):
         dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
         ms, per, _ = time_fn(lambda: ops.gcs_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta,
                                                  w.chunk_tokens), steps, warmup, lib)
@@ -162,7 +164,7 @@ def extra_variants(steps, warmup, lib):
         del dev
     # forward + backward on the differentiation workload
     w = WORKLOADS["layer16_32f_chunk4f_bwd"]
-    for io in ("bf16", "f32"):
+    for io in (("bf16", "f32") if "fwd_bwd" in forms else ()):
         dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io, with_dO=True)
 
         def fb():
@@ -182,17 +184,23 @@ def extra_variants(steps, warmup, lib):
         del dev
     # batched forward: 8 uneven sequences, BF16
     w = WORKLOADS["batch8_uneven_chunk8f_bf16"]
-    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16")
     cu = w.cu_seqlens()
-    O = torch.empty_like(dev["Q"])
-    ms, per, _ = time_fn(lambda: ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta,
-                                                 w.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
-    kms = per["fwd_step"]["ms_per_call"]
-    ach = alg_flops(w) / (kms * 1e-3) / 1e12
-    res["batched_fwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                   kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
-                                                              unit="TFLOP/s", frac=ach / PEAK["bf16"]))
-    del dev, O
+    if "batched_fwd" not in forms and "batched_fwd_bwd" not in forms:
+        return res
+    if "batched_fwd" in forms:
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16")
+        O = torch.empty_like(dev["Q"])
+        ms, per, _ = time_fn(lambda: ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta,
+                                                     w.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
+        kms = per["fwd_step"]["ms_per_call"]
+        ach = alg_flops(w) / (kms * 1e-3) / 1e12
+        res["batched_fwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                       kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                                                  unit="TFLOP/s", frac=ach / PEAK["bf16"]))
+        del dev, O
+    if "batched_fwd_bwd" not in forms:
+        torch.cuda.empty_cache()
+        return res
     # batched forward (with checkpoints) + batched backward: 8 uneven sequences, BF16
     dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16", with_dO=True)
 
@@ -261,7 +269,7 @@ def main():
               f"{variants[io]['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
     extra = {}
     if not a.no_extra:
-        extra = extra_variants(a.steps, a.warmup, lib)
+        extra = extra_variants(a.steps, a.warmup, lib, tuple(f for f in a.forms.split(",") if f))
         for k, v in extra.items():
             print(f"# {k}: {v['ms_per_step']:.3f} ms/step, {v['tokens_per_s']:.4g} tokens/s", file=sys.stderr,
                   flush=True)
