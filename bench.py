@@ -33,8 +33,8 @@ def parse():
     ap.add_argument("--cpu-heads", type=int, default=16)
     ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
     ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
-    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd",
-                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd)")
+    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu",
+                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd, amu)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -141,7 +141,7 @@ def time_fn(fn, steps, warmup, lib):
     return (t1 - t0) * 1e3 / steps, per, out
 
 
-def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd")):
+def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd", "amu")):
     """The other forms on their own workloads: GCS forward (same layer
     workload), forward+backward (differentiation workload), batched forward
     (8 uneven sequences)."""
@@ -162,6 +162,26 @@ def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "
                                     kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
                                                                unit="TFLOP/s", frac=ach / PEAK[io]))
         del dev
+    # the paper's memory unit (SwiGLU, dot-product loss, token-wise steps) on the layer workload
+    for io in (("bf16", "f32") if "amu" in forms else ()):
+        from workloads import make_eta_tok
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        W3 = torch.randn(dev["W1"].shape, generator=g, device="cuda") / float(w.d_head) ** 0.5
+        et = torch.from_numpy(make_eta_tok(w.n_tokens, w.n_heads, w.chunk_tokens, 20.0, 0)).cuda()
+        O = torch.empty_like(dev["Q"])
+        for sync in ("chain", "gcs"):
+            ms, per, _ = time_fn(lambda: ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3,
+                                                     w.chunk_tokens, sync=sync, want_final=False, out=O),
+                                 steps, warmup, lib)
+            kms = per["fwd_step"]["ms_per_call"]
+            # 12 d h per token-head for the update (K W1, K W3, E W2^T, three token sums) + 6 d h apply
+            ach = 18.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (kms * 1e-3) / 1e12
+            res[f"amu_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                           kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
+                                                                      unit="TFLOP/s", frac=ach / PEAK[io]))
+        del dev, O, W3, et
     # forward + backward on the differentiation workload
     w = WORKLOADS["layer16_32f_chunk4f_bwd"]
     for io in (("bf16", "f32") if "fwd_bwd" in forms else ()):

@@ -181,6 +181,28 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
                          void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes,
                          void* hip_stream);
 
+/* The paper's adaptive memory unit (Supp. A; Sec. 4.2 Eq. 8-10) over one
+ * sequence: per head a SwiGLU fast network
+ *     f_W(x) = (SiLU(x W1) * (x W3)) W2,   W1, W3: [d][h], W2: [h][d],
+ * the dot-product inner loss with token-wise step sizes,
+ *     L_c(W) = - sum_{i in chunk c} eta_i <f_W(k_i), v_i>,
+ * the step W <- W - grad_W L_c(W) (the step sizes are inside the loss, so
+ * p->eta is not used), and the apply O_c = f_W(Q_c) after the update.
+ *   sync      TTT_SYNC_CHAIN: chunks in sequence order, each updates then maps
+ *             its queries; TTT_SYNC_GCS: every chunk's gradient at W_0 is
+ *             summed, one update W*, every query mapped with W* (Eq. 10).
+ *   eta_tok   [N][H] f32 token-wise step sizes (predicted by the model in the
+ *             paper; an input here).
+ *   W3_0      [H][d][h] f32; W3_T likewise (W1_T, W2_T, W3_T all or none).
+ *   ws        ws_bytes >= ttt_amu_workspace_bytes(p).
+ * Q, K, V, O, normalisation flags, TTT_MMA_BF16 and strides as in
+ * ttt_chunk_fwd; TTT_SAVE_CKPT / TTT_EMIT_LOSS return TTT_ENOTSUP. */
+enum { TTT_SYNC_CHAIN = 0, TTT_SYNC_GCS = 1 };
+size_t ttt_amu_workspace_bytes(const ttt_problem_t* p);
+ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,
+                         const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,
+                         void* O, float* W1_T, float* W2_T, float* W3_T, void* ws, size_t ws_bytes,
+                         void* hip_stream);
 /* Benchmark instrumentation.  While enabled, every launch the library
  * enqueues is bracketed by a pair of HIP events on the launch stream (events
  * come from a pool the library owns; enabling clears earlier records).

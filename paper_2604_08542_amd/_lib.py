@@ -11,9 +11,11 @@ TTT_OK, TTT_EINVAL, TTT_ESHAPE, TTT_EWORKSPACE, TTT_EHIP, TTT_ENOTSUP = range(6)
 TTT_F32, TTT_BF16 = 0, 1
 TTT_NORM_Q, TTT_NORM_K, TTT_NORM_V = 1, 2, 4
 TTT_SAVE_CKPT, TTT_EMIT_LOSS, TTT_MMA_BF16 = 8, 16, 32
+TTT_SYNC_CHAIN, TTT_SYNC_GCS = 0, 1
 
 EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd", "ttt_batched_fwd_ckpt",
-            "ttt_batched_bwd", "ttt_gcs_fwd", "ttt_gcs_bwd", "ttt_profile_enable", "ttt_profile_read",
+            "ttt_batched_bwd", "ttt_gcs_fwd", "ttt_gcs_bwd", "ttt_amu_workspace_bytes", "ttt_amu_fwd",
+            "ttt_profile_enable", "ttt_profile_read",
             "ttt_status_string", "ttt_version")
 
 
@@ -79,6 +81,10 @@ def load(path: str = LIB_PATH):
     lib.ttt_gcs_fwd.restype = st
     lib.ttt_gcs_bwd.argtypes = [P, vp, vp, vp, fp, fp, vp, vp, vp, vp, fp, fp, fp, vp, sz, vp]
     lib.ttt_gcs_bwd.restype = st
+    lib.ttt_amu_workspace_bytes.argtypes = [P]
+    lib.ttt_amu_workspace_bytes.restype = sz
+    lib.ttt_amu_fwd.argtypes = [P, ctypes.c_int32, vp, vp, vp, fp, fp, fp, fp, vp, fp, fp, fp, vp, sz, vp]
+    lib.ttt_amu_fwd.restype = st
     lib.ttt_profile_enable.argtypes = [ctypes.c_int32]
     lib.ttt_profile_enable.restype = st
     lib.ttt_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]

@@ -530,6 +530,97 @@ ttt_status_t batched_fwd_impl(const ttt_problem_t* p, int32_t n_seqs, const int6
   return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt, nullptr,
                      tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
 }
+// ---------------------------------------------------------------- paper AMU
+struct AmuWs {
+  size_t partial, pp, prep, total;
+  int64_t slot_cap;
+};
+
+AmuWs amu_ws_layout(const Shape& s) {
+  AmuWs L{};
+  L.slot_cap = std::max<int64_t>(s.H, SLOT_CAP_MIN);
+  const size_t wbytes = (size_t)3 * s.dh() * sizeof(float);
+  size_t off = 0;
+  L.partial = off;
+  off = align_up(off + (size_t)L.slot_cap * wbytes);
+  L.pp = off;  // ping-pong packed weights per head
+  off = align_up(off + 2 * (size_t)s.H * wbytes);
+  L.prep = off;  // 4 operand matrices per head (float-sized slots)
+  off = align_up(off + (size_t)s.H * 4 * s.dh() * sizeof(float));
+  L.total = off;
+  return L;
+}
+
+// Chain: for s = 0..C one operand-preparation launch (W_s), one step launch
+// (gradient of chunk s, apply of chunk s-1) and, while chunk s exists, one
+// update launch.  GCS: the gradients of all chunks at W0 are one
+// shard-parallel gradient over every token (the dot-product loss has no
+// per-chunk normalisation, so the sum over chunks is the sum over tokens),
+// one update, then one apply over every token.
+ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const void* Q, const void* K, const void* V,
+                     const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0, void* O,
+                     float* W1_T, float* W2_T, float* W3_T, void* ws, size_t ws_bytes, hipStream_t st) {
+  const AmuWs L = amu_ws_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t H = S.H, N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  float* partial = at<float>(ws, L.partial);
+  float* pp[2] = {at<float>(ws, L.pp), at<float>(ws, L.pp) + H * 3 * dh};
+  void* prep = at<char>(ws, L.prep);
+  const int target = default_target_wgs(S);
+  auto grid_g = [&](int64_t len) {
+    const int64_t tiles = std::max<int64_t>((len + TT - 1) / TT, 1);
+    return std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, tiles, L.slot_cap / H}));
+  };
+  const AmuWeights w0{W1_0, W2_0, W3_0, dh};
+  auto packed = [&](const float* b) { return AmuWeights{b, b + dh, b + 2 * dh, 3 * dh}; };
+  auto do_prep = [&](const AmuWeights& w) {
+    AmuPrepArgs a{};
+    a.src = w; a.prep = prep; a.H = (int32_t)H; a.h = S.h;
+    return timed_launch(4, st, [&] { return launch_amu_prep(a, S.mma_bf16, st); });
+  };
+  auto do_step = [&](int64_t G, int64_t gs, int64_t gl, int64_t as, int64_t al) {
+    AmuStepArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = O; a.eta_tok = eta_tok;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep; a.partial = partial;
+    a.grad_start = gs; a.grad_len = (int32_t)gl; a.app_start = as; a.app_len = (int32_t)al;
+    return timed_launch(0, st, [&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); });
+  };
+  auto do_update = [&](const AmuWeights& src, int64_t G, float* dst, bool last) {
+    AmuUpdArgs u{};
+    u.src = src; u.partial = partial; u.G = (int32_t)G; u.H = (int32_t)H; u.h = S.h; u.w_dst = dst;
+    u.wT1 = last ? W1_T : nullptr; u.wT2 = last ? W2_T : nullptr; u.wT3 = last ? W3_T : nullptr;
+    return timed_launch(1, st, [&] { return launch_amu_update(u, st); });
+  };
+  if (C == 0) {  // no tokens: W_T = W_0
+    if (W1_T && !do_update(w0, 0, pp[0], true)) return TTT_EHIP;
+    return TTT_OK;
+  }
+  auto mlen = [&](int64_t c) { return std::min<int64_t>(M, N - c * M); };
+  if (sync == TTT_SYNC_CHAIN) {
+    AmuWeights cur = w0;
+    for (int64_t s = 0; s <= C; ++s) {
+      const int64_t gl = s < C ? mlen(s) : 0, al = s >= 1 ? mlen(s - 1) : 0;
+      const int64_t G = grid_g(std::max(gl, al));
+      if (!do_prep(cur)) return TTT_EHIP;
+      if (!do_step(G, s * M, gl, (s - 1) * M, al)) return TTT_EHIP;
+      if (s < C) {
+        if (!do_update(cur, G, pp[s % 2], s == C - 1)) return TTT_EHIP;
+        cur = packed(pp[s % 2]);
+      }
+    }
+    return TTT_OK;
+  }
+  const int64_t G = grid_g(N);
+  if (!do_prep(w0)) return TTT_EHIP;
+  if (!do_step(G, 0, N, 0, 0)) return TTT_EHIP;
+  if (!do_update(w0, G, pp[0], true)) return TTT_EHIP;
+  if (!do_prep(packed(pp[0]))) return TTT_EHIP;
+  if (!do_step(G, 0, 0, 0, N)) return TTT_EHIP;
+  return TTT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -670,6 +761,35 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
       if (q && !aligned16(q)) return TTT_EINVAL;
     return run_gcs_backward(p, S, Q, K, V, W1_0, W2_0, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
                             static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+size_t ttt_amu_workspace_bytes(const ttt_problem_t* p) {
+  Shape S{};
+  if (check_problem(p, &S) != TTT_OK) return 0;
+  return amu_ws_layout(S).total;
+}
+
+ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,
+                         const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0, void* O,
+                         float* W1_T, float* W2_T, float* W3_T, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
+    if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
+    if (!W1_0 || !W2_0 || !W3_0) return TTT_EINVAL;
+    if ((W1_T == nullptr) != (W2_T == nullptr) || (W1_T == nullptr) != (W3_T == nullptr)) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!Q || !K || !V || !eta_tok || !O)) return TTT_EINVAL;
+    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)W3_0, (const void*)O,
+                          (const void*)W1_T, (const void*)W2_T, (const void*)W3_T})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (p->n_tokens == 0 && !W1_T) return TTT_OK;
+    return run_amu(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, O, W1_T, W2_T, W3_T, ws, ws_bytes,
+                   static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;
   }

@@ -12,4 +12,7 @@ hipError_t launch_bwd_step_bf(const BwdStepArgs& a, int n_blocks, int h, bool io
 hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st);
 hipError_t launch_bwd_prep(const BwdPrepArgs& a, int n_active, bool mma_bf16, hipStream_t st);
 hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st);
+hipError_t launch_amu_step(const AmuStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
+hipError_t launch_amu_update(const AmuUpdArgs& a, hipStream_t st);
+hipError_t launch_amu_prep(const AmuPrepArgs& a, bool mma_bf16, hipStream_t st);
 }  // namespace ttt

@@ -309,3 +309,34 @@ def gcs_bwd(Q, K, V, W1, W2, eta, chunk_tokens, dO, *, norm=True, mma_bf16=False
                          _ptr(dK), _ptr(dV), _ptr(dW1), _ptr(dW2), _ptr(deta), _ptr(ws), ws.numel(), _stream(dev))
     L.check(st, "ttt_gcs_bwd")
     return dict(dQ=dQ, dK=dK, dV=dV, dW1_0=dW1, dW2_0=dW2, deta=deta)
+
+
+def amu_fwd(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, *, sync="chain", norm=True, mma_bf16=False,
+            want_final=True, out=None, ws=None):
+    """The paper's adaptive memory unit over one sequence: SwiGLU fast network
+    (W1, W3: [H][d][h], W2: [H][h][d]), dot-product inner loss with the
+    token-wise step sizes eta_tok [N][H] (float32), chain or GCS ("gcs")
+    synchronisation.  Returns O and, if want_final, W1_T, W2_T, W3_T."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    if W3.shape != W1.shape or W3.dtype != torch.float32 or not W3.is_contiguous():
+        raise ValueError("W3 must be a contiguous float32 tensor shaped like W1")
+    if eta_tok.shape != (N, H) or eta_tok.dtype != torch.float32 or not eta_tok.is_contiguous():
+        raise ValueError("eta_tok must be a contiguous float32 [N][H] tensor")
+    sync_id = {"chain": L.TTT_SYNC_CHAIN, "gcs": L.TTT_SYNC_GCS}[sync]
+    prob = problem(Q, h, N, chunk_tokens, 0.0, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    O = _like_tokens(Q, out)
+    fin = [torch.empty_like(W) if want_final else None for W in (W1, W2, W3)]
+    if ws is None:
+        nbytes = lib.ttt_amu_workspace_bytes(ctypes.byref(prob))
+        if nbytes == 0:
+            raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_amu_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = lib.ttt_amu_fwd(ctypes.byref(prob), sync_id, _ptr(Q), _ptr(K), _ptr(V), _ptr(eta_tok), _ptr(W1), _ptr(W2),
+                         _ptr(W3), _ptr(O), _ptr(fin[0]), _ptr(fin[1]), _ptr(fin[2]), _ptr(ws), ws.numel(),
+                         _stream(dev))
+    L.check(st, "ttt_amu_fwd")
+    return dict(O=O, W1_T=fin[0], W2_T=fin[1], W3_T=fin[2])

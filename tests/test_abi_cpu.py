@@ -133,6 +133,26 @@ def test_batched_ckpt_and_bwd_validation(lib):
     assert bwd(good, nws=64) == L.TTT_EWORKSPACE
 
 
+def test_amu_validation(lib):
+    def call(p, sync=0, **kw):
+        a = dict(Q=FAKE, eta=FAKE, W3=FAKE, W1T=None, W2T=None, W3T=None, ws=FAKE, nws=1 << 40)
+        a.update(kw)
+        return lib.ttt_amu_fwd(ctypes.byref(p), sync, a["Q"], FAKE, FAKE, a["eta"], FAKE, FAKE, a["W3"], FAKE,
+                               a["W1T"], a["W2T"], a["W3T"], a["ws"], a["nws"], None)
+    p = prob(n_tokens=1000, chunk_tokens=100)
+    assert lib.ttt_amu_workspace_bytes(ctypes.byref(p)) >= 1024 * 3 * 64 * 256 * 4
+    assert lib.ttt_amu_workspace_bytes(ctypes.byref(prob(d_hidden=96))) == 0
+    assert call(p, sync=2) == L.TTT_EINVAL
+    assert call(p, eta=None) == L.TTT_EINVAL
+    assert call(p, W3=None) == L.TTT_EINVAL
+    assert call(p, W1T=FAKE, W2T=FAKE) == L.TTT_EINVAL          # W3_T missing
+    assert call(prob(n_tokens=1000, flags=7 | L.TTT_SAVE_CKPT)) == L.TTT_ENOTSUP
+    assert call(prob(d_head=32)) == L.TTT_ESHAPE
+    assert call(p, Q=ctypes.c_void_p((1 << 20) + 4)) == L.TTT_EINVAL
+    assert call(p, ws=None) == L.TTT_EWORKSPACE
+    assert call(prob(n_tokens=0)) == L.TTT_OK                     # nothing to do, nothing enqueued
+
+
 def test_status_strings(lib):
     for s in range(6):
         assert lib.ttt_status_string(s).startswith(b"TTT_")

@@ -130,3 +130,12 @@ def make_inputs_torch(n_tokens: int, n_heads: int, d: int, h: int, seed: int = 0
     if with_dO:
         out["dO"] = torch.randn(shape, generator=g, device=device, dtype=torch.float32).to(tdt)
     return out
+
+
+def make_eta_tok(n_tokens: int, n_heads: int, chunk_tokens: int, eta: float, seed: int = 0):
+    """Token-wise step sizes for the paper's memory unit, [N][H] float32:
+    uniform in [0.5, 1.5] x eta / chunk_tokens (the unit's loss is a plain sum
+    over the chunk, so this keeps a chunk's step comparable to a mean-loss
+    step of size eta)."""
+    rng = np.random.default_rng(seed + 7919)
+    return (rng.uniform(0.5, 1.5, (n_tokens, n_heads)) * (eta / chunk_tokens)).astype(np.float32)
