@@ -285,10 +285,18 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
     if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
 
+  // With one launch group per step, each reduction also writes the operand
+  // copies of the next step (its adjoint output is the next step's input).
+  bool prep_ready = false;
   for (int64_t r = 0; r <= cmax; ++r) {
     std::vector<int> act;
     for (int b = 0; b < B; ++b)
       if (r <= cb[b]) act.push_back(b);
+    std::vector<int> next_slot(B, -1);
+    int n_next = 0;
+    for (int b = 0; b < B; ++b)
+      if (r + 1 <= cb[b]) next_slot[b] = n_next++;
+    const bool fuse = r < cmax && (int64_t)act.size() <= MAXS && n_next <= MAXS;
     for (size_t base = 0; base < act.size(); base += MAXS) {
       const int na = (int)std::min<size_t>(MAXS, act.size() - base);
       const int64_t n_chains = (int64_t)na * H;
@@ -304,6 +312,16 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
       BwdReduceArgs rd{};
       rd.partial = partial; rd.partial_deta = pdeta; rd.n_active = na; rd.G = (int32_t)G;
       rd.H = (int32_t)H; rd.h = S.h;
+      rd.wh_src_base = r == 0 ? nullptr : adj[(r + 1) % 2];
+      rd.wh_dst_base = adj[r % 2];
+      rd.fin_base = shared_w0 ? fin : nullptr;
+      rd.dst1 = dW1_0; rd.dst2 = dW2_0; rd.dst_per_seq = w0_per_seq ? 1 : 0;
+      rd.deta_base = deta_seq;
+      if (fuse) {
+        rd.prep_next = prep;
+        rd.prep_bf16 = S.mma_bf16 ? 1 : 0;
+        rd.ckpt = ckpt;
+      }
       for (int i = 0; i < na; ++i) {
         const int b = act[base + i];
         const int64_t s = cb[b] - r;
@@ -314,21 +332,18 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
         bs.grad_len[i] = s < cb[b] ? mlen(b, s) : 0;
         bs.app_start[i] = cu[b] + (s - 1) * M;
         bs.app_len[i] = s >= 1 ? mlen(b, s - 1) : 0;
-        rd.wh_src[i] = whs;
-        rd.wh_dst[i] = adj[r % 2] + b * H * wsz;
-        if (s == 0 && shared_w0) rd.wh_dst[i] = fin + b * H * wsz;
-        if (s == 0 && !shared_w0) {
-          rd.dst1[i] = dW1_0 + (w0_per_seq ? b * H * dh : 0);
-          rd.dst2[i] = dW2_0 + (w0_per_seq ? b * H * dh : 0);
-        }
-        rd.deta[i] = deta_seq + (B == 1 ? 0 : b * H);
-        rd.deta_first[i] = r == 0;
+        rd.seq[i] = B == 1 ? 0 : b;
+        rd.flags[i] = (s == 0 ? 1 : 0) | (r == 0 ? 2 : 0);
+        rd.next_slot[i] = fuse ? next_slot[b] : -1;
+        rd.ckpt_row[i] = ckoff[b] + s - 1;  // this sequence's W at step r + 1 (read only when next_slot >= 0)
       }
-      if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, na, S.mma_bf16, st); })) return TTT_EHIP;
+      if (!prep_ready && !timed_launch(4, st, [&] { return launch_bwd_prep(pa, na, S.mma_bf16, st); }))
+        return TTT_EHIP;
       if (!timed_launch(2, st, [&] { return launch_bwd_step(bs, (int)(n_chains * G), S.h, S.io_bf16, S.mma_bf16, st); }))
         return TTT_EHIP;
       if (!timed_launch(3, st, [&] { return launch_bwd_reduce(rd, (int)(n_chains * nbpc), st); })) return TTT_EHIP;
     }
+    prep_ready = fuse;
   }
   if (B > 1) {  // d(eta) over sequences, and the shared initial weights' gradient
     BwdSumArgs sm{};
@@ -424,11 +439,12 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   float* w0 = at<float>(ws, L.adj) + H * 2 * dh;         // W0 packed [W1 | W2] per head
   void* prep = at<char>(ws, L.prep);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
-  auto reduce_args = [&](const float* src, float* dst, float* d1, float* d2, int first, int64_t G) {
+  // single sequence: chain (0, head) of an adjoint buffer is at base + head * 2dh
+  auto reduce_args = [&](const float* src, float* dst, bool final, int first, int64_t G) {
     BwdReduceArgs r{};
-    r.wh_src[0] = src; r.wh_dst[0] = dst; r.dst1[0] = d1; r.dst2[0] = d2;
-    r.deta[0] = deta; r.deta_first[0] = first;
+    r.wh_src_base = src; r.wh_dst_base = dst; r.dst1 = dW1_0; r.dst2 = dW2_0; r.deta_base = deta;
     r.partial = partial; r.partial_deta = pdeta; r.n_active = 1; r.G = (int32_t)G; r.H = (int32_t)H; r.h = S.h;
+    r.seq[0] = 0; r.flags[0] = (final ? 1 : 0) | (first ? 2 : 0); r.next_slot[0] = -1;
     return r;
   };
   auto prep_args = [&](const float* w, const float* whs) {
@@ -446,7 +462,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
     return b;
   };
   if (C == 0) {  // no tokens: zero gradients
-    const BwdReduceArgs r = reduce_args(nullptr, nullptr, dW1_0, dW2_0, 1, 0);
+    const BwdReduceArgs r = reduce_args(nullptr, nullptr, true, 1, 0);
     return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
   }
   // W* (no outputs)
@@ -476,7 +492,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
     const BwdStepArgs b = step_args(G, 0, 0, 0, (int32_t)N);
     if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
-    const BwdReduceArgs r = reduce_args(nullptr, wh, nullptr, nullptr, 1, G);
+    const BwdReduceArgs r = reduce_args(nullptr, wh, false, 1, G);
     if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   // update adjoint of each chunk at W0 against Wh, accumulated on top of Wh
@@ -491,8 +507,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
     const BwdStepArgs b = step_args(G, c * M, len, 0, 0);
     if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
-    const BwdReduceArgs r = reduce_args(prev, acc[c % 2], c == C - 1 ? dW1_0 : nullptr, c == C - 1 ? dW2_0 : nullptr,
-                                        0, G);
+    const BwdReduceArgs r = reduce_args(prev, acc[c % 2], c == C - 1, 0, G);
     if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
     prev = acc[c % 2];
   }

@@ -483,6 +483,29 @@ hipError_t launch_bwd_prep(const BwdPrepArgs& a, int n_active, bool mma_bf16, hi
   return hipGetLastError();
 }
 
+// Four consecutive elements idx..idx+3 of one chain's [W1 | W2] (W) and of
+// its adjoint (Wh) into the 8 operand matrices of ttt_bwd_prep.
+template <typename MT>
+__device__ __forceinline__ void prep_scatter4(MT* o, int idx, int dh, int h, const f32x4& w, const f32x4& wh) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ie = idx + e;
+    if (ie < dh) {
+      const int d = ie / h, hh = ie % h;
+      o[0 * dh + hh * D + d] = (MT)w[e];
+      o[4 * dh + ie] = (MT)w[e];
+      o[2 * dh + hh * D + d] = (MT)wh[e];
+      o[6 * dh + ie] = (MT)wh[e];
+    } else {
+      const int i2 = ie - dh, hh2 = i2 / D, d2 = i2 % D;
+      o[1 * dh + i2] = (MT)w[e];
+      o[5 * dh + d2 * h + hh2] = (MT)w[e];
+      o[3 * dh + i2] = (MT)wh[e];
+      o[7 * dh + d2 * h + hh2] = (MT)wh[e];
+    }
+  }
+}
+
 // Per (active sequence, head): Wh_dst = Wh_src (0 if null) + the sum of the
 // G shard partials, in fixed order; deta[head] (+)= the sum of the dη
 // partials.  dst may be split into W1 / W2 destinations (the final dW1_0 /
@@ -494,26 +517,40 @@ __global__ __launch_bounds__(256) void ttt_bwd_reduce(BwdReduceArgs p) {
   const int lin = xcd_linear_block();
   const int chain = lin / nbpc, k = lin % nbpc;
   const int ai = chain / p.H, head = chain % p.H;
+  const int b = p.seq[ai];
+  const bool final = p.flags[ai] & 1, first = p.flags[ai] & 2;
+  const int64_t cw = ((int64_t)b * p.H + head) * 2 * dh;  // this chain in the adjoint buffers
   const int i4 = k * 256 + threadIdx.x;
   if (i4 < n4) {
     const int idx = 4 * i4;
     f32x4 s = {0.f, 0.f, 0.f, 0.f};
-    if (p.wh_src[ai]) s = *reinterpret_cast<const f32x4*>(p.wh_src[ai] + (int64_t)head * 2 * dh + idx);
+    if (p.wh_src_base) s = *reinterpret_cast<const f32x4*>(p.wh_src_base + cw + idx);
     const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)chain * p.G * 2 * dh) + i4;
     for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
-    if (p.dst1[ai]) {
+    if (final && !p.fin_base) {
+      const int64_t fo = ((int64_t)(p.dst_per_seq ? b : 0) * p.H + head) * dh;
       if (idx < dh)
-        *reinterpret_cast<f32x4*>(p.dst1[ai] + (int64_t)head * dh + idx) = s;
+        *reinterpret_cast<f32x4*>(p.dst1 + fo + idx) = s;
       else
-        *reinterpret_cast<f32x4*>(p.dst2[ai] + (int64_t)head * dh + (idx - dh)) = s;
+        *reinterpret_cast<f32x4*>(p.dst2 + fo + (idx - dh)) = s;
     } else {
-      *reinterpret_cast<f32x4*>(p.wh_dst[ai] + (int64_t)head * 2 * dh + idx) = s;
+      *reinterpret_cast<f32x4*>((final ? p.fin_base : p.wh_dst_base) + cw + idx) = s;
+    }
+    if (p.prep_next && p.next_slot[ai] >= 0) {
+      const int64_t pc = ((int64_t)p.next_slot[ai] * p.H + head) * 8 * dh;
+      const f32x4 wv =
+          *reinterpret_cast<const f32x4*>(p.ckpt + (p.ckpt_row[ai] * p.H + head) * 2 * dh + idx);
+      if (p.prep_bf16)
+        prep_scatter4(static_cast<bf16*>(p.prep_next) + pc, idx, dh, p.h, wv, s);
+      else
+        prep_scatter4(static_cast<float*>(p.prep_next) + pc, idx, dh, p.h, wv, s);
     }
   }
   if (k == 0 && threadIdx.x == 0) {
-    float sd = p.deta_first[ai] ? 0.f : p.deta[ai][head];
+    float* dt = p.deta_base + (int64_t)b * p.H + head;
+    float sd = first ? 0.f : *dt;
     for (int gg = 0; gg < p.G; ++gg) sd += p.partial_deta[(int64_t)chain * p.G + gg];
-    p.deta[ai][head] = sd;
+    *dt = sd;
   }
 }
 

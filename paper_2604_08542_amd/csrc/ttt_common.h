@@ -226,18 +226,31 @@ struct BwdPrepArgs {
   int32_t H, h;
 };
 
-// Per active sequence: wh_dst = wh_src (0 if null) + the sum of its G shard
-// partials in fixed order; deta[head] (+)= the sum of its dη partials.
+// Per active sequence i (sequence seq[i]): its adjoint output = its adjoint
+// input (0 if wh_src_base is null) + the sum of its G shard partials in fixed
+// order; deta (+)= the sum of its dη partials.  Chain (b, head) of the
+// adjoint buffers lives at base + (b*H + head) * 2*D*h.
 struct BwdReduceArgs {
-  const float* wh_src[MAXS];  // previous adjoint (null = 0)
-  float* wh_dst[MAXS];        // next adjoint [H][2*D*h] (unused when dst1 is set)
-  float* dst1[MAXS];          // split destinations dW1 [H][D][h], dW2 [H][h][D]; nullable
-  float* dst2[MAXS];
-  float* deta[MAXS];          // [H]
-  int32_t deta_first[MAXS];
+  const float* wh_src_base;  // null: zero adjoint
+  float* wh_dst_base;
+  float* fin_base;           // final adjoints of a shared W0 (nullable)
+  float* dst1;               // final gradients, split: dW1 + (per_seq ? b : 0)*H*D*h + head*D*h
+  float* dst2;
+  int32_t dst_per_seq;
+  float* deta_base;          // deta of sequence b at deta_base + b*H
   const float* partial;
   const float* partial_deta;
   int32_t n_active, G, H, h;
+  int32_t seq[MAXS];
+  int32_t flags[MAXS];       // bit 0: final step of this sequence; bit 1: first step (deta starts at 0)
+  // Fused operand preparation for the next reverse step (prep_next null =
+  // none): active sequence i becomes slot next_slot[i] (< 0: not active next
+  // step), whose W_s is checkpoint row ckpt_row[i]; layout as in ttt_bwd_prep.
+  void* prep_next;
+  int32_t prep_bf16;
+  const float* ckpt;
+  int32_t next_slot[MAXS];
+  int64_t ckpt_row[MAXS];
 };
 
 // Shared initial weights over B sequences: dW1/dW2 = sum over b of the
