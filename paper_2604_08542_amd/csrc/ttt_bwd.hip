@@ -41,6 +41,10 @@ __device__ __forceinline__ T* opaque(T* ptr) {
   return ptr;
 }
 
+#ifndef BWD_F32_NW256
+#define BWD_F32_NW256 8
+#endif
+
 template <typename IOT, bool BF, int NW, int NB>
 __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   constexpr int HH = NW * 32 * NB;  // hidden size: NW waves x NB 32-wide blocks each
@@ -90,6 +94,14 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   const float eta = p.eta;
   // prepared operand block of this head: 8 matrices of D*h elements
   const MT* prep0 = static_cast<const MT*>(p.prep) + (int64_t)slot * 8 * DH;
+  // Operand fragments by buffer loads: one descriptor for the 8 prepared
+  // matrices of this head, matrix offsets in scalar registers.
+  const __amdgpu_buffer_rsrc_t prsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<MT*>(prep0), (short)0, (int)(8 * DH * sizeof(MT)), 0x00020000);
+  auto bload = [&](int voff, int soff) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(prsrc, voff, soff, 0));
+  };
   const int64_t hoff = (int64_t)head * p.stride_head;
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
 
@@ -98,9 +110,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   // ttt_bwd_prep) are [hid][d] or [d][hid] matrices in the operand type.
   // 32x32 block C[tok][hid] (hidden block j of this wave) = X[tok][:] F with
   // F(d, hid) = M[hid][d].
-  auto th = [&](const float* X, const MT* M, int j) {
+  auto th = [&](const float* X, int k, int j) {
     f32x16 c = {};
-    const MT* mrow = M + (li.hid0 + 32 * j) * D;
+    const int voff = (int)(((li.hid0 + 32 * j) * D) * sizeof(MT));
     if constexpr (BF) {
 #pragma unroll 2
       for (int m = 0; m < 4; ++m) {
@@ -109,7 +121,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
         const f32x4 x1 = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0 + 4]);
         const bf16x8 a = as_bf16x8(pack_bf16x2(x0[0], x0[1]), pack_bf16x2(x0[2], x0[3]),
                                    pack_bf16x2(x1[0], x1[1]), pack_bf16x2(x1[2], x1[3]));
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(mrow + d0);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, bload(voff + d0 * (int)sizeof(MT), k * DH * (int)sizeof(MT)));
         c = mma32(a, b, c);
       }
     } else {
@@ -117,7 +129,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       for (int s4 = 0; s4 < 8; ++s4) {
         const int d0 = 32 * li.hf + 4 * s4;
         const f32x4 x = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
-        const f32x4 b = *reinterpret_cast<const f32x4*>(mrow + d0);
+        const f32x4 b = __builtin_bit_cast(f32x4, bload(voff + 128 * li.hf, k * DH * 4 + 16 * s4));
 #pragma unroll
         for (int e = 0; e < 4; ++e) c = mma32(x[e], b[e], c);
       }
@@ -127,16 +139,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   };
   // 16x16 block C[tok][d] (token block tb, feature block db) = S[tok][:] F,
   // S staged [tok][hidden] in LDS, F(hid, d) = M[d][hid].
-  auto td = [&](const MT* S, int tb, int db, const MT* M) {
+  auto td = [&](const MT* S, int tb, int db, int k) {
     f32x4 c = {};
     const int arow = 16 * tb + li.l16, dcol = 16 * db + li.l16;
-    const MT* mrow = M + dcol * HH;
+    const int voff = (int)((dcol * HH + (HH / 4) * li.g4) * sizeof(MT));
     if constexpr (BF) {
 #pragma unroll 2
       for (int u = 0; u < HH / 32; ++u) {
         const int k0 = (HH / 4) * li.g4 + 8 * u;
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + k0]);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(mrow + k0);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, bload(voff, k * DH * 2 + 16 * u));
         c = mma16(a, b, c);
       }
     } else {
@@ -144,7 +156,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       for (int u = 0; u < HH / 16; ++u) {
         const int k0 = (HH / 4) * li.g4 + 4 * u;
         const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + k0]);
-        const f32x4 b = *reinterpret_cast<const f32x4*>(mrow + k0);
+        const f32x4 b = __builtin_bit_cast(f32x4, bload(voff, k * DH * 4 + 16 * u));
 #pragma unroll
         for (int e = 0; e < 4; ++e) c = mma16(a[e], b[e], c);
       }
@@ -262,15 +274,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   for (int t = g; t < n_gt; t += G) {
     const int64_t t0 = grad_start + (int64_t)t * TT;
     const int nv = min(TT, gl - t * TT);
-    const MT* pr = opaque(prep0);
-    const MT* W1t = pr + 0 * DH;   // [hid][d] of W1
-    const MT* W2n = pr + 1 * DH;   // [hid][d] of W2
-    const MT* H1t = pr + 2 * DH;   // [hid][d] of Wh1
-    const MT* H2n = pr + 3 * DH;   // [hid][d] of Wh2
-    const MT* W1n = pr + 4 * DH;   // [d][hid] of W1
-    const MT* W2t = pr + 5 * DH;   // [d][hid] of W2
-    const MT* H1n = pr + 6 * DH;   // [d][hid] of Wh1
-    const MT* H2t = pr + 7 * DH;   // [d][hid] of Wh2
+    // prepared operand indices: [hid][d] of W1, W2, Wh1, Wh2, then [d][hid] of the same
+    constexpr int W1t = 0, W2n = 1, H1t = 2, H2n = 3, W1n = 4, W2t = 5, H1n = 6, H2t = 7;
     refresh();
     load_rows(p.K, t0, nv, xs, norm_k, 0);
     load_rows(p.V, t0, nv, vs, norm_v, 1);
@@ -384,10 +389,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   for (int t = g; t < n_at; t += G) {
     const int64_t t0 = app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
-    const MT* pr = opaque(prep0);
-    const MT* W1t = pr + 0 * DH;
-    const MT* W2n = pr + 1 * DH;
-    const MT* W1n = pr + 4 * DH;
+    constexpr int W1t = 0, W2n = 1, W1n = 4;
     refresh();
     load_rows(p.Q, t0, nv, xs, norm_q, 0);
     load_rows(p.dO, t0, nv, dys, false, -1);
@@ -584,23 +586,17 @@ hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One wave per 32-wide hidden block: 4 waves at h=128, 8 at h=256.
-template <typename IOT, bool BF, int NW, int NB>
+// FP32 operands: one wave per 32-wide hidden block (4 waves at h=128, 8 at
+// h=256); BF16 operands: ttt_bwd_step_bf.
+template <int NW, int NB>
 static hipError_t launch_bwd_step_t(const BwdStepArgs& a, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL((ttt_bwd_step<IOT, BF, NW, NB>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  hipLaunchKernelGGL((ttt_bwd_step<float, false, NW, NB>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st) {
-  if (mma_bf16) return launch_bwd_step_bf(a, n_blocks, h, io_bf16, st);
-  if (h == 128) {
-    if (io_bf16) return launch_bwd_step_t<bf16, true, 4, 1>(a, n_blocks, st);
-    return mma_bf16 ? launch_bwd_step_t<float, true, 4, 1>(a, n_blocks, st)
-                    : launch_bwd_step_t<float, false, 4, 1>(a, n_blocks, st);
-  }
-  if (io_bf16) return launch_bwd_step_t<bf16, true, 8, 1>(a, n_blocks, st);
-  return mma_bf16 ? launch_bwd_step_t<float, true, 8, 1>(a, n_blocks, st)
-                  : launch_bwd_step_t<float, false, 8, 1>(a, n_blocks, st);
+  if (mma_bf16 || io_bf16) return launch_bwd_step_bf(a, n_blocks, h, io_bf16, st);
+  return h == 128 ? launch_bwd_step_t<4, 1>(a, n_blocks, st) : launch_bwd_step_t<BWD_F32_NW256, 256 / (32 * BWD_F32_NW256)>(a, n_blocks, st);
 }
 
 hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st) {
