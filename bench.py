@@ -89,7 +89,7 @@ def run_variant(w, dev_inputs, io, steps, warmup, lib):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    lib.ttt_profile_enable(1)
+    lib.ttt_profile_enable(2)  # events around the chunk-step kernels only (the roofline kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -107,8 +107,6 @@ def run_variant(w, dev_inputs, io, steps, warmup, lib):
         io=io, ms_per_step=ms_step, tokens_per_s=w.n_tokens / (ms_step * 1e-3),
         step_kernel=dict(launches_per_pass=n[0] / steps, avg_launch_us=ms[0] / max(n[0], 1) * 1e3,
                          ms_per_pass=kern_ms_per_pass),
-        update_kernel=dict(launches_per_pass=n[1] / steps, avg_launch_us=ms[1] / max(n[1], 1) * 1e3,
-                           ms_per_pass=ms[1] / steps),
         roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[io], unit="TFLOP/s",
                       frac=achieved / PEAK[io], traffic=measured_traffic(io, w.name),
                       traffic_unit="HBM bytes per step-kernel launch"),

@@ -211,6 +211,9 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
  * chunk-step kernel, 3 = backward reduction kernel, 4 = backward operand
  * preparation kernel), the summed elapsed
  * milliseconds and the number of launches; arrays have n_kinds entries.
+ * `on`: 0 = off, 1 (or -1) = every kind, otherwise bit k+1 of `on` selects
+ * kind k (e.g. 2 = chunk-step kernels only, which keeps the event records out
+ * of the other launches).
  * Not meant for production calls: it adds event records to the stream. */
 ttt_status_t ttt_profile_enable(int32_t on);
 ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches);

@@ -95,12 +95,13 @@ int default_target_wgs(const Shape& s) { return s.h == 256 ? 256 : 512; }
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = 0;                 // kinds recorded while on
   std::vector<hipEvent_t> pool;      // 2 events per record
   std::vector<int> kinds;            // kind of record i
   size_t used = 0;
   int begin(int kind, hipStream_t st) {
     std::lock_guard<std::mutex> g(mu);
-    if (!on) return -1;
+    if (!on || !((mask >> kind) & 1u)) return -1;
     if (2 * used + 2 > pool.size()) {
       for (int i = 0; i < 2; ++i) {
         hipEvent_t e;
@@ -814,6 +815,7 @@ ttt_status_t ttt_profile_enable(int32_t on) {
   Profiler& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
   P.on = on != 0;
+  P.mask = on == 1 || on == -1 ? 0xffffffffu : (uint32_t)on >> 1;
   P.used = 0;
   return TTT_OK;
 }
