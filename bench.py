@@ -33,8 +33,9 @@ def parse():
     ap.add_argument("--cpu-heads", type=int, default=16)
     ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
     ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
-    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu",
-                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd, amu)")
+    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu,single_head",
+                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd, amu, "
+                         "single_head)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -139,7 +140,8 @@ def time_fn(fn, steps, warmup, lib):
     return (t1 - t0) * 1e3 / steps, per, out
 
 
-def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd", "amu")):
+def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd", "amu",
+                                             "single_head")):
     """The other forms on their own workloads: GCS forward (same layer
     workload), forward+backward (differentiation workload), batched forward
     (8 uneven sequences)."""
@@ -180,6 +182,51 @@ def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "
                                            kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
                                                                       unit="TFLOP/s", frac=ach / PEAK[io]))
         del dev, O, W3, et
+    # single-head chains: 4 chunks x 1374 tokens (FP32) and 256 chunks x 1374 tokens (BF16, precision form)
+    for name, io in ((("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16"))
+                     if "single_head" in forms else ()):
+        ws_ = WORKLOADS[name]
+        dev = make_inputs_torch(ws_.n_tokens, ws_.n_heads, ws_.d_head, ws_.d_hidden, seed=0, io_dtype=io)
+        O = torch.empty_like(dev["Q"])
+        ms, per, _ = time_fn(lambda: ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], ws_.eta,
+                                                   ws_.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
+        kms = per["fwd_step"]["ms_per_call"]
+        ach = alg_flops(ws_) / (kms * 1e-3) / 1e12
+        key = name if name.endswith(io) else f"{name}_{io}"
+        res[key] = dict(workload=name, ms_per_step=ms, tokens_per_s=ws_.n_tokens / (ms * 1e-3),
+                                   kernels=per, roofline=dict(bound="latency (one chain)", achieved=ach,
+                                                              peak=PEAK[io], unit="TFLOP/s", frac=ach / PEAK[io]))
+        # the same pass replayed from a captured HIP graph (no host launch cost per chunk step)
+        prob = ops.problem(dev["Q"], ws_.d_hidden, ws_.n_tokens, ws_.chunk_tokens, ws_.eta, ops._flags(True))
+        wsb = ops.workspace(prob, 1, dev["Q"].device)
+
+        def one():
+            ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], ws_.eta, ws_.chunk_tokens, out=O,
+                          want_final=False, ws=wsb)
+        one()
+        torch.cuda.synchronize()
+        ref = O.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            one()
+        torch.cuda.synchronize()
+        O.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(O, ref))
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t0) * 1e3 / steps
+        res[key].update(graph_ms_per_step=gms, graph_tokens_per_s=ws_.n_tokens / (gms * 1e-3),
+                                   graph_replay_matches_eager=same)
+        del dev, O, graph, wsb
     # forward + backward on the differentiation workload
     w = WORKLOADS["layer16_32f_chunk4f_bwd"]
     for io in (("bf16", "f32") if "fwd_bwd" in forms else ()):
