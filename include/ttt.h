@@ -72,7 +72,7 @@ typedef struct {
   int32_t d_hidden;     /* h, 128 or 256 */
   int64_t n_tokens;     /* N for single-sequence calls (ignored by ttt_batched_fwd) */
   int64_t chunk_tokens; /* tokens per update chunk, >= 1 */
-  int64_t stride_tok;   /* elements between consecutive tokens; 0 = H*d */
+  int64_t stride_tok;   /* elements between consecutive tokens; 0 = H*d; at most 2^22 */
   int64_t stride_head;  /* elements between consecutive heads; 0 = d */
   float eta;            /* inner step size (one scalar for all heads and chunks) */
   uint32_t flags;       /* TTT_* bits */

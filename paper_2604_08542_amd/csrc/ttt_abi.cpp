@@ -19,6 +19,7 @@ using namespace ttt;
 
 constexpr uint32_t KNOWN_FLAGS = TTT_NORM_Q | TTT_NORM_K | TTT_NORM_V | TTT_SAVE_CKPT | TTT_EMIT_LOSS | TTT_MMA_BF16;
 constexpr int64_t SLOT_CAP_MIN = 1024;  // shard-partial slots available per chunk step
+constexpr int64_t MAX_STRIDE_TOK = int64_t(1) << 22;  // elements; token tiles are addressed with 32-bit offsets
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -43,6 +44,7 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   const int64_t st = p->stride_tok ? p->stride_tok : (int64_t)p->n_heads * p->d_head;
   const int64_t sh = p->stride_head ? p->stride_head : p->d_head;
   if (st <= 0 || sh <= 0 || (st % 8) || (sh % 8)) return TTT_ESHAPE;
+  if (st > MAX_STRIDE_TOK) return TTT_ESHAPE;  // a 32-token tile spans < 2^31 bytes
   s->H = p->n_heads;
   s->d = p->d_head;
   s->h = p->d_hidden;

@@ -101,6 +101,26 @@ __device__ __forceinline__ void store_vec(IOT* p, const float (&x)[N]) {
   }
 }
 
+// Sum over each aligned group of N consecutive lanes (N = 1, 2, 4, 8, 16),
+// returned in every lane of the group.  DPP lane moves folded into the adds:
+// lane^1 and lane^2 within a quad, then the mirror within 8 and within 16
+// lanes (after the quad sums, the mirrored lane holds the other quad's / the
+// other half's sum).  Both lanes of every pair add the same two values, so
+// all lanes of a group get the bitwise-same result.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int N>
+__device__ __forceinline__ float lane_group_sum(float x) {
+  static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "groups of 1 to 16 lanes");
+  if constexpr (N >= 2) x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+  if constexpr (N >= 4) x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+  if constexpr (N >= 8) x += dpp_move<0x141>(x);  // row_half_mirror
+  if constexpr (N >= 16) x += dpp_move<0x140>(x); // row_mirror
+  return x;
+}
+
 // One token row of D elements is spread over TPR = D/EPT consecutive lanes,
 // EPT elements each.  Loads the row (zeros for masked rows) and, when asked,
 // divides by max(||row||_2, eps); `inv` returns that divisor's reciprocal
@@ -120,8 +140,7 @@ __device__ __forceinline__ void load_row_norm(const IOT* rowp, bool valid, bool 
     float ss = 0.f;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    ss = lane_group_sum<TPR>(ss);
     inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) x[i] *= inv;

@@ -407,16 +407,25 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 // BF16-operand chunk step, software-pipelined over token tiles.  Iteration
 // i holds, between two barriers each,
 //   phase A: Y_i = A_i W2 -> residual -> E_i (staged), O_i = Aq_i W2 (stored),
-//            Z_{i+1} = K_{i+1} W1 -> SiLU -> A_{i+1} (staged), Zq_{i+1} = Q_{i+1} W1
+//            Z_{i+1} = K_{i+1} W1 -> SiLU, s'(Z) (kept in registers)
 //   phase B: P_i = E_i W2^T, D_i = P_i s'(Z_i), grad W1 += K_i^T D_i,
-//            grad W2 += A_i^T E_i, SiLU(Zq_{i+1}) -> Aq_{i+1} (staged),
-//            rows of tile i+2 normalised into LDS, rows of tile i+3 prefetched
-// so that every phase mixes matrix-core products with the transcendental-heavy
-// activations of the neighbouring tile.  -log2(e) is folded into the W1
-// operand (the exponent comes straight out of the product) and -ln(2) into
-// the W2 operand of Y and O; the A-side gradient is rescaled once at the end.
-// Per-tile register state (packed A, s'(Z) in f16, packed Zq) is held for two
-// tiles, so the loop is unrolled by two to keep register indices static.
+//            grad W2 += A_i^T E_i; A_{i+1} staged from registers;
+//            Zq_{i+1}^T = W1^T Q_{i+1}^T -> SiLU -> Aq_{i+1} (staged);
+//            rows of tile i+2 normalised into LDS, rows of tile i+3 fetched
+// which balances matrix-core products against the transcendental-heavy
+// activations in both phases, and lets A, Aq, E and E^T live in one LDS
+// buffer each (each is written in one phase and read in the next).
+// -log2(e) is folded into the W1 operand (the exponent comes straight out of
+// the product) and -ln(2) into the W2 operand of Y and O; the A-side gradient
+// is rescaled once at the end.
+//
+// Token rows are fetched and O is stored through buffer resources that cover
+// exactly the valid rows of the tile, so rows past a chunk's end read as zero
+// and their stores are dropped by the hardware range check: the loop body is
+// free of branches, and zero rows add nothing to the gradient or the loss
+// (K = V = 0 gives Z = 0, A = 0, Y = 0, R = 0).  A block whose shard has both
+// gradient and apply tiles runs the fused body; shards with only one kind run
+// a body without the other's work.
 template <typename IOT, int NW>
 __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   constexpr int HH = NW * 32;
@@ -433,17 +442,18 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   constexpr int DH = D * HH;
   constexpr float LOG2E = 1.4426950408889634f;
   constexpr float LN2 = 0.6931471805599453f;
-  typedef _Float16 h16;
   typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-  __shared__ __attribute__((aligned(16))) bf16 xs[3][TT * XS_LD];    // K rows
+  __shared__ __attribute__((aligned(16))) bf16 xs[2][TT * XS_LD];    // K rows
   __shared__ __attribute__((aligned(16))) bf16 xts[3][D * XT_LD];    // K^T
   __shared__ __attribute__((aligned(16))) float vs[2][TT * VS_LD];   // V rows (f32)
   __shared__ __attribute__((aligned(16))) bf16 qs[2][TT * XS_LD];    // Q rows
-  __shared__ __attribute__((aligned(16))) bf16 as_[2][TT * AS_LD];   // A' = -log2(e) SiLU(K W1)
-  __shared__ __attribute__((aligned(16))) bf16 aqs[2][TT * AS_LD];   // -log2(e) SiLU(Q W1)
-  __shared__ __attribute__((aligned(16))) bf16 es[2][TT * XS_LD];    // E
-  __shared__ __attribute__((aligned(16))) bf16 ets[2][D * XT_LD];    // E^T
+  __shared__ __attribute__((aligned(16))) bf16 as_[TT * AS_LD];      // A' = -log2(e) SiLU(K W1)
+  __shared__ __attribute__((aligned(16))) bf16 aqs[TT * AS_LD];      // -log2(e) SiLU(Q W1)
+  __shared__ __attribute__((aligned(16))) bf16 es[TT * XS_LD];       // E
+  __shared__ __attribute__((aligned(16))) bf16 ets[D * XT_LD];       // E^T
   __shared__ float red[NW];
 
   const int tid = threadIdx.x;
@@ -459,10 +469,10 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
 
   // Register-resident operands, packed once; the empty asm pins each packed
   // word so that the compiler keeps it instead of re-deriving it from the
-  // source floats inside the token loop.
+  // source floats inside the token loop.  w1b serves as the B operand of
+  // Z = K W1 and, unchanged, as the A operand of Zq^T = W1^T Q^T.
   bf16x8 w1b[4], w2b[4], w2y[8 / NW][HH / 32];
   auto pin8 = [](bf16x8& v) {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     u32x4 u = __builtin_bit_cast(u32x4, v);
     asm volatile("" : "+v"(u));
     v = __builtin_bit_cast(bf16x8, u);
@@ -507,77 +517,67 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   const int iters = max(my_g, my_a);
   const float e_scale = gl > 0 ? 2.0f / (float)gl : 0.f;
 
-  // prefetched raw rows kept in the io type (4 or 8 elements per thread);
-  // running row pointers advance by one tile stride per fetch.
-  typedef IOT iovec __attribute__((ext_vector_type(EPT)));
-  iovec rk, rv, rq;
-  const int64_t tile_step = (int64_t)G * TT * p.stride_tok;
-  const int64_t row0 = (int64_t)(g * TT + row) * p.stride_tok + hoff + col0;
-  const IOT* kp = static_cast<const IOT*>(p.K) + gs * p.stride_tok + row0;
-  const IOT* vp = static_cast<const IOT*>(p.V) + gs * p.stride_tok + row0;
-  const IOT* qp = static_cast<const IOT*>(p.Q) + as0 * p.stride_tok + row0;
-  int tr_next = g * TT + row;  // token index (in the chunk) of the next fetch
-  int it_next = 0;
-  auto fetch = [&]() {
-    const bool kv = it_next < my_g && tr_next < gl, qv = it_next < my_a && tr_next < al;
-    const iovec zero = {};
-    rk = zero;
-    rv = zero;
-    rq = zero;
-    if (kv) {
-      rk = *reinterpret_cast<const iovec*>(kp);
-      rv = *reinterpret_cast<const iovec*>(vp);
-    }
-    if (qv) rq = *reinterpret_cast<const iovec*>(qp);
-    kp += tile_step;
-    vp += tile_step;
-    qp += tile_step;
-    tr_next += G * TT;
-    ++it_next;
+  // Buffer resource over the valid rows of tile `it` of this shard (token
+  // rows t0 .. t0+rows-1 of a region of `len` rows starting at `base`);
+  // stride_tok * TT * 4 bytes fits 31 bits (checked by the host).
+  const int tok_bytes = (int)p.stride_tok * (int)sizeof(IOT);
+  auto tile_rsrc = [&](const void* base, int len, int it) {
+    const int t0 = (g + it * G) * TT;
+    const int rows = min(max(len - t0, 0), TT);
+    const int bytes = max(rows * tok_bytes - tok_bytes + D * (int)sizeof(IOT), 0);  // 0 rows: 0 bytes
+    IOT* b = const_cast<IOT*>(static_cast<const IOT*>(base)) + (int64_t)t0 * p.stride_tok;
+    return __builtin_amdgcn_make_buffer_rsrc(b, (short)0, bytes, 0x00020000);
   };
-  // 1 / max(||x||, eps) = rsq(max(||x||^2, eps^2))
+  const IOT* const Kb = static_cast<const IOT*>(p.K) + gs * p.stride_tok + hoff;
+  const IOT* const Vb = static_cast<const IOT*>(p.V) + gs * p.stride_tok + hoff;
+  const IOT* const Qb = static_cast<const IOT*>(p.Q) + as0 * p.stride_tok + hoff;
+  IOT* const Ob = static_cast<IOT*>(p.O) + as0 * p.stride_tok + hoff;
+  const int row_voff = row * tok_bytes + col0 * (int)sizeof(IOT);
+
+  // prefetched raw rows kept in the io type (EPT elements per thread)
+  typedef IOT iovec __attribute__((ext_vector_type(EPT)));
+  iovec rk = {}, rv = {}, rq = {};
+  auto load_rows = [&](__amdgpu_buffer_rsrc_t r) -> iovec {
+    constexpr int BYTES = EPT * (int)sizeof(IOT);
+    if constexpr (BYTES == 8) {
+      return __builtin_bit_cast(iovec, __builtin_amdgcn_raw_buffer_load_b64(r, row_voff, 0, 0));
+    } else if constexpr (BYTES == 16) {
+      return __builtin_bit_cast(iovec, __builtin_amdgcn_raw_buffer_load_b128(r, row_voff, 0, 0));
+    } else {
+      static_assert(BYTES == 32, "4 or 8 elements of 2 or 4 bytes");
+      typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+      const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, row_voff, 0, 0);
+      const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, row_voff + 16, 0, 0);
+      return __builtin_bit_cast(iovec, (u32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+    }
+  };
+
+  // 1 / max(||x||, eps) = rsq(max(||x||^2, eps^2)); computed whether or not
+  // the rows are normalised (a select instead of a branch in the loop body)
   auto normalise = [&](float (&x)[EPT], bool do_norm) {
-    if (!do_norm) return;
     float ss = 0.f;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
-    const float inv = __builtin_amdgcn_rsqf(fmaxf(ss, NORM_EPS * NORM_EPS));
+    ss = lane_group_sum<TPR>(ss);
+    const float inv = do_norm ? __builtin_amdgcn_rsqf(fmaxf(ss, NORM_EPS * NORM_EPS)) : 1.0f;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) x[i] *= inv;
   };
-  // normalise the fetched rows of tile `it` into LDS buffers
-  auto stage_rows = [&](int it) {
-    const int b3 = it % 3, b2 = it & 1;
-    float fk[EPT], fv[EPT], fq[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      fk[i] = (float)rk[i];
-      fv[i] = (float)rv[i];
-      fq[i] = (float)rq[i];
-    }
-    normalise(fk, norm_k);
-    normalise(fv, norm_v);
-    normalise(fq, norm_q);
-    uint16_t* xt16 = reinterpret_cast<uint16_t*>(xts[b3]);
-#pragma unroll
-    for (int i = 0; i < EPT; i += 2) {
-      const uint32_t kp = pack_bf16x2(fk[i], fk[i + 1]);
-      *reinterpret_cast<uint32_t*>(&xs[b3][row * XS_LD + col0 + i]) = kp;
-      *reinterpret_cast<uint32_t*>(&qs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fq[i], fq[i + 1]);
-      xt16[(col0 + i) * XT_LD + row] = (uint16_t)kp;
-      xt16[(col0 + i + 1) * XT_LD + row] = (uint16_t)(kp >> 16);
-      vs[b2][row * VS_LD + col0 + i] = fv[i];
-      vs[b2][row * VS_LD + col0 + i + 1] = fv[i + 1];
-    }
-  };
-  auto z_block = [&](const bf16* X) {
+  auto z_block = [&](const bf16* X) {  // Z' = X W1' (token rows, hidden columns)
     f32x16 z = {};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
       z = mma32(a, w1b[m], z);
+    }
+    return z;
+  };
+  auto zt_block = [&](const bf16* X) {  // Z'^T = W1'^T X^T (hidden rows, token columns)
+    f32x16 z = {};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
+      z = mma32(w1b[m], b, z);
     }
     return z;
   };
@@ -591,147 +591,213 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     }
     return y;
   };
-  // z' = -log2(e) z:  sigma = 1/(1+2^z'),  A' = z' sigma = -log2(e) SiLU(z),
-  // s'(z) = sigma + A (1 - sigma) = sigma + A' ln2 (sigma - 1).  Results are
-  // packed in pairs: A' as bf16 (token-contraction operand and the staged
-  // copy), s'(z) as f16.
-  auto act_grad = [&](const f32x16& z, uint32_t (&apk)[8], h16x2 (&s1h)[8], bf16* S) {
-    uint16_t* S16 = reinterpret_cast<uint16_t*>(S);
-#pragma unroll
-    for (int r = 0; r < 16; r += 2) {
-      const float z0 = z[r], z1 = z[r + 1];
-      const float g0 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z0));
-      const float g1 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z1));
-      const float a0 = z0 * g0, a1 = z1 * g1;
-      const float s0 = fmaf(a0, fmaf(g0, LN2, -LN2), g0);
-      const float s1 = fmaf(a1, fmaf(g1, LN2, -LN2), g1);
-      const uint32_t pa = pack_bf16x2(a0, a1);
-      apk[r >> 1] = pa;
-      s1h[r >> 1] = __builtin_convertvector((f32x2){s0, s1}, h16x2);
-      S16[c32_row(r, hf) * AS_LD + hid] = (uint16_t)pa;
-      S16[c32_row(r + 1, hf) * AS_LD + hid] = (uint16_t)(pa >> 16);
-    }
-  };
-  auto act_apply = [&](const f32x16& z, bf16* S) {
-    uint16_t* S16 = reinterpret_cast<uint16_t*>(S);
-#pragma unroll
-    for (int r = 0; r < 16; r += 2) {
-      const float z0 = z[r], z1 = z[r + 1];
-      const float g0 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z0));
-      const float g1 = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z1));
-      const uint32_t pa = pack_bf16x2(z0 * g0, z1 * g1);
-      S16[c32_row(r, hf) * AS_LD + hid] = (uint16_t)pa;
-      S16[c32_row(r + 1, hf) * AS_LD + hid] = (uint16_t)(pa >> 16);
-    }
-  };
 
   f32x16 gw1[2] = {}, gw2[2] = {};
   float lacc = 0.f;
   uint32_t apk[2][8];     // per tile parity: A' packed in bf16 pairs (token-contraction operand)
   h16x2 s1h[2][8];        // per tile parity: s'(Z) in f16 pairs
 
-  // phase A of iteration `it` (tile parity P = it & 1)
-  auto phase_a = [&](int it, auto PC) {
-    constexpr int P = decltype(PC)::value;
-    if (it < my_g) {
+  auto run = [&](auto MC) {
+    constexpr int MODE = decltype(MC)::value;
+    constexpr bool DO_G = (MODE & 1) != 0, DO_A = (MODE & 2) != 0;
+
+    auto fetch = [&](int it) {
+      if constexpr (DO_G) {
+        rk = load_rows(tile_rsrc(Kb, gl, it));
+        rv = load_rows(tile_rsrc(Vb, gl, it));
+      }
+      if constexpr (DO_A) rq = load_rows(tile_rsrc(Qb, al, it));
+    };
+    // normalise the fetched rows of tile `it` into LDS
+    auto stage_rows = [&](int it) {
+      const int b3 = it % 3, b2 = it & 1;
+      if constexpr (DO_G) {
+        float fk[EPT], fv[EPT];
 #pragma unroll
-      for (int bi = 0; bi < 8 / NW; ++bi) {
-        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-        const f32x4 y = y_block(as_[P], tb, bi);
-        const int dcol = 16 * db + l16;
-        float ev[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tok = 16 * tb + 4 * g4 + r;
-          const float R = y[r] - vs[P][tok * VS_LD + dcol];
-          lacc = fmaf(R, R, lacc);
-          ev[r] = e_scale * R;
+        for (int i = 0; i < EPT; ++i) {
+          fk[i] = (float)rk[i];
+          fv[i] = (float)rv[i];
         }
-        const uint32_t e01 = pack_bf16x2(ev[0], ev[1]), e23 = pack_bf16x2(ev[2], ev[3]);
-        const int tok0 = 16 * tb + 4 * g4;
-        *reinterpret_cast<uint64_t*>(&ets[P][dcol * XT_LD + tok0]) = ((uint64_t)e23 << 32) | e01;
-        uint16_t* es16 = reinterpret_cast<uint16_t*>(es[P]);
-        es16[(tok0 + 0) * XS_LD + dcol] = (uint16_t)e01;
-        es16[(tok0 + 1) * XS_LD + dcol] = (uint16_t)(e01 >> 16);
-        es16[(tok0 + 2) * XS_LD + dcol] = (uint16_t)e23;
-        es16[(tok0 + 3) * XS_LD + dcol] = (uint16_t)(e23 >> 16);
-      }
-    }
-    if (it < my_a) {
-      IOT* O = static_cast<IOT*>(p.O) + (as0 + (int64_t)(g + it * G) * TT) * p.stride_tok + hoff;
-      const int t_base = (g + it * G) * TT;
+        normalise(fk, norm_k);
+        normalise(fv, norm_v);
+        uint16_t* xt16 = reinterpret_cast<uint16_t*>(xts[b3]);
 #pragma unroll
-      for (int bi = 0; bi < 8 / NW; ++bi) {
-        const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-        const f32x4 y = y_block(aqs[P], tb, bi);
-        const int dcol = 16 * db + l16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int tok = 16 * tb + 4 * g4 + r;
-          if (t_base + tok < al) O[(int64_t)tok * p.stride_tok + dcol] = from_f<IOT>(y[r]);
+        for (int i = 0; i < EPT; i += 2) {
+          const uint32_t kp = pack_bf16x2(fk[i], fk[i + 1]);
+          *reinterpret_cast<uint32_t*>(&xs[b2][row * XS_LD + col0 + i]) = kp;
+          xt16[(col0 + i) * XT_LD + row] = (uint16_t)kp;
+          xt16[(col0 + i + 1) * XT_LD + row] = (uint16_t)(kp >> 16);
         }
-      }
-    }
-    if (it + 1 < iters) {
-      const int nb3 = (it + 1) % 3;
-      if (it + 1 < my_g) act_grad(z_block(xs[nb3]), apk[P ^ 1], s1h[P ^ 1], as_[P ^ 1]);
-      if (it + 1 < my_a) act_apply(z_block(qs[P ^ 1]), aqs[P ^ 1]);
-    }
-  };
-  // phase B of iteration `it`
-  auto phase_b = [&](int it, auto PC) {
-    constexpr int P = decltype(PC)::value;
-    if (it < my_g) {
-      const int b3 = it % 3;
-      f32x16 pz = {};
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[P][l32 * XS_LD + 16 * m + 8 * hf]);
-        pz = mma32(a, w2b[m], pz);
+        for (int i = 0; i < EPT; i += 4)
+          *reinterpret_cast<f32x4*>(&vs[b2][row * VS_LD + col0 + i]) = (f32x4){fv[i], fv[i + 1], fv[i + 2], fv[i + 3]};
       }
-      uint32_t dw[8];
+      if constexpr (DO_A) {
+        float fq[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) fq[i] = (float)rq[i];
+        normalise(fq, norm_q);
+#pragma unroll
+        for (int i = 0; i < EPT; i += 2)
+          *reinterpret_cast<uint32_t*>(&qs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fq[i], fq[i + 1]);
+      }
+    };
+    // z' = -log2(e) z:  sigma = 1/(1+2^z'),  A' = z' sigma = -log2(e) SiLU(z),
+    // s'(z) = sigma + A (1 - sigma) = sigma + A' ln2 (sigma - 1).  Results
+    // are packed in pairs: A' as bf16 (token-contraction operand, staged to
+    // LDS one phase later), s'(z) as f16.
+    auto act_grad = [&](const f32x16& z, uint32_t (&ap)[8], h16x2 (&sh)[8]) {
 #pragma unroll
       for (int r = 0; r < 16; r += 2) {
-        const h16x2 sv = s1h[P][r >> 1];
-        dw[r >> 1] = pack_bf16x2(fmaf(pz[r], (float)sv[0], 0.0f), fmaf(pz[r + 1], (float)sv[1], 0.0f));
+        const float z0 = z[r], z1 = z[r + 1];
+        const float s0g = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z0));
+        const float s1g = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z1));
+        const float a0 = z0 * s0g, a1 = z1 * s1g;
+        ap[r >> 1] = pack_bf16x2(a0, a1);
+        sh[r >> 1] = __builtin_convertvector((f32x2){fmaf(a0, fmaf(s0g, LN2, -LN2), s0g),
+                                                      fmaf(a1, fmaf(s1g, LN2, -LN2), s1g)}, h16x2);
       }
-      const bf16x8 dpk[2] = {as_bf16x8(dw[0], dw[1], dw[2], dw[3]), as_bf16x8(dw[4], dw[5], dw[6], dw[7])};
-      const bf16x8 apv[2] = {as_bf16x8(apk[P][0], apk[P][1], apk[P][2], apk[P][3]),
-                             as_bf16x8(apk[P][4], apk[P][5], apk[P][6], apk[P][7])};
+    };
+    // A' of one tile from its packed register copy into the [token][hidden] tile
+    auto put_a = [&](const uint32_t (&ap)[8]) {
+      uint16_t* S16 = reinterpret_cast<uint16_t*>(as_);
 #pragma unroll
-      for (int db = 0; db < 2; ++db) {
-        const int dd = 32 * db + l32;
+      for (int r = 0; r < 16; r += 2) {
+        S16[c32_row(r, hf) * AS_LD + hid] = (uint16_t)ap[r >> 1];
+        S16[c32_row(r + 1, hf) * AS_LD + hid] = (uint16_t)(ap[r >> 1] >> 16);
+      }
+    };
+    // Aq' from Zq'^T: lane (token l32) holds 4 runs of 4 consecutive hidden
+    // units, each written as one 8-byte word of the [token][hidden] tile.
+    auto act_apply_t = [&](const f32x16& zt) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 4 * hf]);
-          const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 8 + 4 * hf]);
-          const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
-          gw1[db] = mma32(ka, dpk[m], gw1[db]);
-          const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 4 * hf]);
-          const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[P][dd * XT_LD + 16 * m + 8 + 4 * hf]);
-          const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
-          gw2[db] = mma32(apv[m], eb, gw2[db]);
+      for (int j = 0; j < 4; ++j) {
+        float a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float z = zt[4 * j + q];
+          a[q] = z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z));
+        }
+        *reinterpret_cast<u32x2*>(&aqs[l32 * AS_LD + 32 * w + 8 * j + 4 * hf]) =
+            (u32x2){pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3])};
+      }
+    };
+
+    // phase A of iteration `it` (tile parity P = it & 1)
+    auto phase_a = [&](int it, auto PC) {
+      constexpr int P = decltype(PC)::value;
+      // the next tile's product first: its activation (the long VALU part)
+      // then overlaps the Y and O products
+      f32x16 zn;
+      if constexpr (DO_G) zn = z_block(xs[P ^ 1]);
+      if constexpr (DO_G) {
+#pragma unroll
+        for (int bi = 0; bi < 8 / NW; ++bi) {
+          const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+          const f32x4 y = y_block(as_, tb, bi);
+          const int dcol = 16 * db + l16;
+          float ev[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int tok = 16 * tb + 4 * g4 + r;
+            const float R = y[r] - vs[P][tok * VS_LD + dcol];
+            lacc = fmaf(R, R, lacc);
+            ev[r] = e_scale * R;
+          }
+          const uint32_t e01 = pack_bf16x2(ev[0], ev[1]), e23 = pack_bf16x2(ev[2], ev[3]);
+          const int tok0 = 16 * tb + 4 * g4;
+          *reinterpret_cast<u32x2*>(&ets[dcol * XT_LD + tok0]) = (u32x2){e01, e23};
+          uint16_t* es16 = reinterpret_cast<uint16_t*>(es);
+          es16[(tok0 + 0) * XS_LD + dcol] = (uint16_t)e01;
+          es16[(tok0 + 1) * XS_LD + dcol] = (uint16_t)(e01 >> 16);
+          es16[(tok0 + 2) * XS_LD + dcol] = (uint16_t)e23;
+          es16[(tok0 + 3) * XS_LD + dcol] = (uint16_t)(e23 >> 16);
         }
       }
-    }
-    if (it + 2 < iters) {
+      if constexpr (DO_A) {
+        const auto ro = tile_rsrc(Ob, al, it);
+#pragma unroll
+        for (int bi = 0; bi < 8 / NW; ++bi) {
+          const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+          const f32x4 y = y_block(aqs, tb, bi);
+          const int voff = (16 * tb + 4 * g4) * tok_bytes + (16 * db + l16) * (int)sizeof(IOT);
+          // whole-vector bit cast: this compiler turns a bit cast of one
+          // vector element (y[r]) into a read of element 0
+          const u32x4 yu = __builtin_bit_cast(u32x4, y);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (std::is_same_v<IOT, float>)
+              __builtin_amdgcn_raw_buffer_store_b32(yu[r], ro, voff, r * tok_bytes, 0);
+            else
+              __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (bf16)y[r]), ro, voff, r * tok_bytes, 0);
+          }
+        }
+      }
+      if constexpr (DO_G) act_grad(zn, apk[P ^ 1], s1h[P ^ 1]);
+    };
+    // phase B of iteration `it`
+    auto phase_b = [&](int it, auto PC) {
+      constexpr int P = decltype(PC)::value;
+      f32x16 zq;
+      if constexpr (DO_A) zq = zt_block(qs[P ^ 1]);
+      if constexpr (DO_G) {
+        const int b3 = it % 3;
+        f32x16 pz = {};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
+          pz = mma32(a, w2b[m], pz);
+        }
+        const bf16x8 apv[2] = {as_bf16x8(apk[P][0], apk[P][1], apk[P][2], apk[P][3]),
+                               as_bf16x8(apk[P][4], apk[P][5], apk[P][6], apk[P][7])};
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const int dd = 32 * db + l32;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
+            const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
+            const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
+            gw2[db] = mma32(apv[m], eb, gw2[db]);
+          }
+        }
+        uint32_t dw[8];
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const h16x2 sv = s1h[P][r >> 1];
+          dw[r >> 1] = pack_bf16x2(fmaf(pz[r], (float)sv[0], 0.0f), fmaf(pz[r + 1], (float)sv[1], 0.0f));
+        }
+        const bf16x8 dpk[2] = {as_bf16x8(dw[0], dw[1], dw[2], dw[3]), as_bf16x8(dw[4], dw[5], dw[6], dw[7])};
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const int dd = 32 * db + l32;
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 4 * hf]);
+            const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 8 + 4 * hf]);
+            const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
+            gw1[db] = mma32(ka, dpk[m], gw1[db]);
+          }
+        }
+        put_a(apk[P ^ 1]);
+      }
+      if constexpr (DO_A) act_apply_t(zq);
       stage_rows(it + 2);
-      if (it + 3 < iters) fetch();
-    }
-  };
+      fetch(it + 3);
+    };
 
-  if (iters > 0) {
     // prologue: rows of tiles 0 and 1 staged, activations of tile 0 staged
-    fetch();
+    fetch(0);
     stage_rows(0);
-    if (iters > 1) fetch();
+    fetch(1);
     __syncthreads();
-    if (my_g > 0) act_grad(z_block(xs[0]), apk[0], s1h[0], as_[0]);
-    if (my_a > 0) act_apply(z_block(qs[0]), aqs[0]);
-    if (iters > 1) {
-      stage_rows(1);
-      if (iters > 2) fetch();
+    if constexpr (DO_G) {
+      act_grad(z_block(xs[0]), apk[0], s1h[0]);
+      put_a(apk[0]);
     }
+    if constexpr (DO_A) act_apply_t(zt_block(qs[0]));
+    stage_rows(1);
+    fetch(2);
     __syncthreads();
     for (int it = 0; it < iters; it += 2) {
       phase_a(it, std::integral_constant<int, 0>{});
@@ -745,7 +811,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         __syncthreads();
       }
     }
-  }
+  };
+  if (my_g > 0 && my_a > 0)
+    run(std::integral_constant<int, 3>{});
+  else if (my_g > 0)
+    run(std::integral_constant<int, 1>{});
+  else if (my_a > 0)
+    run(std::integral_constant<int, 2>{});
 
   if (gl > 0) {
     float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
