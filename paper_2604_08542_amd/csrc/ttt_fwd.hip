@@ -413,8 +413,11 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 //            Zq_{i+1}^T = W1^T Q_{i+1}^T -> SiLU -> Aq_{i+1} (staged);
 //            rows of tile i+2 normalised into LDS, rows of tile i+3 fetched
 // which balances matrix-core products against the transcendental-heavy
-// activations in both phases, and lets A, Aq, E and E^T live in one LDS
-// buffer each (each is written in one phase and read in the next).
+// activations in both phases, and lets A, Aq and E live in one LDS buffer
+// each (each is written in one phase and read in the next).  Every tile is
+// staged row-major only: the token-contraction operands K^T and E^T and the
+// residual's V columns are read with the transposing LDS load
+// (ds_read_b64_tr_b16), so no tile is ever written transposed.
 // -log2(e) is folded into the W1 operand (the exponent comes straight out of
 // the product) and -ln(2) into the W2 operand of Y and O; the A-side gradient
 // is rescaled once at the end.
@@ -433,11 +436,6 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   constexpr int EPT = D * TT / NT;
   constexpr int TPR = D / EPT;
   constexpr int XS_LD = D + 8;
-  // 36: transposed [d][token] tiles are written by 16 lanes at stride 4 rows
-  // and read as 8-byte runs by 32 lanes; an 18-dword row pitch makes both
-  // patterns bank-conflict free and keeps 8-byte alignment.
-  constexpr int XT_LD = TT + 4;
-  constexpr int VS_LD = D + 4;
   constexpr int AS_LD = HH + 8;
   constexpr int DH = D * HH;
   constexpr float LOG2E = 1.4426950408889634f;
@@ -446,14 +444,12 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-  __shared__ __attribute__((aligned(16))) bf16 xs[2][TT * XS_LD];    // K rows
-  __shared__ __attribute__((aligned(16))) bf16 xts[3][D * XT_LD];    // K^T
-  __shared__ __attribute__((aligned(16))) float vs[2][TT * VS_LD];   // V rows (f32)
+  __shared__ __attribute__((aligned(16))) bf16 xs[3][TT * XS_LD];    // K rows
+  __shared__ __attribute__((aligned(16))) bf16 vs[2][TT * XS_LD];    // V rows
   __shared__ __attribute__((aligned(16))) bf16 qs[2][TT * XS_LD];    // Q rows
   __shared__ __attribute__((aligned(16))) bf16 as_[TT * AS_LD];      // A' = -log2(e) SiLU(K W1)
   __shared__ __attribute__((aligned(16))) bf16 aqs[TT * AS_LD];      // -log2(e) SiLU(Q W1)
   __shared__ __attribute__((aligned(16))) bf16 es[TT * XS_LD];       // E
-  __shared__ __attribute__((aligned(16))) bf16 ets[D * XT_LD];       // E^T
   __shared__ float red[NW];
 
   const int tid = threadIdx.x;
@@ -592,6 +588,28 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     return y;
   };
 
+  // Transposing read of a row-major bf16 tile T (pitch XS_LD): in each
+  // group of 16 lanes, lane j receives T[t0 + q][c0 + j] for q = 0..3.  The
+  // instruction hands lane j element j%4 of the 8-byte runs addressed by
+  // lanes j/4 + 4q of its group, so lane i points at row t0 + i/4, columns
+  // c0 + 4(i%4) .. +3.
+  // `off` = this lane's element offset; the per-lane part is computed once
+  // below, the rest are immediates of the load.
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+  auto tr4 = [&](const bf16* T, int off) -> bf16x4 {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(T + off)));
+  };
+  const int tr_lane = (l16 >> 2) * XS_LD + 4 * (l16 & 3);
+  // token-contraction operand of a row-major [token][d] tile: lane (d = 32 db
+  // + l32, hf) holds tokens 16m + 4hf + 0..3 and 16m + 8 + 4hf + 0..3, the
+  // token slots of result registers 8m .. 8m+7 of a 32x32 block
+  const int tok_lane = tr_lane + 4 * hf * XS_LD + 16 * ((l >> 4) & 1);
+  auto tok_frag = [&](const bf16* T, int m, int db) -> bf16x8 {
+    const bf16x4 lo = tr4(T, tok_lane + 16 * m * XS_LD + 32 * db);
+    const bf16x4 hi = tr4(T, tok_lane + (16 * m + 8) * XS_LD + 32 * db);
+    return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  };
+
   f32x16 gw1[2] = {}, gw2[2] = {};
   float lacc = 0.f;
   uint32_t apk[2][8];     // per tile parity: A' packed in bf16 pairs (token-contraction operand)
@@ -620,17 +638,11 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         }
         normalise(fk, norm_k);
         normalise(fv, norm_v);
-        uint16_t* xt16 = reinterpret_cast<uint16_t*>(xts[b3]);
 #pragma unroll
         for (int i = 0; i < EPT; i += 2) {
-          const uint32_t kp = pack_bf16x2(fk[i], fk[i + 1]);
-          *reinterpret_cast<uint32_t*>(&xs[b2][row * XS_LD + col0 + i]) = kp;
-          xt16[(col0 + i) * XT_LD + row] = (uint16_t)kp;
-          xt16[(col0 + i + 1) * XT_LD + row] = (uint16_t)(kp >> 16);
+          *reinterpret_cast<uint32_t*>(&xs[b3][row * XS_LD + col0 + i]) = pack_bf16x2(fk[i], fk[i + 1]);
+          *reinterpret_cast<uint32_t*>(&vs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fv[i], fv[i + 1]);
         }
-#pragma unroll
-        for (int i = 0; i < EPT; i += 4)
-          *reinterpret_cast<f32x4*>(&vs[b2][row * VS_LD + col0 + i]) = (f32x4){fv[i], fv[i + 1], fv[i + 2], fv[i + 3]};
       }
       if constexpr (DO_A) {
         float fq[EPT];
@@ -689,24 +701,23 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
       // the next tile's product first: its activation (the long VALU part)
       // then overlaps the Y and O products
       f32x16 zn;
-      if constexpr (DO_G) zn = z_block(xs[P ^ 1]);
+      if constexpr (DO_G) zn = z_block(xs[(it + 1) % 3]);
       if constexpr (DO_G) {
 #pragma unroll
         for (int bi = 0; bi < 8 / NW; ++bi) {
           const int b = w + NW * bi, tb = b & 1, db = b >> 1;
           const f32x4 y = y_block(as_, tb, bi);
           const int dcol = 16 * db + l16;
+          const int tok0 = 16 * tb + 4 * g4;
+          const bf16x4 vv = tr4(vs[P], tr_lane + tok0 * XS_LD + 16 * db);  // V[tok0 + r][dcol]
           float ev[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int tok = 16 * tb + 4 * g4 + r;
-            const float R = y[r] - vs[P][tok * VS_LD + dcol];
+            const float R = y[r] - (float)vv[r];
             lacc = fmaf(R, R, lacc);
             ev[r] = e_scale * R;
           }
           const uint32_t e01 = pack_bf16x2(ev[0], ev[1]), e23 = pack_bf16x2(ev[2], ev[3]);
-          const int tok0 = 16 * tb + 4 * g4;
-          *reinterpret_cast<u32x2*>(&ets[dcol * XT_LD + tok0]) = (u32x2){e01, e23};
           uint16_t* es16 = reinterpret_cast<uint16_t*>(es);
           es16[(tok0 + 0) * XS_LD + dcol] = (uint16_t)e01;
           es16[(tok0 + 1) * XS_LD + dcol] = (uint16_t)(e01 >> 16);
@@ -751,16 +762,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         const bf16x8 apv[2] = {as_bf16x8(apk[P][0], apk[P][1], apk[P][2], apk[P][3]),
                                as_bf16x8(apk[P][4], apk[P][5], apk[P][6], apk[P][7])};
 #pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const int dd = 32 * db + l32;
+        for (int db = 0; db < 2; ++db)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
-            const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
-            const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
-            gw2[db] = mma32(apv[m], eb, gw2[db]);
-          }
-        }
+          for (int m = 0; m < 2; ++m) gw2[db] = mma32(apv[m], tok_frag(es, m, db), gw2[db]);
         uint32_t dw[8];
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
@@ -769,16 +773,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         }
         const bf16x8 dpk[2] = {as_bf16x8(dw[0], dw[1], dw[2], dw[3]), as_bf16x8(dw[4], dw[5], dw[6], dw[7])};
 #pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const int dd = 32 * db + l32;
+        for (int db = 0; db < 2; ++db)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 4 * hf]);
-            const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[b3][dd * XT_LD + 16 * m + 8 + 4 * hf]);
-            const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
-            gw1[db] = mma32(ka, dpk[m], gw1[db]);
-          }
-        }
+          for (int m = 0; m < 2; ++m) gw1[db] = mma32(tok_frag(xs[b3], m, db), dpk[m], gw1[db]);
         put_a(apk[P ^ 1]);
       }
       if constexpr (DO_A) act_apply_t(zq);
