@@ -164,8 +164,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
       float ss = 0.f;
 #pragma unroll
       for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-      for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+      ss = lane_group_sum<TPR>(ss);
       scale = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
     }
     if (times_eta) scale *= valid ? -p.eta_tok[(t0 + row) * p.H + head] : 0.f;

@@ -227,8 +227,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       float ss = 0.f;
 #pragma unroll
       for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-      for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+      ss = lane_group_sum<TPR>(ss);
       const float nrm = sqrtf(ss);
       const float inv = 1.0f / fmaxf(nrm, NORM_EPS);
 #pragma unroll
@@ -253,8 +252,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
       dot = fmaf(v[i], xh[i], dot);
     }
     if (did_norm) {
-#pragma unroll
-      for (int m = 1; m < TPR; m <<= 1) dot += __shfl_xor(dot, m, 64);
+      dot = lane_group_sum<TPR>(dot);
       const float inv = ninv[ns][li.row];
       const bool above = nabove[ns][li.row];
 #pragma unroll

@@ -231,8 +231,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
       float ss = 0.f;
 #pragma unroll
       for (int i = 0; i < 8; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-      for (int m = 1; m < 8; m <<= 1) ss += __shfl_xor(ss, m, 64);
+      ss = lane_group_sum<8>(ss);
       const float nrm = sqrtf(ss);
       const float inv = 1.0f / fmaxf(nrm, NORM_EPS);
 #pragma unroll
@@ -278,8 +277,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_step_bf(BwdStepArgs p) {
       }
     }
     if (did_norm) {
-#pragma unroll
-      for (int m = 1; m < 8; m <<= 1) dot += __shfl_xor(dot, m, 64);
+      dot = lane_group_sum<8>(dot);
       const float inv = ninv[ns * TT + row];
       const bool ab = above[ns * TT + row];
 #pragma unroll

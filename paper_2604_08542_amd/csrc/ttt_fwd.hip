@@ -137,8 +137,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     float ss = 0.f;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
-#pragma unroll
-    for (int m = 1; m < TPR; m <<= 1) ss += __shfl_xor(ss, m, 64);
+    ss = lane_group_sum<TPR>(ss);
     const float inv = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) x[i] *= inv;
