@@ -27,35 +27,27 @@
 
 namespace ttt {
 
-template <typename IOT, bool BF, int NW>
+// FP32-operand chunk step.  FP32 tiles need twice the LDS of BF16 ones, so
+// the gradient tiles and the apply tiles run in two loops over single-
+// buffered LDS tiles (4 barriers per tile); the next tile's rows are
+// prefetched into registers while the current tile computes.
+template <typename IOT, int NW>
 __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   constexpr int HH = NW * 32;  // hidden size
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;  // row elements per thread when loading
   constexpr int TPR = D / EPT;
-  using MT = std::conditional_t<BF, bf16, float>;
-  // BF16 operands: the gradient tile and the apply tile of one iteration are
-  // processed together, token rows are prefetched one iteration ahead and
-  // double-buffered in LDS (3 barriers per iteration).  FP32 operands need
-  // twice the LDS per staged tile, so gradient and apply tiles run in two
-  // loops with single-buffered LDS (4 barriers per tile), still prefetched.
-  constexpr int NB = BF ? 2 : 1;
-  constexpr int XS_LD = D + (BF ? 8 : 4);
-  constexpr int XT_LD = TT + 8;
+  constexpr int XS_LD = D + 4;
   constexpr int VS_LD = D + 4;
-  constexpr int AS_LD = HH + (BF ? 8 : 4);
-  constexpr int W2T_LD = HH + (BF ? 8 : 4);
+  constexpr int AS_LD = HH + 4;
+  constexpr int W2T_LD = HH + 4;
   constexpr int DH = D * HH;
 
-  __shared__ __attribute__((aligned(16))) MT xs[NB][TT * XS_LD];     // K rows (normalised)
-  __shared__ __attribute__((aligned(16))) bf16 xts[NB][BF ? D * XT_LD : 8];  // K^T (bf16 only)
-  __shared__ __attribute__((aligned(16))) float vs[NB][TT * VS_LD];  // V rows (normalised, f32)
-  __shared__ __attribute__((aligned(16))) MT qs[BF ? NB : 1][BF ? TT * XS_LD : 8];  // Q rows (bf16 path)
-  __shared__ __attribute__((aligned(16))) MT as_[TT * AS_LD];        // A = SiLU(K W1)
-  __shared__ __attribute__((aligned(16))) MT aqs[BF ? TT * AS_LD : 8];  // SiLU(Q W1) (bf16 path)
-  __shared__ __attribute__((aligned(16))) MT es[TT * XS_LD];         // E
-  __shared__ __attribute__((aligned(16))) bf16 ets[BF ? D * XT_LD : 8];  // E^T (bf16 only)
-  __shared__ __attribute__((aligned(16))) MT w2t[BF ? 8 : D * W2T_LD];  // W2^T (FP32 path)
+  __shared__ __attribute__((aligned(16))) float xs[TT * XS_LD];   // K (or Q) rows, normalised
+  __shared__ __attribute__((aligned(16))) float vs[TT * VS_LD];   // V rows, normalised
+  __shared__ __attribute__((aligned(16))) float as_[TT * AS_LD];  // A = SiLU(K W1) (or of Q)
+  __shared__ __attribute__((aligned(16))) float es[TT * XS_LD];   // E
+  __shared__ __attribute__((aligned(16))) float w2t[D * W2T_LD];  // W2^T
   __shared__ float red[NW];
 
   const int tid = threadIdx.x;
@@ -71,43 +63,17 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
   const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
 
-  // B operand of Y = A W2 over the full hidden axis: FP32 path from LDS
-  // (W2^T), BF16 path from registers (each wave keeps the W2 columns of the
-  // 16-wide feature blocks it produces).
-  if constexpr (!BF) {
-    for (int idx = tid; idx < DH; idx += NT) {
-      const int hh = idx / D, dd = idx % D;
-      w2t[dd * W2T_LD + hh] = (MT)W2[idx];
-    }
-  }
-  bf16x8 w2y[BF ? 8 / NW : 1][BF ? HH / 32 : 1];
-  if constexpr (BF) {
-#pragma unroll
-    for (int bi = 0; bi < 8 / NW; ++bi) {
-      const int dcol = 16 * ((w + NW * bi) >> 1) + l16;
-#pragma unroll
-      for (int u = 0; u < HH / 32; ++u)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) w2y[bi][u][e] = (bf16)W2[((HH / 4) * g4 + 8 * u + e) * D + dcol];
-    }
+  // B operand of Y = A W2 over the full hidden axis, from LDS (W2^T).
+  for (int idx = tid; idx < DH; idx += NT) {
+    const int hh = idx / D, dd = idx % D;
+    w2t[dd * W2T_LD + hh] = W2[idx];
   }
   // Register-resident operand slices of this wave's hidden block.
-  bf16x8 w1b[4], w2b[4];
-  float w1f[BF ? 1 : 32], w2f[BF ? 1 : 32];
-  if constexpr (BF) {
+  float w1f[32], w2f[32];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        w1b[m][e] = (bf16)W1[(16 * m + 8 * hf + e) * HH + hid];
-        w2b[m][e] = (bf16)W2[hid * D + 16 * m + 8 * hf + e];
-      }
-  } else {
-#pragma unroll
-    for (int s = 0; s < 32; ++s) {
-      w1f[s] = W1[(32 * hf + s) * HH + hid];
-      w2f[s] = W2[hid * D + 32 * hf + s];
-    }
+  for (int s = 0; s < 32; ++s) {
+    w1f[s] = W1[(32 * hf + s) * HH + hid];
+    w2f[s] = W2[hid * D + 32 * hf + s];
   }
 
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
@@ -122,7 +88,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 
   // ---- phase helpers
   // raw row fetch (registers) for tile `it` of this work-group; zeros when
-  // the row is past the chunk end or the tile does not exist.
+  // the row is past the chunk end.
   auto fetch_row = [&](const void* base, int64_t start, int len, int it, float (&x)[EPT]) {
     const int tr = (g + it * G) * TT + row;  // token index within the chunk
     if (tr < len) {
@@ -143,48 +109,31 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     for (int i = 0; i < EPT; ++i) x[i] *= inv;
   };
   // Z = X W1 for this wave's hidden block: 32x32 result, rows = tokens.
-  auto z_block = [&](const MT* X) {
+  auto z_block = [&](const float* X) {
     f32x16 z = {};
-    if constexpr (BF) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
-        z = mma32(a, w1b[m], z);
-      }
-    } else {
+    for (int s4 = 0; s4 < 8; ++s4) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&X[l32 * XS_LD + 32 * hf + 4 * s4]);
 #pragma unroll
-      for (int s4 = 0; s4 < 8; ++s4) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&X[l32 * XS_LD + 32 * hf + 4 * s4]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) z = mma32(a[e], w1f[4 * s4 + e], z);
-      }
+      for (int e = 0; e < 4; ++e) z = mma32(a[e], w1f[4 * s4 + e], z);
     }
     return z;
   };
-  // 16x16 block (token block tb, feature block db = the wave's bi-th) of
-  // S W2, S staged [tok][h].
-  auto y_block = [&](const MT* S, int tb, int db, int bi) {
+  // 16x16 block (token block tb, feature block db) of S W2, S staged [tok][h].
+  auto y_block = [&](const float* S, int tb, int db) {
     f32x4 y = {};
     const int arow = 16 * tb + l16, dcol = 16 * db + l16;
-    if constexpr (BF) {
 #pragma unroll
-      for (int u = 0; u < HH / 32; ++u) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + (HH / 4) * g4 + 8 * u]);
-        y = mma16(a, w2y[bi][u], y);
-      }
-    } else {
+    for (int u = 0; u < HH / 16; ++u) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + (HH / 4) * g4 + 4 * u]);
+      const f32x4 b = *reinterpret_cast<const f32x4*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 4 * u]);
 #pragma unroll
-      for (int u = 0; u < HH / 16; ++u) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + (HH / 4) * g4 + 4 * u]);
-        const f32x4 b = *reinterpret_cast<const f32x4*>(&w2t[dcol * W2T_LD + (HH / 4) * g4 + 4 * u]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) y = mma16(a[e], b[e], y);
-      }
+      for (int e = 0; e < 4; ++e) y = mma16(a[e], b[e], y);
     }
     return y;
   };
   // A = SiLU(Z) staged to S; keeps s'(Z) and A (in za) for the gradient.
-  auto silu_stage = [&](f32x16& za, float (&s1)[16], MT* S) {
+  auto silu_stage = [&](f32x16& za, float (&s1)[16], float* S) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float zr = za[r];
@@ -192,41 +141,39 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
       const float av = zr * sg;
       s1[r] = fmaf(av, 1.0f - sg, sg);
       za[r] = av;
-      S[c32_row(r, hf) * AS_LD + hid] = (MT)av;
+      S[c32_row(r, hf) * AS_LD + hid] = av;
     }
   };
-  auto silu_stage_apply = [&](const f32x16& za, MT* S) {
+  auto silu_stage_apply = [&](const f32x16& za, float* S) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float zr = za[r];
-      S[c32_row(r, hf) * AS_LD + hid] = (MT)(zr * sigmoid(zr));
+      S[c32_row(r, hf) * AS_LD + hid] = zr * sigmoid(zr);
     }
   };
-  // Residual, loss and E for this wave's Y blocks (E staged for phase 4).
-  auto residual = [&](int b_vs, float& lacc) {
+  // Residual, loss and E for this wave's Y blocks (E staged for the gradient).
+  auto residual = [&](float& lacc) {
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 y = y_block(as_, tb, db, bi);
+      const f32x4 y = y_block(as_, tb, db);
       const int dcol = 16 * db + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int tok = 16 * tb + 4 * g4 + r;
-        const float R = y[r] - vs[b_vs][tok * VS_LD + dcol];
+        const float R = y[r] - vs[tok * VS_LD + dcol];
         lacc = fmaf(R, R, lacc);
-        const float E = e_scale * R;
-        es[tok * XS_LD + dcol] = (MT)E;
-        if constexpr (BF) ets[dcol * XT_LD + tok] = (bf16)E;
+        es[tok * XS_LD + dcol] = e_scale * R;
       }
     }
   };
-  auto apply_out = [&](const MT* S, int it) {
+  auto apply_out = [&](int it) {
     IOT* O = static_cast<IOT*>(p.O);
     const int t_base = (g + it * G) * TT;
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
-      const f32x4 y = y_block(S, tb, db, bi);
+      const f32x4 y = y_block(as_, tb, db);
       const int dcol = 16 * db + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -236,69 +183,34 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     }
   };
   // P = E W2^T, D = P * s'(Z), grad W1 += K^T D, grad W2 += A^T E.
-  auto grad_update = [&](int bx, const f32x16& za, const float (&s1)[16], f32x16 (&gw1)[2], f32x16 (&gw2)[2]) {
+  auto grad_update = [&](const f32x16& za, const float (&s1)[16], f32x16 (&gw1)[2], f32x16 (&gw2)[2]) {
     f32x16 pz = {};
-    if constexpr (BF) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
-        pz = mma32(a, w2b[m], pz);
-      }
-    } else {
+    for (int s4 = 0; s4 < 8; ++s4) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&es[l32 * XS_LD + 32 * hf + 4 * s4]);
 #pragma unroll
-      for (int s4 = 0; s4 < 8; ++s4) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&es[l32 * XS_LD + 32 * hf + 4 * s4]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) pz = mma32(a[e], w2f[4 * s4 + e], pz);
-      }
+      for (int e = 0; e < 4; ++e) pz = mma32(a[e], w2f[4 * s4 + e], pz);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) pz[r] *= s1[r];
-    if constexpr (BF) {
-      bf16x8 dpk[2], apk[2];
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+    for (int db = 0; db < 2; ++db) {
+      const int dd = 32 * db + l32;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          dpk[m][e] = (bf16)pz[8 * m + e];
-          apk[m][e] = (bf16)za[8 * m + e];
-        }
-#pragma unroll
-      for (int db = 0; db < 2; ++db) {
-        const int dd = 32 * db + l32;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const bf16x4 klo = *reinterpret_cast<const bf16x4*>(&xts[bx][dd * XT_LD + 16 * m + 4 * hf]);
-          const bf16x4 khi = *reinterpret_cast<const bf16x4*>(&xts[bx][dd * XT_LD + 16 * m + 8 + 4 * hf]);
-          const bf16x8 ka = {klo[0], klo[1], klo[2], klo[3], khi[0], khi[1], khi[2], khi[3]};
-          gw1[db] = mma32(ka, dpk[m], gw1[db]);
-          const bf16x4 elo = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 4 * hf]);
-          const bf16x4 ehi = *reinterpret_cast<const bf16x4*>(&ets[dd * XT_LD + 16 * m + 8 + 4 * hf]);
-          const bf16x8 eb = {elo[0], elo[1], elo[2], elo[3], ehi[0], ehi[1], ehi[2], ehi[3]};
-          gw2[db] = mma32(apk[m], eb, gw2[db]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int db = 0; db < 2; ++db) {
-        const int dd = 32 * db + l32;
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int tk = c32_row(s, hf);
-          gw1[db] = mma32(xs[bx][tk * XS_LD + dd], pz[s], gw1[db]);
-          gw2[db] = mma32(za[s], es[tk * XS_LD + dd], gw2[db]);
-        }
+      for (int s = 0; s < 16; ++s) {
+        const int tk = c32_row(s, hf);
+        gw1[db] = mma32(xs[tk * XS_LD + dd], pz[s], gw1[db]);
+        gw2[db] = mma32(za[s], es[tk * XS_LD + dd], gw2[db]);
       }
     }
   };
-  auto stage_kv = [&](int bx, float (&xk)[EPT], float (&xv)[EPT]) {
+  auto stage_kv = [&](float (&xk)[EPT], float (&xv)[EPT]) {
     normalise(xk, norm_k);
     normalise(xv, norm_v);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      xs[bx][row * XS_LD + col0 + i] = (MT)xk[i];
-      vs[bx][row * VS_LD + col0 + i] = xv[i];
-      if constexpr (BF) xts[bx][(col0 + i) * XT_LD + row] = (bf16)xk[i];
+      xs[row * XS_LD + col0 + i] = xk[i];
+      vs[row * VS_LD + col0 + i] = xv[i];
     }
   };
 
@@ -306,78 +218,39 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   float lacc = 0.f;
   float rk[EPT], rv[EPT], rq[EPT];
 
-  if constexpr (BF) {
-    const int iters = max(my_g, my_a);
-    if (iters > 0) {
-      fetch_row(p.K, gs, my_g > 0 ? gl : 0, 0, rk);
-      fetch_row(p.V, gs, my_g > 0 ? gl : 0, 0, rv);
-      fetch_row(p.Q, as0, my_a > 0 ? al : 0, 0, rq);
+  // gradient tiles
+  if (my_g > 0) {
+    fetch_row(p.K, gs, gl, 0, rk);
+    fetch_row(p.V, gs, gl, 0, rv);
+  }
+  for (int it = 0; it < my_g; ++it) {
+    stage_kv(rk, rv);
+    if (it + 1 < my_g) {
+      fetch_row(p.K, gs, gl, it + 1, rk);
+      fetch_row(p.V, gs, gl, it + 1, rv);
     }
-    for (int it = 0; it < iters; ++it) {
-      const int bx = it & 1;
-      const bool hg = it < my_g, ha = it < my_a;
-      // P1: normalise the prefetched rows into LDS buffer bx, prefetch next.
-      stage_kv(bx, rk, rv);
-      normalise(rq, norm_q);
+    __syncthreads();
+    f32x16 za = z_block(xs);
+    float s1[16];
+    silu_stage(za, s1, as_);
+    __syncthreads();
+    residual(lacc);
+    __syncthreads();
+    grad_update(za, s1, gw1, gw2);
+    __syncthreads();
+  }
+  // apply tiles
+  if (my_a > 0) fetch_row(p.Q, as0, al, 0, rq);
+  for (int it = 0; it < my_a; ++it) {
+    normalise(rq, norm_q);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) qs[bx][row * XS_LD + col0 + i] = (MT)rq[i];
-      if (it + 1 < iters) {
-        fetch_row(p.K, gs, it + 1 < my_g ? gl : 0, it + 1, rk);
-        fetch_row(p.V, gs, it + 1 < my_g ? gl : 0, it + 1, rv);
-        fetch_row(p.Q, as0, it + 1 < my_a ? al : 0, it + 1, rq);
-      }
-      __syncthreads();
-      // P2: Z = K W1 and Zq = Q W1, SiLU, stage both activations.
-      f32x16 za = {};
-      float s1[16];
-      if (hg) {
-        za = z_block(xs[bx]);
-        silu_stage(za, s1, as_);
-      }
-      if (ha) silu_stage_apply(z_block(qs[bx]), aqs);
-      __syncthreads();
-      // P3: Y -> residual -> E (gradient tile); O = SiLU(Q W1) W2 (apply tile).
-      if (hg) residual(bx, lacc);
-      if (ha) apply_out(aqs, it);
-      __syncthreads();
-      // P4: gradient outer products.
-      if (hg) grad_update(bx, za, s1, gw1, gw2);
-    }
-  } else {
-    // gradient tiles
-    if (my_g > 0) {
-      fetch_row(p.K, gs, gl, 0, rk);
-      fetch_row(p.V, gs, gl, 0, rv);
-    }
-    for (int it = 0; it < my_g; ++it) {
-      stage_kv(0, rk, rv);
-      if (it + 1 < my_g) {
-        fetch_row(p.K, gs, gl, it + 1, rk);
-        fetch_row(p.V, gs, gl, it + 1, rv);
-      }
-      __syncthreads();
-      f32x16 za = z_block(xs[0]);
-      float s1[16];
-      silu_stage(za, s1, as_);
-      __syncthreads();
-      residual(0, lacc);
-      __syncthreads();
-      grad_update(0, za, s1, gw1, gw2);
-      __syncthreads();
-    }
-    // apply tiles
-    if (my_a > 0) fetch_row(p.Q, as0, al, 0, rq);
-    for (int it = 0; it < my_a; ++it) {
-      normalise(rq, norm_q);
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) xs[0][row * XS_LD + col0 + i] = (MT)rq[i];
-      if (it + 1 < my_a) fetch_row(p.Q, as0, al, it + 1, rq);
-      __syncthreads();
-      silu_stage_apply(z_block(xs[0]), as_);
-      __syncthreads();
-      apply_out(as_, it);
-      __syncthreads();
-    }
+    for (int i = 0; i < EPT; ++i) xs[row * XS_LD + col0 + i] = rq[i];
+    if (it + 1 < my_a) fetch_row(p.Q, as0, al, it + 1, rq);
+    __syncthreads();
+    silu_stage_apply(z_block(xs), as_);
+    __syncthreads();
+    apply_out(it);
+    __syncthreads();
   }
 
   if (gl > 0) {
@@ -900,7 +773,7 @@ static hipError_t launch_fwd_step_t(const FwdStepArgs& a, int n_blocks, hipStrea
   if constexpr (BF)
     hipLaunchKernelGGL((ttt_fwd_step_bf<IOT, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   else
-    hipLaunchKernelGGL((ttt_fwd_step<IOT, BF, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+    hipLaunchKernelGGL((ttt_fwd_step<IOT, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
