@@ -33,9 +33,9 @@ def parse():
     ap.add_argument("--cpu-heads", type=int, default=16)
     ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
     ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
-    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu,single_head",
+    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu,single_head,length_sweep",
                     help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd, amu, "
-                         "single_head)")
+                         "single_head, length_sweep)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -140,8 +140,36 @@ def time_fn(fn, steps, warmup, lib):
     return (t1 - t0) * 1e3 / steps, per, out
 
 
+def length_sweep(steps, warmup, lib, frames=(150, 270, 510, 990)):
+    """One sequence of F frames x 1374 tokens, 16 heads x 64, h = 256,
+    chunks of 8 frames, BF16 operands, for F in `frames` (the layer shape at
+    growing sequence length): with every chunk step filling the chip,
+    tokens/s should not depend on the length."""
+    import torch
+
+    from paper_2604_08542_amd import ops
+    from workloads import make_inputs_torch
+    H, d, h, M, eta = 16, 64, 256, 8 * 1374, 0.05
+    rows = {}
+    for f in frames:
+        n = f * 1374
+        dev = make_inputs_torch(n, H, d, h, seed=0, io_dtype="bf16")
+        O = torch.empty_like(dev["Q"])
+        ms, per, _ = time_fn(lambda: ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], eta, M, out=O,
+                                                   want_final=False), max(2, steps // 4), max(1, warmup // 2), lib)
+        kms = per["fwd_step"]["ms_per_call"]
+        ach = 14.0 * d * h * n * H / (kms * 1e-3) / 1e12
+        rows[str(f)] = dict(tokens=n, chunks=-(-n // M), ms_per_step=ms, tokens_per_s=n / (ms * 1e-3),
+                            step_kernel_tflops=ach, frac_bf16_peak=ach / PEAK["bf16"])
+        del dev, O
+        torch.cuda.empty_cache()
+    tps = [r["tokens_per_s"] for r in rows.values()]
+    return dict(workload="one sequence, 16x64, h256, chunk 8 frames, bf16", frames=rows,
+                tokens_per_s_max_over_min=max(tps) / min(tps))
+
+
 def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd", "amu",
-                                             "single_head")):
+                                             "single_head", "length_sweep")):
     """The other forms on their own workloads: GCS forward (same layer
     workload), forward+backward (differentiation workload), batched forward
     (8 uneven sequences)."""
@@ -150,6 +178,8 @@ def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "
     from paper_2604_08542_amd import ops
     from workloads import WORKLOADS, make_inputs_torch
     res = {}
+    if "length_sweep" in forms:
+        res["length_sweep_bf16"] = length_sweep(steps, warmup, lib)
     # GCS forward on the layer workload, BF16 and FP32 operands
     w = WORKLOADS["layer16_64f_chunk8f"]
     for io in (("bf16", "f32") if "gcs" in forms else ()):
@@ -302,6 +332,15 @@ def cpu_baseline(w, host_inputs, gpu_out, n_heads):
     dt = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     tok_s = w.n_tokens * (n_heads / w.n_heads) / dt
+    # the same oracle on one thread, one head
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        oracle.ttt_forward_batched(x["Q"][:, :1], x["K"][:, :1], x["V"][:, :1], cu, W1[:1], W2[:1], w.eta,
+                                   w.chunk_tokens)
+        dt1 = time.perf_counter() - t1
+    one = dict(value=w.n_tokens / w.n_heads / dt1, unit="tokens/s", cores=1,
+               sample=f"1 of {w.n_heads} heads over all {w.n_tokens} tokens ({dt1:.1f} s), scaled to all heads")
     errs = {}
     for io, out in gpu_out.items():
         O = out["O"][:, sl].float().cpu().numpy().astype(np.float64)
@@ -309,7 +348,7 @@ def cpu_baseline(w, host_inputs, gpu_out, n_heads):
     return dict(value=tok_s, unit="tokens/s", cores=threads, kind="oracle",
                 sample=f"FP64 numpy oracle forward on {n_heads} of {w.n_heads} heads over all "
                        f"{w.n_tokens} tokens ({dt:.1f} s), scaled to all heads",
-                seconds=dt), errs
+                seconds=dt, single_thread=one), errs
 
 
 def main():
@@ -336,6 +375,11 @@ def main():
     if not a.no_extra:
         extra = extra_variants(a.steps, a.warmup, lib, tuple(f for f in a.forms.split(",") if f))
         for k, v in extra.items():
+            if "frames" in v:
+                for f, r in v["frames"].items():
+                    print(f"# {k} {f} frames: {r['ms_per_step']:.3f} ms/step, {r['tokens_per_s']:.4g} tokens/s",
+                          file=sys.stderr, flush=True)
+                continue
             print(f"# {k}: {v['ms_per_step']:.3f} ms/step, {v['tokens_per_s']:.4g} tokens/s", file=sys.stderr,
                   flush=True)
     if a.copy_calib:
