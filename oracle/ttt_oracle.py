@@ -507,3 +507,124 @@ def ttt_forward_swiglu(Q, K, V, W1_0, W2_0, W3_0, eta_tok, chunk_tokens, sync="c
         for i in range(3):
             WT[i][hd] = W[i]
     return dict(O=O, W1_T=WT[0], W2_T=WT[1], W3_T=WT[2])
+
+
+def swiglu_apply_adjoint(q, dO, W1, W2, W3):
+    """Reverse mode of O = f_W(q) for the outer loss sum <O, dO>: returns the
+    adjoints (dW1, dW2, dW3) and dq.
+
+    Zq1 = q W1, Zq3 = q W3, S = SiLU(Zq1), Hq = S * Zq3, O = Hq W2;
+    dW2 = Hq^T dO, dHq = dO W2^T, dZq3 = dHq * S, dZq1 = dHq * Zq3 * s'(Zq1),
+    dW1 = q^T dZq1, dW3 = q^T dZq3, dq = dZq1 W1^T + dZq3 W3^T."""
+    Z1 = q @ W1
+    Z3 = q @ W3
+    S, S1, _ = activation(Z1)
+    Hq = S * Z3
+    dH = dO @ W2.T
+    dZ3 = dH * S
+    dZ1 = dH * Z3 * S1
+    return (q.T @ dZ1, Hq.T @ dO, q.T @ dZ3), dZ1 @ W1.T + dZ3 @ W3.T
+
+
+def swiglu_update_adjoint(k, v, eta_tok, W1, W2, W3, Wh1, Wh2, Wh3):
+    """Reverse mode of one update W' = W - G(W), G = swiglu_dot_grad, given the
+    adjoint Wh of W'.  Returns (the contribution -dG/dW^T Wh to the adjoint of
+    W as three matrices, dk, dv, deta_tok); the identity part of W' = W - ...
+    (adjoint Wh passed through) is left to the caller.
+
+    G is the gradient of L(W) = sum_i <f_W(k_i), E_i> with E_i = -eta_i v_i,
+    so for any input X the needed product (dG/dX)^T Wh is the gradient with
+    respect to X of phi = <G, Wh> = d/dt L(W + t Wh) at t = 0, the derivative
+    of L along Wh:
+      dot Z1 = k Wh1, dot Z3 = k Wh3, dot S = s'(Z1) dot Z1,
+      dot H = dot S * Z3 + S * dot Z3, dot Y = dot H W2 + H Wh2,
+      phi = sum_i <dot Y_i, E_i>.
+    Its reverse mode, line by line:
+      dH = E W2^T, dHh = E Wh2^T        (adjoints of dot H and H)
+      grad_W2 phi = dot H^T E,  grad_E phi = dot Y
+      dot S: dH * Z3;  Z3: dH * dot S + dHh * S;  S: dH * dot Z3 + dHh * Z3
+      dot Z3: dH * S;  dot Z1: (dH * Z3) s'(Z1)
+      Z1: (dH * Z3) s''(Z1) dot Z1 + (adjoint of S) s'(Z1)
+      grad_W1 phi = k^T (adjoint of Z1), grad_W3 phi = k^T (adjoint of Z3)
+      grad_k phi = adj(Z1) W1^T + adj(Z3) W3^T + adj(dot Z1) Wh1^T + adj(dot Z3) Wh3^T.
+    The update subtracts G, so the contributions are minus these; through
+    E_i = -eta_i v_i: dv_i = eta_i dot Y_i and deta_i = <v_i, dot Y_i>."""
+    Z1 = k @ W1
+    Z3 = k @ W3
+    S, S1, S2 = activation(Z1)
+    Hd = S * Z3
+    E = -eta_tok[:, None] * v
+    Zd1 = k @ Wh1
+    Zd3 = k @ Wh3
+    Sd = S1 * Zd1
+    Hdot = Sd * Z3 + S * Zd3
+    Ydot = Hdot @ W2 + Hd @ Wh2
+    dH = E @ W2.T
+    dHh = E @ Wh2.T
+    aSd = dH * Z3
+    aZ3 = dH * Sd + dHh * S
+    aS = dH * Zd3 + dHh * Z3
+    aZd3 = dH * S
+    aZd1 = aSd * S1
+    aZ1 = aSd * S2 * Zd1 + aS * S1
+    gW = (k.T @ aZ1, Hdot.T @ E, k.T @ aZ3)
+    gk = aZ1 @ W1.T + aZ3 @ W3.T + aZd1 @ Wh1.T + aZd3 @ Wh3.T
+    return tuple(-g for g in gW), -gk, eta_tok[:, None] * Ydot, np.sum(v * Ydot, axis=1)
+
+
+def ttt_backward_swiglu(Q, K, V, W1_0, W2_0, W3_0, eta_tok, chunk_tokens, dO, sync="chain", norm=(True, True, True)):
+    """Reverse mode of ttt_forward_swiglu for the outer loss sum <O, dO>:
+    dQ, dK, dV, deta_tok [N][H] and dW1_0, dW2_0, dW3_0.
+
+    chain: for c = C-1 .. 0 the adjoint of W_{c+1} collects chunk c's apply
+    adjoint (at W_{c+1}), then the update adjoint of chunk c (at W_c) gives
+    the adjoint of W_c.  gcs: the adjoint of W* collects every token's apply
+    adjoint; each chunk's update adjoint is taken at W0 with that adjoint, and
+    dW0 = adjoint of W* + the sum of the chunks' contributions."""
+    Q, K, V, W1_0, W2_0, W3_0, eta_tok, dO = _as_f64(Q, K, V, W1_0, W2_0, W3_0, eta_tok, dO)
+    N, H, d = K.shape
+    bounds = chunk_bounds(N, chunk_tokens)
+    dQ, dK, dV = np.zeros_like(Q), np.zeros_like(K), np.zeros_like(V)
+    deta = np.zeros_like(eta_tok)
+    dW = [np.zeros_like(W1_0), np.zeros_like(W2_0), np.zeros_like(W3_0)]
+    for hd in range(H):
+        q = _prep(Q[:, hd, :], norm[0])
+        k = _prep(K[:, hd, :], norm[1])
+        v = _prep(V[:, hd, :], norm[2])
+        et = eta_tok[:, hd]
+        do = dO[:, hd, :]
+        dq, dk, dv = np.zeros_like(q), np.zeros_like(k), np.zeros_like(v)
+        W0 = [W1_0[hd], W2_0[hd], W3_0[hd]]
+        if sync == "chain":
+            Ws = [W0]
+            for (s, e) in bounds:
+                G = swiglu_dot_grad(k[s:e], v[s:e], et[s:e], *Ws[-1])
+                Ws.append([Ws[-1][i] - G[i] for i in range(3)])
+            Wh = [np.zeros_like(x) for x in W0]
+            for c in range(len(bounds) - 1, -1, -1):
+                s, e = bounds[c]
+                ga, dq[s:e] = swiglu_apply_adjoint(q[s:e], do[s:e], *Ws[c + 1])
+                Wh = [Wh[i] + ga[i] for i in range(3)]
+                gu, dk[s:e], dv[s:e], deta[s:e, hd] = swiglu_update_adjoint(k[s:e], v[s:e], et[s:e], *Ws[c], *Wh)
+                Wh = [Wh[i] + gu[i] for i in range(3)]
+        elif sync == "gcs":
+            tot = [np.zeros_like(x) for x in W0]
+            for (s, e) in bounds:
+                G = swiglu_dot_grad(k[s:e], v[s:e], et[s:e], *W0)
+                tot = [tot[i] + G[i] for i in range(3)]
+            Wstar = [W0[i] - tot[i] for i in range(3)]
+            ga, dq = swiglu_apply_adjoint(q, do, *Wstar)
+            Wh = list(ga)
+            acc = [x.copy() for x in ga]
+            for (s, e) in bounds:
+                gu, dk[s:e], dv[s:e], deta[s:e, hd] = swiglu_update_adjoint(k[s:e], v[s:e], et[s:e], *W0, *Wh)
+                acc = [acc[i] + gu[i] for i in range(3)]
+            Wh = acc
+        else:
+            raise ValueError(sync)
+        for i in range(3):
+            dW[i][hd] = Wh[i]
+        dQ[:, hd, :] = l2norm_rows_bwd(Q[:, hd, :], dq) if norm[0] else dq
+        dK[:, hd, :] = l2norm_rows_bwd(K[:, hd, :], dk) if norm[1] else dk
+        dV[:, hd, :] = l2norm_rows_bwd(V[:, hd, :], dv) if norm[2] else dv
+    return dict(dQ=dQ, dK=dK, dV=dV, deta_tok=deta, dW1_0=dW[0], dW2_0=dW[1], dW3_0=dW[2])
