@@ -203,6 +203,27 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
                          const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,
                          void* O, float* W1_T, float* W2_T, float* W3_T, void* ws, size_t ws_bytes,
                          void* hip_stream);
+
+/* Reverse mode of ttt_amu_fwd (same sync, same inputs) for the outer loss
+ * sum <O, dO>, second-order terms through every inner update included:
+ *   dQ, dK, dV  [N][H][d] in the io dtype (through the L2 normalisation);
+ *   deta_tok    [N][H] f32, the derivative along each token's step size;
+ *   dW1_0, dW3_0 [H][d][h], dW2_0 [H][h][d] f32.
+ * The update of one chunk is W' = W - G(W) with G the gradient of
+ * L(W) = sum_i <f_W(k_i), E_i>, E_i = -eta_i v_i; its adjoint needs
+ * (dG/dX)^T Wh for the carried adjoint Wh of W', which is the gradient with
+ * respect to X of the derivative of L along Wh (Supp. A network, Eq. 8-10).
+ * TTT_SYNC_CHAIN recomputes W_1..W_C (no checkpoint argument) and walks the
+ * chunks in reverse; TTT_SYNC_GCS recomputes W* and needs one apply-adjoint
+ * and one update-adjoint pass over all tokens.  Every output is overwritten;
+ * with n_tokens = 0 the weight adjoints are zero.  ws_bytes >=
+ * ttt_amu_bwd_workspace_bytes(p, sync) (it grows with the chunk count for the
+ * chain).  Errors as ttt_amu_fwd. */
+size_t ttt_amu_bwd_workspace_bytes(const ttt_problem_t* p, int32_t sync);
+ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,
+                         const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,
+                         const void* dO, void* dQ, void* dK, void* dV, float* deta_tok, float* dW1_0,
+                         float* dW2_0, float* dW3_0, void* ws, size_t ws_bytes, void* hip_stream);
 /* Benchmark instrumentation.  While enabled, every launch the library
  * enqueues is bracketed by a pair of HIP events on the launch stream (events
  * come from a pool the library owns; enabling clears earlier records).

@@ -594,14 +594,14 @@ ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const voi
   auto packed = [&](const float* b) { return AmuWeights{b, b + dh, b + 2 * dh, 3 * dh}; };
   auto do_prep = [&](const AmuWeights& w) {
     AmuPrepArgs a{};
-    a.src = w; a.prep = prep; a.H = (int32_t)H; a.h = S.h;
+    a.src = w; a.prep = prep; a.n_mats = 4; a.H = (int32_t)H; a.h = S.h;
     return timed_launch(4, st, [&] { return launch_amu_prep(a, S.mma_bf16, st); });
   };
   auto do_step = [&](int64_t G, int64_t gs, int64_t gl, int64_t as, int64_t al) {
     AmuStepArgs a{};
     a.Q = Q; a.K = K; a.V = V; a.O = O; a.eta_tok = eta_tok;
     a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
-    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep; a.partial = partial;
+    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep; a.n_prep = 4; a.partial = partial;
     a.grad_start = gs; a.grad_len = (int32_t)gl; a.app_start = as; a.app_len = (int32_t)al;
     return timed_launch(0, st, [&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); });
   };
@@ -636,6 +636,156 @@ ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const voi
   if (!do_update(w0, G, pp[0], true)) return TTT_EHIP;
   if (!do_prep(packed(pp[0]))) return TTT_EHIP;
   if (!do_step(G, 0, 0, 0, N)) return TTT_EHIP;
+  return TTT_OK;
+}
+
+
+// Reverse mode of the paper's memory unit.  Workspace: shard partials, the
+// carried adjoint Wh [H][3dh], the weights the backward needs ([C+1][H][3dh]
+// for the chain: every W_c, recomputed; [1][H][3dh] for GCS: W*), and three
+// sets of six operand copies per head (weights at the update, weights at the
+// apply, Wh).
+struct AmuBwdWs {
+  size_t partial, wh, wlist, prep_u, prep_a, prep_h, total;
+  int64_t slot_cap;
+};
+
+AmuBwdWs amu_bwd_ws_layout(const Shape& s, int64_t n_tokens, int sync) {
+  AmuBwdWs L{};
+  L.slot_cap = std::max<int64_t>(s.H, SLOT_CAP_MIN);
+  const size_t wbytes = (size_t)3 * s.dh() * sizeof(float);
+  const int64_t C = (n_tokens + s.M - 1) / s.M;
+  const int64_t n_w = sync == TTT_SYNC_CHAIN ? C + 1 : 1;
+  const size_t pbytes = (size_t)s.H * 6 * s.dh() * sizeof(float);
+  size_t off = 0;
+  L.partial = off;
+  off = align_up(off + (size_t)L.slot_cap * wbytes);
+  L.wh = off;
+  off = align_up(off + (size_t)s.H * wbytes);
+  L.wlist = off;
+  off = align_up(off + (size_t)n_w * s.H * wbytes);
+  L.prep_u = off;
+  off = align_up(off + pbytes);
+  L.prep_a = off;
+  off = align_up(off + pbytes);
+  L.prep_h = off;
+  off = align_up(off + pbytes);
+  L.total = off;
+  return L;
+}
+
+// chain: recompute W_1..W_C (one gradient launch and one update per chunk),
+// then for c = C-1..0: Wh += apply adjoint of chunk c at W_{c+1}; Wh += update
+// adjoint of chunk c at W_c along Wh.  gcs: W* = W0 - (gradient over all
+// tokens); Wh = apply adjoint over all tokens at W*; dW0 = Wh + update
+// adjoint over all tokens at W0 along Wh (the chunks' update adjoints at W0
+// with the same Wh sum to one pass over the tokens: no per-chunk
+// normalisation in this loss).
+ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const void* Q, const void* K,
+                         const void* V, const float* eta_tok, const float* W1_0, const float* W2_0,
+                         const float* W3_0, const void* dO, void* dQ, void* dK, void* dV, float* deta_tok,
+                         float* dW1_0, float* dW2_0, float* dW3_0, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t H = S.H, N = p->n_tokens, M = S.M, dh = S.dh();
+  const AmuBwdWs L = amu_bwd_ws_layout(S, N, sync);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t C = (N + M - 1) / M;
+  float* partial = at<float>(ws, L.partial);
+  float* wh = at<float>(ws, L.wh);
+  float* wlist = at<float>(ws, L.wlist);
+  void* prep_u = at<char>(ws, L.prep_u);
+  void* prep_a = at<char>(ws, L.prep_a);
+  void* prep_h = at<char>(ws, L.prep_h);
+  const int target = default_target_wgs(S);
+  auto grid_g = [&](int64_t len) {
+    const int64_t tiles = std::max<int64_t>((len + TT - 1) / TT, 1);
+    return std::max<int64_t>(1, std::min<int64_t>({(target + H - 1) / H, tiles, L.slot_cap / H}));
+  };
+  const AmuWeights w0{W1_0, W2_0, W3_0, dh};
+  auto packed = [&](const float* b) { return AmuWeights{b, b + dh, b + 2 * dh, 3 * dh}; };
+  auto do_prep = [&](const AmuWeights& w, void* dst) {
+    AmuPrepArgs a{};
+    a.src = w; a.prep = dst; a.n_mats = 6; a.H = (int32_t)H; a.h = S.h;
+    return timed_launch(4, st, [&] { return launch_amu_prep(a, S.mma_bf16, st); });
+  };
+  auto do_grad = [&](int64_t start, int64_t len) {  // gradient partials at the weights in prep_u
+    AmuStepArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = nullptr; a.eta_tok = eta_tok;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    const int64_t G = grid_g(len);
+    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep_u; a.n_prep = 6; a.partial = partial;
+    a.grad_start = start; a.grad_len = (int32_t)len; a.app_start = 0; a.app_len = 0;
+    if (!timed_launch(0, st, [&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return int64_t(-1);
+    return G;
+  };
+  auto do_update = [&](const AmuWeights& src, int64_t G, float* dst) {
+    AmuUpdArgs u{};
+    u.src = src; u.partial = partial; u.G = (int32_t)G; u.H = (int32_t)H; u.h = S.h; u.w_dst = dst;
+    return timed_launch(1, st, [&] { return launch_amu_update(u, st); });
+  };
+  auto bwd_args = [&](int64_t start, int64_t len, int64_t G) {
+    AmuBwdArgs a{};
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.partial = partial;
+    a.start = start; a.len = (int32_t)len;
+    return a;
+  };
+  auto do_apply_adj = [&](int64_t start, int64_t len) {  // at the weights in prep_a
+    const int64_t G = grid_g(len);
+    AmuBwdArgs a = bwd_args(start, len, G);
+    a.X = Q; a.Y = dO; a.dX = dQ; a.prep_w = prep_a;
+    if (!timed_launch(2, st, [&] { return launch_amu_bwd_apply(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return int64_t(-1);
+    return G;
+  };
+  auto do_update_adj = [&](int64_t start, int64_t len) {  // at prep_u along prep_h
+    const int64_t G = grid_g(len);
+    AmuBwdArgs a = bwd_args(start, len, G);
+    a.X = K; a.Y = V; a.dX = dK; a.dY = dV; a.eta_tok = eta_tok; a.deta_tok = deta_tok;
+    a.prep_w = prep_u; a.prep_a = prep_h;
+    if (!timed_launch(2, st, [&] { return launch_amu_bwd_update(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      return int64_t(-1);
+    return G;
+  };
+  auto do_psum = [&](int64_t G, const float* base, float* dst, bool final) {
+    AmuPsumArgs a{};
+    a.partial = partial; a.G = (int32_t)G; a.H = (int32_t)H; a.h = S.h; a.base = base; a.dst = dst;
+    if (final) { a.out1 = dW1_0; a.out2 = dW2_0; a.out3 = dW3_0; }
+    return timed_launch(3, st, [&] { return launch_amu_psum(a, st); });
+  };
+
+  if (C == 0) {  // no tokens: O is empty, every adjoint is zero
+    return do_psum(0, nullptr, wh, true) ? TTT_OK : TTT_EHIP;
+  }
+  if (sync == TTT_SYNC_GCS) {
+    float* wstar = wlist;
+    if (!do_prep(w0, prep_u)) return TTT_EHIP;
+    const int64_t Gg = do_grad(0, N);
+    if (Gg < 0 || !do_update(w0, Gg, wstar)) return TTT_EHIP;
+    if (!do_prep(packed(wstar), prep_a)) return TTT_EHIP;
+    const int64_t Ga = do_apply_adj(0, N);
+    if (Ga < 0 || !do_psum(Ga, nullptr, wh, false)) return TTT_EHIP;
+    if (!do_prep(packed(wh), prep_h)) return TTT_EHIP;
+    const int64_t Gu = do_update_adj(0, N);
+    if (Gu < 0 || !do_psum(Gu, wh, wh, true)) return TTT_EHIP;
+    return TTT_OK;
+  }
+  // chain: W_c at wlist + c * H * 3dh (c >= 1); W_0 is the caller's
+  auto wc = [&](int64_t c) { return c == 0 ? w0 : packed(wlist + c * H * 3 * dh); };
+  auto mlen = [&](int64_t c) { return std::min<int64_t>(M, N - c * M); };
+  for (int64_t c = 0; c < C; ++c) {
+    if (!do_prep(wc(c), prep_u)) return TTT_EHIP;
+    const int64_t G = do_grad(c * M, mlen(c));
+    if (G < 0 || !do_update(wc(c), G, wlist + (c + 1) * H * 3 * dh)) return TTT_EHIP;
+  }
+  for (int64_t c = C - 1; c >= 0; --c) {
+    if (!do_prep(wc(c + 1), prep_a)) return TTT_EHIP;
+    const int64_t Ga = do_apply_adj(c * M, mlen(c));
+    if (Ga < 0 || !do_psum(Ga, c == C - 1 ? nullptr : wh, wh, false)) return TTT_EHIP;
+    if (!do_prep(wc(c), prep_u) || !do_prep(packed(wh), prep_h)) return TTT_EHIP;
+    const int64_t Gu = do_update_adj(c * M, mlen(c));
+    if (Gu < 0 || !do_psum(Gu, wh, wh, c == 0)) return TTT_EHIP;
+  }
   return TTT_OK;
 }
 
@@ -808,6 +958,36 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
     if (p->n_tokens == 0 && !W1_T) return TTT_OK;
     return run_amu(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, O, W1_T, W2_T, W3_T, ws, ws_bytes,
                    static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+size_t ttt_amu_bwd_workspace_bytes(const ttt_problem_t* p, int32_t sync) {
+  Shape S{};
+  if (check_problem(p, &S) != TTT_OK || (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS)) return 0;
+  return amu_bwd_ws_layout(S, p->n_tokens, sync).total;
+}
+
+ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,
+                         const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,
+                         const void* dO, void* dQ, void* dK, void* dV, float* deta_tok, float* dW1_0, float* dW2_0,
+                         float* dW3_0, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    const ttt_status_t e = check_problem(p, &S);
+    if (e != TTT_OK) return e;
+    if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
+    if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
+    if (!W1_0 || !W2_0 || !W3_0 || !dW1_0 || !dW2_0 || !dW3_0) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!Q || !K || !V || !eta_tok || !dO || !dQ || !dK || !dV || !deta_tok))
+      return TTT_EINVAL;
+    for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)W1_0,
+                          (const void*)W2_0, (const void*)W3_0, (const void*)dW1_0, (const void*)dW2_0,
+                          (const void*)dW3_0})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    return run_amu_bwd(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, dO, dQ, dK, dV, deta_tok, dW1_0, dW2_0,
+                       dW3_0, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;
   }

@@ -48,10 +48,10 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   const int64_t hoff = (int64_t)head * p.stride_head;
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
   // operand copies of this head: W1, W3, W2 as [hid][d], W2 as [d][hid]
-  const MT* W1t = static_cast<const MT*>(p.prep) + (int64_t)head * 4 * DH;
-  const MT* W3t = W1t + DH;
-  const MT* W2n = W1t + 2 * DH;
-  const MT* W2d = W1t + 3 * DH;
+  const MT* W1t = static_cast<const MT*>(p.prep) + (int64_t)head * p.n_prep * DH;
+  const MT* W3t = W1t + AMU_W3T * DH;
+  const MT* W2n = W1t + AMU_W2N * DH;
+  const MT* W2d = W1t + AMU_W2D * DH;
 
   // 32x32 block C[token][hid] = X[token][:] M[hid][:]^T (M rows contiguous).
   auto th = [&](const float* X, const MT* M) {
@@ -270,7 +270,8 @@ __global__ __launch_bounds__(256) void ttt_amu_update(AmuUpdArgs p) {
   if (fin) *reinterpret_cast<f32x4*>(fin + (int64_t)head * dh + off) = wn;
 }
 
-// Operand copies per head: W1 and W3 as [hid][d], W2 as [hid][d] and [d][hid].
+// Operand copies per head: W1 and W3 as [hid][d], W2 as [hid][d] and [d][hid],
+// and with n_mats = 6 also W1 and W3 as [d][hid] (their own layout).
 template <typename MT>
 __global__ __launch_bounds__(256) void ttt_amu_prep(AmuPrepArgs p) {
   const int h = p.h, dh = D * h;
@@ -278,14 +279,19 @@ __global__ __launch_bounds__(256) void ttt_amu_prep(AmuPrepArgs p) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= dh) return;
   const int64_t hb = (int64_t)head * p.src.stride;
-  MT* o = static_cast<MT*>(p.prep) + (int64_t)head * 4 * dh;
+  MT* o = static_cast<MT*>(p.prep) + (int64_t)head * p.n_mats * dh;
   const int d = idx / h, hh = idx % h;    // W1 / W3 element (d, hh)
   const int hh2 = idx / D, d2 = idx % D;  // W2 element (hh2, d2)
-  o[0 * dh + hh * D + d] = (MT)p.src.w1[hb + idx];
-  o[1 * dh + hh * D + d] = (MT)p.src.w3[hb + idx];
+  const float w1 = p.src.w1[hb + idx], w3 = p.src.w3[hb + idx];
+  o[AMU_W1T * dh + hh * D + d] = (MT)w1;
+  o[AMU_W3T * dh + hh * D + d] = (MT)w3;
   const float w2 = p.src.w2[hb + idx];
-  o[2 * dh + idx] = (MT)w2;
-  o[3 * dh + d2 * h + hh2] = (MT)w2;
+  o[AMU_W2N * dh + idx] = (MT)w2;
+  o[AMU_W2D * dh + d2 * h + hh2] = (MT)w2;
+  if (p.n_mats == 6) {
+    o[AMU_W1D * dh + idx] = (MT)w1;
+    o[AMU_W3D * dh + idx] = (MT)w3;
+  }
 }
 
 template <typename IOT, bool BF, int NW>

@@ -99,7 +99,6 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   const __amdgpu_buffer_rsrc_t prsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<MT*>(prep0), (short)0, (int)(8 * DH * sizeof(MT)), 0x00020000);
   auto bload = [&](int voff, int soff) {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(prsrc, voff, soff, 0));
   };
   const int64_t hoff = (int64_t)head * p.stride_head;

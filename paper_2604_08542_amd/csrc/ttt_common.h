@@ -284,50 +284,4 @@ struct BwdSumArgs {
   int32_t B, H, h;
 };
 
-// ----------------------------------------------------------------- paper AMU
-// Weights of the SwiGLU fast network per head: W1 [d][h], W2 [h][d], W3 [d][h]
-// at w1/w2/w3 + head * stride.
-struct AmuWeights {
-  const float* w1;
-  const float* w2;
-  const float* w3;
-  int64_t stride;
-};
-
-// One chunk step of one sequence, every head: gradient of chunk s over a
-// token shard (work-group = head * G + shard) and apply of chunk s-1.
-struct AmuStepArgs {
-  const void* Q;
-  const void* K;
-  const void* V;
-  void* O;
-  const float* eta_tok;  // [N][H] token-wise step sizes
-  int64_t stride_tok, stride_head;
-  int32_t H;
-  uint32_t flags;
-  int32_t G;
-  const void* prep;      // [H][4][D*h] operand copies (ttt_amu_prep)
-  float* partial;        // [H*G][3*D*h]: grad W1 | grad W2 | grad W3
-  int64_t grad_start;
-  int32_t grad_len;
-  int64_t app_start;
-  int32_t app_len;
-};
-
-struct AmuUpdArgs {
-  AmuWeights src;
-  const float* partial;
-  int32_t G, H, h;
-  float* w_dst;          // [H][3*D*h] packed W1 | W2 | W3
-  float* wT1;            // final split copies, nullable
-  float* wT2;
-  float* wT3;
-};
-
-struct AmuPrepArgs {
-  AmuWeights src;
-  void* prep;
-  int32_t H, h;
-};
-
 }  // namespace ttt

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "ttt_amu.h"
 #include "ttt_common.h"
 
 namespace ttt {
@@ -15,4 +16,8 @@ hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st);
 hipError_t launch_amu_step(const AmuStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_amu_update(const AmuUpdArgs& a, hipStream_t st);
 hipError_t launch_amu_prep(const AmuPrepArgs& a, bool mma_bf16, hipStream_t st);
+hipError_t launch_amu_bwd_apply(const AmuBwdArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
+hipError_t launch_amu_bwd_update(const AmuBwdArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16,
+                                 hipStream_t st);
+hipError_t launch_amu_psum(const AmuPsumArgs& a, hipStream_t st);
 }  // namespace ttt

@@ -340,3 +340,34 @@ def amu_fwd(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, *, sync="chain", norm=Tr
                          _stream(dev))
     L.check(st, "ttt_amu_fwd")
     return dict(O=O, W1_T=fin[0], W2_T=fin[1], W3_T=fin[2])
+
+
+def amu_bwd(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, dO, *, sync="chain", norm=True, mma_bf16=False, ws=None):
+    """Reverse mode of amu_fwd for sum <O, dO> (same inputs and sync): returns
+    dQ, dK, dV (io dtype), deta_tok [N][H] and dW1_0, dW2_0, dW3_0 (float32)."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    if W3.shape != W1.shape or W3.dtype != torch.float32 or not W3.is_contiguous():
+        raise ValueError("W3 must be a contiguous float32 tensor shaped like W1")
+    if eta_tok.shape != (N, H) or eta_tok.dtype != torch.float32 or not eta_tok.is_contiguous():
+        raise ValueError("eta_tok must be a contiguous float32 [N][H] tensor")
+    sync_id = {"chain": L.TTT_SYNC_CHAIN, "gcs": L.TTT_SYNC_GCS}[sync]
+    prob = problem(Q, h, N, chunk_tokens, 0.0, _flags(norm, mma_bf16=mma_bf16))
+    dev = Q.device
+    dQ, dK, dV = (_like_tokens(Q, None) for _ in range(3))
+    if dO.shape != Q.shape or dO.stride() != Q.stride() or dO.dtype != Q.dtype:
+        raise ValueError("dO must match Q's shape, strides and dtype")
+    deta = torch.empty_like(eta_tok)
+    dW = [torch.empty_like(W) for W in (W1, W2, W3)]
+    if ws is None:
+        nbytes = lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(prob), sync_id)
+        if nbytes == 0:
+            raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_amu_bwd_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = lib.ttt_amu_bwd(ctypes.byref(prob), sync_id, _ptr(Q), _ptr(K), _ptr(V), _ptr(eta_tok), _ptr(W1), _ptr(W2),
+                         _ptr(W3), _ptr(dO), _ptr(dQ), _ptr(dK), _ptr(dV), _ptr(deta), _ptr(dW[0]), _ptr(dW[1]),
+                         _ptr(dW[2]), _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_amu_bwd")
+    return dict(dQ=dQ, dK=dK, dV=dV, deta_tok=deta, dW1_0=dW[0], dW2_0=dW[1], dW3_0=dW[2])

@@ -153,6 +153,31 @@ def test_amu_validation(lib):
     assert call(prob(n_tokens=0)) == L.TTT_OK                     # nothing to do, nothing enqueued
 
 
+def test_amu_bwd_validation(lib):
+    """Argument checks of the memory unit's reverse mode (all rejected before
+    anything is enqueued, so no GPU is needed)."""
+    def call(p, sync=0, **kw):
+        a = dict(Q=FAKE, eta=FAKE, dO=FAKE, dW3=FAKE, ws=FAKE, nws=1 << 40)
+        a.update(kw)
+        return lib.ttt_amu_bwd(ctypes.byref(p), sync, a["Q"], FAKE, FAKE, a["eta"], FAKE, FAKE, FAKE, a["dO"], FAKE,
+                               FAKE, FAKE, FAKE, FAKE, FAKE, a["dW3"], a["ws"], a["nws"], None)
+    p = prob(n_tokens=1000, chunk_tokens=100)
+    chain = lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(p), L.TTT_SYNC_CHAIN)
+    gcs = lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(p), L.TTT_SYNC_GCS)
+    assert chain > gcs >= 1024 * 3 * 64 * 256 * 4           # the chain keeps every W_c (10 chunks)
+    assert lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(p), 5) == 0
+    assert call(p, sync=2) == L.TTT_EINVAL
+    assert call(p, eta=None) == L.TTT_EINVAL
+    assert call(p, dO=None) == L.TTT_EINVAL
+    assert call(p, dW3=None) == L.TTT_EINVAL
+    assert call(prob(n_tokens=1000, flags=7 | L.TTT_EMIT_LOSS)) == L.TTT_ENOTSUP
+    assert call(prob(d_hidden=192)) == L.TTT_ESHAPE
+    assert call(prob(stride_tok=1 << 23)) == L.TTT_ESHAPE
+    assert call(p, Q=ctypes.c_void_p((1 << 20) + 4)) == L.TTT_EINVAL
+    assert call(p, ws=None) == L.TTT_EWORKSPACE
+    assert call(p, nws=gcs) == L.TTT_EWORKSPACE                # chain needs more than GCS
+
+
 def test_status_strings(lib):
     for s in range(6):
         assert lib.ttt_status_string(s).startswith(b"TTT_")

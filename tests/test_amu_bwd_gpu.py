@@ -1,0 +1,89 @@
+"""Reverse mode of the paper's memory unit on the GPU (SwiGLU fast network,
+dot-product inner loss, token-wise step sizes; chain and synchronised forms)
+against the FP64 oracle: dQ, dK, dV, d eta_i and the three weight adjoints."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from gpu_util import TOL, host, inputs, rel
+from workloads import make_eta_tok
+
+pytestmark = pytest.mark.gpu
+
+AMU_ETA = 20.0  # eta_i ~ 20 / M, as in the forward tests of this unit
+
+
+def ops():
+    from paper_2604_08542_amd import ops
+    return ops
+
+
+def w3_like(W1, seed):
+    return (np.random.default_rng(seed).standard_normal(W1.shape) / np.sqrt(W1.shape[-2])).astype(np.float32)
+
+
+def run_bwd(N, H, h, M, io, sync, seed, mma_bf16=False, eta=AMU_ETA):
+    x, dev = inputs(N, H, h, seed=seed, io=io, with_dO=True)
+    W3 = w3_like(x["W1"], seed + 1)
+    et = make_eta_tok(N, H, M, eta, seed)
+    print(f"amu bwd N={N} H={H} h={h} M={M} io={io} mma_bf16={mma_bf16} sync={sync} eta={eta}", flush=True)
+    r = ops().amu_bwd(dev["Q"], dev["K"], dev["V"], torch.from_numpy(et).cuda(), dev["W1"], dev["W2"],
+                      torch.from_numpy(W3).cuda(), M, dev["dO"], sync=sync, mma_bf16=mma_bf16)
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_swiglu(x["Q"], x["K"], x["V"], x["W1"], x["W2"], W3, et, M, x["dO"], sync=sync)
+    errs = {k: rel(host(r[k]), ref[k]) for k in ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0")}
+    print("   " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    return errs
+
+
+CASES = [
+    (1100, 2, 256, 400, "f32", False, "chain"),
+    (1100, 2, 256, 400, "f32", False, "gcs"),
+    (700, 2, 128, 256, "f32", False, "chain"),
+    (700, 1, 128, 700, "f32", False, "gcs"),
+    (90, 1, 256, 40, "f32", False, "chain"),
+    (1000, 2, 256, 333, "f32", True, "chain"),
+    (1000, 2, 256, 333, "bf16", True, "gcs"),
+    (2748, 1, 128, 1374, "bf16", True, "chain"),
+]
+
+
+@pytest.mark.parametrize("N,H,h,M,io,mma,sync", CASES)
+def test_amu_bwd_matches_oracle(gpu, N, H, h, M, io, mma, sync):
+    errs = run_bwd(N, H, h, M, io, sync, seed=800 + N + H, mma_bf16=mma)
+    tol = TOL["bf16" if (mma or io == "bf16") else "f32"]
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("sync", ["chain", "gcs"])
+def test_amu_bwd_large_steps(gpu, sync):
+    """eta_i ~ 200 / M: the second-order terms through the updates make up
+    10-27% of the weight adjoints (1-3% at the default step sizes)."""
+    errs = run_bwd(1100, 2, 256, 400, "f32", sync, seed=840, eta=200.0)
+    for k, v in errs.items():
+        assert v <= TOL["f32"], (k, v)
+
+
+def test_amu_bwd_zero_tokens(gpu):
+    """n_tokens = 0: the weight adjoints are zero (no output depends on W)."""
+    W1 = torch.randn(2, 64, 128, device="cuda")
+    W2 = torch.randn(2, 128, 64, device="cuda")
+    Q = torch.empty(0, 2, 64, device="cuda")
+    r = ops().amu_bwd(Q, Q, Q, torch.empty(0, 2, device="cuda"), W1, W2, W1.clone(), 64, Q, sync="chain")
+    torch.cuda.synchronize()
+    for k in ("dW1_0", "dW2_0", "dW3_0"):
+        assert float(r[k].abs().max()) == 0.0
+
+
+def test_amu_bwd_one_chunk_chain_equals_gcs(gpu):
+    """With a single chunk both schedules differentiate the same function."""
+    x, dev = inputs(600, 2, 128, seed=820, io="f32", with_dO=True)
+    W3 = torch.from_numpy(w3_like(x["W1"], 821)).cuda()
+    et = torch.from_numpy(make_eta_tok(600, 2, 600, AMU_ETA, 820)).cuda()
+    a = ops().amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, 600, dev["dO"], sync="chain")
+    b = ops().amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, 600, dev["dO"], sync="gcs")
+    torch.cuda.synchronize()
+    for k in ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0"):
+        assert rel(host(a[k]), host(b[k])) <= 1e-5, k
