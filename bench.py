@@ -211,6 +211,20 @@ def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "
             res[f"amu_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
                                            kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
                                                                       unit="TFLOP/s", frac=ach / PEAK[io]))
+            # forward + reverse mode (the backward recomputes the weights it needs)
+            dO = torch.randn(dev["Q"].shape, generator=g, device="cuda").to(dev["Q"].dtype)
+
+            def fb():
+                ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens, sync=sync,
+                            want_final=False, out=O)
+                return ops.amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens, dO,
+                                   sync=sync)
+            ms, per, _ = time_fn(fb, max(2, steps // 2), 1, lib)
+            bk = per["bwd_step"]
+            res[f"amu_fwd_bwd_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms,
+                                                   tokens_per_s=w.n_tokens / (ms * 1e-3), kernels=per,
+                                                   bwd_kernels_ms=bk["ms_per_call"])
+            del dO
         del dev, O, W3, et
     # single-head chains: 4 chunks x 1374 tokens (FP32) and 256 chunks x 1374 tokens (BF16, precision form)
     for name, io in ((("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16"))
