@@ -87,3 +87,23 @@ def test_amu_bwd_one_chunk_chain_equals_gcs(gpu):
     torch.cuda.synchronize()
     for k in ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0"):
         assert rel(host(a[k]), host(b[k])) <= 1e-5, k
+
+
+def test_amu_bwd_strided_views(gpu):
+    """Q/K/V/dO as views into fused [N][4][H][d] storage (padded token
+    stride); the gradients come back with the same strides."""
+    N, H, h, M = 640, 2, 128, 200
+    x, _ = inputs(N, H, h, seed=850, io="f32", with_dO=True)
+    W3 = w3_like(x["W1"], 851)
+    et = make_eta_tok(N, H, M, AMU_ETA, 850)
+    big = torch.zeros((N, 4, H, 64), device="cuda")
+    for i, k in enumerate(("Q", "K", "V", "dO")):
+        big[:, i] = torch.from_numpy(x[k]).cuda()
+    Q, K, V, dO = big[:, 0], big[:, 1], big[:, 2], big[:, 3]
+    r = ops().amu_bwd(Q, K, V, torch.from_numpy(et).cuda(), torch.from_numpy(x["W1"]).cuda(),
+                      torch.from_numpy(x["W2"]).cuda(), torch.from_numpy(W3).cuda(), M, dO, sync="chain")
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_swiglu(x["Q"], x["K"], x["V"], x["W1"], x["W2"], W3, et, M, x["dO"], sync="chain")
+    assert r["dQ"].stride() == Q.stride()
+    for k in ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0"):
+        assert rel(host(r[k]), ref[k]) <= TOL["f32"], k
