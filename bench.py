@@ -116,27 +116,33 @@ def run_variant(w, dev_inputs, io, steps, warmup, lib):
 
 
 def time_fn(fn, steps, warmup, lib):
-    """Wall time per call (synchronised) and per-kind kernel times from the
-    library's event instrumentation over the timed calls."""
+    """Wall time per call (synchronised, no instrumentation: the events the
+    library records around every launch cost host time that would inflate
+    launch-heavy forms), then per-kind kernel times from the library's event
+    instrumentation over a separate, shorter run of calls."""
     import ctypes
 
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    lib.ttt_profile_enable(1)
     t0 = time.perf_counter()
     for _ in range(steps):
         out = fn()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    k = max(2, steps // 4)
+    lib.ttt_profile_enable(1)
+    for _ in range(k):
+        fn()
+    torch.cuda.synchronize()
     ms = (ctypes.c_double * 5)()
     n = (ctypes.c_int64 * 5)()
     lib.ttt_profile_read(5, ms, n)
     lib.ttt_profile_enable(0)
     kinds = ["fwd_step", "update", "bwd_step", "bwd_reduce", "bwd_prep"]
-    per = {k: dict(ms_per_call=ms[i] / steps, launches_per_call=n[i] / steps,
-                   avg_launch_us=ms[i] / max(n[i], 1) * 1e3) for i, k in enumerate(kinds) if n[i]}
+    per = {kd: dict(ms_per_call=ms[i] / k, launches_per_call=n[i] / k,
+                    avg_launch_us=ms[i] / max(n[i], 1) * 1e3) for i, kd in enumerate(kinds) if n[i]}
     return (t1 - t0) * 1e3 / steps, per, out
 
 
