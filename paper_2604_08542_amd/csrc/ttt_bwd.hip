@@ -45,7 +45,7 @@ __device__ __forceinline__ T* opaque(T* ptr) {
 #define BWD_F32_NW256 8
 #endif
 
-template <typename IOT, bool BF, int NW, int NB>
+template <typename IOT, int NW, int NB>
 __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   constexpr int HH = NW * 32 * NB;  // hidden size: NW waves x NB 32-wide blocks each
   constexpr int NT = NW * 64;
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   constexpr int TPR = D / EPT;
   constexpr int DH = D * HH;
   constexpr int LD = D + 4;  // f32 [token][d] tiles
-  using MT = std::conditional_t<BF, bf16, float>;
-  constexpr int AS_LD = HH + (BF ? 8 : 4);
+  using MT = float;  // FP32 operands (BF16 operands: ttt_bwd_step_bf)
+  constexpr int AS_LD = HH + 4;
 
   __shared__ __attribute__((aligned(16))) float xs[TT * LD];    // K or Q rows (normalised)
   __shared__ __attribute__((aligned(16))) float vs[TT * LD];    // V rows (normalised)
@@ -112,26 +112,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
   auto th = [&](const float* X, int k, int j) {
     f32x16 c = {};
     const int voff = (int)(((li.hid0 + 32 * j) * D) * sizeof(MT));
-    if constexpr (BF) {
 #pragma unroll 2
-      for (int m = 0; m < 4; ++m) {
-        const int d0 = 16 * m + 8 * li.hf;
-        const f32x4 x0 = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
-        const f32x4 x1 = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0 + 4]);
-        const bf16x8 a = as_bf16x8(pack_bf16x2(x0[0], x0[1]), pack_bf16x2(x0[2], x0[3]),
-                                   pack_bf16x2(x1[0], x1[1]), pack_bf16x2(x1[2], x1[3]));
-        const bf16x8 b = __builtin_bit_cast(bf16x8, bload(voff + d0 * (int)sizeof(MT), k * DH * (int)sizeof(MT)));
-        c = mma32(a, b, c);
-      }
-    } else {
-#pragma unroll 2
-      for (int s4 = 0; s4 < 8; ++s4) {
-        const int d0 = 32 * li.hf + 4 * s4;
-        const f32x4 x = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
-        const f32x4 b = __builtin_bit_cast(f32x4, bload(voff + 128 * li.hf, k * DH * 4 + 16 * s4));
+    for (int s4 = 0; s4 < 8; ++s4) {
+      const int d0 = 32 * li.hf + 4 * s4;
+      const f32x4 x = *reinterpret_cast<const f32x4*>(&X[li.l32 * LD + d0]);
+      const f32x4 b = bload(voff + 128 * li.hf, k * DH * 4 + 16 * s4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) c = mma32(x[e], b[e], c);
-      }
+      for (int e = 0; e < 4; ++e) c = mma32(x[e], b[e], c);
     }
     __builtin_amdgcn_sched_barrier(0);
     return c;
@@ -142,23 +129,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
     f32x4 c = {};
     const int arow = 16 * tb + li.l16, dcol = 16 * db + li.l16;
     const int voff = (int)((dcol * HH + (HH / 4) * li.g4) * sizeof(MT));
-    if constexpr (BF) {
 #pragma unroll 2
-      for (int u = 0; u < HH / 32; ++u) {
-        const int k0 = (HH / 4) * li.g4 + 8 * u;
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&S[arow * AS_LD + k0]);
-        const bf16x8 b = __builtin_bit_cast(bf16x8, bload(voff, k * DH * 2 + 16 * u));
-        c = mma16(a, b, c);
-      }
-    } else {
-#pragma unroll 2
-      for (int u = 0; u < HH / 16; ++u) {
-        const int k0 = (HH / 4) * li.g4 + 4 * u;
-        const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + k0]);
-        const f32x4 b = __builtin_bit_cast(f32x4, bload(voff, k * DH * 4 + 16 * u));
+    for (int u = 0; u < HH / 16; ++u) {
+      const int k0 = (HH / 4) * li.g4 + 4 * u;
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&S[arow * AS_LD + k0]);
+      const f32x4 b = bload(voff, k * DH * 4 + 16 * u);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) c = mma16(a[e], b[e], c);
-      }
+      for (int e = 0; e < 4; ++e) c = mma16(a[e], b[e], c);
     }
     __builtin_amdgcn_sched_barrier(0);
     return c;
@@ -169,42 +146,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_bwd_step(BwdStepArgs p) {
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
       const int dd = 32 * db + li.l32;
-      if constexpr (BF) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          uint32_t aw[4], bw[4];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            aw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, li.hf) * LD + dd], X[c32_row(8 * m + e + 1, li.hf) * LD + dd]);
-            bw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
-          }
-          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) acc[db] = mma32(X[c32_row(s, li.hf) * LD + dd], Yw[s], acc[db]);
-      }
+      for (int s = 0; s < 16; ++s) acc[db] = mma32(X[c32_row(s, li.hf) * LD + dd], Yw[s], acc[db]);
     }
   };
   auto tok_sum_w2 = [&](f32x16 (&acc)[2], const f32x16& Yw, const float* X) {
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
       const int dd = 32 * db + li.l32;
-      if constexpr (BF) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          uint32_t aw[4], bw[4];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            aw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
-            bw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, li.hf) * LD + dd], X[c32_row(8 * m + e + 1, li.hf) * LD + dd]);
-          }
-          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 16; ++s) acc[db] = mma32(Yw[s], X[c32_row(s, li.hf) * LD + dd], acc[db]);
-      }
+      for (int s = 0; s < 16; ++s) acc[db] = mma32(Yw[s], X[c32_row(s, li.hf) * LD + dd], acc[db]);
     }
   };
   auto stage = [&](MT* S, const f32x16& Yw, int j) {
@@ -587,7 +538,7 @@ hipError_t launch_bwd_sum(const BwdSumArgs& a, hipStream_t st) {
 // h=256); BF16 operands: ttt_bwd_step_bf.
 template <int NW, int NB>
 static hipError_t launch_bwd_step_t(const BwdStepArgs& a, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL((ttt_bwd_step<float, false, NW, NB>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  hipLaunchKernelGGL((ttt_bwd_step<float, NW, NB>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
