@@ -365,10 +365,16 @@ def cpu_baseline(w, host_inputs, gpu_out, n_heads):
     for io, out in gpu_out.items():
         O = out["O"][:, sl].float().cpu().numpy().astype(np.float64)
         errs[io] = float(np.linalg.norm(O - ref["O"]) / np.linalg.norm(ref["O"]))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=tok_s, unit="tokens/s", cores=threads, kind="oracle",
                 sample=f"FP64 numpy oracle forward on {n_heads} of {w.n_heads} heads over all "
                        f"{w.n_tokens} tokens ({dt:.1f} s), scaled to all heads",
-                seconds=dt, single_thread=one), errs
+                seconds=dt, single_thread=one, host_cpus=os.cpu_count(), cpu_model=model), errs
 
 
 def main():
