@@ -371,3 +371,34 @@ def amu_bwd(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, dO, *, sync="chain", nor
                          _ptr(dW[2]), _ptr(ws), ws.numel(), _stream(dev))
     L.check(st, "ttt_amu_bwd")
     return dict(dQ=dQ, dK=dK, dV=dV, deta_tok=deta, dW1_0=dW[0], dW2_0=dW[1], dW3_0=dW[2])
+
+
+class AMUChunk(torch.autograd.Function):
+    """O = the paper's memory unit (SwiGLU fast network, dot-product inner
+    loss with token-wise step sizes, chain or GCS) over one sequence,
+    differentiable in (Q, K, V, eta_tok, W1_0, W2_0, W3_0).  The backward
+    recomputes the weights it needs in the HIP reverse-mode kernels (nothing
+    beyond the inputs is saved)."""
+
+    @staticmethod
+    def forward(ctx, Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, sync="chain", norm=True, mma_bf16=False):
+        r = amu_fwd(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, sync=sync, norm=norm, mma_bf16=mma_bf16,
+                    want_final=False)
+        ctx.chunk_tokens, ctx.sync, ctx.norm, ctx.mma_bf16 = chunk_tokens, sync, norm, mma_bf16
+        ctx.save_for_backward(Q, K, V, eta_tok, W1, W2, W3)
+        return r["O"]
+
+    @staticmethod
+    def backward(ctx, dO):
+        Q, K, V, eta_tok, W1, W2, W3 = ctx.saved_tensors
+        if dO.stride() != Q.stride() or dO.dtype != Q.dtype:
+            dO = torch.empty_strided(Q.size(), Q.stride(), dtype=Q.dtype, device=Q.device).copy_(dO)
+        g = amu_bwd(Q, K, V, eta_tok, W1, W2, W3, ctx.chunk_tokens, dO, sync=ctx.sync, norm=ctx.norm,
+                    mma_bf16=ctx.mma_bf16)
+        return (g["dQ"], g["dK"], g["dV"], g["deta_tok"], g["dW1_0"], g["dW2_0"], g["dW3_0"], None, None, None,
+                None)
+
+
+def amu_chunk(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, sync="chain", norm=True, mma_bf16=False):
+    """Differentiable paper memory unit (see AMUChunk)."""
+    return AMUChunk.apply(Q, K, V, eta_tok, W1, W2, W3, chunk_tokens, sync, norm, mma_bf16)

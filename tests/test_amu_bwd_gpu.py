@@ -107,3 +107,21 @@ def test_amu_bwd_strided_views(gpu):
     assert r["dQ"].stride() == Q.stride()
     for k in ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0"):
         assert rel(host(r[k]), ref[k]) <= TOL["f32"], k
+
+
+def test_amu_autograd_function(gpu):
+    """ops.amu_chunk under torch.autograd: the gradients of a scalar loss
+    equal the oracle's reverse mode for dO = d loss / d O."""
+    N, H, h, M = 700, 2, 128, 300
+    x, dev = inputs(N, H, h, seed=860, io="f32", with_dO=True)
+    W3 = w3_like(x["W1"], 861)
+    et = make_eta_tok(N, H, M, AMU_ETA, 860)
+    leaves = [dev["Q"].clone().requires_grad_(), dev["K"].clone().requires_grad_(), dev["V"].clone().requires_grad_(),
+              torch.from_numpy(et).cuda().requires_grad_(), dev["W1"].clone().requires_grad_(),
+              dev["W2"].clone().requires_grad_(), torch.from_numpy(W3).cuda().requires_grad_()]
+    O = ops().amu_chunk(*leaves, M, sync="gcs")
+    (O * dev["dO"]).sum().backward()
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_swiglu(x["Q"], x["K"], x["V"], x["W1"], x["W2"], W3, et, M, x["dO"], sync="gcs")
+    for t, k in zip(leaves, ("dQ", "dK", "dV", "deta_tok", "dW1_0", "dW2_0", "dW3_0")):
+        assert rel(host(t.grad), ref[k]) <= TOL["f32"], k
