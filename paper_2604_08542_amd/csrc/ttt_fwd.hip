@@ -618,9 +618,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
       }
       if constexpr (DO_G) act_grad(zn, apk[P ^ 1], s1h[P ^ 1]);
     };
-    // phase B of iteration `it`
+    // phase B of iteration `it`.  The LDS writes that depend only on
+    // registers (the rows of tile i+2, A of tile i+1) go first: their buffers
+    // are not read in this phase, and issued early their latency overlaps
+    // the products instead of delaying the closing barrier.
     auto phase_b = [&](int it, auto PC) {
       constexpr int P = decltype(PC)::value;
+      stage_rows(it + 2);
+      fetch(it + 3);
+      if constexpr (DO_G) put_a(apk[P ^ 1]);
       f32x16 zq;
       if constexpr (DO_A) zq = zt_block(qs[P ^ 1]);
       if constexpr (DO_G) {
@@ -648,11 +654,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
         for (int db = 0; db < 2; ++db)
 #pragma unroll
           for (int m = 0; m < 2; ++m) gw1[db] = mma32(tok_frag(xs[b3], m, db), dpk[m], gw1[db]);
-        put_a(apk[P ^ 1]);
       }
       if constexpr (DO_A) act_apply_t(zq);
-      stage_rows(it + 2);
-      fetch(it + 3);
     };
 
     // prologue: rows of tiles 0 and 1 staged, activations of tile 0 staged
