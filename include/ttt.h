@@ -167,7 +167,10 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
  * mapped with W*: O = f_{W*}(Q).  Equal to ttt_chunk_fwd when there is one
  * chunk.  Buffers as in ttt_chunk_fwd; W1_T/W2_T receive W* (nullable);
  * loss [H][C] (iff TTT_EMIT_LOSS) holds each chunk's loss at W0.
- * TTT_SAVE_CKPT is not used (the only weights are W0 and W*). */
+ * TTT_SAVE_CKPT is not used (the only weights are W0 and W*).  All chunks'
+ * shard partials of one gradient pass live in the workspace at once, so
+ * chunks x heads may not exceed max(H, 1024): beyond that the call returns
+ * TTT_ENOTSUP with nothing enqueued. */
 ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                          const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
                          float* loss, void* ws, size_t ws_bytes, void* hip_stream);
@@ -175,7 +178,8 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
 /* Backward of ttt_gcs_fwd for sum <O, dO>: the adjoint of W* collects the
  * apply adjoint of every token, each chunk's update adjoint is taken at W0
  * against it, and dW0 = adjoint of W* + the sum of the chunks' terms.
- * Outputs as in ttt_chunk_bwd; W* is recomputed, no checkpoint is needed. */
+ * Outputs as in ttt_chunk_bwd; W* is recomputed, no checkpoint is needed.
+ * Same chunks x heads limit as ttt_gcs_fwd (TTT_ENOTSUP, nothing enqueued). */
 ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                          const float* W1_0, const float* W2_0, const void* dO, void* dQ, void* dK,
                          void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes,
