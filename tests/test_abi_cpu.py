@@ -73,6 +73,8 @@ def test_fwd_validation(lib):
     assert fwd(lib, prob(flags=7 | L.TTT_EMIT_LOSS)) == L.TTT_EINVAL
     assert fwd(lib, prob(), Q=ctypes.c_void_p((1 << 20) + 4)) == L.TTT_EINVAL  # misaligned
     assert fwd(lib, prob(), ws=None) == L.TTT_EWORKSPACE
+    assert fwd(lib, prob(stride_tok=(1 << 22) + 64)) == L.TTT_ESHAPE   # just past the 32-bit tile addressing
+    assert fwd(lib, prob(stride_tok=1 << 22), ws=None) == L.TTT_EWORKSPACE  # the largest stride is accepted
     assert fwd(lib, prob(), nws=16) == L.TTT_EWORKSPACE
     assert fwd(lib, prob(n_tokens=0)) == L.TTT_OK                  # nothing to do, nothing enqueued
 
