@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void ttt_amu_update(AmuUpdArgs p) {
   const int idx = 4 * i4;
   f32x4 s = {0.f, 0.f, 0.f, 0.f};
   const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)head * p.G * 3 * dh) + i4;
-  for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+  s = add_shards(s, part, n4, p.G);
   const int mat = idx / dh, off = idx % dh;
   const float* src = mat == 0 ? p.src.w1 : (mat == 1 ? p.src.w2 : p.src.w3);
   const f32x4 wn = *reinterpret_cast<const f32x4*>(src + (int64_t)head * p.src.stride + off) - s;

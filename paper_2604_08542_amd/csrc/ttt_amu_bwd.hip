@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) void ttt_amu_psum(AmuPsumArgs p) {
   const int64_t hb = (int64_t)head * 3 * dh;
   f32x4 s = p.base ? *reinterpret_cast<const f32x4*>(p.base + hb + idx) : (f32x4){0.f, 0.f, 0.f, 0.f};
   const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)head * p.G * 3 * dh) + i4;
-  for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+  s = add_shards(s, part, n4, p.G);
   if (p.dst) *reinterpret_cast<f32x4*>(p.dst + hb + idx) = s;
   const int mat = idx / dh, off = idx % dh;
   float* out = mat == 0 ? p.out1 : (mat == 1 ? p.out2 : p.out3);

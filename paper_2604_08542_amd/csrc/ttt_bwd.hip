@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void ttt_bwd_reduce(BwdReduceArgs p) {
     f32x4 s = {0.f, 0.f, 0.f, 0.f};
     if (p.wh_src_base) s = *reinterpret_cast<const f32x4*>(p.wh_src_base + cw + idx);
     const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + (int64_t)chain * p.G * 2 * dh) + i4;
-    for (int gg = 0; gg < p.G; ++gg) s += part[(int64_t)gg * n4];
+    s = add_shards(s, part, n4, p.G);
     if (final && !p.fin_base) {
       const int64_t fo = ((int64_t)(p.dst_per_seq ? b : 0) * p.H + head) * dh;
       if (idx < dh)

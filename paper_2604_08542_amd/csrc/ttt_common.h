@@ -58,6 +58,23 @@ __device__ __forceinline__ constexpr int c32_row(int r, int hf) { return 8 * (r 
 
 // ----------------------------------------------------------------- SiLU family
 // sigma(z) from one exp2 and one reciprocal (both hardware transcendentals).
+// s + part[0] + part[stride] + ... + part[(G-1) stride], added one shard at
+// a time in shard order.  The loads of 8 shards are issued before their
+// additions so that they are in flight together; the additions, and so the
+// result, are those of the plain loop.
+__device__ __forceinline__ f32x4 add_shards(f32x4 s, const f32x4* part, int64_t stride, int G) {
+  int gg = 0;
+  for (; gg + 8 <= G; gg += 8) {
+    f32x4 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(gg + q) * stride];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+  }
+  for (; gg < G; ++gg) s += part[(int64_t)gg * stride];
+  return s;
+}
+
 __device__ __forceinline__ float sigmoid(float z) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }

@@ -716,10 +716,21 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
 // Fixed-order reduction of the G shard partials of each active chain and the
 // step W_{s+1} = W_s - eta * grad.  Also writes the checkpoint W_s, the final
 // weights after a sequence's last chunk, and the chunk's inner loss.
+//
+// The shard sums of each float4 of the gradient form four streams (shards
+// q, q+4, q+8, ..., with the shards past the last multiple of 4 appended to
+// stream 0, in order) combined as (s0 + s1) + (s2 + s3).  SPLIT = 1: one lane
+// runs the four streams.  SPLIT = 4: lane q of a quad runs stream q and the
+// sums are combined through two quad exchanges, so each lane has a quarter
+// of the dependent loads in flight; the additions, and the result, are the
+// same.  The split pays when few chains leave most of the GPU idle.  A
+// chain's float4s are spread over SPLIT x as many work-groups as float4s / 256.
+template <int SPLIT>
 __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
+  static_assert(SPLIT == 1 || SPLIT == 4, "one lane or a quad per float4");
   const int dh = D * p.h;
   const int n4 = (2 * dh) / 4;
-  const int nbpc = (n4 + 255) / 256;
+  const int nbpc = SPLIT * ((n4 + 255) / 256);
   const int lin = xcd_linear_block();
   const int slot = lin / nbpc, k = lin % nbpc;
   const bool gcs = p.gcs_chunks > 0;
@@ -728,23 +739,51 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
   if (gl <= 0) return;
   const int chain = gcs ? head : p.seq_id[ai] * p.H + head;
   const int n_ent = gcs ? p.gcs_chunks : 1;
-  const int i4 = k * 256 + threadIdx.x;
+  const int q = SPLIT == 4 ? (threadIdx.x & 3) : 0;
+  const int i4 = SPLIT == 4 ? k * 64 + (threadIdx.x >> 2) : k * 256 + threadIdx.x;  // quad-uniform
   if (i4 < n4) {
-    // fixed order: entries, then shards; four independent partial sums
-    f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0, s3 = s0;
-    for (int e = 0; e < n_ent; ++e) {
-      const int64_t sl = gcs ? (int64_t)e * p.H + head : slot;
-      const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + sl * p.G * 2 * dh) + i4;
-      int gg = 0;
-      for (; gg + 4 <= p.G; gg += 4) {
-        s0 += part[(int64_t)gg * n4];
-        s1 += part[(int64_t)(gg + 1) * n4];
-        s2 += part[(int64_t)(gg + 2) * n4];
-        s3 += part[(int64_t)(gg + 3) * n4];
+    // fixed order: entries, then shards
+    f32x4 s;
+    if constexpr (SPLIT == 4) {
+      f32x4 sq = {0.f, 0.f, 0.f, 0.f};  // stream q
+      const int g4 = p.G & ~3;
+      for (int e = 0; e < n_ent; ++e) {
+        const int64_t sl = gcs ? (int64_t)e * p.H + head : slot;
+        const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + sl * p.G * 2 * dh) + i4;
+        int gg = q;
+        for (; gg + 28 < g4; gg += 32) {  // 8 loads in flight, added in shard order
+          f32x4 v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(gg + 4 * j) * n4];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) sq += v[j];
+        }
+        for (; gg < g4; gg += 4) sq += part[(int64_t)gg * n4];
+        if (q == 0)
+          for (gg = g4; gg < p.G; ++gg) sq += part[(int64_t)gg * n4];
       }
-      for (; gg < p.G; ++gg) s0 += part[(int64_t)gg * n4];
+      f32x4 t;  // lanes 0 and 2: s0 + s1 and s2 + s3
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] = sq[c] + __shfl_xor(sq[c], 1, 64);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[c] = t[c] + __shfl_xor(t[c], 2, 64);  // lane 0
+      if (q != 0) return;
+    } else {
+      f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0, s3 = s0;
+      for (int e = 0; e < n_ent; ++e) {
+        const int64_t sl = gcs ? (int64_t)e * p.H + head : slot;
+        const f32x4* part = reinterpret_cast<const f32x4*>(p.partial + sl * p.G * 2 * dh) + i4;
+        int gg = 0;
+        for (; gg + 4 <= p.G; gg += 4) {
+          s0 += part[(int64_t)gg * n4];
+          s1 += part[(int64_t)(gg + 1) * n4];
+          s2 += part[(int64_t)(gg + 2) * n4];
+          s3 += part[(int64_t)(gg + 3) * n4];
+        }
+        for (; gg < p.G; ++gg) s0 += part[(int64_t)gg * n4];
+      }
+      s = (s0 + s1) + (s2 + s3);
     }
-    const f32x4 s = (s0 + s1) + (s2 + s3);
     const int idx = 4 * i4;
     const int64_t wc = (int64_t)(chain % p.w_mod) * p.w_cstride;
     const f32x4 wv = idx < dh ? *reinterpret_cast<const f32x4*>(p.w1_src + wc + idx)
@@ -792,7 +831,12 @@ hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf
 }
 
 hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL(ttt_update, dim3(n_blocks), dim3(256), 0, st, a);
+  // n_blocks = active chains x float4s / 256; below one work-group per CU
+  // the quad split spreads the reduction over four times as many
+  if (n_blocks < 256)
+    hipLaunchKernelGGL(ttt_update<4>, dim3(4 * n_blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(ttt_update<1>, dim3(n_blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
