@@ -51,7 +51,7 @@ typedef enum {
   TTT_ESHAPE = 2,      /* unsupported d / h / strides */
   TTT_EWORKSPACE = 3,  /* workspace missing or smaller than ttt_workspace_bytes */
   TTT_EHIP = 4,        /* a HIP launch failed */
-  TTT_ENOTSUP = 5      /* valid request this build does not implement */
+  TTT_ENOTSUP = 5      /* valid request this library does not implement */
 } ttt_status_t;
 
 typedef enum { TTT_F32 = 0, TTT_BF16 = 1 } ttt_dtype_t;
