@@ -149,38 +149,53 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
     }
   };
   // Rows [t0, t0+nv) of a token tensor into an f32 LDS tile (zeros beyond
-  // nv), optionally L2-normalised, optionally scaled by -eta_i.
-  auto load_rows = [&](const void* base, int64_t t0, int nv, float* dst, bool do_norm, bool times_eta) {
+  // nv), optionally L2-normalised, optionally scaled by -eta_i: fetched into
+  // registers one tile ahead (fetch_rows), written to LDS when the tile
+  // starts (stage_rows), so the global-load latency overlaps a tile's work.
+  struct RawRows {
     float x[EPT];
+    float et;  // eta_i of this thread's row (0 past nv)
+  };
+  auto fetch_rows = [&](const void* base, int64_t t0, int nv, bool times_eta, RawRows& r) {
     const bool valid = row < nv;
     if (valid) {
-      load_vec<IOT, EPT>(static_cast<const IOT*>(base) + (t0 + row) * p.stride_tok + hoff + col0, x);
+      load_vec<IOT, EPT>(static_cast<const IOT*>(base) + (t0 + row) * p.stride_tok + hoff + col0, r.x);
     } else {
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) x[i] = 0.f;
+      for (int i = 0; i < EPT; ++i) r.x[i] = 0.f;
     }
+    r.et = (times_eta && valid) ? p.eta_tok[(t0 + row) * p.H + head] : 0.f;
+  };
+  auto stage_rows = [&](const RawRows& r, float* dst, bool do_norm, bool times_eta) {
     float scale = 1.f;
     if (do_norm) {
       float ss = 0.f;
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) ss = fmaf(x[i], x[i], ss);
+      for (int i = 0; i < EPT; ++i) ss = fmaf(r.x[i], r.x[i], ss);
       ss = lane_group_sum<TPR>(ss);
       scale = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
     }
-    if (times_eta) scale *= valid ? -p.eta_tok[(t0 + row) * p.H + head] : 0.f;
+    if (times_eta) scale *= -r.et;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) dst[row * LD + col0 + i] = x[i] * scale;
+    for (int i = 0; i < EPT; ++i) dst[row * LD + col0 + i] = r.x[i] * scale;
   };
 
   f32x16 g1[2] = {}, g2[2] = {}, g3[2] = {};
 
   // ------------------------------------------------ gradient of chunk s
   const int gl = p.grad_len;
-  for (int t = g; t * TT < gl; t += G) {
+  RawRows rk, rv;
+  auto fetch_grad = [&](int t) {
     const int64_t t0 = p.grad_start + (int64_t)t * TT;
     const int nv = min(TT, gl - t * TT);
-    load_rows(p.K, t0, nv, xs, norm_k, false);
-    load_rows(p.V, t0, nv, es, norm_v, true);
+    fetch_rows(p.K, t0, nv, false, rk);
+    fetch_rows(p.V, t0, nv, true, rv);
+  };
+  if (g * TT < gl) fetch_grad(g);
+  for (int t = g; t * TT < gl; t += G) {
+    stage_rows(rk, xs, norm_k, false);
+    stage_rows(rv, es, norm_v, true);
+    if ((t + G) * TT < gl) fetch_grad(t + G);
     __syncthreads();
     const f32x16 Z1 = th(xs, W1t);
     const f32x16 Z3 = th(xs, W3t);
@@ -203,10 +218,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
 
   // ------------------------------------------------ apply of chunk s-1
   const int al = p.app_len;
+  RawRows rq;
+  auto fetch_app = [&](int t) {
+    fetch_rows(p.Q, p.app_start + (int64_t)t * TT, min(TT, al - t * TT), false, rq);
+  };
+  if (g * TT < al) fetch_app(g);
   for (int t = g; t * TT < al; t += G) {
     const int64_t t0 = p.app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
-    load_rows(p.Q, t0, nv, xs, norm_q, false);
+    stage_rows(rq, xs, norm_q, false);
+    if ((t + G) * TT < al) fetch_app(t + G);
     __syncthreads();
     {
       const f32x16 Zq1 = th(xs, W1t);
