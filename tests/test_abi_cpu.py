@@ -193,3 +193,24 @@ def test_gcs_chunk_slot_limit(lib):
                            None) == L.TTT_ENOTSUP
     assert lib.ttt_gcs_bwd(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
                            FAKE, 1 << 40, None) == L.TTT_ENOTSUP
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # a fresh interpreter: the loader raises instead of falling back to anything else
+    import subprocess
+    import sys
+    code = ("from paper_2604_08542_amd import _lib\n"
+            f"_lib.load({str(tmp_path / 'absent' / 'libttt_hip.so')!r})\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "not built" in r.stderr
+
+
+def test_product_never_touches_the_oracle():
+    # the oracle is test infrastructure: nothing in the package or the C ABI refers to it
+    pkg = os.path.join(ROOT, "paper_2604_08542_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b", src), os.path.join(dirpath, f)
+    assert not re.search(r"\boracle\b", open(os.path.join(ROOT, "include", "ttt.h")).read())
