@@ -21,12 +21,12 @@ def w3_like(W1, seed):
     return (np.random.default_rng(seed).standard_normal(W1.shape) / np.sqrt(W1.shape[-2])).astype(np.float32)
 
 
-def run_case(N, H, h, M, eta, io, sync, seed):
+def run_case(N, H, h, M, eta, io, sync, seed, mma=False):
     x, dev = inputs(N, H, h, seed=seed, io=io)
     W3 = w3_like(x["W1"], seed + 1)
     et = make_eta_tok(N, H, M, eta, seed)
     r = ops().amu_fwd(dev["Q"], dev["K"], dev["V"], torch.from_numpy(et).cuda(), dev["W1"], dev["W2"],
-                      torch.from_numpy(W3).cuda(), M, sync=sync)
+                      torch.from_numpy(W3).cuda(), M, sync=sync, mma_bf16=mma)
     torch.cuda.synchronize()
     ref = orc.ttt_forward_swiglu(x["Q"], x["K"], x["V"], x["W1"], x["W2"], W3, et, M, sync=sync)
     W0 = dict(W1_T=x["W1"], W2_T=x["W2"], W3_T=W3)
@@ -48,6 +48,8 @@ CASES = [
     (96, 1, 128, 40, 20.0, "f32", "chain"),
     (1000, 2, 256, 333, 20.0, "bf16", "chain"),
     (2748, 1, 128, 1374, 20.0, "bf16", "gcs"),
+    (1100, 2, 256, 400, 20.0, "f32", "gcs"),
+    (1000, 2, 256, 500, 20.0, "bf16", "gcs"),
 ]
 
 
@@ -57,6 +59,15 @@ def test_amu_matches_oracle(gpu, N, H, h, M, eta, io, sync):
     print(f"amu N={N} H={H} h={h} M={M} {io} {sync}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= TOL[io], (k, v)
+
+
+@pytest.mark.parametrize("sync", ["chain", "gcs"])
+def test_amu_bf16_operands_f32_tokens(gpu, sync):
+    # FP32 token tensors with BF16 matrix-core operands (FP32 accumulation)
+    errs, _, _ = run_case(1000, 2, 256, 333, AMU_ETA, "f32", sync, seed=901, mma=True)
+    print(f"amu f32 io, bf16 operands, {sync}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL["bf16"], (k, v)
 
 
 def test_amu_one_chunk_chain_equals_gcs(gpu):
