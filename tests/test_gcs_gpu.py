@@ -47,3 +47,19 @@ def test_gcs_backward(gpu, N, H, h, M, eta, io):
     print(f"gcs bwd N={N} H={H} h={h} M={M} {io}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= TOL[io], (k, v)
+
+
+def test_gcs_bf16_operands_f32_tokens(gpu):
+    """FP32 token tensors with BF16 matrix-core operands, forward and reverse mode."""
+    N, H, h, M, eta = 1200, 2, 256, 400, 0.05
+    x, d = inputs(N, H, h, seed=377, io="f32", with_dO=True)
+    r = ops().gcs_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, mma_bf16=True)
+    g = ops().gcs_bwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, d["dO"], mma_bf16=True)
+    torch.cuda.synchronize()
+    ref = orc.ttt_forward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M)
+    refb = orc.ttt_backward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M, x["dO"])
+    errs = dict(O=rel(host(r["O"]), ref["O"]), W1_T=rel(host(r["W1_T"]), ref["W1_T"]))
+    errs.update({k: rel(host(g[k]), refb[k]) for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0", "deta")})
+    print("gcs f32 io, bf16 operands: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL["bf16"], (k, v)
