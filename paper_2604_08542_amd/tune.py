@@ -6,8 +6,8 @@ For one workload it times the batched forward for each candidate launch shape
 (total work-groups aimed for per chunk step, or a fixed number of
 work-groups per chain), keeps the fastest, and records it in
 tuned_tiles.json under a key made of (hidden size, io dtype, chunk tokens,
-chains).  ops.batched_fwd and ops.chunk_fwd use the recorded shape when the
-caller passes none.
+chains).  ops.batched_fwd uses the recorded shape when the caller passes
+none.
 """
 from __future__ import annotations
 
