@@ -111,10 +111,10 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
 
 
-def _tile_cfg(tile_cfg, Q, h, chunk_tokens, n_chains):
+def _tile_cfg(tile_cfg, Q, h, chunk_tokens, n_chains, kind="fwd"):
     if tile_cfg is None:
         from .tune import lookup
-        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), n_chains)
+        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), n_chains, kind)
     if tile_cfg is None:
         return None
     return L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
@@ -191,10 +191,8 @@ def batched_bwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, c
     dW2 = torch.empty_like(W2)
     deta = torch.empty((H,), dtype=torch.float32, device=dev)
     cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
-    # the tuned table holds forward launch shapes; the backward takes an
-    # explicit shape or the library's heuristic
-    cfg = None if tile_cfg is None else L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)),
-                                                  int(tile_cfg.get("target_wgs", 0)))
+    # an explicit shape, else the tuned backward shape, else the library's heuristic
+    cfg = _tile_cfg(tile_cfg, Q, h, chunk_tokens, B * H, "bwd")
     if ws is None:
         ws = workspace(prob, B, dev)
     st = lib.ttt_batched_bwd(ctypes.byref(prob), B, cu_arr, _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2),

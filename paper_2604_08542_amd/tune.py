@@ -1,13 +1,14 @@
-"""Launch-shape autotuner for the chunked TTT forward.
+"""Launch-shape autotuner for the chunked TTT forward and backward.
 
-    python -m paper_2604_08542_amd.tune --workload batch8_uneven_chunk8f_bf16
+    python -m paper_2604_08542_amd.tune --workload batch8_uneven_chunk8f_bf16 [--backward]
 
-For one workload it times the batched forward for each candidate launch shape
-(total work-groups aimed for per chunk step, or a fixed number of
-work-groups per chain), keeps the fastest, and records it in
-tuned_tiles.json under a key made of (hidden size, io dtype, chunk tokens,
-chains).  ops.batched_fwd uses the recorded shape when the caller passes
-none.
+For one workload it times the batched forward (or, with --backward, the
+batched backward) for each candidate launch shape (total work-groups aimed
+for per chunk step, or a fixed number of work-groups per chain), keeps the
+fastest, and records it in tuned_tiles.json under a key made of (hidden
+size, io dtype, chunk tokens, chains, and "_bwd" for the backward).
+ops.batched_fwd / ops.batched_bwd use the recorded shape when the caller
+passes none.
 """
 from __future__ import annotations
 
@@ -20,8 +21,8 @@ import time
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
 
 
-def key(h: int, io: str, chunk_tokens: int, n_chains: int) -> str:
-    return f"h{h}_{io}_m{chunk_tokens}_c{n_chains}"
+def key(h: int, io: str, chunk_tokens: int, n_chains: int, kind: str = "fwd") -> str:
+    return f"h{h}_{io}_m{chunk_tokens}_c{n_chains}" + ("_bwd" if kind == "bwd" else "")
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -31,16 +32,16 @@ def load_table(path: str = TABLE) -> dict:
         return json.load(f)
 
 
-def lookup(h: int, io: str, chunk_tokens: int, n_chains: int, table=None):
+def lookup(h: int, io: str, chunk_tokens: int, n_chains: int, kind: str = "fwd", table=None):
     t = load_table() if table is None else table
-    return t.get(key(h, io, chunk_tokens, n_chains), {}).get("tile_cfg")
+    return t.get(key(h, io, chunk_tokens, n_chains, kind), {}).get("tile_cfg")
 
 
 CANDIDATES = [dict(target_wgs=t) for t in (128, 256, 384, 512, 768, 1024)] + \
              [dict(wg_per_chain=g) for g in (1, 2, 4, 8, 16, 32)]
 
 
-def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: bool = True):
+def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: bool = True, backward: bool = False):
     import torch
 
     from . import ops
@@ -48,16 +49,24 @@ def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: boo
     from workloads import WORKLOADS, make_inputs_torch
     w = WORKLOADS[workload]
     io = io or w.io_dtype
-    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=seed, io_dtype=io)
+    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=seed, io_dtype=io, with_dO=backward)
     cu = w.cu_seqlens()
     O = torch.empty_like(dev["Q"])
     prob = ops.problem(dev["Q"], w.d_hidden, 0, w.chunk_tokens, w.eta, ops._flags(True))
     ws = ops.workspace(prob, len(cu) - 1, dev["Q"].device)
+    ckpt = None
+    if backward:  # the backward needs the forward's checkpoints (default shape)
+        ckpt = ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                               save_ckpt=True, want_final=False)["ckpt"]
     results = []
     for cfg in CANDIDATES:
         def run():
-            ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
-                            tile_cfg=cfg, out=O, ws=ws, want_final=False)
+            if backward:
+                ops.batched_bwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens, ckpt,
+                                dev["dO"], tile_cfg=cfg)
+            else:
+                ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                tile_cfg=cfg, out=O, ws=ws, want_final=False)
         run()
         torch.cuda.synchronize()
         st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -71,7 +80,7 @@ def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: boo
         print(f"  {cfg}: {ms:.3f} ms", flush=True)
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
-    k = key(w.d_hidden, io, w.chunk_tokens, w.n_heads * len(w.frames))
+    k = key(w.d_hidden, io, w.chunk_tokens, w.n_heads * len(w.frames), "bwd" if backward else "fwd")
     entry = dict(tile_cfg=best, ms=best_ms, workload=workload, tuned_at=time.strftime("%Y-%m-%d"),
                  candidates={json.dumps(c): m for m, c in results})
     if write:
@@ -88,6 +97,7 @@ if __name__ == "__main__":
     ap.add_argument("--workload", action="append", required=True)
     ap.add_argument("--io", default=None)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--backward", action="store_true", help="tune the batched backward instead of the forward")
     a = ap.parse_args()
     for wl in a.workload:
-        tune(wl, a.io, a.reps)
+        tune(wl, a.io, a.reps, backward=a.backward)
