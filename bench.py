@@ -1,18 +1,29 @@
 """Benchmark of the chunked TTT hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 
-A step is one whole forward (every chunk update and apply of every head) over
-the workload's synthetic token stream, inputs resident in HBM.  The default
-workload is 16 heads x 64, fast-MLP hidden 256, 64 frames x 1374 tokens,
-chunks of 8 frames, eta 0.05, FP32 (the plain path); the BF16-operand path on
-the same workload is timed beside it.  Prints one JSON line.
+A step is one whole forward (every chunk update and apply of every head of
+every sequence) over the headline workload: 8 sequences of uneven length
+(12, 24, 40, 64, 96, 128, 200, 300 frames x 1374 tokens, 1,187,136 tokens),
+16 heads x 64, fast-MLP hidden 256, chunks of 8 frames (10,992 tokens, each
+sequence's last chunk ragged where its length is not a multiple), eta 0.05,
+BF16 operands with FP32 accumulation and FP32 fast weights.  Inputs are
+synthetic and resident in HBM before the timed region.  The FP32 path on the
+same workload, the other forms (single-sequence layer, single-head chains,
+forward + backward, GCS, the paper's memory unit, the length sweep) and the
+FP64 oracle timed on the host cores are reported beside it.  Prints one JSON
+line.
+
+Every time is taken with HIP events on the stream the library launches on
+(torch's current stream), around whole library calls, after warm-up.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -21,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TTT fwd / fwd+bwd tokens/s, BF16 vs FP32 at stated error vs FP64 oracle"
 PEAK = {"f32": 157.3, "bf16": 2516.6}   # dense matrix-core TFLOP/s (MI355X)
+HEADLINE = "batch8_uneven_chunk8f_bf16"
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttt_fwd_persist_batch8_uneven_hbm_counters.md")
 
 
 def parse():
@@ -28,41 +41,52 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="layer16_64f_chunk8f")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-heads", type=int, default=16)
-    ap.add_argument("--variants", default="f32,bf16", help="comma list of operand paths to time")
-    ap.add_argument("--no-extra", action="store_true", help="skip the GCS / fwd+bwd / batched forms")
-    ap.add_argument("--forms", default="gcs,fwd_bwd,batched_fwd,batched_fwd_bwd,amu,single_head,length_sweep",
-                    help="comma list of the other forms to time (gcs, fwd_bwd, batched_fwd, batched_fwd_bwd, amu, "
-                         "single_head, length_sweep)")
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a plain 512 MiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--quick", action="store_true", help="headline only (no other forms, no oracle timings)")
+    ap.add_argument("--forms", default="layer,stepwise,single_head,fwd_bwd,batched_fwd_bwd,gcs,amu,length_sweep",
+                    help="comma list of the other forms to time")
     return ap.parse_args()
 
 
-def alg_flops(w):
-    # forward: 10*d*h per token-head for the update chain + 4*d*h for the apply
-    return 14.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads
+def fwd_flops(d, h, tokens, heads):
+    # 10 d h per token-head for the update chain (K W1, A W2, E W2^T and the
+    # two token sums) + 4 d h for the apply (Q W1, A W2)
+    return 14.0 * d * h * tokens * heads
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttt_fwd_step_layer16_64f_hbm_counters.md")
+def timed(fn, steps, warmup):
+    """Milliseconds per call: HIP events on the current stream around `steps`
+    calls after `warmup` calls, bracketed by device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.record()
+    for _ in range(steps):
+        fn()
+    en.record()
+    torch.cuda.synchronize()
+    return st.elapsed_time(en) / steps
 
 
-def measured_traffic(io, workload):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration),
-    or None when that summary is for other kernel sources or another
-    workload."""
-    import hashlib
-    if workload != "layer16_64f_chunk8f" or not os.path.exists(TRAFFIC_PROFILE):
-        return None
+def sources_hash():
     h = hashlib.sha256()
     for f in ("ttt_fwd.hip", "ttt_common.h"):
         with open(os.path.join(ROOT, "paper_2604_08542_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(io):
+    """HBM bytes per launch of the persistent forward kernel on the headline
+    workload, from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE scaled by the copy-kernel calibration), or None when that
+    summary was taken for other kernel sources."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
     text = open(TRAFFIC_PROFILE).read()
-    if f"ttt_fwd.hip+ttt_common.h: {h.hexdigest()[:16]}" not in text:
+    if f"ttt_fwd.hip+ttt_common.h: {sources_hash()}" not in text:
         return None
     for line in text.splitlines():
         if line.startswith(f"traffic_per_launch_bytes {io} = "):
@@ -70,385 +94,285 @@ def measured_traffic(io, workload):
     return None
 
 
-def run_variant(w, dev_inputs, io, steps, warmup, lib):
-    import ctypes
-
-    import torch
-
-    from paper_2604_08542_amd import ops
-    dt = torch.float32 if io == "f32" else torch.bfloat16
-    Q, K, V = (dev_inputs[n].to(dt) for n in ("Q", "K", "V"))
-    W1, W2 = dev_inputs["W1"], dev_inputs["W2"]
-    cu = w.cu_seqlens()
-    O = torch.empty_like(Q)
-    prob = ops.problem(Q, w.d_hidden, 0, w.chunk_tokens, w.eta, ops._flags(True))
-    ws = ops.workspace(prob, len(cu) - 1, Q.device)
-
-    def step():
-        return ops.batched_fwd(Q, K, V, cu, W1, W2, w.eta, w.chunk_tokens, out=O, ws=ws)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    lib.ttt_profile_enable(2)  # events around the chunk-step kernels only (the roofline kernel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        r = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
-    lib.ttt_profile_read(4, ms, n)
-    lib.ttt_profile_enable(0)
-    ms_step = (t1 - t0) * 1e3 / steps
-    kern_ms_per_pass = ms[0] / steps
-    achieved = alg_flops(w) / (kern_ms_per_pass * 1e-3) / 1e12
-    return dict(
-        io=io, ms_per_step=ms_step, tokens_per_s=w.n_tokens / (ms_step * 1e-3),
-        step_kernel=dict(launches_per_pass=n[0] / steps, avg_launch_us=ms[0] / max(n[0], 1) * 1e3,
-                         ms_per_pass=kern_ms_per_pass),
-        roofline=dict(bound="mfma", achieved=achieved, peak=PEAK[io], unit="TFLOP/s",
-                      frac=achieved / PEAK[io], traffic=measured_traffic(io, w.name),
-                      traffic_unit="HBM bytes per step-kernel launch"),
-        out=r,
-    )
-
-
-def time_fn(fn, steps, warmup, lib):
-    """Wall time per call (synchronised, no instrumentation: the events the
-    library records around every launch cost host time that would inflate
-    launch-heavy forms), then per-kind kernel times from the library's event
-    instrumentation over a separate, shorter run of calls."""
-    import ctypes
-
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = fn()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k = max(2, steps // 4)
-    lib.ttt_profile_enable(1)
-    for _ in range(k):
-        fn()
-    torch.cuda.synchronize()
-    ms = (ctypes.c_double * 5)()
-    n = (ctypes.c_int64 * 5)()
-    lib.ttt_profile_read(5, ms, n)
-    lib.ttt_profile_enable(0)
-    kinds = ["fwd_step", "update", "bwd_step", "bwd_reduce", "bwd_prep"]
-    per = {kd: dict(ms_per_call=ms[i] / k, launches_per_call=n[i] / k,
-                    avg_launch_us=ms[i] / max(n[i], 1) * 1e3) for i, kd in enumerate(kinds) if n[i]}
-    return (t1 - t0) * 1e3 / steps, per, out
-
-
-def length_sweep(steps, warmup, lib, frames=(150, 270, 510, 990)):
-    """One sequence of F frames x 1374 tokens, 16 heads x 64, h = 256,
-    chunks of 8 frames, BF16 operands, for F in `frames` (the layer shape at
-    growing sequence length): with every chunk step filling the chip,
-    tokens/s should not depend on the length."""
+def forward_form(w, io, steps, warmup, cfg=None, dev=None):
+    """Batched forward of workload w on the io path; returns timing, roofline
+    and the output tensor."""
     import torch
 
     from paper_2604_08542_amd import ops
     from workloads import make_inputs_torch
-    H, d, h, M, eta = 16, 64, 256, 8 * 1374, 0.05
-    rows = {}
-    for f in frames:
-        n = f * 1374
-        dev = make_inputs_torch(n, H, d, h, seed=0, io_dtype="bf16")
-        O = torch.empty_like(dev["Q"])
-        ms, per, _ = time_fn(lambda: ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], eta, M, out=O,
-                                                   want_final=False), max(2, steps // 4), max(1, warmup // 2), lib)
-        kms = per["fwd_step"]["ms_per_call"]
-        ach = 14.0 * d * h * n * H / (kms * 1e-3) / 1e12
-        rows[str(f)] = dict(tokens=n, chunks=-(-n // M), ms_per_step=ms, tokens_per_s=n / (ms * 1e-3),
-                            step_kernel_tflops=ach, frac_bf16_peak=ach / PEAK["bf16"])
-        del dev, O
-        torch.cuda.empty_cache()
-    tps = [r["tokens_per_s"] for r in rows.values()]
-    return dict(workload="one sequence, 16x64, h256, chunk 8 frames, bf16", frames=rows,
-                tokens_per_s_max_over_min=max(tps) / min(tps))
+    if dev is None:
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
+    cu = w.cu_seqlens()
+    O = torch.empty_like(dev["Q"])
+    prob = ops.problem(dev["Q"], w.d_hidden, 0, w.chunk_tokens, w.eta, ops._flags(True))
+    ws = ops.workspace(prob, len(cu) - 1, dev["Q"].device)
+
+    def step():
+        ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens, out=O, ws=ws,
+                        want_final=False, tile_cfg=cfg)
+    ms = timed(step, steps, warmup)
+    status = ops.workspace_status(ws)
+    ach = fwd_flops(w.d_head, w.d_hidden, w.n_tokens, w.n_heads) / (ms * 1e-3) / 1e12
+    return dict(workload=w.name, io=io, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                device_error_word=status,
+                roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io], unit="TFLOP/s", frac=ach / PEAK[io])), O, dev
 
 
-def extra_variants(steps, warmup, lib, forms=("gcs", "fwd_bwd", "batched_fwd", "batched_fwd_bwd", "amu",
-                                             "single_head", "length_sweep")):
-    """The other forms on their own workloads: GCS forward (same layer
-    workload), forward+backward (differentiation workload), batched forward
-    (8 uneven sequences)."""
+def other_forms(forms, steps, warmup):
     import torch
 
     from paper_2604_08542_amd import ops
-    from workloads import WORKLOADS, make_inputs_torch
+    from workloads import WORKLOADS, make_eta_tok, make_inputs_torch
     res = {}
-    if "length_sweep" in forms:
-        res["length_sweep_bf16"] = length_sweep(steps, warmup, lib)
-    # GCS forward on the layer workload, BF16 and FP32 operands
-    w = WORKLOADS["layer16_64f_chunk8f"]
-    for io in (("bf16", "f32") if "gcs" in forms else ()):
-        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
-        ms, per, _ = time_fn(lambda: ops.gcs_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta,
-                                                 w.chunk_tokens), steps, warmup, lib)
-        kms = per["fwd_step"]["ms_per_call"]
-        ach = alg_flops(w) / (kms * 1e-3) / 1e12
-        res[f"gcs_fwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                    kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
-                                                               unit="TFLOP/s", frac=ach / PEAK[io]))
-        del dev
-    # the paper's memory unit (SwiGLU, dot-product loss, token-wise steps) on the layer workload
-    for io in (("bf16", "f32") if "amu" in forms else ()):
-        from workloads import make_eta_tok
-        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
-        g = torch.Generator(device="cuda")
-        g.manual_seed(1)
-        W3 = torch.randn(dev["W1"].shape, generator=g, device="cuda") / float(w.d_head) ** 0.5
-        et = torch.from_numpy(make_eta_tok(w.n_tokens, w.n_heads, w.chunk_tokens, 20.0, 0)).cuda()
-        O = torch.empty_like(dev["Q"])
-        for sync in ("chain", "gcs"):
-            ms, per, _ = time_fn(lambda: ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3,
-                                                     w.chunk_tokens, sync=sync, want_final=False, out=O),
-                                 steps, warmup, lib)
-            kms = per["fwd_step"]["ms_per_call"]
-            # 12 d h per token-head for the update (K W1, K W3, E W2^T, three token sums) + 6 d h apply
-            ach = 18.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (kms * 1e-3) / 1e12
-            res[f"amu_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                           kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
-                                                                      unit="TFLOP/s", frac=ach / PEAK[io]))
-            # forward + reverse mode (the backward recomputes the weights it needs)
-            dO = torch.randn(dev["Q"].shape, generator=g, device="cuda").to(dev["Q"].dtype)
+    few = max(2, steps // 4)
+    if "layer" in forms:  # one sequence of 64 frames: the BF16 / FP32 speed-up
+        w = WORKLOADS["layer16_64f_chunk8f"]
+        for io in ("f32", "bf16"):
+            r, _, _ = forward_form(w, io, steps, warmup)
+            res[f"layer16_64f_{io}"] = r
+        res["layer16_64f_speedup_bf16_over_f32"] = (res["layer16_64f_f32"]["ms_per_step"] /
+                                                    res["layer16_64f_bf16"]["ms_per_step"])
+    if "stepwise" in forms:  # the same forwards with one step + one update launch per chunk step
+        for name in ("layer16_64f_chunk8f", HEADLINE):
+            w = WORKLOADS[name]
+            r, _, _ = forward_form(w, "bf16", few, 2, cfg=dict(schedule="stepwise", wg_per_chain=16))
+            res[f"stepwise_{name}_bf16"] = r
+    if "single_head" in forms:  # single-head chains: latency-bound
+        for name, io in (("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16")):
+            w = WORKLOADS[name]
+            r, _, _ = forward_form(w, io, steps, warmup)
+            r["roofline"]["bound"] = "latency (one chain, serial in its chunks)"
+            res[f"{name}_{io}" if not name.endswith(io) else name] = r
+    if "fwd_bwd" in forms:  # forward with checkpoints + backward through every inner update
+        w = WORKLOADS["layer16_32f_chunk4f_bwd"]
+        for io in ("f32", "bf16"):
+            dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io, with_dO=True)
 
             def fb():
-                ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens, sync=sync,
-                            want_final=False, out=O)
-                return ops.amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens, dO,
-                                   sync=sync)
-            ms, per, _ = time_fn(fb, max(2, steps // 2), 1, lib)
-            bk = per["bwd_step"]
-            res[f"amu_fwd_bwd_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms,
-                                                   tokens_per_s=w.n_tokens / (ms * 1e-3), kernels=per,
-                                                   bwd_kernels_ms=bk["ms_per_call"])
-            del dO
-        del dev, O, W3, et
-    # single-head chains: 4 chunks x 1374 tokens (FP32) and 256 chunks x 1374 tokens (BF16, precision form)
-    for name, io in ((("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16"))
-                     if "single_head" in forms else ()):
-        ws_ = WORKLOADS[name]
-        dev = make_inputs_torch(ws_.n_tokens, ws_.n_heads, ws_.d_head, ws_.d_hidden, seed=0, io_dtype=io)
-        O = torch.empty_like(dev["Q"])
-        ms, per, _ = time_fn(lambda: ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], ws_.eta,
-                                                   ws_.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
-        kms = per["fwd_step"]["ms_per_call"]
-        ach = alg_flops(ws_) / (kms * 1e-3) / 1e12
-        key = name if name.endswith(io) else f"{name}_{io}"
-        res[key] = dict(workload=name, ms_per_step=ms, tokens_per_s=ws_.n_tokens / (ms * 1e-3),
-                                   kernels=per, roofline=dict(bound="latency (one chain)", achieved=ach,
-                                                              peak=PEAK[io], unit="TFLOP/s", frac=ach / PEAK[io]))
-        # the same pass replayed from a captured HIP graph (no host launch cost per chunk step)
-        prob = ops.problem(dev["Q"], ws_.d_hidden, ws_.n_tokens, ws_.chunk_tokens, ws_.eta, ops._flags(True))
-        wsb = ops.workspace(prob, 1, dev["Q"].device)
+                f = ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                  save_ckpt=True, want_final=False)
+                ops.chunk_bwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens, f["ckpt"],
+                              dev["dO"])
+            ms = timed(fb, few, 1)
+            ach = 3.0 * fwd_flops(w.d_head, w.d_hidden, w.n_tokens, w.n_heads) / (ms * 1e-3) / 1e12
+            res[f"fwd_bwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                        pass_roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
+                                                           unit="TFLOP/s (42 d h per token-head, whole pass)",
+                                                           frac=ach / PEAK[io]))
+            del dev
+    if "batched_fwd_bwd" in forms:
+        w = WORKLOADS[HEADLINE]
+        cu = w.cu_seqlens()
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16", with_dO=True)
 
-        def one():
-            ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], ws_.eta, ws_.chunk_tokens, out=O,
-                          want_final=False, ws=wsb)
-        one()
-        torch.cuda.synchronize()
-        ref = O.clone()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=side):
-            one()
-        torch.cuda.synchronize()
-        O.zero_()
-        graph.replay()
-        torch.cuda.synchronize()
-        same = bool(torch.equal(O, ref))
-        for _ in range(warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        gms = (time.perf_counter() - t0) * 1e3 / steps
-        res[key].update(graph_ms_per_step=gms, graph_tokens_per_s=ws_.n_tokens / (gms * 1e-3),
-                                   graph_replay_matches_eager=same)
-        del dev, O, graph, wsb
-    # forward + backward on the differentiation workload
-    w = WORKLOADS["layer16_32f_chunk4f_bwd"]
-    for io in (("bf16", "f32") if "fwd_bwd" in forms else ()):
-        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io, with_dO=True)
-
-        def fb():
-            f = ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
-                              save_ckpt=True, want_final=False)
-            return ops.chunk_bwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
-                                 f["ckpt"], dev["dO"])
-        ms, per, _ = time_fn(fb, max(2, steps // 2), 1, lib)
-        # algorithmic: forward 14 d h + backward 28 d h per token-head
-        fl = 42.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads
-        bms = per["bwd_step"]["ms_per_call"]
-        bach = 28.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (bms * 1e-3) / 1e12
-        res[f"fwd_bwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                    alg_tflops_per_s=fl / (ms * 1e-3) / 1e12, kernels=per,
-                                    bwd_step_roofline=dict(bound="mfma", achieved=bach, peak=PEAK[io],
-                                                           unit="TFLOP/s", frac=bach / PEAK[io]))
+        def bfb():
+            f = ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                save_ckpt=True, want_final=False)
+            ops.batched_bwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens, f["ckpt"],
+                            dev["dO"])
+        ms = timed(bfb, 2, 1)
+        ach = 3.0 * fwd_flops(w.d_head, w.d_hidden, w.n_tokens, w.n_heads) / (ms * 1e-3) / 1e12
+        res["batched_fwd_bwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                           pass_roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                                              unit="TFLOP/s (42 d h per token-head, whole pass)",
+                                                              frac=ach / PEAK["bf16"]))
         del dev
-    # batched forward: 8 uneven sequences, BF16
-    w = WORKLOADS["batch8_uneven_chunk8f_bf16"]
-    cu = w.cu_seqlens()
-    if "batched_fwd" not in forms and "batched_fwd_bwd" not in forms:
-        return res
-    if "batched_fwd" in forms:
-        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16")
-        O = torch.empty_like(dev["Q"])
-        ms, per, _ = time_fn(lambda: ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta,
-                                                     w.chunk_tokens, out=O, want_final=False), steps, warmup, lib)
-        kms = per["fwd_step"]["ms_per_call"]
-        ach = alg_flops(w) / (kms * 1e-3) / 1e12
-        res["batched_fwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                       kernels=per, roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
-                                                                  unit="TFLOP/s", frac=ach / PEAK["bf16"]))
-        del dev, O
-    if "batched_fwd_bwd" not in forms:
-        torch.cuda.empty_cache()
-        return res
-    # batched forward (with checkpoints) + batched backward: 8 uneven sequences, BF16
-    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16", with_dO=True)
+    w = WORKLOADS["layer16_64f_chunk8f"]
+    if "gcs" in forms:  # Global Context Synchronization form
+        for io in ("f32", "bf16"):
+            dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io)
+            ms = timed(lambda: ops.gcs_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                           want_final=False), steps, warmup)
+            ach = fwd_flops(w.d_head, w.d_hidden, w.n_tokens, w.n_heads) / (ms * 1e-3) / 1e12
+            res[f"gcs_fwd_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                        roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io], unit="TFLOP/s",
+                                                      frac=ach / PEAK[io]))
+            del dev
+    if "amu" in forms:  # the paper's memory unit: SwiGLU, dot-product loss, token-wise steps
+        for io in ("f32", "bf16"):
+            dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=io, with_dO=True)
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1)
+            W3 = torch.randn(dev["W1"].shape, generator=g, device="cuda") / float(w.d_head) ** 0.5
+            et = torch.from_numpy(make_eta_tok(w.n_tokens, w.n_heads, w.chunk_tokens, 20.0, 0)).cuda()
+            O = torch.empty_like(dev["Q"])
+            for sync in ("chain", "gcs"):
+                ms = timed(lambda: ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3,
+                                               w.chunk_tokens, sync=sync, want_final=False, out=O), steps, warmup)
+                # 12 d h per token-head for the update (K W1, K W3, E W2^T, three token sums) + 6 d h apply
+                ach = 18.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (ms * 1e-3) / 1e12
+                res[f"amu_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                               roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io],
+                                                             unit="TFLOP/s", frac=ach / PEAK[io]))
 
-    def bfb():
-        f = ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
-                            save_ckpt=True, want_final=False)
-        return ops.batched_bwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
-                               f["ckpt"], dev["dO"])
-    ms, per, _ = time_fn(bfb, max(2, steps // 4), 1, lib)
-    bms = per["bwd_step"]["ms_per_call"]
-    bach = 28.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (bms * 1e-3) / 1e12
-    res["batched_fwd_bwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
-                                       kernels=per,
-                                       bwd_step_roofline=dict(bound="mfma", achieved=bach, peak=PEAK["bf16"],
-                                                              unit="TFLOP/s", frac=bach / PEAK["bf16"]))
-    del dev
+                def fb():
+                    ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens, sync=sync,
+                                want_final=False, out=O)
+                    ops.amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, w.chunk_tokens,
+                                dev["dO"], sync=sync)
+                ms = timed(fb, few, 1)
+                res[f"amu_fwd_bwd_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms,
+                                                       tokens_per_s=w.n_tokens / (ms * 1e-3))
+            del dev, O, W3, et
+    if "length_sweep" in forms:  # one sequence of F frames (the shape of the paper's length table)
+        from workloads import Workload
+        rows = {}
+        for f in (150, 270, 510, 990):
+            wl = Workload(f"len{f}", 16, 64, 256, (f,), 8, 0.05, "bf16")
+            r, _, _ = forward_form(wl, "bf16", few, 1)
+            rows[str(f)] = dict(tokens=wl.n_tokens, ms_per_step=r["ms_per_step"], tokens_per_s=r["tokens_per_s"],
+                                frac_bf16_peak=r["roofline"]["frac"])
+            torch.cuda.empty_cache()
+        tps = [r["tokens_per_s"] for r in rows.values()]
+        res["length_sweep_bf16"] = dict(workload="one sequence, 16x64, h256, chunk 8 frames, bf16", frames=rows,
+                                        tokens_per_s_max_over_min=max(tps) / min(tps))
     torch.cuda.empty_cache()
     return res
 
 
-def cpu_baseline(w, host_inputs, gpu_out, n_heads):
-    """Time the FP64 oracle on the host for `n_heads` heads of the same
-    inputs (a bounded sample of the workload) and compare those heads."""
+def _median_time(fn, reps=3):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return statistics.median(ts), out
+
+
+def cpu_baselines(w, dev, O_gpu, full):
+    """The FP64 oracle on the host cores.  Headline: one head of every
+    sequence of the batch (head (5b+3) mod 16 of sequence b: 1,187,136
+    token-heads, 1/16 of the workload), one warm-up on the shortest
+    sequence, median of 3, scaled to all heads.  With `full`, the other
+    workloads' oracle timings on bounded samples as well."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     import oracle
-    sl = slice(0, n_heads)
-    x = {k: host_inputs[k][:, sl] for k in ("Q", "K", "V")}
-    W1, W2 = host_inputs["W1"][sl], host_inputs["W2"][sl]
+    from workloads import WORKLOADS, make_inputs
     cu = w.cu_seqlens()
-    t0 = time.perf_counter()
-    ref = oracle.ttt_forward_batched(x["Q"], x["K"], x["V"], cu, W1, W2, w.eta, w.chunk_tokens)
-    dt = time.perf_counter() - t0
+    heads = [(5 * b + 3) % w.n_heads for b in range(len(cu) - 1)]
+    xs = []
+    for b, hd in enumerate(heads):
+        sl = slice(cu[b], cu[b + 1])
+        xs.append({k: dev[k][sl, hd:hd + 1].float().cpu().numpy() for k in ("Q", "K", "V")})
+    W1 = dev["W1"].cpu().numpy()
+    W2 = dev["W2"].cpu().numpy()
+
+    def run_sample():
+        return [oracle.ttt_forward(x["Q"], x["K"], x["V"], W1[hd:hd + 1], W2[hd:hd + 1], w.eta, w.chunk_tokens)
+                for x, hd in zip(xs, heads)]
+    oracle.ttt_forward(xs[0]["Q"], xs[0]["K"], xs[0]["V"], W1[:1], W2[:1], w.eta, w.chunk_tokens)  # warm-up
+    dt, refs = _median_time(run_sample)
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    tok_s = w.n_tokens * (n_heads / w.n_heads) / dt
-    # the same oracle on one thread, one head
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        t1 = time.perf_counter()
-        oracle.ttt_forward_batched(x["Q"][:, :1], x["K"][:, :1], x["V"][:, :1], cu, W1[:1], W2[:1], w.eta,
-                                   w.chunk_tokens)
-        dt1 = time.perf_counter() - t1
-    one = dict(value=w.n_tokens / w.n_heads / dt1, unit="tokens/s", cores=1,
-               sample=f"1 of {w.n_heads} heads over all {w.n_tokens} tokens ({dt1:.1f} s), scaled to all heads")
-    errs = {}
-    for io, out in gpu_out.items():
-        O = out["O"][:, sl].float().cpu().numpy().astype(np.float64)
-        errs[io] = float(np.linalg.norm(O - ref["O"]) / np.linalg.norm(ref["O"]))
+    # error of the GPU output on the sampled heads, per output row and overall
+    errs = []
+    num = den = 0.0
+    worst_row = 0.0
+    maxabs = maxref = 0.0
+    for b, (hd, ref) in enumerate(zip(heads, refs)):
+        o = O_gpu[cu[b]:cu[b + 1], hd].float().cpu().numpy().astype(np.float64)
+        r = ref["O"][:, 0]
+        num += float(np.sum((o - r) ** 2))
+        den += float(np.sum(r * r))
+        worst_row = max(worst_row, float(np.max(np.linalg.norm(o - r, axis=1) / np.linalg.norm(r, axis=1))))
+        maxabs = max(maxabs, float(np.max(np.abs(o - r))))
+        maxref = max(maxref, float(np.max(np.abs(r))))
+        errs.append(float(np.linalg.norm(o - r) / np.linalg.norm(r)))
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=tok_s, unit="tokens/s", cores=threads, kind="oracle",
-                sample=f"FP64 numpy oracle forward on {n_heads} of {w.n_heads} heads over all "
-                       f"{w.n_tokens} tokens ({dt:.1f} s), scaled to all heads",
-                seconds=dt, single_thread=one, host_cpus=os.cpu_count(), cpu_model=model), errs
+    base = dict(value=w.n_tokens / w.n_heads / dt, unit="tokens/s", cores=threads, kind="oracle",
+                sample=f"FP64 numpy oracle forward of one head of each of the 8 sequences ({w.n_tokens} "
+                       f"token-heads = 1/{w.n_heads} of the workload), median of 3 ({dt:.1f} s), scaled to all "
+                       f"{w.n_heads} heads", seconds=dt, host_cpus=os.cpu_count(), cpu_model=model)
+    accuracy = dict(O_rel_norm=(num / den) ** 0.5, O_worst_row_rel=worst_row, O_maxabs=maxabs,
+                    O_maxabs_over_max_ref=maxabs / maxref, per_sequence_rel=errs,
+                    note="GPU BF16 path vs FP64 oracle on the same BF16-rounded inputs, sampled heads")
+    if not full:
+        return base, accuracy
+    # the other workloads' oracle timings on bounded samples (median of 3 each)
+    other = {}
+    for name, n_heads_s, kind in (("single_head_4x1374", 1, "fwd"), ("single_head_256x1374_bf16", 1, "fwd"),
+                                  ("layer16_64f_chunk8f", 1, "fwd"), ("layer16_32f_chunk4f_bwd", 1, "fwd+bwd")):
+        wl = WORKLOADS[name]
+        x = make_inputs(wl.n_tokens, n_heads_s, wl.d_head, wl.d_hidden, seed=0, with_dO=kind != "fwd")
+        if kind == "fwd":
+            f = lambda: oracle.ttt_forward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], wl.eta, wl.chunk_tokens)
+        else:
+            def f():
+                oracle.ttt_forward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], wl.eta, wl.chunk_tokens)
+                return oracle.ttt_backward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], wl.eta, wl.chunk_tokens,
+                                           x["dO"])
+        t, _ = _median_time(f)
+        other[name] = dict(pass_=kind, tokens_per_s=wl.n_tokens * n_heads_s / wl.n_heads / t,
+                           gflop_per_s=(42.0 if kind != "fwd" else 14.0) * wl.d_head * wl.d_hidden * wl.n_tokens *
+                           n_heads_s / t / 1e9,
+                           sample=f"{n_heads_s} of {wl.n_heads} heads, all {wl.n_tokens} tokens, median of 3 "
+                                  f"({t:.2f} s), scaled to all heads")
+    base["other_workloads"] = other
+    return base, accuracy
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); chains shard over GPUs by "
-              f"(sequence, head) but no multi-GPU path is built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): chains shard over GPUs by "
+              f"(sequence, head), but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2604_08542_amd as P
-    from workloads import WORKLOADS, make_inputs_torch
-    lib = P.load()
-    w = WORKLOADS[a.workload]
-    dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype=w.io_dtype)
-    variants = {}
-    for io in a.variants.split(","):
-        variants[io] = run_variant(w, dev, io, a.steps, a.warmup, lib)
-        print(f"# {io}: {variants[io]['ms_per_step']:.3f} ms/step, "
-              f"{variants[io]['tokens_per_s']:.4g} tokens/s, step-kernel "
-              f"{variants[io]['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
-    extra = {}
-    if not a.no_extra:
-        extra = extra_variants(a.steps, a.warmup, lib, tuple(f for f in a.forms.split(",") if f))
-        for k, v in extra.items():
-            if "frames" in v:
-                for f, r in v["frames"].items():
-                    print(f"# {k} {f} frames: {r['ms_per_step']:.3f} ms/step, {r['tokens_per_s']:.4g} tokens/s",
-                          file=sys.stderr, flush=True)
-                continue
+    from workloads import WORKLOADS
+    P.load()
+    w = WORKLOADS[HEADLINE]
+    head, O, dev = forward_form(w, "bf16", a.steps, a.warmup)
+    head["roofline"]["traffic"] = measured_traffic("bf16")
+    head["roofline"]["traffic_unit"] = "HBM bytes per launch"
+    print(f"# headline {HEADLINE} bf16: {head['ms_per_step']:.3f} ms/step, {head['tokens_per_s']:.4g} tokens/s, "
+          f"{head['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    cpu = acc = None
+    if not a.no_cpu_baseline:
+        cpu, acc = cpu_baselines(w, dev, O, full=not a.quick)
+        print(f"# oracle: {cpu['value']:.4g} tokens/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+    del dev, O
+    torch.cuda.empty_cache()
+    f32, _, _ = forward_form(w, "f32", max(2, a.steps // 4), 2)
+    f32["roofline"]["traffic"] = measured_traffic("f32")
+    print(f"# {HEADLINE} f32: {f32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    extra = {} if a.quick else other_forms(tuple(f for f in a.forms.split(",") if f), a.steps, a.warmup)
+    for k, v in extra.items():
+        if isinstance(v, dict) and "ms_per_step" in v:
             print(f"# {k}: {v['ms_per_step']:.3f} ms/step, {v['tokens_per_s']:.4g} tokens/s", file=sys.stderr,
                   flush=True)
-    if a.copy_calib:
-        src = torch.empty(128 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    main_io = w.io_dtype if w.io_dtype in variants else next(iter(variants))
-    m = variants[main_io]
-    cpu = None
-    errs = {}
-    if not a.no_cpu_baseline:
-        host = {k: dev[k][:, : a.cpu_heads].float().cpu().numpy() for k in ("Q", "K", "V")}
-        host["W1"] = dev["W1"].cpu().numpy()
-        host["W2"] = dev["W2"].cpu().numpy()
-        cpu, errs = cpu_baseline(w, host, {io: variants[io]["out"] for io in variants}, a.cpu_heads)
-        if main_io == "f32":
-            # the BF16 variant's inputs were rounded from these FP32 values
-            errs["bf16_incl_input_rounding"] = errs.pop("bf16")
     line = {
         "metric": METRIC,
-        "value": m["tokens_per_s"],
+        "value": head["tokens_per_s"],
         "unit": "tokens/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": m["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": main_io,
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": w.name, "heads": w.n_heads, "d_head": w.d_head, "d_hidden": w.d_hidden,
-                   "frames": list(w.frames), "tokens": w.n_tokens, "chunk_tokens": w.chunk_tokens,
-                   "eta": w.eta, "pass": "forward"},
-        "roofline": m["roofline"],
+        "config": {"workload": HEADLINE, "sequences_frames": list(w.frames), "tokens": w.n_tokens,
+                   "heads": w.n_heads, "d_head": w.d_head, "d_hidden": w.d_hidden, "chunk_tokens": w.chunk_tokens,
+                   "eta": w.eta, "pass": "forward", "arithmetic": "BF16 operands, FP32 accumulate / weights / norms",
+                   "schedule": "persistent (one launch)"},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "variants": {io: {k: v for k, v in var.items() if k != "out"} for io, var in variants.items()},
-        "speedup_bf16_over_f32": (variants["f32"]["ms_per_step"] / variants["bf16"]["ms_per_step"]
-                                  if "f32" in variants and "bf16" in variants else None),
-        "rel_err_vs_oracle_sampled_heads": errs,
+        "accuracy_vs_oracle": acc,
+        "device_error_word": head["device_error_word"],
+        "variants": {"f32": f32, "bf16": {k: v for k, v in head.items() if k != "roofline"}},
+        "speedup_bf16_over_f32": f32["ms_per_step"] / head["ms_per_step"],
         "other_forms": extra,
     }
     print(json.dumps(line))

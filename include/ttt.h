@@ -33,7 +33,9 @@
  *     exception crosses this boundary.  Calls from different host threads
  *     are safe; calls that share a workspace must be stream-ordered.
  *   - Supported shapes: d = 64, h in {128, 256}; other sizes return
- *     TTT_ESHAPE.  n_tokens may be 0 (nothing is enqueued).
+ *     TTT_ESHAPE.  n_tokens may be 0: token pointers may then be NULL,
+ *     the final weights (if asked for) are the initial ones and nothing
+ *     else is written.
  */
 #ifndef TTT_H_
 #define TTT_H_
@@ -80,12 +82,27 @@ typedef struct {
 } ttt_problem_t;
 
 /* Optional launch shape; pass NULL for the built-in heuristic or the tuned
- * table.  wg_per_chain: work-groups that share one chunk of one chain
- * (0 = automatic); target_wgs: total work-groups aimed for per chunk step
- * (0 = automatic). */
+ * table.
+ *   wg_per_chain  work-groups that share the chunks of one chain (0 =
+ *                 automatic): each takes every wg_per_chain-th 32-token tile.
+ *   target_wgs    total work-groups aimed for (0 = automatic: every
+ *                 work-group the GPU can hold at once for the persistent
+ *                 schedule, a per-step target for the stepwise one).
+ *   schedule      TTT_SCHED_PERSISTENT (0): one launch walks every chunk of
+ *                 every chain; the work-groups of a chain meet at barriers
+ *                 between chunks and are sized so that all are resident.
+ *                 TTT_SCHED_STEPWISE (1): one step launch and one update
+ *                 launch per chunk step (the stream orders the steps).
+ *   spin_limit    persistent schedule: polls a barrier wait may take before
+ *                 it gives up and flags the workspace (see
+ *                 ttt_workspace_status); 0 = default (about a second or
+ *                 more).  Only meant to test that path. */
+enum { TTT_SCHED_PERSISTENT = 0, TTT_SCHED_STEPWISE = 1 };
 typedef struct {
   int32_t wg_per_chain;
   int32_t target_wgs;
+  int32_t schedule;
+  int32_t spin_limit;
 } ttt_tile_cfg_t;
 
 /* Bytes of device workspace needed by any call on `p` with `n_seqs`
@@ -242,6 +259,14 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
  * Not meant for production calls: it adds event records to the stream. */
 ttt_status_t ttt_profile_enable(int32_t on);
 ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches);
+
+/* Device-side status of the last call that used workspace `ws`: copies the
+ * workspace's error word to *flags_host (bit 0: a barrier wait of the
+ * persistent forward gave up, so that call's outputs are invalid; 0: no
+ * error).  The word is cleared by every forward call that has tokens
+ * (ttt_chunk_fwd, ttt_batched_fwd, ttt_batched_fwd_ckpt).  This is the one
+ * entry point that synchronises: it waits for `hip_stream`. */
+ttt_status_t ttt_workspace_status(const void* ws, size_t ws_bytes, uint32_t* flags_host, void* hip_stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* ttt_status_string(ttt_status_t s);

@@ -16,7 +16,7 @@ TTT_SYNC_CHAIN, TTT_SYNC_GCS = 0, 1
 EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batched_fwd", "ttt_batched_fwd_ckpt",
             "ttt_batched_bwd", "ttt_gcs_fwd", "ttt_gcs_bwd", "ttt_amu_workspace_bytes", "ttt_amu_fwd",
             "ttt_amu_bwd_workspace_bytes", "ttt_amu_bwd",
-            "ttt_profile_enable", "ttt_profile_read",
+            "ttt_profile_enable", "ttt_profile_read", "ttt_workspace_status",
             "ttt_status_string", "ttt_version")
 
 
@@ -35,8 +35,12 @@ class Problem(ctypes.Structure):
     ]
 
 
+TTT_SCHED_PERSISTENT, TTT_SCHED_STEPWISE = 0, 1
+
+
 class TileCfg(ctypes.Structure):
-    _fields_ = [("wg_per_chain", ctypes.c_int32), ("target_wgs", ctypes.c_int32)]
+    _fields_ = [("wg_per_chain", ctypes.c_int32), ("target_wgs", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int32)]
 
 
 class TTTError(RuntimeError):
@@ -95,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.ttt_profile_enable.restype = st
     lib.ttt_profile_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.ttt_profile_read.restype = st
+    lib.ttt_workspace_status.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_uint32), vp]
+    lib.ttt_workspace_status.restype = st
     lib.ttt_version.argtypes = []
     lib.ttt_version.restype = ctypes.c_int32
     _lib = lib

@@ -33,7 +33,7 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Werror",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-o", tmp] + sources()
     if verbose:

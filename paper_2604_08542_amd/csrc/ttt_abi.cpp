@@ -12,6 +12,7 @@
 
 #include "../../include/ttt.h"
 #include "ttt_internal.h"
+#include "ttt_tuned.h"
 
 namespace {
 
@@ -57,9 +58,16 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
 }
 
 struct WsLayout {
-  size_t partial, partial_loss, pp, adj, wlast, prep, fin, deta_seq, total;
+  size_t sync, partial, partial_loss, pp, adj, wlast, prep, fin, deta_seq, total;
   int64_t slot_cap;
 };
+
+// Words at the start of every workspace: the device error word (word 0, read
+// by ttt_workspace_status), the persistent forward's chain counter (word 1),
+// its group barrier counters, group chain slots and group XCD sets.
+constexpr int SYNC_ERR = 0, SYNC_NEXT = 1, SYNC_BAR = 4;
+constexpr int MAX_GROUPS = 2048;
+constexpr size_t SYNC_BYTES = (size_t)(SYNC_BAR + 3 * MAX_GROUPS) * sizeof(uint32_t);
 
 // n_chains = sequences x heads of the call.
 WsLayout ws_layout(const Shape& s, int64_t n_chains) {
@@ -67,6 +75,8 @@ WsLayout ws_layout(const Shape& s, int64_t n_chains) {
   L.slot_cap = std::max<int64_t>(n_chains, SLOT_CAP_MIN);
   const size_t wbytes = (size_t)2 * s.dh() * sizeof(float);  // one chain's [W1 | W2]
   size_t off = 0;
+  L.sync = off;
+  off = align_up(off + SYNC_BYTES);
   L.partial = off;
   off = align_up(off + (size_t)L.slot_cap * wbytes);
   L.partial_loss = off;
@@ -91,6 +101,22 @@ WsLayout ws_layout(const Shape& s, int64_t n_chains) {
 }
 
 int default_target_wgs(const Shape& s) { return s.h == 256 ? 256 : 512; }
+
+// The launch shape of a call: the caller's, else the autotuner's recorded
+// shape for this (h, operand path, chunk size, chains, direction), else the
+// built-in heuristic (stepwise schedule, automatic sizes).
+ttt_tile_cfg_t resolve_cfg(const ttt_tile_cfg_t* given, const Shape& S, int64_t n_chains, bool bwd) {
+  if (given) return *given;
+  const bool f32_ops = !S.io_bf16 && !S.mma_bf16;
+  for (const TunedShape& t : kTuned) {
+    if (t.h == S.h && t.chunk_tokens == S.M && t.chains == n_chains && (t.bwd != 0) == bwd &&
+        ((t.bf16 != 0) == S.io_bf16) && (S.io_bf16 || f32_ops))
+      return t.cfg;
+  }
+  ttt_tile_cfg_t c{};
+  c.schedule = TTT_SCHED_STEPWISE;
+  return c;
+}
 
 // ---------------------------------------------------------------- profiling
 // Optional event pairs around launches (benchmark instrumentation only).
@@ -137,6 +163,160 @@ bool timed_launch(int kind, hipStream_t st, F&& f) {
 }
 
 template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+
+// Sequences without tokens take no chunk step: their final weights (when
+// asked for) are their initial weights.
+// Also clears the workspace's error word when there are tokens: every
+// forward call starts here (a call without tokens enqueues nothing else).
+ttt_status_t copy_w0_to_final(const Shape& S, int B, const int64_t* cu, const float* W1_0, const float* W2_0,
+                              int w0_per_seq, float* W1_T, float* W2_T, void* ws, size_t ws_bytes, hipStream_t st) {
+  const WsLayout L = ws_layout(S, (int64_t)B * S.H);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  if (cu[B] > 0 &&
+      !timed_launch(5, st, [&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
+    return TTT_EHIP;
+  if (!W1_T) return TTT_OK;
+  const int64_t dh = S.dh();
+  for (int b = 0; b < B; ++b) {
+    if (cu[b + 1] > cu[b]) continue;
+    const int64_t src = (int64_t)(w0_per_seq ? b : 0) * S.H * dh, dst = (int64_t)b * S.H * dh;
+    if (hipMemcpyAsync(W1_T + dst, W1_0 + src, S.H * dh * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(W2_T + dst, W2_0 + src, S.H * dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
+// ---------------------------------------------------------------- persistent forward
+// Launch shape of the persistent forward: groups of G work-groups, each group
+// walking whole chains.  Every work-group of the grid must be resident at
+// once (the groups wait for each other at barriers), so the grid is sized
+// from this kernel's occupancy; with 8 XCDs the groups are laid out so that
+// each group's members share one XCD (and its L2).
+struct PersistPlan {
+  int G = 0, n_groups = 0, grid = 0;
+  bool xcd = false;
+};
+
+ttt_status_t plan_persist(const Shape& S, const std::vector<int64_t>& nb, int64_t M, const ttt_tile_cfg_t* cfg,
+                          int64_t slot_cap, PersistPlan* out) {
+  int bpc = 0, threads = 0, dev = 0, n_cu = 0;
+  if (persist_occupancy(S.h, S.io_bf16, S.mma_bf16, &bpc, &threads) != hipSuccess || bpc < 1) return TTT_EHIP;
+  if (hipGetDevice(&dev) != hipSuccess) return TTT_EHIP;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+    return TTT_EHIP;
+  const int64_t resident = (int64_t)bpc * n_cu;
+  int64_t T = resident;
+  if (cfg && cfg->target_wgs > 0) T = std::min<int64_t>(cfg->target_wgs, resident);
+  int64_t n_chains = 0, L = 0, W = 0, tiles_max = 1;
+  for (int64_t n : nb) {
+    if (n <= 0) continue;
+    const int64_t steps = (n + M - 1) / M + 1;
+    n_chains += S.H;
+    L = std::max(L, steps);
+    W += steps * S.H;
+    tiles_max = std::max(tiles_max, (std::min(n, M) + TT - 1) / TT);
+  }
+  if (n_chains == 0) return TTT_OK;
+  int64_t G;
+  if (cfg && cfg->wg_per_chain > 0) {
+    G = cfg->wg_per_chain;
+  } else {
+    // enough members that the longest chain is not the critical path of a
+    // longest-first list schedule, and enough to fill T when chains are few
+    const int64_t g_lpt = (T * L + W - 1) / W;
+    const int64_t g_fill = std::max<int64_t>(1, T / n_chains);
+    G = 1;
+    while (G < std::max(g_lpt, g_fill)) G *= 2;
+    G = std::min(G, tiles_max);
+  }
+  G = std::max<int64_t>(1, std::min<int64_t>(G, resident));
+  int64_t n_groups = std::max<int64_t>(1, std::min<int64_t>(n_chains, T / G));
+  if (n_groups >= 8) n_groups -= n_groups % 8;
+  n_groups = std::min<int64_t>({n_groups, (int64_t)MAX_GROUPS, slot_cap / G});
+  if (n_groups < 1) return TTT_EINVAL;
+  const bool xcd = n_cu % 8 == 0 && G <= resident / 8;
+  if (xcd) {
+    const int64_t per_xcd = resident / 8;
+    int64_t gpx = (n_groups + 7) / 8;
+    while (gpx * G > per_xcd) --gpx;
+    n_groups = std::min<int64_t>(n_groups, gpx * 8);
+    out->grid = (int)(8 * gpx * G);
+  } else {
+    n_groups = std::min<int64_t>(n_groups, resident / G);
+    out->grid = (int)(n_groups * G);
+  }
+  out->G = (int)G;
+  out->n_groups = (int)n_groups;
+  out->xcd = xcd;
+  return TTT_OK;
+}
+
+constexpr uint32_t DEFAULT_SPIN_LIMIT = 1u << 22;  // polls of a barrier wait (about a second or more)
+
+// The whole forward of B sequences in one persistent launch per MAXS
+// sequences (non-empty sequences longest first).
+ttt_status_t run_forward_persist(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, const void* Q,
+                                 const void* K, const void* V, const float* W1_0, const float* W2_0, int w0_per_seq,
+                                 void* O, float* W1_T, float* W2_T, float* ckpt, float* loss,
+                                 const ttt_tile_cfg_t* cfg, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t nch_total = (int64_t)B * S.H;
+  const WsLayout Lw = ws_layout(S, nch_total);
+  if (!ws || ws_bytes < Lw.total) return TTT_EWORKSPACE;
+  const int64_t M = S.M;
+  std::vector<int64_t> nb(B), ckrow(B, 0);
+  for (int b = 0; b < B; ++b) {
+    nb[b] = cu[b + 1] - cu[b];
+    if (b > 0) ckrow[b] = ckrow[b - 1] + (nb[b - 1] + M - 1) / M;
+  }
+  const ttt_status_t e0 = copy_w0_to_final(S, B, cu, W1_0, W2_0, w0_per_seq, W1_T, W2_T, ws, ws_bytes, st);
+  if (e0 != TTT_OK || cu[B] == 0) return e0;
+  PersistPlan plan;
+  ttt_status_t e = plan_persist(S, nb, M, cfg, Lw.slot_cap, &plan);
+  if (e != TTT_OK) return e;
+  uint32_t* sync = at<uint32_t>(ws, Lw.sync);
+  constexpr int SYNC_WORDS = SYNC_BAR + 3 * MAX_GROUPS;
+  std::vector<int> order;
+  for (int b = 0; b < B; ++b)
+    if (nb[b] > 0) order.push_back(b);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nb[x] > nb[y]; });
+  for (size_t base = 0; base < order.size(); base += MAXS) {
+    const int na = (int)std::min<size_t>(MAXS, order.size() - base);
+    PersistArgs a{};
+    a.Q = Q; a.K = K; a.V = V; a.O = O;
+    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+    a.w1_0 = W1_0; a.w2_0 = W2_0; a.w0_per_seq = w0_per_seq;
+    a.H = S.H; a.flags = p->flags; a.eta = p->eta;
+    a.G = plan.G; a.n_groups = plan.n_groups; a.n_chains = na * S.H; a.xcd_map = plan.xcd ? 1 : 0;
+    a.spin_limit = (cfg && cfg->spin_limit > 0) ? (uint32_t)cfg->spin_limit : DEFAULT_SPIN_LIMIT;
+    a.M = M;
+    a.partial = at<float>(ws, Lw.partial);
+    a.partial_loss = at<float>(ws, Lw.partial_loss);
+    a.wbuf = at<float>(ws, Lw.pp);
+    a.err = sync + SYNC_ERR;
+    a.next = sync + SYNC_NEXT;
+    a.bar = sync + SYNC_BAR;
+    a.slot = sync + SYNC_BAR + MAX_GROUPS;
+    a.xcds = sync + SYNC_BAR + 2 * MAX_GROUPS;
+    a.ckpt = ckpt; a.wT1 = W1_T; a.wT2 = W2_T;
+    a.loss = loss; a.loss_stride = (int32_t)((nb[0] + M - 1) / M);
+    // schedule entry i (longest first) is sequence order[base + i]
+    for (int i = 0; i < na; ++i) {
+      const int b = order[base + i];
+      a.seq_id[i] = b;
+      a.seq_start[i] = cu[b];
+      a.seq_len[i] = nb[b];
+      a.ck_row[i] = ckrow[b];
+    }
+    // counters of this launch (and, for the call's first launch, the error word)
+    const int z0 = base == 0 ? SYNC_ERR : SYNC_NEXT;
+    if (!timed_launch(5, st, [&] { return launch_zero_words(sync + z0, SYNC_WORDS - z0, st); })) return TTT_EHIP;
+    if (!timed_launch(0, st, [&] { return launch_fwd_persist(a, plan.grid, S.h, S.io_bf16, S.mma_bf16, st); }))
+      return TTT_EHIP;
+  }
+  return TTT_OK;
+}
 
 // The whole forward: for s = 0..C_max, one fwd-step launch (gradient of chunk
 // s, apply of chunk s-1) and, while any chunk s exists, one update launch.
@@ -261,7 +441,9 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
   float* fin = at<float>(ws, L.fin);
   float* deta_seq = B == 1 ? deta : at<float>(ws, L.deta_seq);
   const bool shared_w0 = B > 1 && !w0_per_seq;
-  const int target = (cfg && cfg->target_wgs > 0) ? cfg->target_wgs : default_target_wgs(S);
+  const ttt_tile_cfg_t rc = resolve_cfg(cfg, S, (int64_t)B * H, true);
+  cfg = &rc;
+  const int target = cfg->target_wgs > 0 ? cfg->target_wgs : default_target_wgs(S);
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
   const int64_t tiles = std::max<int64_t>((std::min(M, nmax) + TT - 1) / TT, 1);
   auto mlen = [&](int b, int64_t c) { return (int32_t)std::min<int64_t>(M, nb[b] - c * M); };
@@ -524,7 +706,8 @@ ttt_status_t check_batch(const ttt_problem_t* p, int32_t n_seqs, const int64_t* 
   if (cu[0] != 0) return TTT_EINVAL;
   for (int b = 0; b < n_seqs; ++b)
     if (cu[b + 1] < cu[b]) return TTT_EINVAL;
-  if (tile_cfg && (tile_cfg->wg_per_chain < 0 || tile_cfg->target_wgs < 0)) return TTT_EINVAL;
+  if (tile_cfg && (tile_cfg->wg_per_chain < 0 || tile_cfg->target_wgs < 0 || tile_cfg->spin_limit < 0))
+    return TTT_EINVAL;
   (void)p;
   return TTT_OK;
 }
@@ -537,16 +720,30 @@ ttt_status_t batched_fwd_impl(const ttt_problem_t* p, int32_t n_seqs, const int6
   ttt_status_t e = check_problem(p, &S);
   if (e != TTT_OK) return e;
   if ((e = check_batch(p, n_seqs, cu_seqlens_host, w0_per_seq, tile_cfg)) != TTT_OK) return e;
-  if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+  if (!W1_0 || !W2_0) return TTT_EINVAL;
+  const bool any = cu_seqlens_host[n_seqs] > 0;
+  // token tensors and checkpoints may be empty (null) when there are no tokens
+  if (any && (!Q || !K || !V || !O)) return TTT_EINVAL;
   if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
-  if (((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
+  if (any && ((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
   if (p->flags & TTT_EMIT_LOSS) return TTT_ENOTSUP;
+  if (tile_cfg && tile_cfg->schedule != TTT_SCHED_PERSISTENT && tile_cfg->schedule != TTT_SCHED_STEPWISE)
+    return TTT_EINVAL;
   for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
                         (const void*)W2_T, (const void*)ckpt})
     if (q && !aligned16(q)) return TTT_EINVAL;
-  if (cu_seqlens_host[n_seqs] == 0) return TTT_OK;
-  return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt, nullptr,
-                     tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const ttt_tile_cfg_t cfg = resolve_cfg(tile_cfg, S, (int64_t)n_seqs * S.H, false);
+  if (cfg.schedule == TTT_SCHED_STEPWISE) {
+    // sequences without tokens take no chunk step: their final weights are W_0
+    const ttt_status_t e0 = copy_w0_to_final(S, n_seqs, cu_seqlens_host, W1_0, W2_0, w0_per_seq, W1_T, W2_T, ws,
+                                             ws_bytes, st);
+    if (e0 != TTT_OK || !any) return e0;
+    return run_forward(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt, nullptr,
+                       &cfg, ws, ws_bytes, st);
+  }
+  return run_forward_persist(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt,
+                             nullptr, &cfg, ws, ws_bytes, st);
 }
 // ---------------------------------------------------------------- paper AMU
 struct AmuWs {
@@ -806,17 +1003,24 @@ ttt_status_t ttt_chunk_fwd(const ttt_problem_t* p, const void* Q, const void* K,
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+    if (!W1_0 || !W2_0) return TTT_EINVAL;
+    // token tensors may be empty (null) when there are no tokens
+    if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
     if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
-    if (((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
-    if (((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
+    if (p->n_tokens > 0 && ((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
+    if (p->n_tokens > 0 && ((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
     for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
                           (const void*)W2_T, (const void*)ckpt})
       if (q && !aligned16(q)) return TTT_EINVAL;
-    if (p->n_tokens == 0) return TTT_OK;
     const int64_t cu[2] = {0, p->n_tokens};
-    return run_forward(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, nullptr, ws, ws_bytes,
-                       static_cast<hipStream_t>(hip_stream));
+    const ttt_tile_cfg_t cfg = resolve_cfg(nullptr, S, S.H, false);
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (cfg.schedule == TTT_SCHED_STEPWISE) {
+      if (p->n_tokens == 0) return copy_w0_to_final(S, 1, cu, W1_0, W2_0, 0, W1_T, W2_T, ws, ws_bytes, st);
+      return run_forward(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes, st);
+    }
+    return run_forward_persist(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes,
+                               st);
   } catch (...) {
     return TTT_EINVAL;
   }
@@ -899,14 +1103,23 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (!Q || !K || !V || !W1_0 || !W2_0 || !O) return TTT_EINVAL;
+    if (!W1_0 || !W2_0) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
     if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
     if (p->flags & TTT_SAVE_CKPT) return TTT_EINVAL;
-    if (((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
+    if (p->n_tokens > 0 && ((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
     for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
                           (const void*)W2_T})
       if (q && !aligned16(q)) return TTT_EINVAL;
-    if (p->n_tokens == 0) return TTT_OK;
+    if (p->n_tokens == 0) {  // no chunks: W* = W0
+      if (!W1_T) return TTT_OK;
+      const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+      const size_t bytes = (size_t)S.H * S.dh() * sizeof(float);
+      if (hipMemcpyAsync(W1_T, W1_0, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(W2_T, W2_0, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return TTT_EHIP;
+      return TTT_OK;
+    }
     return run_gcs_forward(p, S, Q, K, V, W1_0, W2_0, O, W1_T, W2_T, loss, ws, ws_bytes,
                            static_cast<hipStream_t>(hip_stream), nullptr);
   } catch (...) {
@@ -1017,6 +1230,16 @@ ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches) {
   return TTT_OK;
 }
 
+ttt_status_t ttt_workspace_status(const void* ws, size_t ws_bytes, uint32_t* flags_host, void* hip_stream) {
+  if (!ws || !flags_host || ws_bytes < SYNC_BYTES) return TTT_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(flags_host, static_cast<const uint32_t*>(ws) + SYNC_ERR, sizeof(uint32_t),
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TTT_EHIP;
+  return TTT_OK;
+}
+
 const char* ttt_status_string(ttt_status_t s) {
   switch (s) {
     case TTT_OK: return "TTT_OK";
@@ -1029,6 +1252,6 @@ const char* ttt_status_string(ttt_status_t s) {
   return "unknown status";
 }
 
-int32_t ttt_version(void) { return 100; }
+int32_t ttt_version(void) { return 200; }
 
 }  // extern "C"

@@ -56,8 +56,7 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, 
 // Row index held by result register r of a 32x32 block in lane-half hf.
 __device__ __forceinline__ constexpr int c32_row(int r, int hf) { return 8 * (r >> 2) + 4 * hf + (r & 3); }
 
-// ----------------------------------------------------------------- SiLU family
-// sigma(z) from one exp2 and one reciprocal (both hardware transcendentals).
+// ----------------------------------------------------------------- shard sums
 // s + part[0] + part[stride] + ... + part[(G-1) stride], added one shard at
 // a time in shard order.  The loads of 8 shards are issued before their
 // additions so that they are in flight together; the additions, and so the
@@ -75,6 +74,8 @@ __device__ __forceinline__ f32x4 add_shards(f32x4 s, const f32x4* part, int64_t 
   return s;
 }
 
+// ----------------------------------------------------------------- SiLU family
+// sigma(z) from one exp2 and one reciprocal (both hardware transcendentals).
 __device__ __forceinline__ float sigmoid(float z) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
@@ -196,6 +197,74 @@ struct FwdStepArgs {
   int32_t grad_len[MAXS];  // 0: no gradient chunk this step
   int64_t app_start[MAXS];
   int32_t app_len[MAXS];   // 0: no apply chunk this step
+};
+
+// What one work-group computes in one chunk step of one chain: the gradient
+// partial of its token shard of chunk s (tiles g, g+G, g+2G, ... of the
+// chunk) and the apply of its shard of chunk s-1, both with the weights W_s.
+struct StepCtx {
+  const void* Q;
+  const void* K;
+  const void* V;
+  void* O;
+  int64_t stride_tok, stride_head;
+  uint32_t flags;
+  const float* W1;   // W_s of the chain: [D][h]
+  const float* W2;   // [h][D]
+  int32_t head, g, G;
+  int64_t gs;        // first token of the gradient chunk
+  int32_t gl;        // its length (0: no gradient this step)
+  int64_t as0;       // first token of the apply chunk
+  int32_t al;        // its length (0: no apply this step)
+  float* part;       // this work-group's gradient partial [2*D*h] (written iff gl > 0)
+  float* part_loss;  // this work-group's loss partial
+};
+
+// The whole forward of many chains in one launch.  Work-groups form groups of
+// G; a group takes the next chain (sequences in `order`, heads within a
+// sequence) from a device counter and walks all of its chunk steps: every
+// step, each member computes its shard (StepCtx), the members meet at a
+// barrier, each reduces a 1/G slice of the G shard partials in a fixed order
+// into W_{s+1} (and the checkpoint / final weights / loss), and they meet
+// again before the next step reads W_{s+1}.  Barriers are counters in device
+// memory with bounded waits (a wait that exceeds spin_limit polls sets *err
+// and gives up); a group whose members share one XCD synchronises through
+// that XCD's L2 alone.  All members of all groups must be resident at once; the
+// host sizes the grid from the occupancy of this kernel.
+struct PersistArgs {
+  const void* Q;
+  const void* K;
+  const void* V;
+  void* O;
+  int64_t stride_tok, stride_head;
+  const float* w1_0;   // W1_0 of (sequence b, head) at w1_0 + ((w0_per_seq ? b * H : 0) + head) * D * h
+  const float* w2_0;
+  int32_t w0_per_seq;
+  int32_t H;
+  uint32_t flags;
+  float eta;
+  int32_t G, n_groups, n_chains;
+  int32_t xcd_map;      // 1: groups mapped to XCDs (grid a multiple of 8 * G)
+  uint32_t spin_limit;
+  int64_t M;            // tokens per chunk
+  float* partial;       // [n_groups][G][2*D*h]
+  float* partial_loss;  // [n_groups][G]
+  float* wbuf;          // [n_groups][2][2*D*h] ping-pong weights
+  uint32_t* bar;        // [n_groups] barrier counters, zero at launch
+  uint32_t* slot;       // [n_groups] chain taken by the group
+  uint32_t* next;       // next chain counter, zero at launch
+  uint32_t* xcds;       // [n_groups] set of XCDs of the group's members, zero at launch
+  uint32_t* err;        // bit 0: a barrier wait gave up
+  float* ckpt;          // nullable; chunk c of entry e, head: row ck_row[e] + c of [rows][H][2*D*h]
+  float* wT1;           // nullable; [B][H][D][h]
+  float* wT2;           // [B][H][h][D]
+  float* loss;          // nullable (single sequence): loss[head * loss_stride + c]
+  int32_t loss_stride;
+  // schedule entry e (chains e*H .. e*H+H-1), longest sequence first:
+  int32_t seq_id[MAXS];     // its sequence b (index of W_0 with w0_per_seq, and of W_T)
+  int64_t seq_start[MAXS];  // its first token
+  int64_t seq_len[MAXS];    // its token count (> 0)
+  int64_t ck_row[MAXS];     // its chunk-0 checkpoint row
 };
 
 // Reduction of the gradient partials and the fast-weight step W <- W - eta*g.

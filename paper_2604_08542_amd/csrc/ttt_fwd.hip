@@ -31,8 +31,8 @@ namespace ttt {
 // the gradient tiles and the apply tiles run in two loops over single-
 // buffered LDS tiles (4 barriers per tile); the next tile's rows are
 // prefetched into registers while the current tile computes.
-template <typename IOT, int NW>
-__global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
+template <typename IOT, int NW, bool OPAQUE_TID = false>
+__device__ __forceinline__ void fwd_body_f32(const StepCtx& p) {
   constexpr int HH = NW * 32;  // hidden size
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;  // row elements per thread when loading
@@ -50,18 +50,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   __shared__ __attribute__((aligned(16))) float w2t[D * W2T_LD];  // W2^T
   __shared__ float red[NW];
 
-  const int tid = threadIdx.x;
+  // in a loop that calls this body (the persistent kernel) the lane index is
+  // made opaque to the compiler, so that nothing derived from it is hoisted
+  // out of the loop (it would hold registers across the whole loop)
+  int tid = threadIdx.x;
+  if constexpr (OPAQUE_TID) asm volatile("" : "+v"(tid));
   const int w = tid >> 6, l = tid & 63, l32 = l & 31, hf = l >> 5, l16 = l & 15, g4 = l >> 4;
-  const int lin = xcd_linear_block();
-  const int G = p.G;
-  const int slot = lin / G, g = lin % G;
-  const int ai = slot / p.H, head = slot % p.H;
-  const int seq = p.seq_id[ai];
-  const int chain = seq * p.H + head;
+  const int G = p.G, g = p.g, head = p.head;
   const int hid = w * 32 + l32;
-
-  const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
-  const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  const float* W1 = p.W1;
+  const float* W2 = p.W2;
 
   // B operand of Y = A W2 over the full hidden axis, from LDS (W2^T).
   for (int idx = tid; idx < DH; idx += NT) {
@@ -79,8 +77,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
   const int row = tid / TPR, col0 = (tid % TPR) * EPT;
   const int64_t hoff = (int64_t)head * p.stride_head;
-  const int gl = p.grad_len[ai], al = p.app_len[ai];
-  const int64_t gs = p.grad_start[ai], as0 = p.app_start[ai];
+  const int gl = p.gl, al = p.al;
+  const int64_t gs = p.gs, as0 = p.as0;
   const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
   const int my_g = n_gt > g ? (n_gt - g + G - 1) / G : 0;  // tiles of this work-group
   const int my_a = n_at > g ? (n_at - g + G - 1) / G : 0;
@@ -255,7 +253,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 
   if (gl > 0) {
     // Shard partials: grad W1 [D][h] then grad W2 [h][D].
-    float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
+    float* part = p.part;
 #pragma unroll
     for (int db = 0; db < 2; ++db)
 #pragma unroll
@@ -271,7 +269,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
     if (tid == 0) {
       float s = 0.f;
       for (int i = 0; i < NW; ++i) s += red[i];
-      p.partial_loss[(int64_t)slot * G + g] = s;
+      *p.part_loss = s;
     }
   }
 }
@@ -301,8 +299,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
 // (K = V = 0 gives Z = 0, A = 0, Y = 0, R = 0).  A block whose shard has both
 // gradient and apply tiles runs the fused body; shards with only one kind run
 // a body without the other's work.
-template <typename IOT, int NW>
-__global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
+template <typename IOT, int NW, bool OPAQUE_TID = false>
+__device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
   constexpr int HH = NW * 32;
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;
@@ -324,16 +322,16 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   __shared__ __attribute__((aligned(16))) bf16 es[TT * XS_LD];       // E
   __shared__ float red[NW];
 
-  const int tid = threadIdx.x;
+  // in a loop that calls this body (the persistent kernel) the lane index is
+  // made opaque to the compiler, so that nothing derived from it is hoisted
+  // out of the loop (it would hold registers across the whole loop)
+  int tid = threadIdx.x;
+  if constexpr (OPAQUE_TID) asm volatile("" : "+v"(tid));
   const int w = tid >> 6, l = tid & 63, l32 = l & 31, hf = l >> 5, l16 = l & 15, g4 = l >> 4;
-  const int lin = xcd_linear_block();
-  const int G = p.G;
-  const int slot = lin / G, g = lin % G;
-  const int ai = slot / p.H, head = slot % p.H;
-  const int chain = p.seq_id[ai] * p.H + head;
+  const int G = p.G, g = p.g, head = p.head;
   const int hid = w * 32 + l32;
-  const float* W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
-  const float* W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  const float* W1 = p.W1;
+  const float* W2 = p.W2;
 
   // Register-resident operands, packed once; the empty asm pins each packed
   // word so that the compiler keeps it instead of re-deriving it from the
@@ -377,8 +375,8 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
   const bool norm_q = p.flags & 1u, norm_k = p.flags & 2u, norm_v = p.flags & 4u;
   const int row = tid / TPR, col0 = (tid % TPR) * EPT;
   const int64_t hoff = (int64_t)head * p.stride_head;
-  const int gl = p.grad_len[ai], al = p.app_len[ai];
-  const int64_t gs = p.grad_start[ai], as0 = p.app_start[ai];
+  const int gl = p.gl, al = p.al;
+  const int64_t gs = p.gs, as0 = p.as0;
   const int n_gt = (gl + TT - 1) / TT, n_at = (al + TT - 1) / TT;
   const int my_g = n_gt > g ? (n_gt - g + G - 1) / G : 0;
   const int my_a = n_at > g ? (n_at - g + G - 1) / G : 0;
@@ -692,7 +690,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     run(std::integral_constant<int, 2>{});
 
   if (gl > 0) {
-    float* part = p.partial + ((int64_t)slot * G + g) * (2 * DH);
+    float* part = p.part;
 #pragma unroll
     for (int db = 0; db < 2; ++db)
 #pragma unroll
@@ -708,7 +706,7 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_step_bf(FwdStepArgs p) {
     if (tid == 0) {
       float s = 0.f;
       for (int i = 0; i < NW; ++i) s += red[i];
-      p.partial_loss[(int64_t)slot * G + g] = s;
+      *p.part_loss = s;
     }
   }
 }
@@ -809,13 +807,252 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
   }
 }
 
+// ----------------------------------------------------------------- step kernel
+// One chunk step for every active chain of a launch plan (one work-group per
+// (chain, token shard)); the partials are reduced by ttt_update.
+template <typename IOT, int NW, bool BF>
+__global__ __launch_bounds__(NW * 64) void ttt_fwd_step(FwdStepArgs p) {
+  constexpr int DH = D * NW * 32;
+  const int lin = xcd_linear_block();
+  const int slot = lin / p.G, g = lin % p.G;
+  const int ai = slot / p.H, head = slot % p.H;
+  const int chain = p.seq_id[ai] * p.H + head;
+  StepCtx c;
+  c.Q = p.Q; c.K = p.K; c.V = p.V; c.O = p.O;
+  c.stride_tok = p.stride_tok; c.stride_head = p.stride_head; c.flags = p.flags;
+  c.W1 = p.w1_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  c.W2 = p.w2_src + (int64_t)(chain % p.w_mod) * p.w_cstride;
+  c.head = head; c.g = g; c.G = p.G;
+  c.gs = p.grad_start[ai]; c.gl = p.grad_len[ai];
+  c.as0 = p.app_start[ai]; c.al = p.app_len[ai];
+  c.part = p.partial + ((int64_t)slot * p.G + g) * (2 * DH);
+  c.part_loss = p.partial_loss + (int64_t)slot * p.G + g;
+  if constexpr (BF)
+    fwd_body_bf<IOT, NW>(c);
+  else
+    fwd_body_f32<IOT, NW>(c);
+}
+
+// ----------------------------------------------------------------- persistent forward
+// Barrier of the G work-groups of a group: every member adds one to the
+// group's counter once its earlier stores are complete, and waits until the
+// counter reaches `target`.  The wait polls at most spin_limit times; past
+// that, or once another wait has given up, it sets bit 0 of *err and returns,
+// so that no wave waits forever (the results are then invalid and the error
+// word says so).
+//
+// Two protocols.  LOCAL (every member of the group runs on the same XCD,
+// checked at run time): the members share that XCD's L2, and a store is
+// visible there once it has completed (the vector L1 is write-through), so a
+// member waits for its own stores (vmcnt 0, every wave), increments the
+// counter, and after the wait drops its CU's L1 lines (buffer_inv sc0) so
+// that its loads read the L2.  AGENT (members on several XCDs, whose L2s are
+// not coherent with each other): release / acquire at agent scope, which
+// writes the L2 back and invalidates it, several microseconds per barrier.
+template <bool LOCAL>
+__device__ __forceinline__ void group_barrier(uint32_t* ctr, uint32_t target, uint32_t* err, uint32_t spin_limit) {
+  if constexpr (LOCAL) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if constexpr (LOCAL)
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t n = 0;
+    while (__hip_atomic_load(ctr, LOCAL ? __ATOMIC_RELAXED : __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      ++n;
+      if (n > spin_limit ||
+          ((n & 255u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+        __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if constexpr (LOCAL) asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+  }
+  __syncthreads();
+}
+__device__ __forceinline__ void group_barrier(bool local, uint32_t* ctr, uint32_t target, uint32_t* err,
+                                              uint32_t spin_limit) {
+  if (local)
+    group_barrier<true>(ctr, target, err, spin_limit);
+  else
+    group_barrier<false>(ctr, target, err, spin_limit);
+}
+
+// Slice g of G of the chain's step: W_{s+1} = W_s - eta * (sum of the G shard
+// partials, in the fixed order of ttt_update: four streams of shards q, q+4,
+// ... combined as (s0 + s1) + (s2 + s3)); also the checkpoint row (W_s), the
+// final weights after the last chunk and, by member 0, the chunk's loss.
+template <int NT, int DH>
+__device__ __forceinline__ void group_reduce(const PersistArgs& p, int g, const float* part, const float* ploss,
+                                             const float* w1s, const float* w2s, float* wdst, float* ck, float* t1,
+                                             float* t2, int head, int s, int gl) {
+  constexpr int n4 = 2 * DH / 4;
+  const int G = p.G;
+  const int lo = (int)((int64_t)g * n4 / G), hi = (int)((int64_t)(g + 1) * n4 / G);
+  for (int i4 = lo + (int)threadIdx.x; i4 < hi; i4 += NT) {
+    const f32x4* pp = reinterpret_cast<const f32x4*>(part) + i4;
+    f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0, s3 = s0;
+    int gg = 0;
+    for (; gg + 4 <= G; gg += 4) {
+      s0 += pp[(int64_t)gg * n4];
+      s1 += pp[(int64_t)(gg + 1) * n4];
+      s2 += pp[(int64_t)(gg + 2) * n4];
+      s3 += pp[(int64_t)(gg + 3) * n4];
+    }
+    for (; gg < G; ++gg) s0 += pp[(int64_t)gg * n4];
+    const f32x4 sum = (s0 + s1) + (s2 + s3);
+    const int idx = 4 * i4;
+    const f32x4 wv = idx < DH ? *reinterpret_cast<const f32x4*>(w1s + idx)
+                              : *reinterpret_cast<const f32x4*>(w2s + (idx - DH));
+    const f32x4 wn = wv - p.eta * sum;
+    *reinterpret_cast<f32x4*>(wdst + idx) = wn;
+    if (ck) *reinterpret_cast<f32x4*>(ck + idx) = wv;
+    if (t1) {
+      if (idx < DH)
+        *reinterpret_cast<f32x4*>(t1 + idx) = wn;
+      else
+        *reinterpret_cast<f32x4*>(t2 + (idx - DH)) = wn;
+    }
+  }
+  if (g == 0 && threadIdx.x == 0 && p.loss) {
+    float sum = 0.f;
+    for (int gg = 0; gg < G; ++gg) sum += ploss[gg];
+    p.loss[(int64_t)head * p.loss_stride + s] = sum / (float)gl;
+  }
+}
+
+template <typename IOT, int NW, bool BF>
+__global__ __launch_bounds__(NW * 64) void ttt_fwd_persist(PersistArgs p) {
+  constexpr int NT = NW * 64;
+  constexpr int DH = D * NW * 32;
+  // Loop state lives in LDS and is re-read (volatile) after every step body,
+  // so that none of it occupies registers while the body runs: the body uses
+  // the whole register budget of two waves per SIMD.
+  __shared__ int st_[6];  // chain entry, step, barrier count, chunks of the chain, LOCAL protocol, member
+  volatile int* st = st_;
+  {
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int lin = p.xcd_map ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+    if (lin / p.G >= p.n_groups) return;
+    if (threadIdx.x == 0) st[5] = lin;
+    // every member records its XCD; the first barrier (agent protocol)
+    // publishes the group's set, and the LOCAL protocol is used from then on
+    // iff it is a single XCD
+    if (threadIdx.x == 0) {
+      const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;  // HW_REG_XCC_ID[3:0]
+      __hip_atomic_fetch_or(p.xcds + lin / p.G, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st[2] = 1;
+    }
+    group_barrier<false>(p.bar + lin / p.G, (uint32_t)p.G, p.err, p.spin_limit);
+    if (threadIdx.x == 0) {
+      const uint32_t m = __hip_atomic_load(p.xcds + lin / p.G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st[4] = (m & (m - 1u)) == 0u ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    {
+        const int lin = __builtin_amdgcn_readfirstlane(st[5]);
+      const int grp = lin / p.G, g = lin % p.G;
+      // the group's member 0 takes the next chain; the barrier publishes it
+      if (g == 0 && threadIdx.x == 0) {
+        const uint32_t c = __hip_atomic_fetch_add(p.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p.slot + grp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      const uint32_t nbar = (uint32_t)__builtin_amdgcn_readfirstlane(st[2]) + 1u;
+      group_barrier(st[4] != 0, p.bar + grp, nbar * (uint32_t)p.G, p.err, p.spin_limit);
+      if (threadIdx.x == 0) {
+        st[2] = (int)nbar;
+        const int c = (int)__hip_atomic_load(p.slot + grp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st[0] = c;
+        st[1] = 0;
+        if (c < p.n_chains) {
+          const int64_t N = p.seq_len[c / p.H];
+          st[3] = (int)((N + p.M - 1) / p.M);
+        }
+      }
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(st[0]) >= p.n_chains) break;
+    }
+    for (;;) {
+        const int c = __builtin_amdgcn_readfirstlane(st[0]), s = __builtin_amdgcn_readfirstlane(st[1]),
+                C = __builtin_amdgcn_readfirstlane(st[3]);
+      if (s > C) break;
+      const int lin = __builtin_amdgcn_readfirstlane(st[5]);
+      const int grp = lin / p.G, g = lin % p.G;
+      float* const wb = p.wbuf + (int64_t)grp * 2 * (2 * DH);
+      float* const part = p.partial + (int64_t)grp * p.G * (2 * DH);
+      float* const ploss = p.partial_loss + (int64_t)grp * p.G;
+      const int e = c / p.H, head = c % p.H, b = p.seq_id[e];
+      const int64_t N = p.seq_len[e], start = p.seq_start[e], M = p.M;
+      const int64_t w0 = ((int64_t)(p.w0_per_seq ? b * p.H : 0) + head) * DH;
+      const float* w1s = s == 0 ? p.w1_0 + w0 : wb + (s & 1) * (2 * DH);
+      const float* w2s = s == 0 ? p.w2_0 + w0 : wb + (s & 1) * (2 * DH) + DH;
+      const int gl = s < C ? (int32_t)min(M, N - (int64_t)s * M) : 0;
+      {
+        StepCtx x;
+        x.Q = p.Q; x.K = p.K; x.V = p.V; x.O = p.O;
+        x.stride_tok = p.stride_tok; x.stride_head = p.stride_head; x.flags = p.flags;
+        x.W1 = w1s; x.W2 = w2s;
+        x.head = head; x.g = g; x.G = p.G;
+        x.gs = start + (int64_t)s * M;
+        x.gl = gl;
+        x.as0 = start + (int64_t)(s - 1) * M;
+        x.al = s >= 1 ? (int32_t)min(M, N - (int64_t)(s - 1) * M) : 0;
+        x.part = part + (int64_t)g * (2 * DH);
+        x.part_loss = ploss + g;
+        if constexpr (BF)
+          fwd_body_bf<IOT, NW, true>(x);
+        else
+          fwd_body_f32<IOT, NW, true>(x);
+      }
+      __syncthreads();
+      // everything the reduction needs is re-read here, so that nothing
+      // computed before the step body stays live through it
+      const int ss = __builtin_amdgcn_readfirstlane(st[1]), CC = __builtin_amdgcn_readfirstlane(st[3]);
+      if (ss < CC) {
+            const int cc = __builtin_amdgcn_readfirstlane(st[0]);
+        const uint32_t nbar = (uint32_t)__builtin_amdgcn_readfirstlane(st[2]);
+        const int lin = __builtin_amdgcn_readfirstlane(st[5]);
+        const int grp = lin / p.G, g = lin % p.G;
+        float* const wb = p.wbuf + (int64_t)grp * 2 * (2 * DH);
+        float* const part = p.partial + (int64_t)grp * p.G * (2 * DH);
+        float* const ploss = p.partial_loss + (int64_t)grp * p.G;
+        const int ee = cc / p.H, hh = cc % p.H, bb = p.seq_id[ee];
+        const int64_t NN = p.seq_len[ee], MM = p.M;
+        const int gll = (int32_t)min(MM, NN - (int64_t)ss * MM);
+        const int64_t w00 = ((int64_t)(p.w0_per_seq ? bb * p.H : 0) + hh) * DH;
+        const float* w1r = ss == 0 ? p.w1_0 + w00 : wb + (ss & 1) * (2 * DH);
+        const float* w2r = ss == 0 ? p.w2_0 + w00 : wb + (ss & 1) * (2 * DH) + DH;
+        const bool local = st[4] != 0;
+        group_barrier(local, p.bar + grp, (nbar + 1u) * (uint32_t)p.G, p.err, p.spin_limit);
+        const bool last = ss == CC - 1;
+        const int64_t chain = (int64_t)bb * p.H + hh;
+        float* ck = p.ckpt ? p.ckpt + ((p.ck_row[ee] + ss) * p.H + hh) * (2 * DH) : nullptr;
+        float* t1 = last && p.wT1 ? p.wT1 + chain * DH : nullptr;
+        float* t2 = last && p.wT1 ? p.wT2 + chain * DH : nullptr;
+        group_reduce<NT, DH>(p, g, part, ploss, w1r, w2r, wb + ((ss + 1) & 1) * (2 * DH), ck, t1, t2, hh, ss, gll);
+        group_barrier(local, p.bar + grp, (nbar + 2u) * (uint32_t)p.G, p.err, p.spin_limit);
+        if (threadIdx.x == 0) st[2] = (int)(nbar + 2u);
+      }
+      if (threadIdx.x == 0) st[1] = ss + 1;
+      __syncthreads();
+    }
+  }
+}
+
+// Zero n words (the persistent forward's counters and error word).
+__global__ void ttt_zero_words(uint32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
 // ----------------------------------------------------------------- launchers
 template <typename IOT, bool BF, int NW>
 static hipError_t launch_fwd_step_t(const FwdStepArgs& a, int n_blocks, hipStream_t st) {
-  if constexpr (BF)
-    hipLaunchKernelGGL((ttt_fwd_step_bf<IOT, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
-  else
-    hipLaunchKernelGGL((ttt_fwd_step<IOT, NW>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
+  hipLaunchKernelGGL((ttt_fwd_step<IOT, NW, BF>), dim3(n_blocks), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -837,6 +1074,37 @@ hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st) {
     hipLaunchKernelGGL(ttt_update<4>, dim3(4 * n_blocks), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(ttt_update<1>, dim3(n_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Persistent forward: the kernel instance for (h, io type, operand type).
+template <typename F>
+static auto with_persist_kernel(int h, bool io_bf16, bool mma_bf16, F&& f) {
+  if (h == 128) {
+    if (io_bf16) return f(ttt_fwd_persist<bf16, 4, true>, 4);
+    return mma_bf16 ? f(ttt_fwd_persist<float, 4, true>, 4) : f(ttt_fwd_persist<float, 4, false>, 4);
+  }
+  if (io_bf16) return f(ttt_fwd_persist<bf16, 8, true>, 8);
+  return mma_bf16 ? f(ttt_fwd_persist<float, 8, true>, 8) : f(ttt_fwd_persist<float, 8, false>, 8);
+}
+
+hipError_t persist_occupancy(int h, bool io_bf16, bool mma_bf16, int* blocks_per_cu, int* threads) {
+  return with_persist_kernel(h, io_bf16, mma_bf16, [&](auto kern, int nw) {
+    *threads = nw * 64;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, nw * 64, 0);
+  });
+}
+
+hipError_t launch_fwd_persist(const PersistArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16,
+                              hipStream_t st) {
+  return with_persist_kernel(h, io_bf16, mma_bf16, [&](auto kern, int nw) {
+    hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(nw * 64), 0, st, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_zero_words(uint32_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(ttt_zero_words, dim3(1), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -8,6 +8,10 @@
 namespace ttt {
 hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st);
+hipError_t persist_occupancy(int h, bool io_bf16, bool mma_bf16, int* blocks_per_cu, int* threads);
+hipError_t launch_fwd_persist(const PersistArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16,
+                              hipStream_t st);
+hipError_t launch_zero_words(uint32_t* p, int n, hipStream_t st);
 hipError_t launch_bwd_step(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_bwd_step_bf(const BwdStepArgs& a, int n_blocks, int h, bool io_bf16, hipStream_t st);
 hipError_t launch_bwd_reduce(const BwdReduceArgs& a, int n_blocks, hipStream_t st);

@@ -37,13 +37,13 @@ def _check_tokens(Q, K, V):
     for t in (Q, K, V):
         if not t.is_cuda:
             raise ValueError("token tensors must be on the GPU")
-        if t.dim() != 3 or t.stride(-1) != 1:
+        if t.dim() != 3 or (t.numel() > 0 and t.stride(-1) != 1):
             raise ValueError("token tensors must be [N][H][d] with d contiguous")
         if t.dtype not in _DT:
             raise ValueError(f"unsupported dtype {t.dtype}")
     if not (Q.shape == K.shape == V.shape and Q.dtype == K.dtype == V.dtype):
         raise ValueError("Q, K, V must share shape and dtype")
-    if not (Q.stride() == K.stride() == V.stride()):
+    if Q.numel() > 0 and not (Q.stride() == K.stride() == V.stride()):
         raise ValueError("Q, K, V must share strides")
 
 
@@ -70,9 +70,10 @@ def _check_w(W1, W2, H, lead=()):
 
 def problem(Q, h, n_tokens, chunk_tokens, eta, flags):
     N, H, d = Q.shape
+    # an empty tensor's strides carry no layout: the defaults apply (0)
+    st_tok, st_head = (Q.stride(0), Q.stride(1)) if Q.numel() > 0 else (0, 0)
     return L.Problem(n_heads=H, d_head=d, d_hidden=h, n_tokens=n_tokens, chunk_tokens=int(chunk_tokens),
-                     stride_tok=Q.stride(0), stride_head=Q.stride(1), eta=float(eta), flags=flags,
-                     io_dtype=_DT[Q.dtype])
+                     stride_tok=st_tok, stride_head=st_head, eta=float(eta), flags=flags, io_dtype=_DT[Q.dtype])
 
 
 def workspace(prob, n_seqs, device):
@@ -81,6 +82,16 @@ def workspace(prob, n_seqs, device):
     if nbytes == 0:
         raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_workspace_bytes")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def workspace_status(ws) -> int:
+    """Error word of the last call on workspace `ws` (bit 0: a barrier wait of
+    the persistent forward gave up).  Waits for the current stream."""
+    lib = L.load()
+    out = ctypes.c_uint32(0)
+    L.check(lib.ttt_workspace_status(_ptr(ws), ws.numel(), ctypes.byref(out), _stream(ws.device)),
+            "ttt_workspace_status")
+    return int(out.value)
 
 
 def n_chunks(n_tokens: int, chunk_tokens: int) -> int:
@@ -112,12 +123,15 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
 
 
 def _tile_cfg(tile_cfg, Q, h, chunk_tokens, n_chains, kind="fwd"):
-    if tile_cfg is None:
-        from .tune import lookup
-        tile_cfg = lookup(h, "bf16" if Q.dtype == torch.bfloat16 else "f32", int(chunk_tokens), n_chains, kind)
+    """An explicit launch shape (dict), or None: the library then uses the
+    autotuner's recorded shape for the problem (compiled in), else its
+    heuristic."""
     if tile_cfg is None:
         return None
-    return L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)))
+    sched = {"persistent": L.TTT_SCHED_PERSISTENT, "stepwise": L.TTT_SCHED_STEPWISE}[tile_cfg.get("schedule",
+                                                                                                  "persistent")]
+    return L.TileCfg(int(tile_cfg.get("wg_per_chain", 0)), int(tile_cfg.get("target_wgs", 0)), sched,
+                     int(tile_cfg.get("spin_limit", 0)))
 
 
 def batch_chunks(cu_seqlens: Sequence[int], chunk_tokens: int):
@@ -191,7 +205,6 @@ def batched_bwd(Q, K, V, cu_seqlens: Sequence[int], W1, W2, eta, chunk_tokens, c
     dW2 = torch.empty_like(W2)
     deta = torch.empty((H,), dtype=torch.float32, device=dev)
     cu_arr = (ctypes.c_int64 * (B + 1))(*cu)
-    # an explicit shape, else the tuned backward shape, else the library's heuristic
     cfg = _tile_cfg(tile_cfg, Q, h, chunk_tokens, B * H, "bwd")
     if ws is None:
         ws = workspace(prob, B, dev)
@@ -237,12 +250,17 @@ class TTTChunk(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, Q, K, V, W1, W2, eta, chunk_tokens, norm=True, mma_bf16=False):
+        # eta is a Python number or a one-element tensor (read on the host:
+        # the step size is a launch argument; a GPU tensor costs one sync)
+        if isinstance(eta, torch.Tensor) and eta.numel() != 1:
+            raise ValueError("eta must be a scalar or a one-element tensor")
         eta_f = float(eta)
         need = any(ctx.needs_input_grad[:6])
         r = chunk_fwd(Q, K, V, W1, W2, eta_f, chunk_tokens, norm=norm, save_ckpt=need, mma_bf16=mma_bf16,
                       want_final=False)
         ctx.chunk_tokens, ctx.norm, ctx.mma_bf16, ctx.eta = chunk_tokens, norm, mma_bf16, eta_f
         ctx.eta_is_tensor = isinstance(eta, torch.Tensor)
+        ctx.eta_shape = tuple(eta.shape) if ctx.eta_is_tensor else ()
         if need:
             ctx.save_for_backward(Q, K, V, W1, W2, r["ckpt"])
         return r["O"]
@@ -255,7 +273,7 @@ class TTTChunk(torch.autograd.Function):
             dO = torch.empty_strided(Q.size(), Q.stride(), dtype=Q.dtype, device=Q.device).copy_(dO)
         g = chunk_bwd(Q, K, V, W1, W2, ctx.eta, ctx.chunk_tokens, ckpt, dO.to(Q.dtype), norm=ctx.norm,
                       mma_bf16=ctx.mma_bf16)
-        deta = g["deta"].sum() if ctx.eta_is_tensor else None
+        deta = g["deta"].sum().reshape(ctx.eta_shape) if ctx.eta_is_tensor else None
         return g["dQ"], g["dK"], g["dV"], g["dW1_0"], g["dW2_0"], deta, None, None, None
 
 

@@ -3,12 +3,14 @@
     python -m paper_2604_08542_amd.tune --workload batch8_uneven_chunk8f_bf16 [--backward]
 
 For one workload it times the batched forward (or, with --backward, the
-batched backward) for each candidate launch shape (total work-groups aimed
-for per chunk step, or a fixed number of work-groups per chain), keeps the
-fastest, and records it in tuned_tiles.json under a key made of (hidden
-size, io dtype, chunk tokens, chains, and "_bwd" for the backward).
-ops.batched_fwd / ops.batched_bwd use the recorded shape when the caller
-passes none.
+batched backward) for each candidate launch shape: the schedule (one
+persistent launch, or one step launch and one update launch per chunk step)
+and the work-groups per chain (or the total work-groups aimed for), keeps
+the fastest, and records it in tuned_tiles.json under a key made of (hidden
+size, io dtype, chunk tokens, chains, and "_bwd" for the backward).  The
+table is also written as csrc/ttt_tuned.h, which the library compiles in:
+every caller of the C ABI that passes no launch shape gets the recorded one
+(rebuild after tuning).
 """
 from __future__ import annotations
 
@@ -37,8 +39,35 @@ def lookup(h: int, io: str, chunk_tokens: int, n_chains: int, kind: str = "fwd",
     return t.get(key(h, io, chunk_tokens, n_chains, kind), {}).get("tile_cfg")
 
 
-CANDIDATES = [dict(target_wgs=t) for t in (128, 256, 384, 512, 768, 1024)] + \
-             [dict(wg_per_chain=g) for g in (1, 2, 4, 8, 16, 32)]
+CANDIDATES = [dict(schedule="stepwise", target_wgs=t) for t in (128, 256, 384, 512, 768, 1024)] + \
+             [dict(schedule="stepwise", wg_per_chain=g) for g in (1, 2, 4, 8, 16, 32)] + \
+             [dict(schedule="persistent")] + [dict(schedule="persistent", wg_per_chain=g) for g in (4, 8, 16, 32)]
+BWD_CANDIDATES = [dict(target_wgs=t) for t in (128, 256, 512, 1024)] + \
+                 [dict(wg_per_chain=g) for g in (2, 4, 8, 16, 32)]
+HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "ttt_tuned.h")
+
+
+def write_header(table: dict, path: str = HEADER):
+    """The tuned launch shapes as a C++ table compiled into the library."""
+    import re
+    rows = []
+    for k in sorted(table):
+        m = re.fullmatch(r"h(\d+)_(f32|bf16)_m(\d+)_c(\d+)(_bwd)?", k)
+        if not m:
+            continue
+        c = table[k]["tile_cfg"]
+        sched = 0 if c.get("schedule", "stepwise") == "persistent" else 1
+        rows.append(f"    {{{m.group(1)}, {1 if m.group(2) == 'bf16' else 0}, {m.group(3)}, {m.group(4)}, "
+                    f"{1 if m.group(5) else 0}, {{{int(c.get('wg_per_chain', 0))}, {int(c.get('target_wgs', 0))}, "
+                    f"{sched}, 0}}}},  // {table[k].get('workload', '')}: {table[k]['ms']:.3f} ms")
+    text = ("// Launch shapes recorded by the autotuner (paper_2604_08542_amd/tune.py) on MI355X; generated from\n"
+            "// tuned_tiles.json, do not edit.  Key: hidden size, BF16 operands, chunk tokens, chains, backward.\n"
+            "#pragma once\n#include <stdint.h>\n\n#include \"../../include/ttt.h\"\n\nnamespace ttt {\n"
+            "struct TunedShape {\n  int32_t h, bf16;\n  int64_t chunk_tokens, chains;\n  int32_t bwd;\n"
+            "  ttt_tile_cfg_t cfg;\n};\ninline constexpr TunedShape kTuned[] = {\n" + "\n".join(rows) +
+            "\n};\n}  // namespace ttt\n")
+    with open(path, "w") as f:
+        f.write(text)
 
 
 def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: bool = True, backward: bool = False):
@@ -59,7 +88,7 @@ def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: boo
         ckpt = ops.batched_fwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
                                save_ckpt=True, want_final=False)["ckpt"]
     results = []
-    for cfg in CANDIDATES:
+    for cfg in (BWD_CANDIDATES if backward else CANDIDATES):
         def run():
             if backward:
                 ops.batched_bwd(dev["Q"], dev["K"], dev["V"], cu, dev["W1"], dev["W2"], w.eta, w.chunk_tokens, ckpt,
@@ -88,16 +117,21 @@ def tune(workload: str, io: str = None, reps: int = 5, seed: int = 0, write: boo
         t[k] = entry
         with open(TABLE, "w") as f:
             json.dump(t, f, indent=1, sort_keys=True)
+        write_header(t)
     print(f"best {best} {best_ms:.3f} ms -> {k}")
     return entry
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--workload", action="append", default=[])
     ap.add_argument("--io", default=None)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--backward", action="store_true", help="tune the batched backward instead of the forward")
+    ap.add_argument("--header-only", action="store_true", help="rewrite csrc/ttt_tuned.h from the table and exit")
     a = ap.parse_args()
+    if a.header_only:
+        write_header(load_table())
+        sys.exit(0)
     for wl in a.workload:
         tune(wl, a.io, a.reps, backward=a.backward)

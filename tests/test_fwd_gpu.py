@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle as orc
-from gpu_util import TOL, host, inputs, rel
+from gpu_util import TOL, apply_consistency, check, err_report, fmt, host, inputs, rel, storage_floor
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,11 @@ CASES = [
     (1000, 2, 256, 333, 0.05, "bf16", True),
     (5496, 1, 128, 1374, 0.1, "bf16", True),
     (1500, 2, 256, 500, 0.05, "f32", True),    # f32 io, bf16 matrix-core operands
+    # large steps: the update moves O by 27-57% (oracle), so a BF16 apply that
+    # used stale weights fails the O gate, and delta-O is gated directly
+    (1000, 2, 256, 333, 4.0, "bf16", True),
+    (1200, 1, 128, 100, 2.0, "bf16", True),
+    (1500, 2, 256, 500, 4.0, "f32", True),
 ]
 
 
@@ -34,26 +39,45 @@ def test_forward_matches_oracle(gpu, N, H, h, M, eta, io, mma):
                         mma_bf16=mma)
     torch.cuda.synchronize()
     ref = orc.ttt_forward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M)
+    ref0 = orc.ttt_forward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], 0.0, M)
     tol = TOL["bf16" if mma or io == "bf16" else "f32"]
-    errs = dict(
-        O=rel(host(r["O"]), ref["O"]),
-        W1_T=rel(host(r["W1_T"]), ref["W1_T"]),
-        W2_T=rel(host(r["W2_T"]), ref["W2_T"]),
-        dW1=rel(host(r["W1_T"]) - x["W1"], ref["W1_T"] - x["W1"]),
-        dW2=rel(host(r["W2_T"]) - x["W2"], ref["W2_T"] - x["W2"]),
-        loss=rel(host(r["loss"]), ref["loss"]),
-        ckpt1=rel(host(r["ckpt"])[:, :, :64 * h].reshape(ref["ckpt1"].shape), ref["ckpt1"]),
-    )
-    print(f"N={N} H={H} h={h} M={M} io={io} mma_bf16={mma}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    for k, v in errs.items():
-        assert v <= tol, (k, v)
-    if tol == TOL["f32"]:
-        r0 = ops().chunk_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], 0.0, M)
-        dO_gpu = host(r["O"]) - host(r0["O"])
-        O0 = orc.ttt_forward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], 0.0, M)["O"]
-        e = rel(dO_gpu, ref["O"] - O0)
-        print(f"  delta-O rel err {e:.2e}")
-        assert e <= tol
+    C = (N + M - 1) // M
+    print(f"N={N} H={H} h={h} M={M} eta={eta} io={io} mma_bf16={mma}")
+    O = host(r["O"])
+    check("O", O, ref["O"], tol)
+    check("W1_T", host(r["W1_T"]), ref["W1_T"], tol)
+    check("W2_T", host(r["W2_T"]), ref["W2_T"], tol)
+    check("dW1", host(r["W1_T"]) - x["W1"], ref["W1_T"] - x["W1"], tol, floor=storage_floor(ref["W1_T"], x["W1"]))
+    check("dW2", host(r["W2_T"]) - x["W2"], ref["W2_T"] - x["W2"], tol, floor=storage_floor(ref["W2_T"], x["W2"]))
+    check("loss", host(r["loss"]), ref["loss"], tol)
+    # every checkpoint: W_0 exactly, then each W_c - W_0 against the oracle
+    ck = host(r["ckpt"]).reshape(C, H, 2, -1)
+    assert np.array_equal(ck[0, :, 0].reshape(x["W1"].shape), x["W1"])
+    assert np.array_equal(ck[0, :, 1].reshape(x["W2"].shape), x["W2"])
+    for c in range(1, C):
+        check(f"dW1 ckpt {c}", ck[c, :, 0].reshape(x["W1"].shape) - x["W1"], ref["ckpt1"][c] - x["W1"], tol,
+              floor=storage_floor(ref["ckpt1"][c], x["W1"]))
+        check(f"dW2 ckpt {c}", ck[c, :, 1].reshape(x["W2"].shape) - x["W2"], ref["ckpt2"][c] - x["W2"], tol,
+              floor=storage_floor(ref["ckpt2"][c], x["W2"]))
+    # the output is closer to the updated model than to the initial one
+    e_eta, e_0 = rel(O, ref["O"]), rel(O, ref0["O"])
+    print(f"  |O - O_ref(eta)| {e_eta:.2e} < |O - O_ref(0)| {e_0:.2e}")
+    assert e_eta < e_0
+    # delta-O = O(eta) - O(0) from the same path, against the oracle's
+    r0 = ops().chunk_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], 0.0, M, mma_bf16=mma)
+    dref = ref["O"] - ref0["O"]
+    effect = np.linalg.norm(dref) / np.linalg.norm(ref["O"])
+    rep = err_report(O - host(r0["O"]), dref)
+    print(f"  delta-O (|dO_ref|/|O_ref| = {effect:.2e}): " + fmt("", rep))
+    if tol == TOL["f32"] or effect >= 0.25:
+        # BF16 operand rounding moves O by ~4e-3 of |O|; delta-O is held to the
+        # tolerance where the update's effect is large enough to resolve it
+        assert rep["norm"] <= tol, rep
+    # the apply of every chunk uses the updated weights W_{c+1}
+    worst = apply_consistency(ops().chunk_fwd, d["Q"], d["K"], d["V"], r["ckpt"], r["W1_T"], r["W2_T"], r["O"], M,
+                              mma)
+    print(f"  apply with W_(c+1) (eta=0 rerun) vs chain O: worst chunk rel {worst:.2e}")
+    assert worst <= 1e-6
 
 
 def test_eta_zero_is_plain_mlp(gpu):

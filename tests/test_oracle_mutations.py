@@ -98,3 +98,22 @@ def test_apply_before_update_is_caught(monkeypatch):
     q = torch.nn.functional.normalize(torch.from_numpy(x["Q"][:, 0]), dim=-1).numpy()
     ref = torch.nn.functional.silu(torch.from_numpy(q @ r["W1_T"][0])).numpy() @ r["W2_T"][0]
     assert rel(r["O"][:, 0], ref) > 1e-3
+
+
+def test_floor_branch_with_projection_is_caught(monkeypatch):
+    """A norm adjoint that keeps the projection term (and divides by the
+    true norm) on rows below the floor is caught by the floor-branch pin."""
+    import test_oracle_pins as P
+
+    def bad(x, dxhat, eps=T.NORM_EPS):
+        xhat, den = T.l2norm_rows(x, eps)
+        n = np.sqrt(np.sum(np.asarray(x, np.float64) ** 2, axis=-1, keepdims=True))
+        proj = np.sum(xhat * dxhat, axis=-1, keepdims=True)
+        return (dxhat - xhat * proj) / np.maximum(n, 1e-300)
+    monkeypatch.setattr(T, "l2norm_rows_bwd", bad)
+    monkeypatch.setattr(orc, "l2norm_rows_bwd", bad)
+    try:
+        P.test_l2norm_adjoint_floor_branch()
+    except AssertionError:
+        return
+    raise AssertionError("the floor-branch pin did not catch the planted mistake")

@@ -220,3 +220,26 @@ def test_l2norm_and_adjoint():
     assert rel(dx, tx.grad.numpy()) < 1e-13
     z = np.zeros((1, 3))
     assert np.array_equal(orc.l2norm_rows(z)[0], z)
+
+
+def test_l2norm_adjoint_floor_branch():
+    """Rows whose norm is below the floor eps = 1e-12 are divided by the
+    constant eps, so their adjoint is dxhat / eps with no projection term.
+    Pinned against torch autograd of F.normalize (which clamps the norm
+    from below at the same eps) on rows above, at and below the floor."""
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal((6, 5))
+    x[1] *= 1e-14   # norm ~2e-14: floor active
+    x[2] *= 3e-13   # norm ~6e-13: floor active
+    x[3] = 0.0      # zero row: floor active, xhat = 0
+    x[4] *= 1e-11   # norm ~2e-11: above the floor
+    dxh = rng.standard_normal((6, 5))
+    dx = orc.l2norm_rows_bwd(x, dxh)
+    tx = torch.from_numpy(x).requires_grad_()
+    (torch.nn.functional.normalize(tx, dim=-1, eps=orc.NORM_EPS) * torch.from_numpy(dxh)).sum().backward()
+    g = tx.grad.numpy()
+    for i in range(6):
+        assert rel(dx[i], g[i]) < 1e-12, i
+    # the floor rows carry no projection term: exactly dxhat / eps
+    assert np.allclose(dx[1], dxh[1] / orc.NORM_EPS, rtol=1e-15, atol=0)
+    assert np.allclose(dx[3], dxh[3] / orc.NORM_EPS, rtol=1e-15, atol=0)
