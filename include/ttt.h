@@ -260,6 +260,26 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
 ttt_status_t ttt_profile_enable(int32_t on);
 ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches);
 
+/* ttt_chunk_fwd without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results and errors as ttt_chunk_fwd,
+ * minus ws / ws_bytes: the scratch (shard partials, per-head ping-pong
+ * weights, counters) is one fixed device array of
+ * TTT_NOALLOC_SCRATCH_BYTES inside the library, present on every GPU the
+ * library runs on until the process ends; the call allocates nothing.
+ * Each head needs three fast-weight-sized FP32 blocks (2*d*h floats each:
+ * two ping-pong copies and at least one shard partial), so problems with
+ * more than 106 heads at h = 256 (213 at h = 128) return TTT_EWORKSPACE
+ * with nothing enqueued; the work-groups per head are limited to the shard
+ * partials that fit.  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on a GPU (other streams,
+ * other host threads) race and must not be issued; calls ordered on one
+ * stream are fine.  Always the stepwise schedule. */
+#define TTT_NOALLOC_SCRATCH_BYTES (40u << 20)
+ttt_status_t ttt_chunk_fwd_noalloc(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
+                                   const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
+                                   float* ckpt, float* loss, void* hip_stream);
+
 /* Device-side status of the last call that used workspace `ws`: copies the
  * workspace's error word to *flags_host (bit 0: a barrier wait of the
  * persistent forward gave up, so that call's outputs are invalid; 0: no

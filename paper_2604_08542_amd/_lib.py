@@ -68,6 +68,8 @@ def load(path: str = LIB_PATH):
     lib.ttt_workspace_bytes.restype = sz
     lib.ttt_chunk_fwd.argtypes = [P, vp, vp, vp, fp, fp, vp, fp, fp, fp, fp, vp, sz, vp]
     lib.ttt_chunk_fwd.restype = st
+    lib.ttt_chunk_fwd_noalloc.argtypes = [P, vp, vp, vp, fp, fp, vp, fp, fp, fp, fp, vp]
+    lib.ttt_chunk_fwd_noalloc.restype = st
     lib.ttt_chunk_bwd.argtypes = [P, vp, vp, vp, fp, fp, fp, vp, vp, vp, vp, fp, fp, fp, vp, sz, vp]
     lib.ttt_chunk_bwd.restype = st
     lib.ttt_batched_fwd.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp, fp, fp,

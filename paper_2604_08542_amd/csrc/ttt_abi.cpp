@@ -100,6 +100,30 @@ WsLayout ws_layout(const Shape& s, int64_t n_chains) {
   return L;
 }
 
+// A forward-only layout inside `capacity` bytes (the fixed scratch of
+// ttt_chunk_fwd_noalloc): the error word and counters, as many shard-partial
+// slots as fit, and the ping-pong weights of every chain.  slot_cap < n_chains
+// means the problem does not fit (not even one work-group per chain).
+WsLayout fwd_layout_in(const Shape& s, int64_t n_chains, size_t capacity) {
+  WsLayout L{};
+  const size_t wbytes = (size_t)2 * s.dh() * sizeof(float);
+  const size_t fixed = align_up(SYNC_BYTES) + align_up(2 * (size_t)n_chains * wbytes) + 2 * ALIGN;
+  const int64_t slots = capacity > fixed ? (int64_t)((capacity - fixed) / (wbytes + sizeof(float))) : 0;
+  L.slot_cap = slots;
+  size_t off = 0;
+  L.sync = off;
+  off = align_up(off + SYNC_BYTES);
+  L.partial = off;
+  off = align_up(off + (size_t)slots * wbytes);
+  L.partial_loss = off;
+  off = align_up(off + (size_t)slots * sizeof(float));
+  L.pp = off;
+  off = align_up(off + 2 * (size_t)n_chains * wbytes);
+  L.adj = L.wlast = L.prep = L.fin = L.deta_seq = off;  // not used by the forward
+  L.total = off;
+  return L;
+}
+
 int default_target_wgs(const Shape& s) { return s.h == 256 ? 256 : 512; }
 
 // The launch shape of a call: the caller's, else the autotuner's recorded
@@ -169,8 +193,9 @@ template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*
 // Also clears the workspace's error word when there are tokens: every
 // forward call starts here (a call without tokens enqueues nothing else).
 ttt_status_t copy_w0_to_final(const Shape& S, int B, const int64_t* cu, const float* W1_0, const float* W2_0,
-                              int w0_per_seq, float* W1_T, float* W2_T, void* ws, size_t ws_bytes, hipStream_t st) {
-  const WsLayout L = ws_layout(S, (int64_t)B * S.H);
+                              int w0_per_seq, float* W1_T, float* W2_T, void* ws, size_t ws_bytes, hipStream_t st,
+                              const WsLayout* layout = nullptr) {
+  const WsLayout L = layout ? *layout : ws_layout(S, (int64_t)B * S.H);
   if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
   if (cu[B] > 0 &&
       !timed_launch(5, st, [&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
@@ -323,9 +348,9 @@ ttt_status_t run_forward_persist(const ttt_problem_t* p, const Shape& S, int B, 
 ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, const void* Q,
                          const void* K, const void* V, const float* W1_0, const float* W2_0, int w0_per_seq,
                          void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, const ttt_tile_cfg_t* cfg,
-                         void* ws, size_t ws_bytes, hipStream_t st) {
+                         void* ws, size_t ws_bytes, hipStream_t st, const WsLayout* layout = nullptr) {
   const int64_t nch_total = (int64_t)B * S.H;
-  const WsLayout L = ws_layout(S, nch_total);
+  const WsLayout L = layout ? *layout : ws_layout(S, nch_total);
   if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
   const int64_t M = S.M;
   std::vector<int64_t> nb(B), cb(B);
@@ -988,6 +1013,48 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
 
 }  // namespace
 
+namespace ttt {
+// ttt_chunk_fwd, on a caller workspace (fixed_scratch null) or on a fixed
+// scratch of ws_bytes whose device address fixed_scratch() returns after the
+// arguments are validated (forward-only compact layout, stepwise schedule,
+// work-groups per chain limited by the slots that fit).
+ttt_status_t chunk_fwd_impl(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                            const float* W2_0, void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, void* ws,
+                            size_t ws_bytes, void* (*fixed_scratch)(), hipStream_t st) {
+  Shape S{};
+  const ttt_status_t e = check_problem(p, &S);
+  if (e != TTT_OK) return e;
+  if (!W1_0 || !W2_0) return TTT_EINVAL;
+  // token tensors may be empty (null) when there are no tokens
+  if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
+  if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+  if (p->n_tokens > 0 && ((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
+  if (p->n_tokens > 0 && ((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
+  for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
+                        (const void*)W2_T, (const void*)ckpt})
+    if (q && !aligned16(q)) return TTT_EINVAL;
+  const int64_t cu[2] = {0, p->n_tokens};
+  ttt_tile_cfg_t cfg = resolve_cfg(nullptr, S, S.H, false);
+  WsLayout fixed{};
+  const WsLayout* layout = nullptr;
+  if (fixed_scratch) {
+    fixed = fwd_layout_in(S, S.H, ws_bytes);
+    if (fixed.slot_cap < S.H) return TTT_EWORKSPACE;  // more chains than the scratch holds
+    layout = &fixed;
+    cfg.schedule = TTT_SCHED_STEPWISE;
+    ws = fixed_scratch();  // after validation: the only HIP calls before enqueueing
+    if (!ws) return TTT_EHIP;
+  }
+  if (cfg.schedule == TTT_SCHED_STEPWISE) {
+    const ttt_status_t e0 = copy_w0_to_final(S, 1, cu, W1_0, W2_0, 0, W1_T, W2_T, ws, ws_bytes, st, layout);
+    if (e0 != TTT_OK || p->n_tokens == 0) return e0;
+    return run_forward(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes, st,
+                       layout);
+  }
+  return run_forward_persist(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes, st);
+}
+}  // namespace ttt
+
 extern "C" {
 
 size_t ttt_workspace_bytes(const ttt_problem_t* p, int32_t n_seqs) {
@@ -1000,27 +1067,8 @@ ttt_status_t ttt_chunk_fwd(const ttt_problem_t* p, const void* Q, const void* K,
                            const float* W2_0, void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, void* ws,
                            size_t ws_bytes, void* hip_stream) {
   try {
-    Shape S{};
-    const ttt_status_t e = check_problem(p, &S);
-    if (e != TTT_OK) return e;
-    if (!W1_0 || !W2_0) return TTT_EINVAL;
-    // token tensors may be empty (null) when there are no tokens
-    if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
-    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
-    if (p->n_tokens > 0 && ((p->flags & TTT_SAVE_CKPT) != 0) != (ckpt != nullptr)) return TTT_EINVAL;
-    if (p->n_tokens > 0 && ((p->flags & TTT_EMIT_LOSS) != 0) != (loss != nullptr)) return TTT_EINVAL;
-    for (const void* q : {Q, K, V, (const void*)W1_0, (const void*)W2_0, (const void*)O, (const void*)W1_T,
-                          (const void*)W2_T, (const void*)ckpt})
-      if (q && !aligned16(q)) return TTT_EINVAL;
-    const int64_t cu[2] = {0, p->n_tokens};
-    const ttt_tile_cfg_t cfg = resolve_cfg(nullptr, S, S.H, false);
-    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (cfg.schedule == TTT_SCHED_STEPWISE) {
-      if (p->n_tokens == 0) return copy_w0_to_final(S, 1, cu, W1_0, W2_0, 0, W1_T, W2_T, ws, ws_bytes, st);
-      return run_forward(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes, st);
-    }
-    return run_forward_persist(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, &cfg, ws, ws_bytes,
-                               st);
+    return ttt::chunk_fwd_impl(p, Q, K, V, W1_0, W2_0, O, W1_T, W2_T, ckpt, loss, ws, ws_bytes, nullptr,
+                               static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return TTT_EINVAL;
   }

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/ttt.h"
 #include "ttt_amu.h"
 #include "ttt_common.h"
 
@@ -24,4 +25,10 @@ hipError_t launch_amu_bwd_apply(const AmuBwdArgs& a, int n_blocks, int h, bool i
 hipError_t launch_amu_bwd_update(const AmuBwdArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16,
                                  hipStream_t st);
 hipError_t launch_amu_psum(const AmuPsumArgs& a, hipStream_t st);
+// ttt_chunk_fwd on a caller workspace (fixed_scratch null), or on a fixed
+// scratch buffer of ws_bytes with a forward-only layout whose device address
+// fixed_scratch() returns (called after validation; null on failure).
+ttt_status_t chunk_fwd_impl(const ttt_problem_t* p, const void* Q, const void* K, const void* V, const float* W1_0,
+                            const float* W2_0, void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, void* ws,
+                            size_t ws_bytes, void* (*fixed_scratch)(), hipStream_t st);
 }  // namespace ttt

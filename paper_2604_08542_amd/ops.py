@@ -122,6 +122,32 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
 
 
+def chunk_fwd_noalloc(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False, emit_loss=False,
+                      mma_bf16=False, out=None, W1_T=None, W2_T=None, ckpt=None, loss=None):
+    """chunk_fwd through the allocation-free entry point: the library uses its
+    fixed device scratch instead of a workspace.  Output tensors may be
+    passed in (then nothing at all is allocated here)."""
+    lib = L.load()
+    _check_tokens(Q, K, V)
+    N, H, d = Q.shape
+    _, h = _check_w(W1, W2, H)
+    prob = problem(Q, h, N, chunk_tokens, eta, _flags(norm, save_ckpt, emit_loss, mma_bf16))
+    C = n_chunks(N, chunk_tokens)
+    dev = Q.device
+    O = _like_tokens(Q, out)
+    W1_T = torch.empty_like(W1) if W1_T is None else W1_T
+    W2_T = torch.empty_like(W2) if W2_T is None else W2_T
+    if save_ckpt and ckpt is None:
+        ckpt = torch.empty((C, H, 2 * d * h), dtype=torch.float32, device=dev)
+    if emit_loss and loss is None:
+        loss = torch.empty((H, C), dtype=torch.float32, device=dev)
+    st = lib.ttt_chunk_fwd_noalloc(ctypes.byref(prob), _ptr(Q), _ptr(K), _ptr(V), _ptr(W1), _ptr(W2), _ptr(O),
+                                   _ptr(W1_T), _ptr(W2_T), _ptr(ckpt if save_ckpt else None),
+                                   _ptr(loss if emit_loss else None), _stream(dev))
+    L.check(st, "ttt_chunk_fwd_noalloc")
+    return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
+
+
 def _tile_cfg(tile_cfg, Q, h, chunk_tokens, n_chains, kind="fwd"):
     """An explicit launch shape (dict), or None: the library then uses the
     autotuner's recorded shape for the problem (compiled in), else its
