@@ -245,20 +245,6 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
                          const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,
                          const void* dO, void* dQ, void* dK, void* dV, float* deta_tok, float* dW1_0,
                          float* dW2_0, float* dW3_0, void* ws, size_t ws_bytes, void* hip_stream);
-/* Benchmark instrumentation.  While enabled, every launch the library
- * enqueues is bracketed by a pair of HIP events on the launch stream (events
- * come from a pool the library owns; enabling clears earlier records).
- * ttt_profile_read waits for the recorded events and returns, per kernel
- * kind (0 = chunk-step kernel, 1 = weight-update kernel, 2 = backward
- * chunk-step kernel, 3 = backward reduction kernel, 4 = backward operand
- * preparation kernel), the summed elapsed
- * milliseconds and the number of launches; arrays have n_kinds entries.
- * `on`: 0 = off, 1 (or -1) = every kind, otherwise bit k+1 of `on` selects
- * kind k (e.g. 2 = chunk-step kernels only, which keeps the event records out
- * of the other launches).
- * Not meant for production calls: it adds event records to the stream. */
-ttt_status_t ttt_profile_enable(int32_t on);
-ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches);
 
 /* ttt_chunk_fwd without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

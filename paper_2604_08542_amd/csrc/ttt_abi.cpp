@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <vector>
 
 #include "../../include/ttt.h"
@@ -142,48 +141,10 @@ ttt_tile_cfg_t resolve_cfg(const ttt_tile_cfg_t* given, const Shape& S, int64_t 
   return c;
 }
 
-// ---------------------------------------------------------------- profiling
-// Optional event pairs around launches (benchmark instrumentation only).
-struct Profiler {
-  std::mutex mu;
-  bool on = false;
-  uint32_t mask = 0;                 // kinds recorded while on
-  std::vector<hipEvent_t> pool;      // 2 events per record
-  std::vector<int> kinds;            // kind of record i
-  size_t used = 0;
-  int begin(int kind, hipStream_t st) {
-    std::lock_guard<std::mutex> g(mu);
-    if (!on || !((mask >> kind) & 1u)) return -1;
-    if (2 * used + 2 > pool.size()) {
-      for (int i = 0; i < 2; ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
-        pool.push_back(e);
-      }
-    }
-    const int idx = (int)used++;
-    if ((size_t)idx >= kinds.size()) kinds.resize(idx + 1);
-    kinds[idx] = kind;
-    (void)hipEventRecord(pool[2 * idx], st);
-    return idx;
-  }
-  void end(int idx, hipStream_t st) {
-    if (idx < 0) return;
-    std::lock_guard<std::mutex> g(mu);
-    (void)hipEventRecord(pool[2 * idx + 1], st);
-  }
-};
-Profiler& prof() {
-  static Profiler p;
-  return p;
-}
-
+// A launch helper: true when the launch was accepted.
 template <typename F>
-bool timed_launch(int kind, hipStream_t st, F&& f) {
-  const int idx = prof().begin(kind, st);
-  const bool ok = f() == hipSuccess;
-  prof().end(idx, st);
-  return ok;
+bool launched(F&& f) {
+  return f() == hipSuccess;
 }
 
 template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
@@ -198,7 +159,7 @@ ttt_status_t copy_w0_to_final(const Shape& S, int B, const int64_t* cu, const fl
   const WsLayout L = layout ? *layout : ws_layout(S, (int64_t)B * S.H);
   if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
   if (cu[B] > 0 &&
-      !timed_launch(5, st, [&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
+      !launched([&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
     return TTT_EHIP;
   if (!W1_T) return TTT_OK;
   const int64_t dh = S.dh();
@@ -336,8 +297,8 @@ ttt_status_t run_forward_persist(const ttt_problem_t* p, const Shape& S, int B, 
     }
     // counters of this launch (and, for the call's first launch, the error word)
     const int z0 = base == 0 ? SYNC_ERR : SYNC_NEXT;
-    if (!timed_launch(5, st, [&] { return launch_zero_words(sync + z0, SYNC_WORDS - z0, st); })) return TTT_EHIP;
-    if (!timed_launch(0, st, [&] { return launch_fwd_persist(a, plan.grid, S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_zero_words(sync + z0, SYNC_WORDS - z0, st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_fwd_persist(a, plan.grid, S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
   }
   return TTT_OK;
@@ -414,7 +375,7 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
         grad_here |= a.grad_len[i] > 0;
       }
       const int n_blocks = (int)(na * S.H * G);
-      if (!timed_launch(0, st, [&] { return launch_fwd_step(a, n_blocks, S.h, S.io_bf16, S.mma_bf16, st); }))
+      if (!launched([&] { return launch_fwd_step(a, n_blocks, S.h, S.io_bf16, S.mma_bf16, st); }))
         return TTT_EHIP;
       if (grad_here) {
         any_grad = true;
@@ -426,7 +387,7 @@ ttt_status_t run_forward(const ttt_problem_t* p, const Shape& S, int B, const in
         u.wT1 = W1_T; u.wT2 = W2_T;
         u.loss = loss; u.loss_stride = (int32_t)cmax; u.chunk = (int32_t)s;
         u.n_active = na;
-        if (!timed_launch(1, st, [&] { return launch_update(u, na * S.H * nbpc, st); })) return TTT_EHIP;
+        if (!launched([&] { return launch_update(u, na * S.H * nbpc, st); })) return TTT_EHIP;
       }
     }
     (void)any_grad;
@@ -485,14 +446,14 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
     a.partial = partial; a.partial_loss = pdeta; a.n_active = 1;
     a.seq_id[0] = 0; a.grad_start[0] = cu[b] + (cb[b] - 1) * M; a.grad_len[0] = mlen(b, cb[b] - 1);
     a.app_start[0] = 0; a.app_len[0] = 0;
-    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_fwd_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
     UpdStepArgs u{};
     u.w1_src = a.w1_src; u.w2_src = a.w2_src; u.w_cstride = a.w_cstride; u.w_mod = a.w_mod;
     u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
     u.partial = partial; u.partial_loss = pdeta; u.w_dst = wlast + b * H * wsz;
     u.n_active = 1; u.seq_id[0] = 0; u.grad_len[0] = a.grad_len[0]; u.is_last[0] = 0;
-    if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
 
   // With one launch group per step, each reduction also writes the operand
@@ -547,11 +508,11 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
         rd.next_slot[i] = fuse ? next_slot[b] : -1;
         rd.ckpt_row[i] = ckoff[b] + s - 1;  // this sequence's W at step r + 1 (read only when next_slot >= 0)
       }
-      if (!prep_ready && !timed_launch(4, st, [&] { return launch_bwd_prep(pa, na, S.mma_bf16, st); }))
+      if (!prep_ready && !launched([&] { return launch_bwd_prep(pa, na, S.mma_bf16, st); }))
         return TTT_EHIP;
-      if (!timed_launch(2, st, [&] { return launch_bwd_step(bs, (int)(n_chains * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+      if (!launched([&] { return launch_bwd_step(bs, (int)(n_chains * G), S.h, S.io_bf16, S.mma_bf16, st); }))
         return TTT_EHIP;
-      if (!timed_launch(3, st, [&] { return launch_bwd_reduce(rd, (int)(n_chains * nbpc), st); })) return TTT_EHIP;
+      if (!launched([&] { return launch_bwd_reduce(rd, (int)(n_chains * nbpc), st); })) return TTT_EHIP;
     }
     prep_ready = fuse;
   }
@@ -560,7 +521,7 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
     sm.src = shared_w0 ? fin : nullptr;
     sm.deta_src = deta_seq; sm.dW1 = dW1_0; sm.dW2 = dW2_0; sm.deta = deta;
     sm.B = B; sm.H = (int32_t)H; sm.h = S.h;
-    if (!timed_launch(3, st, [&] { return launch_bwd_sum(sm, st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_bwd_sum(sm, st); })) return TTT_EHIP;
   }
   return TTT_OK;
 }
@@ -603,7 +564,7 @@ ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void*
       a.app_start[i] = 0;
       a.app_len[i] = 0;
     }
-    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(na * H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_fwd_step(a, (int)(na * H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
   }
   UpdStepArgs u{};
@@ -612,7 +573,7 @@ ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void*
   u.partial = partial; u.partial_loss = partial_loss; u.w_dst = wstar;
   u.wT1 = W1_T; u.wT2 = W2_T; u.loss = loss; u.loss_stride = (int32_t)C; u.chunk = 0;
   u.gcs_chunks = (int32_t)C; u.gcs_M = (int32_t)M; u.gcs_last_len = (int32_t)(N - (C - 1) * M);
-  if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+  if (!launched([&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   if (O) {
     FwdStepArgs a{};
     a.Q = Q; a.K = K; a.V = V; a.O = O;
@@ -625,7 +586,7 @@ ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void*
     a.partial = partial; a.partial_loss = partial_loss;
     a.n_active = 1; a.seq_id[0] = 0;
     a.grad_start[0] = 0; a.grad_len[0] = 0; a.app_start[0] = 0; a.app_len[0] = (int32_t)N;
-    if (!timed_launch(0, st, [&] { return launch_fwd_step(a, (int)(H * Ga), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_fwd_step(a, (int)(H * Ga), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
   }
   return TTT_OK;
@@ -673,7 +634,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   };
   if (C == 0) {  // no tokens: zero gradients
     const BwdReduceArgs r = reduce_args(nullptr, nullptr, true, 1, 0);
-    return timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
+    return launched([&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); }) ? TTT_OK : TTT_EHIP;
   }
   // W* (no outputs)
   ttt_status_t e = run_gcs_forward(p, S, Q, K, V, W1_0, W2_0, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, st,
@@ -686,7 +647,7 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
     u.H = (int32_t)H; u.h = S.h; u.eta = 0.f; u.G = 0;
     u.partial = partial; u.partial_loss = pdeta; u.w_dst = w0;
     u.gcs_chunks = 1; u.gcs_M = 1; u.gcs_last_len = 1;
-    if (!timed_launch(1, st, [&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   const int target = default_target_wgs(S);
   auto grid_g = [&](int64_t len) {
@@ -697,28 +658,28 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   // apply adjoint of all tokens at W*  ->  Wh (and dQ), deta starts at 0
   {
     const BwdPrepArgs pa = prep_args(wstar, nullptr);
-    if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
     const int64_t G = grid_g(N);
     const BwdStepArgs b = step_args(G, 0, 0, 0, (int32_t)N);
-    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
     const BwdReduceArgs r = reduce_args(nullptr, wh, false, 1, G);
-    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
   // update adjoint of each chunk at W0 against Wh, accumulated on top of Wh
   {
     const BwdPrepArgs pa = prep_args(w0, wh);
-    if (!timed_launch(4, st, [&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_bwd_prep(pa, 1, S.mma_bf16, st); })) return TTT_EHIP;
   }
   const float* prev = wh;
   for (int64_t c = 0; c < C; ++c) {
     const int32_t len = (int32_t)std::min<int64_t>(M, N - c * M);
     const int64_t G = grid_g(len);
     const BwdStepArgs b = step_args(G, c * M, len, 0, 0);
-    if (!timed_launch(2, st, [&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_bwd_step(b, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return TTT_EHIP;
     const BwdReduceArgs r = reduce_args(prev, acc[c % 2], c == C - 1, 0, G);
-    if (!timed_launch(3, st, [&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
+    if (!launched([&] { return launch_bwd_reduce(r, (int)(H * nbpc), st); })) return TTT_EHIP;
     prev = acc[c % 2];
   }
   return TTT_OK;
@@ -817,7 +778,7 @@ ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const voi
   auto do_prep = [&](const AmuWeights& w) {
     AmuPrepArgs a{};
     a.src = w; a.prep = prep; a.n_mats = 4; a.H = (int32_t)H; a.h = S.h;
-    return timed_launch(4, st, [&] { return launch_amu_prep(a, S.mma_bf16, st); });
+    return launched([&] { return launch_amu_prep(a, S.mma_bf16, st); });
   };
   auto do_step = [&](int64_t G, int64_t gs, int64_t gl, int64_t as, int64_t al) {
     AmuStepArgs a{};
@@ -825,13 +786,13 @@ ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const voi
     a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
     a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep; a.n_prep = 4; a.partial = partial;
     a.grad_start = gs; a.grad_len = (int32_t)gl; a.app_start = as; a.app_len = (int32_t)al;
-    return timed_launch(0, st, [&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); });
+    return launched([&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); });
   };
   auto do_update = [&](const AmuWeights& src, int64_t G, float* dst, bool last) {
     AmuUpdArgs u{};
     u.src = src; u.partial = partial; u.G = (int32_t)G; u.H = (int32_t)H; u.h = S.h; u.w_dst = dst;
     u.wT1 = last ? W1_T : nullptr; u.wT2 = last ? W2_T : nullptr; u.wT3 = last ? W3_T : nullptr;
-    return timed_launch(1, st, [&] { return launch_amu_update(u, st); });
+    return launched([&] { return launch_amu_update(u, st); });
   };
   if (C == 0) {  // no tokens: W_T = W_0
     if (W1_T && !do_update(w0, 0, pp[0], true)) return TTT_EHIP;
@@ -927,7 +888,7 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
   auto do_prep = [&](const AmuWeights& w, void* dst) {
     AmuPrepArgs a{};
     a.src = w; a.prep = dst; a.n_mats = 6; a.H = (int32_t)H; a.h = S.h;
-    return timed_launch(4, st, [&] { return launch_amu_prep(a, S.mma_bf16, st); });
+    return launched([&] { return launch_amu_prep(a, S.mma_bf16, st); });
   };
   auto do_grad = [&](int64_t start, int64_t len) {  // gradient partials at the weights in prep_u
     AmuStepArgs a{};
@@ -936,14 +897,14 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
     const int64_t G = grid_g(len);
     a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G; a.prep = prep_u; a.n_prep = 6; a.partial = partial;
     a.grad_start = start; a.grad_len = (int32_t)len; a.app_start = 0; a.app_len = 0;
-    if (!timed_launch(0, st, [&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_amu_step(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return int64_t(-1);
     return G;
   };
   auto do_update = [&](const AmuWeights& src, int64_t G, float* dst) {
     AmuUpdArgs u{};
     u.src = src; u.partial = partial; u.G = (int32_t)G; u.H = (int32_t)H; u.h = S.h; u.w_dst = dst;
-    return timed_launch(1, st, [&] { return launch_amu_update(u, st); });
+    return launched([&] { return launch_amu_update(u, st); });
   };
   auto bwd_args = [&](int64_t start, int64_t len, int64_t G) {
     AmuBwdArgs a{};
@@ -956,7 +917,7 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
     const int64_t G = grid_g(len);
     AmuBwdArgs a = bwd_args(start, len, G);
     a.X = Q; a.Y = dO; a.dX = dQ; a.prep_w = prep_a;
-    if (!timed_launch(2, st, [&] { return launch_amu_bwd_apply(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_amu_bwd_apply(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return int64_t(-1);
     return G;
   };
@@ -965,7 +926,7 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
     AmuBwdArgs a = bwd_args(start, len, G);
     a.X = K; a.Y = V; a.dX = dK; a.dY = dV; a.eta_tok = eta_tok; a.deta_tok = deta_tok;
     a.prep_w = prep_u; a.prep_a = prep_h;
-    if (!timed_launch(2, st, [&] { return launch_amu_bwd_update(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+    if (!launched([&] { return launch_amu_bwd_update(a, (int)(H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
       return int64_t(-1);
     return G;
   };
@@ -973,7 +934,7 @@ ttt_status_t run_amu_bwd(const ttt_problem_t* p, const Shape& S, int sync, const
     AmuPsumArgs a{};
     a.partial = partial; a.G = (int32_t)G; a.H = (int32_t)H; a.h = S.h; a.base = base; a.dst = dst;
     if (final) { a.out1 = dW1_0; a.out2 = dW2_0; a.out3 = dW3_0; }
-    return timed_launch(3, st, [&] { return launch_amu_psum(a, st); });
+    return launched([&] { return launch_amu_psum(a, st); });
   };
 
   if (C == 0) {  // no tokens: O is empty, every adjoint is zero
@@ -1252,30 +1213,6 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
   } catch (...) {
     return TTT_EINVAL;
   }
-}
-
-ttt_status_t ttt_profile_enable(int32_t on) {
-  Profiler& P = prof();
-  std::lock_guard<std::mutex> g(P.mu);
-  P.on = on != 0;
-  P.mask = on == 1 || on == -1 ? 0xffffffffu : (uint32_t)on >> 1;
-  P.used = 0;
-  return TTT_OK;
-}
-
-ttt_status_t ttt_profile_read(int32_t n_kinds, double* ms, int64_t* launches) {
-  if (n_kinds < 0 || (n_kinds > 0 && (!ms || !launches))) return TTT_EINVAL;
-  Profiler& P = prof();
-  std::lock_guard<std::mutex> g(P.mu);
-  for (int k = 0; k < n_kinds; ++k) { ms[k] = 0.0; launches[k] = 0; }
-  for (size_t i = 0; i < P.used; ++i) {
-    if (hipEventSynchronize(P.pool[2 * i + 1]) != hipSuccess) return TTT_EHIP;
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, P.pool[2 * i], P.pool[2 * i + 1]) != hipSuccess) return TTT_EHIP;
-    const int k = P.kinds[i];
-    if (k < n_kinds) { ms[k] += t; launches[k] += 1; }
-  }
-  return TTT_OK;
 }
 
 ttt_status_t ttt_workspace_status(const void* ws, size_t ws_bytes, uint32_t* flags_host, void* hip_stream) {
