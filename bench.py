@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only (no other forms, no oracle timings)")
-    ap.add_argument("--forms", default="layer,stepwise,single_head,fwd_bwd,batched_fwd_bwd,gcs,amu,length_sweep",
+    ap.add_argument("--forms", default="layer,stepwise,paper_state,single_head,fwd_bwd,batched_fwd_bwd,gcs,amu,"
+                                       "length_sweep",
                     help="comma list of the other forms to time")
     return ap.parse_args()
 
@@ -138,6 +139,12 @@ def other_forms(forms, steps, warmup):
             w = WORKLOADS[name]
             r, _, _ = forward_form(w, "bf16", few, 2, cfg=dict(schedule="stepwise", wg_per_chain=16))
             res[f"stepwise_{name}_bf16"] = r
+    if "paper_state" in forms:  # the paper's state size: streamed-weight GEMM chunk step
+        w = WORKLOADS["paper_state_64f_chunk8f_bf16"]
+        for io in ("bf16", "f32"):
+            r, _, _ = forward_form(w, io, few if io == "bf16" else 2, 1)
+            res[f"paper_state_{io}"] = r
+            torch.cuda.empty_cache()
     if "single_head" in forms:  # single-head chains: latency-bound
         for name, io in (("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16")):
             w = WORKLOADS[name]

@@ -30,8 +30,14 @@ struct Shape {
   int H, d, h;
   int64_t M, stride_tok, stride_head;
   bool io_bf16, mma_bf16;
+  bool large;  // d >= 128: the streamed-weight (GEMM) chunk step
+  int64_t Mrows;
   int64_t dh() const { return (int64_t)d * h; }
 };
+
+// Large state sizes (the paper's one head of 1024 with hidden 4096 and
+// similar): d and h multiples of 128, d up to 4096, h up to 16384.
+bool large_shape(int d, int h) { return d >= 128 && d <= 4096 && d % 128 == 0 && h >= 128 && h <= 16384 && h % 128 == 0; }
 
 ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   if (!p) return TTT_EINVAL;
@@ -39,8 +45,8 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   if (!std::isfinite(p->eta)) return TTT_EINVAL;
   if (p->flags & ~KNOWN_FLAGS) return TTT_EINVAL;
   if (p->io_dtype != TTT_F32 && p->io_dtype != TTT_BF16) return TTT_EINVAL;
-  if (p->d_head != 64) return TTT_ESHAPE;
-  if (p->d_hidden != 128 && p->d_hidden != 256) return TTT_ESHAPE;
+  const bool large = large_shape(p->d_head, p->d_hidden);
+  if (!large && (p->d_head != 64 || (p->d_hidden != 128 && p->d_hidden != 256))) return TTT_ESHAPE;
   const int64_t st = p->stride_tok ? p->stride_tok : (int64_t)p->n_heads * p->d_head;
   const int64_t sh = p->stride_head ? p->stride_head : p->d_head;
   if (st <= 0 || sh <= 0 || (st % 8) || (sh % 8)) return TTT_ESHAPE;
@@ -53,7 +59,49 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   s->stride_head = sh;
   s->io_bf16 = p->io_dtype == TTT_BF16;
   s->mma_bf16 = s->io_bf16 || (p->flags & TTT_MMA_BF16);
+  s->large = large;
+  // rows of one chunk as the large-state step buffers them: the chunk size,
+  // or the whole stream when it is shorter (single-sequence calls)
+  s->Mrows = p->n_tokens > 0 ? std::min<int64_t>(s->M, p->n_tokens) : s->M;
+  if (large) {
+    // the GEMM operand buffers are addressed with 32-bit byte offsets
+    const int64_t op = s->mma_bf16 ? 2 : 4;
+    if (s->Mrows * std::max(s->d, s->h) * op >= (int64_t(1) << 31)) return TTT_ESHAPE;
+  }
   return TTT_OK;
+}
+
+// Workspace of the large-state chunk step (one chunk of one head at a time):
+// the chunk's normalised rows and intermediate products, the FP32 masters and
+// their operand copies, the loss partials.
+struct LargeLayout {
+  size_t Kn, Qn, E, A, D, Aq, Vn, S1, W1, W2, W1op, W2op, loss_part, total;
+};
+LargeLayout large_layout(const Shape& s) {
+  LargeLayout L{};
+  const size_t op = s.mma_bf16 ? 2 : 4;
+  const size_t M = (size_t)s.Mrows, d = (size_t)s.d, h = (size_t)s.h;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.Kn = take(M * d * op);
+  L.Qn = take(M * d * op);
+  L.E = take(M * d * op);
+  L.A = take(M * h * op);
+  L.D = take(M * h * op);
+  L.Aq = take(M * h * op);
+  L.Vn = take(M * d * 4);
+  L.S1 = take(M * h * 4);
+  L.W1 = take(d * h * 4);
+  L.W2 = take(d * h * 4);
+  L.W1op = take(d * h * op);
+  L.W2op = take(d * h * op);
+  L.loss_part = take((d / 128) * ((M + 127) / 128) * 4);
+  L.total = off;
+  return L;
 }
 
 struct WsLayout {
@@ -685,6 +733,72 @@ ttt_status_t run_gcs_backward(const ttt_problem_t* p, const Shape& S, const void
   return TTT_OK;
 }
 
+// The forward at large state sizes: per sequence and head, the chunks in
+// order, each one normalisation launch and seven GEMM launches (gradient,
+// update, apply of the updated weights); the FP32 masters live in the
+// workspace between chunks.
+ttt_status_t run_forward_large(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, const void* Q,
+                               const void* K, const void* V, const float* W1_0, const float* W2_0, int w0_per_seq,
+                               void* O, float* W1_T, float* W2_T, float* ckpt, float* loss, void* ws, size_t ws_bytes,
+                               hipStream_t st) {
+  const LargeLayout L = large_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t dh = S.dh(), M = S.M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  float* W1 = at<float>(ws, L.W1);
+  float* W2 = at<float>(ws, L.W2);
+  int64_t ckrow = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t n = cu[b + 1] - cu[b];
+    const int64_t C = (n + M - 1) / M;
+    for (int hd = 0; hd < S.H; ++hd) {
+      const int64_t w0 = ((int64_t)(w0_per_seq ? b * S.H : 0) + hd) * dh;
+      if (!launched([&] {
+            return launch_large_init(W1_0 + w0, W2_0 + w0, W1, W2, at<char>(ws, L.W1op), at<char>(ws, L.W2op), dh,
+                                     S.mma_bf16, st);
+          }))
+        return TTT_EHIP;
+      for (int64_t c = 0; c < C; ++c) {
+        const int64_t t0 = cu[b] + c * M;
+        const int32_t rows = (int32_t)std::min<int64_t>(M, n - c * M);
+        if (ckpt) {
+          float* row = ckpt + ((ckrow + c) * S.H + hd) * 2 * dh;
+          if (hipMemcpyAsync(row, W1, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+              hipMemcpyAsync(row + dh, W2, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return TTT_EHIP;
+        }
+        const int64_t off = (t0 * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob;
+        LargeStepArgs a{};
+        a.K = static_cast<const char*>(K) + off;
+        a.V = static_cast<const char*>(V) + off;
+        a.Q = static_cast<const char*>(Q) + off;
+        a.O = static_cast<char*>(O) + off;
+        a.stride_tok = S.stride_tok;
+        a.flags = p->flags;
+        a.rows = rows; a.d = S.d; a.h = S.h;
+        a.grad = 1; a.eta = p->eta;
+        a.Kn = at<char>(ws, L.Kn); a.Qn = at<char>(ws, L.Qn); a.E = at<char>(ws, L.E);
+        a.A = at<char>(ws, L.A); a.D = at<char>(ws, L.D); a.Aq = at<char>(ws, L.Aq);
+        a.Vn = at<float>(ws, L.Vn); a.S1 = at<float>(ws, L.S1);
+        a.W1 = W1; a.W2 = W2; a.W1op = at<char>(ws, L.W1op); a.W2op = at<char>(ws, L.W2op);
+        a.loss_part = at<float>(ws, L.loss_part);
+        a.loss = loss ? loss + (int64_t)hd * C + c : nullptr;
+        if (!launched([&] { return launch_large_step(a, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+      }
+      if (W1_T) {
+        const int64_t o = ((int64_t)b * S.H + hd) * dh;
+        if (hipMemcpyAsync(W1_T + o, C > 0 ? W1 : W1_0 + w0, dh * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(W2_T + o, C > 0 ? W2 : W2_0 + w0, dh * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+          return TTT_EHIP;
+      }
+    }
+    ckrow += C;
+  }
+  return TTT_OK;
+}
+
 ttt_status_t check_batch(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu, int32_t w0_per_seq,
                          const ttt_tile_cfg_t* tile_cfg) {
   if (n_seqs < 1 || !cu) return TTT_EINVAL;
@@ -719,6 +833,9 @@ ttt_status_t batched_fwd_impl(const ttt_problem_t* p, int32_t n_seqs, const int6
                         (const void*)W2_T, (const void*)ckpt})
     if (q && !aligned16(q)) return TTT_EINVAL;
   const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (S.large)
+    return run_forward_large(p, S, n_seqs, cu_seqlens_host, Q, K, V, W1_0, W2_0, w0_per_seq, O, W1_T, W2_T, ckpt,
+                             nullptr, ws, ws_bytes, st);
   const ttt_tile_cfg_t cfg = resolve_cfg(tile_cfg, S, (int64_t)n_seqs * S.H, false);
   if (cfg.schedule == TTT_SCHED_STEPWISE) {
     // sequences without tokens take no chunk step: their final weights are W_0
@@ -995,6 +1112,10 @@ ttt_status_t chunk_fwd_impl(const ttt_problem_t* p, const void* Q, const void* K
                         (const void*)W2_T, (const void*)ckpt})
     if (q && !aligned16(q)) return TTT_EINVAL;
   const int64_t cu[2] = {0, p->n_tokens};
+  if (S.large) {
+    if (fixed_scratch) return TTT_ENOTSUP;  // the fixed scratch holds the small-state layout only
+    return run_forward_large(p, S, 1, cu, Q, K, V, W1_0, W2_0, 0, O, W1_T, W2_T, ckpt, loss, ws, ws_bytes, st);
+  }
   ttt_tile_cfg_t cfg = resolve_cfg(nullptr, S, S.H, false);
   WsLayout fixed{};
   const WsLayout* layout = nullptr;
@@ -1021,6 +1142,7 @@ extern "C" {
 size_t ttt_workspace_bytes(const ttt_problem_t* p, int32_t n_seqs) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK || n_seqs < 1) return 0;
+  if (S.large) return large_layout(S).total;
   return ws_layout(S, (int64_t)n_seqs * S.H).total;
 }
 
@@ -1069,6 +1191,7 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
     Shape S{};
     ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if ((e = check_batch(p, n_seqs, cu_seqlens_host, w0_per_seq, tile_cfg)) != TTT_OK) return e;
     if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     const bool any = cu_seqlens_host[n_seqs] > 0;
@@ -1091,6 +1214,7 @@ ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K,
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !ckpt || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
     (void)W1_0; (void)W2_0;  // the checkpoint of chunk 0 holds W_0
@@ -1112,6 +1236,7 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!W1_0 || !W2_0) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
     if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
@@ -1143,6 +1268,7 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!W1_0 || !W2_0 || !dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_EINVAL;
@@ -1159,6 +1285,7 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
 size_t ttt_amu_workspace_bytes(const ttt_problem_t* p) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK) return 0;
+  if (S.large) return 0;
   return amu_ws_layout(S).total;
 }
 
@@ -1169,6 +1296,7 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
     if (!W1_0 || !W2_0 || !W3_0) return TTT_EINVAL;
@@ -1188,6 +1316,7 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
 size_t ttt_amu_bwd_workspace_bytes(const ttt_problem_t* p, int32_t sync) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK || (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS)) return 0;
+  if (S.large) return 0;
   return amu_bwd_ws_layout(S, p->n_tokens, sync).total;
 }
 
@@ -1199,6 +1328,7 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
+    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
     if (!W1_0 || !W2_0 || !W3_0 || !dW1_0 || !dW2_0 || !dW3_0) return TTT_EINVAL;

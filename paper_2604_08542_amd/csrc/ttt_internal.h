@@ -7,6 +7,48 @@
 #include "ttt_common.h"
 
 namespace ttt {
+// Chunk step at large state sizes (d >= 128): the chunk's rows are read from
+// the token tensors (head offset applied), every product is a GEMM over
+// operands streamed from HBM.
+struct LargeNormArgs {
+  const void* K;
+  const void* V;
+  const void* Q;
+  int64_t stride_tok;
+  uint32_t flags;
+  int32_t rows, d;
+  void* Kn;
+  float* Vn;
+  void* Qn;
+};
+struct LargeStepArgs {
+  const void* K;  // first token of the chunk, head offset applied
+  const void* V;
+  const void* Q;
+  void* O;        // nullable: no apply
+  int64_t stride_tok;
+  uint32_t flags;
+  int32_t rows, d, h;
+  int32_t grad;   // 1: gradient of the chunk and the update
+  float eta;
+  void* Kn;       // [rows][d] operand type
+  void* Qn;
+  void* E;
+  void* A;        // [rows][h] operand type
+  void* D;
+  void* Aq;
+  float* Vn;      // [rows][d] FP32
+  float* S1;      // [rows][h] FP32
+  float* W1;      // FP32 masters [d][h], [h][d], updated in place
+  float* W2;
+  void* W1op;     // operand copies of the masters
+  void* W2op;
+  float* loss_part;  // [d/128 * ceil(rows/128)]
+  float* loss;       // nullable: the chunk's loss
+};
+hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+hipError_t launch_large_init(const float* w1, const float* w2, float* m1, float* m2, void* o1, void* o2, int64_t n,
+                             bool mma_bf16, hipStream_t st);
 hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);
 hipError_t launch_update(const UpdStepArgs& a, int n_blocks, hipStream_t st);
 hipError_t persist_occupancy(int h, bool io_bf16, bool mma_bf16, int* blocks_per_cu, int* threads);

@@ -67,12 +67,16 @@ def test_forward_matches_oracle(gpu, N, H, h, M, eta, io, mma):
     r0 = ops().chunk_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], 0.0, M, mma_bf16=mma)
     dref = ref["O"] - ref0["O"]
     effect = np.linalg.norm(dref) / np.linalg.norm(ref["O"])
-    rep = err_report(O - host(r0["O"]), dref)
-    print(f"  delta-O (|dO_ref|/|O_ref| = {effect:.2e}): " + fmt("", rep))
+    O0 = host(r0["O"])
+    rep = err_report(O - O0, dref)
+    # delta-O is the difference of two outputs: their own errors bound how
+    # well it can be resolved (|err O(eta)| + |err O(0)|, relative to |dO|)
+    floor = (np.linalg.norm(O - ref["O"]) + np.linalg.norm(O0 - ref0["O"])) / np.linalg.norm(dref)
+    print(f"  delta-O (|dO_ref|/|O_ref| = {effect:.2e}, resolution floor {floor:.2e}): " + fmt("", rep))
     if tol == TOL["f32"] or effect >= 0.25:
-        # BF16 operand rounding moves O by ~4e-3 of |O|; delta-O is held to the
+        # BF16 operand rounding moves O by ~4e-3 of |O|: delta-O is held to the
         # tolerance where the update's effect is large enough to resolve it
-        assert rep["norm"] <= tol, rep
+        assert rep["norm"] <= tol + floor, rep
     # the apply of every chunk uses the updated weights W_{c+1}
     worst = apply_consistency(ops().chunk_fwd, d["Q"], d["K"], d["V"], r["ckpt"], r["W1_T"], r["W2_T"], r["O"], M,
                               mma)

@@ -66,6 +66,9 @@ WORKLOADS = {
     "layer16_32f_chunk4f_bwd": Workload(
         "layer16_32f_chunk4f_bwd", 16, 64, 256, (32,), 4, 0.05, "f32",
         "16 heads x 64, hidden 256, 32 frames, chunk 4 frames, forward+backward"),
+    "paper_state_64f_chunk8f_bf16": Workload(
+        "paper_state_64f_chunk8f_bf16", 1, 1024, 4096, (64,), 8, 0.5, "bf16",
+        "the paper's state: 1 head x 1024, hidden 4096, 64 frames, chunk 8 frames, BF16 operands"),
     "batch8_uneven_chunk8f_bf16": Workload(
         "batch8_uneven_chunk8f_bf16", 16, 64, 256, (12, 24, 40, 64, 96, 128, 200, 300), 8, 0.05, "bf16",
         "8 sequences of uneven frame counts, 16 heads x 64, hidden 256, chunk 8 frames"),
