@@ -32,8 +32,14 @@
  *     nothing has been launched.  Launch failures return TTT_EHIP.  No C++
  *     exception crosses this boundary.  Calls from different host threads
  *     are safe; calls that share a workspace must be stream-ordered.
- *   - Supported shapes: d = 64, h in {128, 256}; other sizes return
- *     TTT_ESHAPE.  n_tokens may be 0: token pointers may then be NULL,
+ *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
+ *     chip by every entry point), and large states for ttt_chunk_fwd,
+ *     ttt_batched_fwd and ttt_batched_fwd_ckpt: d a multiple of 256 up to
+ *     4096 and h a multiple of 128 up to 16384 (the paper's single head of
+ *     1024 with hidden 4096), where every product of a chunk step is a GEMM
+ *     over weights streamed from HBM and a chunk's rows times max(d, h)
+ *     elements must stay below 2^31 bytes.  Other sizes return TTT_ESHAPE;
+ *     the other entry points return TTT_ENOTSUP for large states.  n_tokens may be 0: token pointers may then be NULL,
  *     the final weights (if asked for) are the initial ones and nothing
  *     else is written.
  */
@@ -70,8 +76,8 @@ enum {
 
 typedef struct {
   int32_t n_heads;      /* H >= 1 */
-  int32_t d_head;       /* d, must be 64 */
-  int32_t d_hidden;     /* h, 128 or 256 */
+  int32_t d_head;       /* d: 64, or a large state (see above) */
+  int32_t d_hidden;     /* h: 128 or 256 with d = 64, else a large state */
   int64_t n_tokens;     /* N for single-sequence calls (ignored by ttt_batched_fwd) */
   int64_t chunk_tokens; /* tokens per update chunk, >= 1 */
   int64_t stride_tok;   /* elements between consecutive tokens; 0 = H*d; at most 2^22 */

@@ -30,14 +30,16 @@ struct Shape {
   int H, d, h;
   int64_t M, stride_tok, stride_head;
   bool io_bf16, mma_bf16;
-  bool large;  // d >= 128: the streamed-weight (GEMM) chunk step
+  bool large;  // d >= 256: the streamed-weight (GEMM) chunk step
   int64_t Mrows;
   int64_t dh() const { return (int64_t)d * h; }
 };
 
 // Large state sizes (the paper's one head of 1024 with hidden 4096 and
-// similar): d and h multiples of 128, d up to 4096, h up to 16384.
-bool large_shape(int d, int h) { return d >= 128 && d <= 4096 && d % 128 == 0 && h >= 128 && h <= 16384 && h % 128 == 0; }
+// similar): d a multiple of 256 up to 4096, h a multiple of 128 up to 16384.
+bool large_shape(int d, int h) {
+  return d >= 256 && d <= 4096 && d % 256 == 0 && h >= 128 && h <= 16384 && h % 128 == 0;
+}
 
 ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   if (!p) return TTT_EINVAL;
@@ -94,7 +96,7 @@ LargeLayout large_layout(const Shape& s) {
   L.D = take(M * h * op);
   L.Aq = take(M * h * op);
   L.Vn = take(M * d * 4);
-  L.S1 = take(M * h * 4);
+  L.S1 = take(M * h * op);
   L.W1 = take(d * h * 4);
   L.W2 = take(d * h * 4);
   L.W1op = take(d * h * op);
@@ -779,7 +781,7 @@ ttt_status_t run_forward_large(const ttt_problem_t* p, const Shape& S, int B, co
         a.grad = 1; a.eta = p->eta;
         a.Kn = at<char>(ws, L.Kn); a.Qn = at<char>(ws, L.Qn); a.E = at<char>(ws, L.E);
         a.A = at<char>(ws, L.A); a.D = at<char>(ws, L.D); a.Aq = at<char>(ws, L.Aq);
-        a.Vn = at<float>(ws, L.Vn); a.S1 = at<float>(ws, L.S1);
+        a.Vn = at<float>(ws, L.Vn); a.S1 = at<char>(ws, L.S1);
         a.W1 = W1; a.W2 = W2; a.W1op = at<char>(ws, L.W1op); a.W2op = at<char>(ws, L.W2op);
         a.loss_part = at<float>(ws, L.loss_part);
         a.loss = loss ? loss + (int64_t)hd * C + c : nullptr;

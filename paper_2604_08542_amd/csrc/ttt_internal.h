@@ -7,7 +7,7 @@
 #include "ttt_common.h"
 
 namespace ttt {
-// Chunk step at large state sizes (d >= 128): the chunk's rows are read from
+// Chunk step at large state sizes (d >= 256): the chunk's rows are read from
 // the token tensors (head offset applied), every product is a GEMM over
 // operands streamed from HBM.
 struct LargeNormArgs {
@@ -38,7 +38,7 @@ struct LargeStepArgs {
   void* D;
   void* Aq;
   float* Vn;      // [rows][d] FP32
-  float* S1;      // [rows][h] FP32
+  void* S1;       // [rows][h] operand type: SiLU'(Z)
   float* W1;      // FP32 masters [d][h], [h][d], updated in place
   float* W2;
   void* W1op;     // operand copies of the masters

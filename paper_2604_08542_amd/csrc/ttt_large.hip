@@ -25,45 +25,52 @@
 namespace ttt {
 namespace large {
 
-constexpr int BM = 128, BN = 128, BK = 32;  // work-group tile and contraction step
-constexpr int NTH = 256;                     // 4 waves, each a 64 x 64 quarter of the tile
+constexpr int BN = 128;   // work-group tile width
+constexpr int NTH = 256;  // 4 waves, each a (BM/2) x 64 quarter of the BM x 128 tile
+// contraction slice per LDS stage: 64 BF16 or 32 FP32 elements (128 bytes)
+template <typename T>
+constexpr int bk() {
+  return sizeof(T) == 2 ? 64 : 32;
+}
 
 // Operand layouts of C[m][n] = sum_k A(m, k) B(k, n):
 //   KMAJ  the operand is stored [m or n][k] (k contiguous), pitch ld
 //   MNMAJ the operand is stored [k][m or n] (m or n contiguous), pitch ld
 enum { KMAJ = 0, MNMAJ = 1 };
 
-template <typename T>
-struct Tile;
-// BF16 operands: 32x32x16 products.  A lane's 8 contraction slots hold, for
-// lane half hf and product step j, k = 16j + 4hf + {0..3} and
-// 16j + 8 + 4hf + {0..3}; both operands use this order (the order of the
-// transposing LDS read), so a k-major and an mn-major operand can be mixed.
-template <>
-struct Tile<bf16> {
-  static constexpr int KLD = BK + 8;    // pitch of a k-major tile [128][BK]
-  static constexpr int MLD = 128 + 8;   // pitch of an mn-major tile [BK][128]
-  static constexpr int ELEMS = 128 * KLD > BK * MLD ? 128 * KLD : BK * MLD;
-};
-// FP32 operands: 32x32x2 products, lane (l32, hf) holds k = 2j + hf.
-template <>
-struct Tile<float> {
-  static constexpr int KLD = BK + 1;
-  static constexpr int MLD = 128 + 4;
-  static constexpr int ELEMS = 128 * KLD > BK * MLD ? 128 * KLD : BK * MLD;
+// LDS tile of ROWS rows (m or n) by BK (contraction).  BF16 operands feed
+// 32x32x16 products: a lane's 8 contraction slots hold, for lane half hf and
+// product step j, k = 16j + 4hf + {0..3} and 16j + 8 + 4hf + {0..3}; both
+// operands use this order (the order of the transposing LDS read), so a
+// k-major and an mn-major operand can be mixed.  FP32 operands feed 32x32x2
+// products, lane (l32, hf) holding k = 2j + hf.
+//
+// Pitches (in 4-byte LDS banks): a k-major BF16 row is 34 banks, so the
+// 8-byte reads of 16 lanes from 16 consecutive rows cover the 32 banks once;
+// an mn-major BF16 row is 72 banks (8 mod 32), so the four rows of 32 bytes
+// that a 16-lane group of the transposing read touches fall on disjoint
+// banks.  FP32: 33 banks (k-major, 4-byte reads down a column), 132 (mn-major,
+// consecutive lanes on consecutive banks).
+template <typename T, int ROWS>
+struct Tile {
+  static constexpr int BK = bk<T>();
+  static constexpr int KLD = sizeof(T) == 2 ? BK + 4 : BK + 1;       // pitch of a k-major tile [ROWS][BK]
+  static constexpr int MLD = sizeof(T) == 2 ? ROWS + 16 : ROWS + 4;  // pitch of an mn-major tile [BK][ROWS]
+  static constexpr int ELEMS = ROWS * KLD > BK * MLD ? ROWS * KLD : BK * MLD;
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// Global -> registers -> LDS staging of one operand tile (rows0 .. +128 of the
-// m/n axis, k0 .. k0+BK of the contraction).  Loads go through a buffer
-// resource that covers exactly the valid part of the operand, so rows past
-// its end (ragged token counts) read as zero.
-template <typename T, int LAYOUT>
+// Global -> registers -> LDS staging of one operand tile (rows mn0 .. +ROWS
+// of the m/n axis, k0 .. k0+BK of the contraction).  Loads go through a
+// buffer resource that covers exactly the valid part of the operand, so rows
+// past its end (ragged token counts) read as zero.
+template <typename T, int LAYOUT, int ROWS>
 struct Stage {
-  static constexpr int BYTES = 128 * BK * (int)sizeof(T);
+  static constexpr int BK = bk<T>();
+  static constexpr int BYTES = ROWS * BK * (int)sizeof(T);
   static constexpr int PER = BYTES / NTH / 16;  // 16-byte loads per thread
+  static constexpr int EPC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   u32x4 r[PER];
   __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int ld, int mn0, int k0) {
     const int tid = threadIdx.x;
@@ -71,14 +78,14 @@ struct Stage {
     for (int i = 0; i < PER; ++i) {
       const int c = tid + i * NTH;  // 16-byte chunk index within the tile
       int row, col;
-      if constexpr (LAYOUT == KMAJ) {  // [128][BK]: BK*sizeof(T)/16 chunks per row
-        constexpr int CPR = BK * (int)sizeof(T) / 16;
+      if constexpr (LAYOUT == KMAJ) {  // [ROWS][BK]
+        constexpr int CPR = BK / EPC;
         row = mn0 + c / CPR;
-        col = k0 + (c % CPR) * (16 / (int)sizeof(T));
-      } else {  // [BK][128]
-        constexpr int CPR = 128 * (int)sizeof(T) / 16;
+        col = k0 + (c % CPR) * EPC;
+      } else {  // [BK][ROWS]
+        constexpr int CPR = ROWS / EPC;
         row = k0 + c / CPR;
-        col = mn0 + (c % CPR) * (16 / (int)sizeof(T));
+        col = mn0 + (c % CPR) * EPC;
       }
       r[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, (row * ld + col) * (int)sizeof(T), 0, 0);
     }
@@ -90,14 +97,19 @@ struct Stage {
       const int c = tid + i * NTH;
       int off;
       if constexpr (LAYOUT == KMAJ) {
-        constexpr int CPR = BK * (int)sizeof(T) / 16;
-        off = (c / CPR) * Tile<T>::KLD + (c % CPR) * (16 / (int)sizeof(T));
+        constexpr int CPR = BK / EPC;
+        off = (c / CPR) * Tile<T, ROWS>::KLD + (c % CPR) * EPC;
       } else {
-        constexpr int CPR = 128 * (int)sizeof(T) / 16;
-        off = (c / CPR) * Tile<T>::MLD + (c % CPR) * (16 / (int)sizeof(T));
+        constexpr int CPR = ROWS / EPC;
+        off = (c / CPR) * Tile<T, ROWS>::MLD + (c % CPR) * EPC;
       }
-      if constexpr (sizeof(T) == 2 || LAYOUT == MNMAJ) {
+      if constexpr (LAYOUT == MNMAJ) {
         *reinterpret_cast<u32x4*>(lds + off) = r[i];
+      } else if constexpr (sizeof(T) == 2) {  // k-major BF16 rows are 8-byte aligned: two 8-byte stores
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x4 v = r[i];
+        reinterpret_cast<u32x2*>(lds + off)[0] = (u32x2){v[0], v[1]};
+        reinterpret_cast<u32x2*>(lds + off)[1] = (u32x2){v[2], v[3]};
       } else {  // FP32 k-major rows have an odd pitch: four 4-byte stores
         const u32x4 v = r[i];
 #pragma unroll
@@ -109,13 +121,14 @@ struct Stage {
 
 // Operand fragment of product step j for the 32-wide block starting at mn
 // (tile-local) of a staged tile.
-template <typename T, int LAYOUT>
+template <typename T, int LAYOUT, int ROWS>
 __device__ __forceinline__ auto frag(const T* t, int mn, int j) {
   const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
+  using TL = Tile<T, ROWS>;
   if constexpr (sizeof(T) == 2) {
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
     if constexpr (LAYOUT == KMAJ) {
-      const bf16* row = t + (mn + l32) * Tile<T>::KLD + 16 * j + 4 * hf;
+      const bf16* row = t + (mn + l32) * TL::KLD + 16 * j + 4 * hf;
       const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row);
       const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 8);
       return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -123,75 +136,90 @@ __device__ __forceinline__ auto frag(const T* t, int mn, int j) {
       // transposing read: in each 16-lane group lane i addresses row
       // t0 + i/4, columns c0 + 4(i%4)..+3 and receives T[t0 + q][c0 + i], q < 4
       const int l16 = l & 15;
-      const int off = (4 * hf + (l16 >> 2)) * Tile<T>::MLD + mn + 16 * ((l >> 4) & 1) + 4 * (l16 & 3);
-      const bf16* p0 = t + off + 16 * j * Tile<T>::MLD;
+      const int off = (4 * hf + (l16 >> 2)) * TL::MLD + mn + 16 * ((l >> 4) & 1) + 4 * (l16 & 3);
+      const bf16* p0 = t + off + 16 * j * TL::MLD;
       const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
           (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0)));
       const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
-          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0 + 8 * Tile<T>::MLD)));
+          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0 + 8 * TL::MLD)));
       return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
   } else {
     if constexpr (LAYOUT == KMAJ)
-      return t[(mn + l32) * Tile<T>::KLD + 2 * j + hf];
+      return t[(mn + l32) * TL::KLD + 2 * j + hf];
     else
-      return t[(2 * j + hf) * Tile<T>::MLD + mn + l32];
+      return t[(2 * j + hf) * TL::MLD + mn + l32];
   }
 }
 
-// Product steps per BK contraction slice.
+// Product steps per contraction slice.
 template <typename T>
 constexpr int ksteps() {
-  return sizeof(T) == 2 ? BK / 16 : BK / 2;
+  return sizeof(T) == 2 ? bk<T>() / 16 : bk<T>() / 2;
 }
 
-// C tile (this work-group's 128 x 128) accumulated over the whole
+// C tile (this work-group's BM x 128) accumulated over the whole
 // contraction, then handed to the epilogue element by element:
-// ep(row, col, value) for every valid row < m_rows (all columns are valid).
-template <typename T, int LA, int LB, typename EP>
+// ep(row, col, value); rows past the operand's end are the epilogue's to skip.
+template <typename T, int LA, int LB, int BM, typename EP>
 __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows, int K,
                                           int m0, int n0, EP& ep) {
-  __shared__ __attribute__((aligned(16))) T sa[2][Tile<T>::ELEMS];
-  __shared__ __attribute__((aligned(16))) T sb[2][Tile<T>::ELEMS];
-  const int w = threadIdx.x >> 6, wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  constexpr int MB = BM / 64;  // 32-row blocks per wave (each wave: BM/2 rows x 64 columns)
+  __shared__ __attribute__((aligned(16))) T sa[2][Tile<T, BM>::ELEMS];
+  __shared__ __attribute__((aligned(16))) T sb[2][Tile<T, BN>::ELEMS];
+  const int w = threadIdx.x >> 6, wm = (w >> 1) * (BM / 2), wn = (w & 1) * 64;
   // buffer resources over the valid rows of each operand
   auto rsrc = [](const T* p, int rows, int ld) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, rows * ld * (int)sizeof(T), 0x00020000);
   };
   const auto ra = rsrc(A, a_rows, lda), rb = rsrc(B, b_rows, ldb);
-  Stage<T, LA> ga;
-  Stage<T, LB> gb;
+  // Three-stage pipeline: while slice kt is multiplied out of one LDS
+  // buffer, slice kt+1 waits in the other and slice kt+2 is in flight from
+  // HBM into registers (two register stages, alternating), so a global load
+  // has two slices of products to arrive before it is needed.
+  Stage<T, LA, BM> ga[2];
+  Stage<T, LB, BN> gb[2];
+  constexpr int BK = bk<T>();
   const int nk = (K + BK - 1) / BK;
-  f32x16 acc[2][2] = {};
-  ga.load(ra, lda, m0, 0);
-  gb.load(rb, ldb, n0, 0);
-  ga.store(sa[0]);
-  gb.store(sb[0]);
+  f32x16 acc[MB][2] = {};
+  ga[0].load(ra, lda, m0, 0);
+  gb[0].load(rb, ldb, n0, 0);
+  if (nk > 1) {
+    ga[1].load(ra, lda, m0, BK);
+    gb[1].load(rb, ldb, n0, BK);
+  }
+  ga[0].store(sa[0]);
+  gb[0].store(sb[0]);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      ga.load(ra, lda, m0, (kt + 1) * BK);
-      gb.load(rb, ldb, n0, (kt + 1) * BK);
+  auto body = [&](int kt, auto PC) {
+    constexpr int P = decltype(PC)::value;  // kt & 1
+    if (kt + 2 < nk) {  // slice kt+2 into register stage P (free: slice kt left it last iteration)
+      ga[P].load(ra, lda, m0, (kt + 2) * BK);
+      gb[P].load(rb, ldb, n0, (kt + 2) * BK);
     }
 #pragma unroll
     for (int j = 0; j < ksteps<T>(); ++j) {
-      const auto a0 = frag<T, LA>(sa[cur], wm, j), a1 = frag<T, LA>(sa[cur], wm + 32, j);
-      const auto b0 = frag<T, LB>(sb[cur], wn, j), b1 = frag<T, LB>(sb[cur], wn + 32, j);
-      acc[0][0] = mma32(a0, b0, acc[0][0]);
-      acc[0][1] = mma32(a0, b1, acc[0][1]);
-      acc[1][0] = mma32(a1, b0, acc[1][0]);
-      acc[1][1] = mma32(a1, b1, acc[1][1]);
+      const auto b0 = frag<T, LB, BN>(sb[P], wn, j), b1 = frag<T, LB, BN>(sb[P], wn + 32, j);
+#pragma unroll
+      for (int bm = 0; bm < MB; ++bm) {
+        const auto a = frag<T, LA, BM>(sa[P], wm + 32 * bm, j);
+        acc[bm][0] = mma32(a, b0, acc[bm][0]);
+        acc[bm][1] = mma32(a, b1, acc[bm][1]);
+      }
     }
-    if (kt + 1 < nk) {
-      ga.store(sa[cur ^ 1]);
-      gb.store(sb[cur ^ 1]);
+    if (kt + 1 < nk) {  // slice kt+1 (register stage P^1) into the other LDS buffer
+      ga[P ^ 1].store(sa[P ^ 1]);
+      gb[P ^ 1].store(sb[P ^ 1]);
     }
     __syncthreads();
+  };
+  for (int kt = 0; kt < nk; kt += 2) {
+    body(kt, std::integral_constant<int, 0>{});
+    if (kt + 1 < nk) body(kt + 1, std::integral_constant<int, 1>{});
   }
   const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
 #pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
+  for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
@@ -220,14 +248,14 @@ struct EpBase {
 template <typename T, bool GRAD>
 struct EpAct : EpBase {
   T* a;
-  float* s1;
+  T* s1;
   int ld, rows;
   __device__ __forceinline__ void operator()(int r, int c, float z) {
     if (r >= rows) return;
     float sg;
     const float av = silu_sig(z, sg);
     put(a + (int64_t)r * ld + c, av);
-    if constexpr (GRAD) s1[(int64_t)r * ld + c] = fmaf(av, 1.0f - sg, sg);
+    if constexpr (GRAD) put(s1 + (int64_t)r * ld + c, fmaf(av, 1.0f - sg, sg));
   }
 };
 // R = Y - V, E = scale * R; sum of R^2 of this tile into loss_part[tile].
@@ -259,11 +287,11 @@ struct EpRes {
 template <typename T>
 struct EpD : EpBase {
   T* d;
-  const float* s1;
+  const T* s1;
   int ld, rows;
   __device__ __forceinline__ void operator()(int r, int c, float p) {
     if (r >= rows) return;
-    put(d + (int64_t)r * ld + c, p * s1[(int64_t)r * ld + c]);
+    put(d + (int64_t)r * ld + c, p * (float)s1[(int64_t)r * ld + c]);
   }
 };
 // W -= eta * G (FP32 master), then the operand copy of the new W.
@@ -294,40 +322,51 @@ struct EpOut : EpBase {
 
 // ------------------------------------------------------------- kernels
 // One launch of one product; grid (N / 128, ceil(M / 128)).
-template <typename T, int LA, int LB, typename EP>
+template <typename T, int LA, int LB, int BM, typename EP>
 __global__ __launch_bounds__(NTH) void k_gemm(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows,
                                                 int K, EP ep) {
-  gemm_tile<T, LA, LB>(A, lda, a_rows, B, ldb, b_rows, K, blockIdx.y * BM, blockIdx.x * BN, ep);
+  gemm_tile<T, LA, LB, BM>(A, lda, a_rows, B, ldb, b_rows, K, blockIdx.y * BM, blockIdx.x * BN, ep);
 }
 
-// Row normalisation of the chunk's K, V, Q rows (one wave per token, the
-// row's elements strided over the lanes, two passes): Kn, Qn in the operand
-// type, Vn in FP32 (the residual is formed in FP32).
+// Row normalisation of the chunk's K, V, Q rows (one wave per token; each
+// lane holds runs of 4 consecutive elements, 256 elements per wave pass, at
+// most 16 passes): Kn, Qn in the operand type, Vn in FP32 (the residual is
+// formed in FP32).
 template <typename IOT, typename T>
 __global__ __launch_bounds__(256) void k_norm(LargeNormArgs p) {
+  typedef IOT iov4 __attribute__((ext_vector_type(4)));
+  typedef T opv4 __attribute__((ext_vector_type(4)));
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (row >= p.rows) return;
+  const int passes = p.d / 256;
   for (int which = 0; which < 3; ++which) {
     const IOT* src = static_cast<const IOT*>(which == 0 ? p.K : which == 1 ? p.V : p.Q) +
                      (int64_t)row * p.stride_tok;
     const bool nrm = (p.flags >> (which == 0 ? 1 : which == 1 ? 2 : 0)) & 1u;
+    f32x4 x[16];
     float ss = 0.f;
-    for (int i = l; i < p.d; i += 64) {
-      const float x = (float)src[i];
-      ss = fmaf(x, x, ss);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < passes) {
+        const iov4 v = *reinterpret_cast<const iov4*>(src + 256 * i + 4 * l);
+        x[i] = (f32x4){(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ss = fmaf(x[i][e], x[i][e], ss);
+      }
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
     const float inv = nrm ? 1.0f / fmaxf(sqrtf(ss), NORM_EPS) : 1.0f;
-    for (int i = l; i < p.d; i += 64) {
-      const float x = (float)src[i] * inv;
-      const int64_t o = (int64_t)row * p.d + i;
-      if (which == 0)
-        static_cast<T*>(p.Kn)[o] = (T)x;
-      else if (which == 1)
-        p.Vn[o] = x;
-      else
-        static_cast<T*>(p.Qn)[o] = (T)x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < passes) {
+        const f32x4 y = x[i] * inv;
+        const int64_t o = (int64_t)row * p.d + 256 * i + 4 * l;
+        if (which == 1)
+          *reinterpret_cast<f32x4*>(p.Vn + o) = y;
+        else
+          *reinterpret_cast<opv4*>(static_cast<T*>(which == 0 ? p.Kn : p.Qn) + o) = (opv4){(T)y[0], (T)y[1], (T)y[2], (T)y[3]};
+      }
     }
   }
 }
@@ -356,7 +395,10 @@ __global__ void k_loss(const float* part, int n, float inv_m, float* out) {
 template <typename T, typename IOT>
 hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
   const int M = a.rows, d = a.d, h = a.h;
-  const int mt = (M + BM - 1) / BM;
+  // tile rows (128 everywhere: two waves per SIMD fit, which a 256-row tile
+  // with its 128 accumulator registers per lane does not)
+  constexpr int BMT = 128, BMW = 128;
+  const int mt = (M + BMT - 1) / BMT;
   T* Kn = static_cast<T*>(a.Kn);
   T* Qn = static_cast<T*>(a.Qn);
   T* E = static_cast<T*>(a.E);
@@ -369,33 +411,33 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_norm<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, na);
   if (a.grad) {
     // Z = Kn W1 -> A, S1
-    EpAct<T, true> e1{{}, Aa, a.S1, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, EpAct<T, true>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M,
+    EpAct<T, true> e1{{}, Aa, static_cast<T*>(a.S1), h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct<T, true>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M,
                        W1o, h, d, d, e1);
     // Y = A W2 -> E, loss partials
     EpRes<T> e2{E, a.Vn, a.loss_part, d, M, 2.0f / (float)M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, EpRes<T>>), dim3(d / BN, mt), dim3(NTH), 0, st, Aa, h, M, W2o, d,
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpRes<T>>), dim3(d / BN, mt), dim3(NTH), 0, st, Aa, h, M, W2o, d,
                        h, h, e2);
     if (a.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, st, a.loss_part, (d / BN) * mt, 1.0f / (float)M,
                                    a.loss);
     // P = E W2^T -> D
-    EpD<T> e3{{}, Dd, a.S1, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, EpD<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, E, d, M, W2o, d, h, d,
+    EpD<T> e3{{}, Dd, static_cast<const T*>(a.S1), h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpD<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, E, d, M, W2o, d, h, d,
                        e3);
     // W1 -= eta Kn^T D ; W2 -= eta A^T E (contractions over the chunk's tokens)
     EpUpd<T> e4{{}, a.W1, W1o, h, a.eta};
-    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, EpUpd<T>>), dim3(h / BN, d / BM), dim3(NTH), 0, st, Kn, d, M, Dd,
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(h / BN, d / BMW), dim3(NTH), 0, st, Kn, d, M, Dd,
                        h, M, M, e4);
     EpUpd<T> e5{{}, a.W2, W2o, d, a.eta};
-    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, EpUpd<T>>), dim3(d / BN, h / BM), dim3(NTH), 0, st, Aa, h, M, E, d,
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(d / BN, h / BMW), dim3(NTH), 0, st, Aa, h, M, E, d,
                        M, M, e5);
   }
   if (a.O) {
     EpAct<T, false> e6{{}, Aq, nullptr, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, EpAct<T, false>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M, W1o,
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct<T, false>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M, W1o,
                        h, d, d, e6);
     EpOut<IOT> e7{{}, static_cast<IOT*>(a.O), a.stride_tok, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, EpOut<IOT>>), dim3(d / BN, mt), dim3(NTH), 0, st, Aq, h, M, W2o, d,
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpOut<IOT>>), dim3(d / BN, mt), dim3(NTH), 0, st, Aq, h, M, W2o, d,
                        h, h, e7);
   }
   return hipGetLastError();
