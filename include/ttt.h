@@ -190,10 +190,11 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
  * mapped with W*: O = f_{W*}(Q).  Equal to ttt_chunk_fwd when there is one
  * chunk.  Buffers as in ttt_chunk_fwd; W1_T/W2_T receive W* (nullable);
  * loss [H][C] (iff TTT_EMIT_LOSS) holds each chunk's loss at W0.
- * TTT_SAVE_CKPT is not used (the only weights are W0 and W*).  All chunks'
- * shard partials of one gradient pass live in the workspace at once, so
- * chunks x heads may not exceed max(H, 1024): beyond that the call returns
- * TTT_ENOTSUP with nothing enqueued. */
+ * TTT_SAVE_CKPT is not used (the only weights are W0 and W*).  The chunks'
+ * shard partials share the workspace's max(H, 1024) partial slots: a stream
+ * with more chunks x heads than that is summed in passes of as many chunks
+ * as fit (each pass's sum added onto the running total in pass order), so
+ * any chunk count runs in the workspace of ttt_workspace_bytes(p, 1). */
 ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                          const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
                          float* loss, void* ws, size_t ws_bytes, void* hip_stream);
@@ -201,8 +202,9 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
 /* Backward of ttt_gcs_fwd for sum <O, dO>: the adjoint of W* collects the
  * apply adjoint of every token, each chunk's update adjoint is taken at W0
  * against it, and dW0 = adjoint of W* + the sum of the chunks' terms.
- * Outputs as in ttt_chunk_bwd; W* is recomputed, no checkpoint is needed.
- * Same chunks x heads limit as ttt_gcs_fwd (TTT_ENOTSUP, nothing enqueued). */
+ * Outputs as in ttt_chunk_bwd; W* is recomputed (as ttt_gcs_fwd, in passes
+ * when the chunks x heads exceed the partial slots), no checkpoint is
+ * needed. */
 ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                          const float* W1_0, const float* W2_0, const void* dO, void* dQ, void* dK,
                          void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes,

@@ -46,7 +46,13 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   if (p->n_heads < 1 || p->chunk_tokens < 1 || p->n_tokens < 0) return TTT_EINVAL;
   if (!std::isfinite(p->eta)) return TTT_EINVAL;
   if (p->flags & ~KNOWN_FLAGS) return TTT_EINVAL;
-  if (p->io_dtype != TTT_F32 && p->io_dtype != TTT_BF16) return TTT_EINVAL;
+  // the dtype field is read as an integer: a C caller may store any value
+  // there, and loading one outside the enumeration as the enum type is
+  // undefined in C++
+  int32_t io_dtype;
+  static_assert(sizeof(io_dtype) == sizeof(p->io_dtype), "ttt_dtype_t is a 32-bit enum");
+  std::memcpy(&io_dtype, &p->io_dtype, sizeof io_dtype);
+  if (io_dtype != TTT_F32 && io_dtype != TTT_BF16) return TTT_EINVAL;
   const bool large = large_shape(p->d_head, p->d_hidden);
   if (!large && (p->d_head != 64 || (p->d_hidden != 128 && p->d_hidden != 256))) return TTT_ESHAPE;
   const int64_t st = p->stride_tok ? p->stride_tok : (int64_t)p->n_heads * p->d_head;
@@ -59,7 +65,7 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
   s->M = p->chunk_tokens;
   s->stride_tok = st;
   s->stride_head = sh;
-  s->io_bf16 = p->io_dtype == TTT_BF16;
+  s->io_bf16 = io_dtype == TTT_BF16;
   s->mma_bf16 = s->io_bf16 || (p->flags & TTT_MMA_BF16);
   s->large = large;
   // rows of one chunk as the large-state step buffers them: the chunk size,
@@ -577,7 +583,11 @@ ttt_status_t run_backward(const ttt_problem_t* p, const Shape& S, int B, const i
 }
 
 // GCS forward: gradient launches over all chunks at W0 (entries = chunks),
-// one summing update into W*, one apply launch over all tokens.
+// one summing update into W*, one apply launch over all tokens.  A stream
+// with more chunks x heads than shard-partial slots is summed in passes of
+// as many chunks as the slots hold: each pass adds its chunks' sum onto a
+// running total (fixed order: pass by pass, chunks in order within a pass),
+// the last one takes the step.
 ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K, const void* V,
                              const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T, float* loss,
                              void* ws, size_t ws_bytes, hipStream_t st, float* wstar_out) {
@@ -589,41 +599,50 @@ ttt_status_t run_gcs_forward(const ttt_problem_t* p, const Shape& S, const void*
   float* partial = at<float>(ws, L.partial);
   float* partial_loss = at<float>(ws, L.partial_loss);
   float* wstar = wstar_out ? wstar_out : at<float>(ws, L.pp);
+  float* acc = at<float>(ws, L.fin);  // [H][2dh] running sum of a multi-pass stream
   const int nbpc = (int)((2 * dh / 4 + 255) / 256);
-  const int64_t n_chains = C * H;
-  if (n_chains > L.slot_cap) return TTT_ENOTSUP;  // more chunks x heads than partial slots
+  const int64_t per_pass = std::min<int64_t>(C, L.slot_cap / H);  // >= 1: slot_cap >= H
+  const int64_t n_chains = per_pass * H;
   const int64_t tiles = (std::min(M, N) + TT - 1) / TT;
   int64_t G = (default_target_wgs(S) + n_chains - 1) / n_chains;
   G = std::max<int64_t>(1, std::min<int64_t>({G, tiles, L.slot_cap / n_chains}));
-  for (int64_t base = 0; base < C; base += MAXS) {
-    const int na = (int)std::min<int64_t>(MAXS, C - base);
-    FwdStepArgs a{};
-    a.Q = Q; a.K = K; a.V = V; a.O = O;
-    a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
-    a.w1_src = W1_0; a.w2_src = W2_0; a.w_cstride = dh; a.w_mod = (int32_t)H;
-    a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G;
-    const int64_t slot0 = base * H * G;
-    a.partial = partial + slot0 * 2 * dh;
-    a.partial_loss = partial_loss + slot0;
-    a.n_active = na;
-    for (int i = 0; i < na; ++i) {
-      const int64_t c = base + i;
-      a.seq_id[i] = 0;
-      a.grad_start[i] = c * M;
-      a.grad_len[i] = (int32_t)std::min<int64_t>(M, N - c * M);
-      a.app_start[i] = 0;
-      a.app_len[i] = 0;
+  const bool passes = per_pass < C;
+  for (int64_t c0 = 0; c0 < C; c0 += per_pass) {
+    const int64_t cp = std::min<int64_t>(per_pass, C - c0);
+    for (int64_t base = 0; base < cp; base += MAXS) {
+      const int na = (int)std::min<int64_t>(MAXS, cp - base);
+      FwdStepArgs a{};
+      a.Q = Q; a.K = K; a.V = V; a.O = O;
+      a.stride_tok = S.stride_tok; a.stride_head = S.stride_head;
+      a.w1_src = W1_0; a.w2_src = W2_0; a.w_cstride = dh; a.w_mod = (int32_t)H;
+      a.H = (int32_t)H; a.flags = p->flags; a.G = (int32_t)G;
+      const int64_t slot0 = base * H * G;
+      a.partial = partial + slot0 * 2 * dh;
+      a.partial_loss = partial_loss + slot0;
+      a.n_active = na;
+      for (int i = 0; i < na; ++i) {
+        const int64_t c = c0 + base + i;
+        a.seq_id[i] = 0;
+        a.grad_start[i] = c * M;
+        a.grad_len[i] = (int32_t)std::min<int64_t>(M, N - c * M);
+        a.app_start[i] = 0;
+        a.app_len[i] = 0;
+      }
+      if (!launched([&] { return launch_fwd_step(a, (int)(na * H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
+        return TTT_EHIP;
     }
-    if (!launched([&] { return launch_fwd_step(a, (int)(na * H * G), S.h, S.io_bf16, S.mma_bf16, st); }))
-      return TTT_EHIP;
+    const bool last = c0 + cp == C;
+    UpdStepArgs u{};
+    u.w1_src = W1_0; u.w2_src = W2_0; u.w_cstride = dh; u.w_mod = (int32_t)H;
+    u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
+    u.partial = partial; u.partial_loss = partial_loss; u.w_dst = wstar;
+    u.wT1 = W1_T; u.wT2 = W2_T; u.loss = loss; u.loss_stride = (int32_t)C; u.chunk = 0;
+    u.gcs_chunks = (int32_t)cp; u.gcs_M = (int32_t)M;
+    u.gcs_last_len = (int32_t)(last ? N - (C - 1) * M : M);
+    u.gcs_acc = passes ? acc : nullptr;
+    u.gcs_entry0 = (int32_t)c0; u.gcs_first = c0 == 0; u.gcs_last = last;
+    if (!launched([&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   }
-  UpdStepArgs u{};
-  u.w1_src = W1_0; u.w2_src = W2_0; u.w_cstride = dh; u.w_mod = (int32_t)H;
-  u.H = (int32_t)H; u.h = S.h; u.eta = p->eta; u.G = (int32_t)G;
-  u.partial = partial; u.partial_loss = partial_loss; u.w_dst = wstar;
-  u.wT1 = W1_T; u.wT2 = W2_T; u.loss = loss; u.loss_stride = (int32_t)C; u.chunk = 0;
-  u.gcs_chunks = (int32_t)C; u.gcs_M = (int32_t)M; u.gcs_last_len = (int32_t)(N - (C - 1) * M);
-  if (!launched([&] { return launch_update(u, (int)(H * nbpc), st); })) return TTT_EHIP;
   if (O) {
     FwdStepArgs a{};
     a.Q = Q; a.K = K; a.V = V; a.O = O;

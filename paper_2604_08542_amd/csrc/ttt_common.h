@@ -294,6 +294,13 @@ struct UpdStepArgs {
   // gcs_chunks chunk entries (entry e, slot (e*H + head)*G + g); chunk e has
   // gcs_M tokens except the last (gcs_last_len).
   int32_t gcs_chunks, gcs_M, gcs_last_len;
+  // Streams with more chunks than partial slots are summed in passes of
+  // gcs_chunks chunks each (the first chunk of this pass is gcs_entry0, the
+  // index of its loss entry).  gcs_acc (nullable: one pass) is the running
+  // sum [H][2*D*h]: a pass that is not the first adds its sum to it, a pass
+  // that is not the last stores the total there and takes no step.
+  float* gcs_acc;
+  int32_t gcs_entry0, gcs_first, gcs_last;
 };
 
 // One reverse chunk step of the backward for every head of the active

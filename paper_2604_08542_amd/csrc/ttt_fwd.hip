@@ -783,13 +783,20 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
       s = (s0 + s1) + (s2 + s3);
     }
     const int idx = 4 * i4;
+    bool step = true;
+    if (gcs && p.gcs_acc) {  // a pass of a multi-pass sum: the running total first, then this pass
+      f32x4* acc = reinterpret_cast<f32x4*>(p.gcs_acc + (int64_t)head * 2 * dh + idx);
+      if (!p.gcs_first) s = *acc + s;
+      if (!p.gcs_last) *acc = s;
+      step = p.gcs_last != 0;
+    }
     const int64_t wc = (int64_t)(chain % p.w_mod) * p.w_cstride;
     const f32x4 wv = idx < dh ? *reinterpret_cast<const f32x4*>(p.w1_src + wc + idx)
                               : *reinterpret_cast<const f32x4*>(p.w2_src + wc + (idx - dh));
     const f32x4 wn = wv - p.eta * s;
-    *reinterpret_cast<f32x4*>(p.w_dst + (int64_t)chain * 2 * dh + idx) = wn;
+    if (step) *reinterpret_cast<f32x4*>(p.w_dst + (int64_t)chain * 2 * dh + idx) = wn;
     if (p.ckpt) *reinterpret_cast<f32x4*>(p.ckpt + p.ckpt_off[ai] + (int64_t)head * 2 * dh + idx) = wv;
-    if ((gcs || p.is_last[ai]) && p.wT1) {
+    if (step && (gcs || p.is_last[ai]) && p.wT1) {
       if (idx < dh)
         *reinterpret_cast<f32x4*>(p.wT1 + (int64_t)chain * dh + idx) = wn;
       else
@@ -802,7 +809,7 @@ __global__ __launch_bounds__(256) void ttt_update(UpdStepArgs p) {
       const int len = gcs ? (e + 1 < n_ent ? p.gcs_M : p.gcs_last_len) : gl;
       float sum = 0.f;
       for (int gg = 0; gg < p.G; ++gg) sum += p.partial_loss[sl * p.G + gg];
-      p.loss[(int64_t)head * p.loss_stride + (gcs ? e : p.chunk)] = sum / (float)len;
+      p.loss[(int64_t)head * p.loss_stride + (gcs ? p.gcs_entry0 + e : p.chunk)] = sum / (float)len;
     }
   }
 }

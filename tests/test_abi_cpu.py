@@ -186,15 +186,6 @@ def test_status_strings(lib):
     assert lib.ttt_version() >= 100
 
 
-def test_gcs_chunk_slot_limit(lib):
-    # chunks x heads beyond the workspace's shard-partial slots: rejected before anything is enqueued
-    p = prob(n_heads=1, n_tokens=2000, chunk_tokens=1)
-    assert lib.ttt_gcs_fwd(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, None, FAKE, 1 << 40,
-                           None) == L.TTT_ENOTSUP
-    assert lib.ttt_gcs_bwd(ctypes.byref(p), FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
-                           FAKE, 1 << 40, None) == L.TTT_ENOTSUP
-
-
 def test_missing_library_fails_loudly(tmp_path):
     # a fresh interpreter: the loader raises instead of falling back to anything else
     import subprocess

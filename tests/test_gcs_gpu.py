@@ -63,3 +63,24 @@ def test_gcs_bf16_operands_f32_tokens(gpu):
     print("gcs f32 io, bf16 operands: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v <= TOL["bf16"], (k, v)
+
+
+@pytest.mark.parametrize("io", ["f32", "bf16"])
+def test_gcs_more_chunks_than_partial_slots(gpu, io):
+    """70 chunks x 16 heads = 1,120 chunk entries, more than the 1,024
+    shard-partial slots of the workspace: the chunks' gradients are summed in
+    two passes (64 + 6 chunks), forward and reverse mode."""
+    N, H, h, M, eta = 69 * 32 + 20, 16, 128, 32, 0.02
+    x, d = inputs(N, H, h, seed=411, io=io, with_dO=True)
+    r = ops().gcs_fwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, emit_loss=True)
+    g = ops().gcs_bwd(d["Q"], d["K"], d["V"], d["W1"], d["W2"], eta, M, d["dO"])
+    torch.cuda.synchronize()
+    ref = orc.ttt_forward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M)
+    refb = orc.ttt_backward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M, x["dO"])
+    errs = dict(O=rel(host(r["O"]), ref["O"]), W1_T=rel(host(r["W1_T"]), ref["W1_T"]),
+                dW1=rel(host(r["W1_T"]) - x["W1"], ref["W1_T"] - x["W1"]),
+                dW2=rel(host(r["W2_T"]) - x["W2"], ref["W2_T"] - x["W2"]), loss=rel(host(r["loss"]), ref["loss"]))
+    errs.update({k: rel(host(g[k]), refb[k]) for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0", "deta")})
+    print(f"gcs, 70 chunks x 16 heads, {io}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL[io], (k, v)
