@@ -10,7 +10,8 @@ sequence's last chunk ragged where its length is not a multiple), eta 0.05,
 BF16 operands with FP32 accumulation and FP32 fast weights.  Inputs are
 synthetic and resident in HBM before the timed region.  The FP32 path on the
 same workload, the other forms (single-sequence layer, single-head chains,
-forward + backward, GCS, the paper's memory unit, the length sweep) and the
+forward + backward, GCS, the paper's memory unit, the layer around the unit
+with its projections and gate, the length sweep) and the
 FP64 oracle timed on the host cores are reported beside it.  Prints one JSON
 line.
 
@@ -47,7 +48,7 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device copy (the reference kernel for HBM byte counters)")
     ap.add_argument("--forms", default="layer,stepwise,paper_state,single_head,fwd_bwd,batched_fwd_bwd,gcs,amu,"
-                                       "length_sweep",
+                                       "gcm,length_sweep",
                     help="comma list of the other forms to time")
     return ap.parse_args()
 
@@ -225,6 +226,32 @@ def other_forms(forms, steps, warmup):
                 res[f"amu_fwd_bwd_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms,
                                                        tokens_per_s=w.n_tokens / (ms * 1e-3))
             del dev, O, W3, et
+    if "gcm" in forms:  # the layer around the memory unit: projections, unit, output projection, gate
+        for name, H, d, h, frames in (("gcm_layer16_64f", 16, 64, 256, 64), ("gcm_paper_state_64f", 1, 1024, 4096, 64)):
+            N, D, M = frames * 1374, H * d, 8 * 1374
+            for io in ("bf16", "f32"):
+                dt = torch.bfloat16 if io == "bf16" else torch.float32
+                g = torch.Generator(device="cuda")
+                g.manual_seed(3)
+                X = torch.randn((N, D), generator=g, device="cuda").to(dt)
+                Wqkv = (torch.randn((D, 3 * D), generator=g, device="cuda") / D ** 0.5).to(dt)
+                Wo = (torch.randn((D, D), generator=g, device="cuda") * (4.0 * d / D) ** 0.5).to(dt)
+                alpha = torch.rand(D, generator=g, device="cuda") + 0.5
+                W1 = torch.randn((H, d, h), generator=g, device="cuda") / d ** 0.5
+                W2 = torch.randn((H, h, d), generator=g, device="cuda") / h ** 0.5
+                Y = torch.empty_like(X)
+                n = few if (io == "bf16" and H > 1) else 2
+                ms = timed(lambda: ops.gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, 0.05, M, out=Y, want_final=False), n, 1)
+                flops = fwd_flops(d, h, N, H) + 8.0 * N * D * D  # unit + the two projections (3 D^2 + D^2 per token)
+                ach = flops / (ms * 1e-3) / 1e12
+                res[f"{name}_{io}"] = dict(workload=f"{name}: {H}x{d}, h{h}, {N} tokens, chunk {M}, D {D}",
+                                           ms_per_step=ms, tokens_per_s=N / (ms * 1e-3),
+                                           roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io], unit="TFLOP/s",
+                                                         frac=ach / PEAK[io],
+                                                         note="unit 14 d h per token-head + projections 8 D^2 per "
+                                                              "token"))
+                del X, Wqkv, Wo, Y
+                torch.cuda.empty_cache()
     if "length_sweep" in forms:  # one sequence of F frames (the shape of the paper's length table)
         from workloads import Workload
         rows = {}

@@ -274,6 +274,32 @@ ttt_status_t ttt_chunk_fwd_noalloc(const ttt_problem_t* p, const void* Q, const 
                                    const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
                                    float* ckpt, float* loss, void* hip_stream);
 
+/* The layer around the memory unit over one sequence (Sec. 4.2: a
+ * query-key-value projection, the memory unit, an output projection; Sec. 4.1
+ * Eq. 5: the gate alpha * GCM(X) + X), for N tokens of width D = H * d:
+ *     [Q | K | V] = X Wqkv (+ bqkv)     head h = features h*d .. h*d+d-1
+ *     O = ttt_chunk_fwd(p, Q, K, V, W1_0, W2_0)
+ *     Y = alpha * (O Wo (+ bo)) + X     alpha a per-feature gate vector
+ *   p       the memory unit's problem; its strides must be 0 (the layer's
+ *           token tensors are packed [N][D]); TTT_SAVE_CKPT / TTT_EMIT_LOSS
+ *           are TTT_ENOTSUP.  D must be a multiple of 128 (TTT_ESHAPE).
+ *   X, Y    [N][D] io_dtype (Y may not alias X).
+ *   Wqkv    [D][3D] io_dtype, row-vector convention (x W): columns 0..D-1
+ *           give Q, D..2D-1 K, 2D..3D-1 V.  bqkv [3D] f32, nullable.
+ *   Wo      [D][D] io_dtype; bo [D] f32, nullable; alpha [D] f32.
+ *   W1_0, W2_0, W1_T, W2_T  as ttt_chunk_fwd.
+ *   ws      ws_bytes >= ttt_gcm_workspace_bytes(p): the projected Q, K, V
+ *           and the unit's output O ([N][D] each, io_dtype) and the unit's
+ *           own workspace.
+ * The projections are matrix-core GEMMs in the io type (BF16 or FP32
+ * operands, FP32 accumulation), each output element summed in a fixed
+ * order.  Returns 0 bytes / TTT_EINVAL etc. as ttt_chunk_fwd. */
+size_t ttt_gcm_workspace_bytes(const ttt_problem_t* p);
+ttt_status_t ttt_gcm_fwd(const ttt_problem_t* p, const void* X, const void* Wqkv, const float* bqkv,
+                         const void* Wo, const float* bo, const float* alpha, const float* W1_0,
+                         const float* W2_0, void* Y, float* W1_T, float* W2_T, void* ws, size_t ws_bytes,
+                         void* hip_stream);
+
 /* Device-side status of the last call that used workspace `ws`: copies the
  * workspace's error word to *flags_host (bit 0: a barrier wait of the
  * persistent forward gave up, so that call's outputs are invalid; 0: no

@@ -628,3 +628,37 @@ def ttt_backward_swiglu(Q, K, V, W1_0, W2_0, W3_0, eta_tok, chunk_tokens, dO, sy
         dK[:, hd, :] = l2norm_rows_bwd(K[:, hd, :], dk) if norm[1] else dk
         dV[:, hd, :] = l2norm_rows_bwd(V[:, hd, :], dv) if norm[2] else dv
     return dict(dQ=dQ, dK=dK, dV=dV, deta_tok=deta, dW1_0=dW[0], dW2_0=dW[1], dW3_0=dW[2])
+
+
+# --------------------------------------------------------------------------
+# the layer around the memory unit (Sec. 4.2; gate of Sec. 4.1 Eq. 5)
+# --------------------------------------------------------------------------
+
+def gcm_layer_forward(X, Wqkv, Wo, alpha, W1_0, W2_0, eta, chunk_tokens, bqkv=None, bo=None,
+                      norm=(True, True, True), act="silu"):
+    """The memory unit's layer for one sequence.
+
+    X: [N][D] input tokens, D = H * d with H = W1_0.shape[0].  The
+    query-key-value projection is one linear map, P = X Wqkv (+ bqkv) with
+    Wqkv [D][3D]: P's first D columns are the queries, the next D the keys,
+    the last D the values, and head h owns features h*d .. h*d+d-1 of each
+    (the multi-head split of Supp. A).  The memory unit maps them
+    (ttt_forward above), the output projection gives G = O Wo (+ bo), and the
+    gate of Sec. 4.1 Eq. 5 returns alpha * G + X with the per-feature vector
+    alpha.  Returns dict(Y, O, W1_T, W2_T)."""
+    X, Wqkv, Wo, alpha = _as_f64(X, Wqkv, Wo, alpha)
+    N, D = X.shape
+    H = W1_0.shape[0]
+    d = D // H
+    P = X @ Wqkv
+    if bqkv is not None:
+        P = P + np.asarray(bqkv, dtype=np.float64)
+    Q = P[:, :D].reshape(N, H, d)
+    K = P[:, D:2 * D].reshape(N, H, d)
+    V = P[:, 2 * D:].reshape(N, H, d)
+    r = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)
+    O = r["O"].reshape(N, D)
+    G = O @ Wo
+    if bo is not None:
+        G = G + np.asarray(bo, dtype=np.float64)
+    return dict(Y=alpha * G + X, O=O, W1_T=r["W1_T"], W2_T=r["W2_T"])

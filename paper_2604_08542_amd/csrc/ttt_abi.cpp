@@ -1366,6 +1366,70 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
   }
 }
 
+// The layer around the memory unit: token buffers Q, K, V, O of [N][D] in
+// the io type, then the memory unit's own workspace.
+static ttt_status_t gcm_check(const ttt_problem_t* p, Shape* S, size_t* tok_bytes, size_t* ttt_bytes) {
+  const ttt_status_t e = check_problem(p, S);
+  if (e != TTT_OK) return e;
+  if (p->stride_tok != 0 || p->stride_head != 0) return TTT_EINVAL;  // the layer's tensors are packed
+  if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
+  const int64_t D = (int64_t)S->H * S->d;
+  if (D % 128 != 0 || D > 16384) return TTT_ESHAPE;
+  *tok_bytes = align_up((size_t)p->n_tokens * (size_t)D * (S->io_bf16 ? 2 : 4));
+  *ttt_bytes = ttt_workspace_bytes(p, 1);
+  return *ttt_bytes ? TTT_OK : TTT_EINVAL;
+}
+
+size_t ttt_gcm_workspace_bytes(const ttt_problem_t* p) {
+  try {
+    Shape S{};
+    size_t tb = 0, wb = 0;
+    if (gcm_check(p, &S, &tb, &wb) != TTT_OK) return 0;
+    return 4 * tb + wb;
+  } catch (...) {
+    return 0;
+  }
+}
+
+ttt_status_t ttt_gcm_fwd(const ttt_problem_t* p, const void* X, const void* Wqkv, const float* bqkv, const void* Wo,
+                         const float* bo, const float* alpha, const float* W1_0, const float* W2_0, void* Y,
+                         float* W1_T, float* W2_T, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    Shape S{};
+    size_t tb = 0, wb = 0;
+    const ttt_status_t e = gcm_check(p, &S, &tb, &wb);
+    if (e != TTT_OK) return e;
+    if (!Wqkv || !Wo || !alpha || !W1_0 || !W2_0) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!X || !Y)) return TTT_EINVAL;
+    if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
+    for (const void* q : {X, Wqkv, Wo, (const void*)Y, (const void*)W1_0, (const void*)W2_0, (const void*)W1_T,
+                          (const void*)W2_T})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (!ws || ws_bytes < 4 * tb + wb) return TTT_EWORKSPACE;
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    char* base = static_cast<char*>(ws);
+    void* q = base;
+    void* k = base + tb;
+    void* v = base + 2 * tb;
+    void* o = base + 3 * tb;
+    if (p->n_tokens > 0) {
+      GcmGemmArgs a{};
+      a.kind = 0; a.D = S.H * S.d; a.rows = p->n_tokens;
+      a.x = X; a.w = Wqkv; a.bias = bqkv; a.q = q; a.k = k; a.v = v;
+      if (launch_gcm_gemm(a, S.io_bf16, st) != hipSuccess) return TTT_EHIP;
+    }
+    const ttt_status_t et = ttt_chunk_fwd(p, q, k, v, W1_0, W2_0, o, W1_T, W2_T, nullptr, nullptr, base + 4 * tb, wb,
+                                          hip_stream);
+    if (et != TTT_OK || p->n_tokens == 0) return et;
+    GcmGemmArgs g{};
+    g.kind = 1; g.D = S.H * S.d; g.rows = p->n_tokens;
+    g.x = X; g.w = Wo; g.bias = bo; g.alpha = alpha; g.o = o; g.y = Y;
+    return launch_gcm_gemm(g, S.io_bf16, st) == hipSuccess ? TTT_OK : TTT_EHIP;
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
 ttt_status_t ttt_workspace_status(const void* ws, size_t ws_bytes, uint32_t* flags_host, void* hip_stream) {
   if (!ws || !flags_host || ws_bytes < SYNC_BYTES) return TTT_EINVAL;
   const hipStream_t st = static_cast<hipStream_t>(hip_stream);

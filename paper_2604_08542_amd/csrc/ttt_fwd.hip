@@ -891,8 +891,8 @@ __device__ __forceinline__ void group_barrier(bool local, uint32_t* ctr, uint32_
 // partials, in the fixed order of ttt_update: four streams of shards q, q+4,
 // ... combined as (s0 + s1) + (s2 + s3)); also the checkpoint row (W_s), the
 // final weights after the last chunk and, by member 0, the chunk's loss.
-template <int NT, int DH>
-__device__ __forceinline__ void group_reduce(const PersistArgs& p, int g, const float* part, const float* ploss,
+template <int NT, int DH, typename PA>
+__device__ __forceinline__ void group_reduce(const PA& p, int g, const float* part, const float* ploss,
                                              const float* w1s, const float* w2s, float* wdst, float* ck, float* t1,
                                              float* t2, int head, int s, int gl) {
   constexpr int n4 = 2 * DH / 4;
@@ -939,6 +939,17 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_persist(PersistArgs p) {
   // the whole register budget of two waves per SIMD.
   __shared__ int st_[6];  // chain entry, step, barrier count, chunks of the chain, LOCAL protocol, member
   volatile int* st = st_;
+  // Inside the loops the arguments are read through a pointer to the kernel
+  // argument segment that the compiler cannot see through, so each step
+  // re-reads them with scalar loads instead of keeping them in scalar
+  // registers across the step body (which spilled them into vector
+  // registers).  p (the first argument) starts the segment.
+  typedef const __attribute__((address_space(4))) PersistArgs* KP;
+  auto kargs = []() -> KP {
+    KP k = (KP)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return k;
+  };
   {
     const int nb = gridDim.x, bid = blockIdx.x;
     const int lin = p.xcd_map ? (bid % 8) * (nb / 8) + bid / 8 : bid;
@@ -960,51 +971,53 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_persist(PersistArgs p) {
     __syncthreads();
   }
   for (;;) {
+    KP q = kargs();
     {
         const int lin = __builtin_amdgcn_readfirstlane(st[5]);
-      const int grp = lin / p.G, g = lin % p.G;
+      const int grp = lin / q->G, g = lin % q->G;
       // the group's member 0 takes the next chain; the barrier publishes it
       if (g == 0 && threadIdx.x == 0) {
-        const uint32_t c = __hip_atomic_fetch_add(p.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(p.slot + grp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t c = __hip_atomic_fetch_add(q->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(q->slot + grp, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
       const uint32_t nbar = (uint32_t)__builtin_amdgcn_readfirstlane(st[2]) + 1u;
-      group_barrier(st[4] != 0, p.bar + grp, nbar * (uint32_t)p.G, p.err, p.spin_limit);
+      group_barrier(st[4] != 0, q->bar + grp, nbar * (uint32_t)q->G, q->err, q->spin_limit);
       if (threadIdx.x == 0) {
         st[2] = (int)nbar;
-        const int c = (int)__hip_atomic_load(p.slot + grp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int c = (int)__hip_atomic_load(q->slot + grp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         st[0] = c;
         st[1] = 0;
-        if (c < p.n_chains) {
-          const int64_t N = p.seq_len[c / p.H];
-          st[3] = (int)((N + p.M - 1) / p.M);
+        if (c < q->n_chains) {
+          const int64_t N = q->seq_len[c / q->H];
+          st[3] = (int)((N + q->M - 1) / q->M);
         }
       }
       __syncthreads();
-      if (__builtin_amdgcn_readfirstlane(st[0]) >= p.n_chains) break;
+      if (__builtin_amdgcn_readfirstlane(st[0]) >= q->n_chains) break;
     }
     for (;;) {
+      KP q = kargs();
         const int c = __builtin_amdgcn_readfirstlane(st[0]), s = __builtin_amdgcn_readfirstlane(st[1]),
                 C = __builtin_amdgcn_readfirstlane(st[3]);
       if (s > C) break;
       const int lin = __builtin_amdgcn_readfirstlane(st[5]);
-      const int grp = lin / p.G, g = lin % p.G;
-      float* const wb = p.wbuf + (int64_t)grp * 2 * (2 * DH);
-      float* const part = p.partial + (int64_t)grp * p.G * (2 * DH);
-      float* const ploss = p.partial_loss + (int64_t)grp * p.G;
-      const int e = c / p.H, head = c % p.H, b = p.seq_id[e];
-      const int64_t N = p.seq_len[e], start = p.seq_start[e], M = p.M;
-      const int64_t w0 = ((int64_t)(p.w0_per_seq ? b * p.H : 0) + head) * DH;
-      const float* w1s = s == 0 ? p.w1_0 + w0 : wb + (s & 1) * (2 * DH);
-      const float* w2s = s == 0 ? p.w2_0 + w0 : wb + (s & 1) * (2 * DH) + DH;
+      const int grp = lin / q->G, g = lin % q->G;
+      float* const wb = q->wbuf + (int64_t)grp * 2 * (2 * DH);
+      float* const part = q->partial + (int64_t)grp * q->G * (2 * DH);
+      float* const ploss = q->partial_loss + (int64_t)grp * q->G;
+      const int e = c / q->H, head = c % q->H, b = q->seq_id[e];
+      const int64_t N = q->seq_len[e], start = q->seq_start[e], M = q->M;
+      const int64_t w0 = ((int64_t)(q->w0_per_seq ? b * q->H : 0) + head) * DH;
+      const float* w1s = s == 0 ? q->w1_0 + w0 : wb + (s & 1) * (2 * DH);
+      const float* w2s = s == 0 ? q->w2_0 + w0 : wb + (s & 1) * (2 * DH) + DH;
       const int gl = s < C ? (int32_t)min(M, N - (int64_t)s * M) : 0;
       {
         StepCtx x;
-        x.Q = p.Q; x.K = p.K; x.V = p.V; x.O = p.O;
-        x.stride_tok = p.stride_tok; x.stride_head = p.stride_head; x.flags = p.flags;
+        x.Q = q->Q; x.K = q->K; x.V = q->V; x.O = q->O;
+        x.stride_tok = q->stride_tok; x.stride_head = q->stride_head; x.flags = q->flags;
         x.W1 = w1s; x.W2 = w2s;
-        x.head = head; x.g = g; x.G = p.G;
+        x.head = head; x.g = g; x.G = q->G;
         x.gs = start + (int64_t)s * M;
         x.gl = gl;
         x.as0 = start + (int64_t)(s - 1) * M;
@@ -1024,25 +1037,25 @@ __global__ __launch_bounds__(NW * 64) void ttt_fwd_persist(PersistArgs p) {
             const int cc = __builtin_amdgcn_readfirstlane(st[0]);
         const uint32_t nbar = (uint32_t)__builtin_amdgcn_readfirstlane(st[2]);
         const int lin = __builtin_amdgcn_readfirstlane(st[5]);
-        const int grp = lin / p.G, g = lin % p.G;
-        float* const wb = p.wbuf + (int64_t)grp * 2 * (2 * DH);
-        float* const part = p.partial + (int64_t)grp * p.G * (2 * DH);
-        float* const ploss = p.partial_loss + (int64_t)grp * p.G;
-        const int ee = cc / p.H, hh = cc % p.H, bb = p.seq_id[ee];
-        const int64_t NN = p.seq_len[ee], MM = p.M;
+        const int grp = lin / q->G, g = lin % q->G;
+        float* const wb = q->wbuf + (int64_t)grp * 2 * (2 * DH);
+        float* const part = q->partial + (int64_t)grp * q->G * (2 * DH);
+        float* const ploss = q->partial_loss + (int64_t)grp * q->G;
+        const int ee = cc / q->H, hh = cc % q->H, bb = q->seq_id[ee];
+        const int64_t NN = q->seq_len[ee], MM = q->M;
         const int gll = (int32_t)min(MM, NN - (int64_t)ss * MM);
-        const int64_t w00 = ((int64_t)(p.w0_per_seq ? bb * p.H : 0) + hh) * DH;
-        const float* w1r = ss == 0 ? p.w1_0 + w00 : wb + (ss & 1) * (2 * DH);
-        const float* w2r = ss == 0 ? p.w2_0 + w00 : wb + (ss & 1) * (2 * DH) + DH;
+        const int64_t w00 = ((int64_t)(q->w0_per_seq ? bb * q->H : 0) + hh) * DH;
+        const float* w1r = ss == 0 ? q->w1_0 + w00 : wb + (ss & 1) * (2 * DH);
+        const float* w2r = ss == 0 ? q->w2_0 + w00 : wb + (ss & 1) * (2 * DH) + DH;
         const bool local = st[4] != 0;
-        group_barrier(local, p.bar + grp, (nbar + 1u) * (uint32_t)p.G, p.err, p.spin_limit);
+        group_barrier(local, q->bar + grp, (nbar + 1u) * (uint32_t)q->G, q->err, q->spin_limit);
         const bool last = ss == CC - 1;
-        const int64_t chain = (int64_t)bb * p.H + hh;
-        float* ck = p.ckpt ? p.ckpt + ((p.ck_row[ee] + ss) * p.H + hh) * (2 * DH) : nullptr;
-        float* t1 = last && p.wT1 ? p.wT1 + chain * DH : nullptr;
-        float* t2 = last && p.wT1 ? p.wT2 + chain * DH : nullptr;
+        const int64_t chain = (int64_t)bb * q->H + hh;
+        float* ck = q->ckpt ? q->ckpt + ((q->ck_row[ee] + ss) * q->H + hh) * (2 * DH) : nullptr;
+        float* t1 = last && q->wT1 ? q->wT1 + chain * DH : nullptr;
+        float* t2 = last && q->wT1 ? q->wT2 + chain * DH : nullptr;
         group_reduce<NT, DH>(p, g, part, ploss, w1r, w2r, wb + ((ss + 1) & 1) * (2 * DH), ck, t1, t2, hh, ss, gll);
-        group_barrier(local, p.bar + grp, (nbar + 2u) * (uint32_t)p.G, p.err, p.spin_limit);
+        group_barrier(local, q->bar + grp, (nbar + 2u) * (uint32_t)q->G, q->err, q->spin_limit);
         if (threadIdx.x == 0) st[2] = (int)(nbar + 2u);
       }
       if (threadIdx.x == 0) st[1] = ss + 1;

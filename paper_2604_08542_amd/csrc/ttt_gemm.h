@@ -1,0 +1,234 @@
+// Matrix-core GEMM tiles for gfx950 shared by the large-state chunk step and
+// the surrounding layer's projections: C[m][n] = sum_k A(m, k) B(k, n) over
+// BF16 (32x32x16 products) or FP32 (32x32x2) operands in their natural
+// layouts, a work-group owning one BM x 128 tile of C and its whole
+// contraction (fixed order, deterministic), the elementwise work of the
+// caller fused into an epilogue functor.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ttt_common.h"
+
+namespace ttt {
+namespace large {
+
+// Epilogues derive from this: finish() runs once per work-group after its
+// last element.
+struct EpBase {
+  __device__ __forceinline__ void finish() {}
+};
+
+constexpr int BN = 128;   // work-group tile width
+constexpr int NTH = 256;  // 4 waves, each a (BM/2) x 64 quarter of the BM x 128 tile
+// contraction slice per LDS stage: 64 BF16 or 32 FP32 elements (128 bytes)
+template <typename T>
+constexpr int bk() {
+  return sizeof(T) == 2 ? 64 : 32;
+}
+
+// Operand layouts of C[m][n] = sum_k A(m, k) B(k, n):
+//   KMAJ  the operand is stored [m or n][k] (k contiguous), pitch ld
+//   MNMAJ the operand is stored [k][m or n] (m or n contiguous), pitch ld
+enum { KMAJ = 0, MNMAJ = 1 };
+
+// LDS tile of ROWS rows (m or n) by BK (contraction).  BF16 operands feed
+// 32x32x16 products: a lane's 8 contraction slots hold, for lane half hf and
+// product step j, k = 16j + 4hf + {0..3} and 16j + 8 + 4hf + {0..3}; both
+// operands use this order (the order of the transposing LDS read), so a
+// k-major and an mn-major operand can be mixed.  FP32 operands feed 32x32x2
+// products, lane (l32, hf) holding k = 2j + hf.
+//
+// Pitches (in 4-byte LDS banks): a k-major BF16 row is 34 banks, so the
+// 8-byte reads of 16 lanes from 16 consecutive rows cover the 32 banks once;
+// an mn-major BF16 row is 72 banks (8 mod 32), so the four rows of 32 bytes
+// that a 16-lane group of the transposing read touches fall on disjoint
+// banks.  FP32: 33 banks (k-major, 4-byte reads down a column), 132 (mn-major,
+// consecutive lanes on consecutive banks).
+template <typename T, int ROWS>
+struct Tile {
+  static constexpr int BK = bk<T>();
+  static constexpr int KLD = sizeof(T) == 2 ? BK + 4 : BK + 1;       // pitch of a k-major tile [ROWS][BK]
+  static constexpr int MLD = sizeof(T) == 2 ? ROWS + 16 : ROWS + 4;  // pitch of an mn-major tile [BK][ROWS]
+  static constexpr int ELEMS = ROWS * KLD > BK * MLD ? ROWS * KLD : BK * MLD;
+};
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Global -> registers -> LDS staging of one operand tile (rows mn0 .. +ROWS
+// of the m/n axis, k0 .. k0+BK of the contraction).  Loads go through a
+// buffer resource that covers exactly the valid part of the operand, so rows
+// past its end (ragged token counts) read as zero.
+template <typename T, int LAYOUT, int ROWS>
+struct Stage {
+  static constexpr int BK = bk<T>();
+  static constexpr int BYTES = ROWS * BK * (int)sizeof(T);
+  static constexpr int PER = BYTES / NTH / 16;  // 16-byte loads per thread
+  static constexpr int EPC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+  u32x4 r[PER];
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int ld, int mn0, int k0) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * NTH;  // 16-byte chunk index within the tile
+      int row, col;
+      if constexpr (LAYOUT == KMAJ) {  // [ROWS][BK]
+        constexpr int CPR = BK / EPC;
+        row = mn0 + c / CPR;
+        col = k0 + (c % CPR) * EPC;
+      } else {  // [BK][ROWS]
+        constexpr int CPR = ROWS / EPC;
+        row = k0 + c / CPR;
+        col = mn0 + (c % CPR) * EPC;
+      }
+      r[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, (row * ld + col) * (int)sizeof(T), 0, 0);
+    }
+  }
+  __device__ __forceinline__ void store(T* lds) const {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = tid + i * NTH;
+      int off;
+      if constexpr (LAYOUT == KMAJ) {
+        constexpr int CPR = BK / EPC;
+        off = (c / CPR) * Tile<T, ROWS>::KLD + (c % CPR) * EPC;
+      } else {
+        constexpr int CPR = ROWS / EPC;
+        off = (c / CPR) * Tile<T, ROWS>::MLD + (c % CPR) * EPC;
+      }
+      if constexpr (LAYOUT == MNMAJ) {
+        *reinterpret_cast<u32x4*>(lds + off) = r[i];
+      } else if constexpr (sizeof(T) == 2) {  // k-major BF16 rows are 8-byte aligned: two 8-byte stores
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const u32x4 v = r[i];
+        reinterpret_cast<u32x2*>(lds + off)[0] = (u32x2){v[0], v[1]};
+        reinterpret_cast<u32x2*>(lds + off)[1] = (u32x2){v[2], v[3]};
+      } else {  // FP32 k-major rows have an odd pitch: four 4-byte stores
+        const u32x4 v = r[i];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) reinterpret_cast<uint32_t*>(lds + off)[e] = v[e];
+      }
+    }
+  }
+};
+
+// Operand fragment of product step j for the 32-wide block starting at mn
+// (tile-local) of a staged tile.
+template <typename T, int LAYOUT, int ROWS>
+__device__ __forceinline__ auto frag(const T* t, int mn, int j) {
+  const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
+  using TL = Tile<T, ROWS>;
+  if constexpr (sizeof(T) == 2) {
+    typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+    if constexpr (LAYOUT == KMAJ) {
+      const bf16* row = t + (mn + l32) * TL::KLD + 16 * j + 4 * hf;
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row);
+      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 8);
+      return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+      // transposing read: in each 16-lane group lane i addresses row
+      // t0 + i/4, columns c0 + 4(i%4)..+3 and receives T[t0 + q][c0 + i], q < 4
+      const int l16 = l & 15;
+      const int off = (4 * hf + (l16 >> 2)) * TL::MLD + mn + 16 * ((l >> 4) & 1) + 4 * (l16 & 3);
+      const bf16* p0 = t + off + 16 * j * TL::MLD;
+      const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0)));
+      const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0 + 8 * TL::MLD)));
+      return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+  } else {
+    if constexpr (LAYOUT == KMAJ)
+      return t[(mn + l32) * TL::KLD + 2 * j + hf];
+    else
+      return t[(2 * j + hf) * TL::MLD + mn + l32];
+  }
+}
+
+// Product steps per contraction slice.
+template <typename T>
+constexpr int ksteps() {
+  return sizeof(T) == 2 ? bk<T>() / 16 : bk<T>() / 2;
+}
+
+// C tile (this work-group's BM x 128) accumulated over the whole
+// contraction, then handed to the epilogue element by element:
+// ep(row, col, value); rows past the operand's end are the epilogue's to skip.
+template <typename T, int LA, int LB, int BM, typename EP>
+__device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows, int K,
+                                          int m0, int n0, EP& ep) {
+  constexpr int MB = BM / 64;  // 32-row blocks per wave (each wave: BM/2 rows x 64 columns)
+  __shared__ __attribute__((aligned(16))) T sa[2][Tile<T, BM>::ELEMS];
+  __shared__ __attribute__((aligned(16))) T sb[2][Tile<T, BN>::ELEMS];
+  const int w = threadIdx.x >> 6, wm = (w >> 1) * (BM / 2), wn = (w & 1) * 64;
+  // buffer resources over the valid rows of each operand
+  auto rsrc = [](const T* p, int rows, int ld) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, rows * ld * (int)sizeof(T), 0x00020000);
+  };
+  const auto ra = rsrc(A, a_rows, lda), rb = rsrc(B, b_rows, ldb);
+  // Three-stage pipeline: while slice kt is multiplied out of one LDS
+  // buffer, slice kt+1 waits in the other and slice kt+2 is in flight from
+  // HBM into registers (two register stages, alternating), so a global load
+  // has two slices of products to arrive before it is needed.
+  Stage<T, LA, BM> ga[2];
+  Stage<T, LB, BN> gb[2];
+  constexpr int BK = bk<T>();
+  const int nk = (K + BK - 1) / BK;
+  f32x16 acc[MB][2] = {};
+  ga[0].load(ra, lda, m0, 0);
+  gb[0].load(rb, ldb, n0, 0);
+  if (nk > 1) {
+    ga[1].load(ra, lda, m0, BK);
+    gb[1].load(rb, ldb, n0, BK);
+  }
+  ga[0].store(sa[0]);
+  gb[0].store(sb[0]);
+  __syncthreads();
+  auto body = [&](int kt, auto PC) {
+    constexpr int P = decltype(PC)::value;  // kt & 1
+    if (kt + 2 < nk) {  // slice kt+2 into register stage P (free: slice kt left it last iteration)
+      ga[P].load(ra, lda, m0, (kt + 2) * BK);
+      gb[P].load(rb, ldb, n0, (kt + 2) * BK);
+    }
+#pragma unroll
+    for (int j = 0; j < ksteps<T>(); ++j) {
+      const auto b0 = frag<T, LB, BN>(sb[P], wn, j), b1 = frag<T, LB, BN>(sb[P], wn + 32, j);
+#pragma unroll
+      for (int bm = 0; bm < MB; ++bm) {
+        const auto a = frag<T, LA, BM>(sa[P], wm + 32 * bm, j);
+        acc[bm][0] = mma32(a, b0, acc[bm][0]);
+        acc[bm][1] = mma32(a, b1, acc[bm][1]);
+      }
+    }
+    if (kt + 1 < nk) {  // slice kt+1 (register stage P^1) into the other LDS buffer
+      ga[P ^ 1].store(sa[P ^ 1]);
+      gb[P ^ 1].store(sb[P ^ 1]);
+    }
+    __syncthreads();
+  };
+  for (int kt = 0; kt < nk; kt += 2) {
+    body(kt, std::integral_constant<int, 0>{});
+    if (kt + 1 < nk) body(kt + 1, std::integral_constant<int, 1>{});
+  }
+  const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
+#pragma unroll
+  for (int bm = 0; bm < MB; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + 32 * bm + c32_row(r, hf), col = n0 + wn + 32 * bn + l32;
+        ep(row, col, acc[bm][bn][r]);
+      }
+  ep.finish();
+}
+
+// One launch of one product; grid (N / 128, ceil(M / 128)).
+template <typename T, int LA, int LB, int BM, typename EP>
+__global__ __launch_bounds__(NTH) void k_gemm(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows,
+                                                int K, EP ep) {
+  gemm_tile<T, LA, LB, BM>(A, lda, a_rows, B, ldb, b_rows, K, blockIdx.y * BM, blockIdx.x * BN, ep);
+}
+
+}  // namespace large
+}  // namespace ttt

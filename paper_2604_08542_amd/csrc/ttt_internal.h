@@ -47,6 +47,24 @@ struct LargeStepArgs {
   float* loss;       // nullable: the chunk's loss
 };
 hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// One projection of the layer around the memory unit (token rows in the io
+// type, D = H * d features): kind 0, [Q | K | V] = X W (+ bias) with W
+// [D][3D]; kind 1, Y = alpha * (O W (+ bias)) + X with W [D][D].
+struct GcmGemmArgs {
+  int32_t kind;
+  int32_t D;
+  int64_t rows;
+  const void* x;   // [rows][D]
+  const void* w;   // kind 0: [D][3D]; kind 1: [D][D] (io type)
+  const float* bias;   // nullable: [3D] or [D]
+  const float* alpha;  // kind 1: [D]
+  void* q;         // kind 0 outputs, [rows][D] each
+  void* k;
+  void* v;
+  const void* o;   // kind 1: the memory unit's output [rows][D]
+  void* y;         // kind 1 output [rows][D]
+};
+hipError_t launch_gcm_gemm(const GcmGemmArgs& a, bool io_bf16, hipStream_t st);
 hipError_t launch_large_init(const float* w1, const float* w2, float* m1, float* m2, void* o1, void* o2, int64_t n,
                              bool mma_bf16, hipStream_t st);
 hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);

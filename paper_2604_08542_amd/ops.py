@@ -122,6 +122,46 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
 
 
+def gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, *, bqkv=None, bo=None, norm=True, want_final=True,
+            out=None, ws=None):
+    """The layer around the memory unit over one sequence: [Q|K|V] = X Wqkv
+    (+ bqkv), O = chunked TTT forward of Q, K, V with H = W1.shape[0] heads,
+    Y = alpha * (O Wo (+ bo)) + X.  X: [N][D] (float32 or bfloat16), Wqkv
+    [D][3D] and Wo [D][D] in X's dtype, biases and alpha float32.  Returns
+    dict(Y, W1_T, W2_T)."""
+    lib = L.load()
+    if X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous [N][D] tensor")
+    N, D = X.shape
+    H = W1.shape[0]
+    if D % H:
+        raise ValueError("D must be a multiple of the head count")
+    d = D // H
+    _, h = _check_w(W1, W2, H)
+    if W1.shape[1] != d:
+        raise ValueError(f"fast weights of head size {W1.shape[1]} for features {D} / {H} heads")
+    for t, shp in ((Wqkv, (D, 3 * D)), (Wo, (D, D))):
+        if tuple(t.shape) != shp or t.dtype != X.dtype or not t.is_contiguous():
+            raise ValueError(f"projection weight must be contiguous {shp} in {X.dtype}")
+    for t, n in ((alpha, D), (bqkv, 3 * D), (bo, D)):
+        if t is not None and (t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous()):
+            raise ValueError("alpha and the biases are contiguous float32 vectors")
+    prob = L.Problem(n_heads=H, d_head=d, d_hidden=h, n_tokens=N, chunk_tokens=int(chunk_tokens), stride_tok=0,
+                     stride_head=0, eta=float(eta), flags=_flags(norm), io_dtype=_DT[X.dtype])
+    Y = torch.empty_like(X) if out is None else out
+    W1_T = torch.empty_like(W1) if want_final else None
+    W2_T = torch.empty_like(W2) if want_final else None
+    if ws is None:
+        nbytes = lib.ttt_gcm_workspace_bytes(ctypes.byref(prob))
+        if nbytes == 0:
+            raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_gcm_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    st = lib.ttt_gcm_fwd(ctypes.byref(prob), _ptr(X), _ptr(Wqkv), _ptr(bqkv), _ptr(Wo), _ptr(bo), _ptr(alpha),
+                         _ptr(W1), _ptr(W2), _ptr(Y), _ptr(W1_T), _ptr(W2_T), _ptr(ws), ws.numel(), _stream(X.device))
+    L.check(st, "ttt_gcm_fwd")
+    return dict(Y=Y, W1_T=W1_T, W2_T=W2_T)
+
+
 def chunk_fwd_noalloc(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False, emit_loss=False,
                       mma_bf16=False, out=None, W1_T=None, W2_T=None, ckpt=None, loss=None):
     """chunk_fwd through the allocation-free entry point: the library uses its

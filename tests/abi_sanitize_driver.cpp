@@ -192,7 +192,33 @@ int main() {
                        nullptr),
            TTT_EINVAL);
   }
-  // status strings, including out-of-range codes
+  // the layer around the memory unit
+  {
+    ttt_problem_t p = prob();
+    p.n_tokens = 5000;
+    p.chunk_tokens = 1000;
+    if (ttt_gcm_workspace_bytes(&p) == 0) ++failures;
+    ttt_problem_t q = p;
+    q.n_heads = 1;  // D = 64: not a multiple of 128
+    if (ttt_gcm_workspace_bytes(&q) != 0) ++failures;
+    q = p;
+    q.stride_tok = 2048;  // the layer's tensors are packed
+    if (ttt_gcm_workspace_bytes(&q) != 0) ++failures;
+    auto gcm = [&](const ttt_problem_t& pp, const float* alpha, void* ws, size_t nws) {
+      return ttt_gcm_fwd(&pp, FAKE, FAKE, nullptr, FAKE, nullptr, alpha, FF, FF, FAKE, nullptr, nullptr, ws, nws,
+                         nullptr);
+    };
+    EXPECT(gcm(p, nullptr, FAKE, BIG), TTT_EINVAL);
+    EXPECT(gcm(p, FF, nullptr, BIG), TTT_EWORKSPACE);
+    EXPECT(gcm(p, FF, FAKE, 64), TTT_EWORKSPACE);
+    q = p;
+    q.flags |= TTT_SAVE_CKPT;
+    EXPECT(gcm(q, FF, FAKE, BIG), TTT_ENOTSUP);
+    q = p;
+    q.n_heads = 1;
+    EXPECT(gcm(q, FF, FAKE, BIG), TTT_ESHAPE);
+  }
+  // status strings
   for (int s = 0; s < 6; ++s)
     if (ttt_status_string((ttt_status_t)s) == nullptr) ++failures;
   if (ttt_version() < 100) ++failures;

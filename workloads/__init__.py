@@ -142,3 +142,26 @@ def make_eta_tok(n_tokens: int, n_heads: int, chunk_tokens: int, eta: float, see
     step of size eta)."""
     rng = np.random.default_rng(seed + 7919)
     return (rng.uniform(0.5, 1.5, (n_tokens, n_heads)) * (eta / chunk_tokens)).astype(np.float32)
+
+
+def make_layer_inputs(n_tokens: int, n_heads: int, d: int, h: int, seed: int = 0, io_dtype: str = "f32",
+                      bias: bool = True):
+    """Inputs of the layer around the memory unit (features D = n_heads * d):
+    tokens X ~ N(0, 1) [N][D]; projections Wqkv ~ N(0, 1/D) [D][3D] and
+    Wo ~ N(0, 4d/D) [D][D] (X and the projections exactly representable in
+    `io_dtype`); biases ~ N(0, 0.02^2) float32 (None without `bias`); the gate
+    alpha ~ U(0.5, 1.5) [D] float32; fast weights W1 ~ N(0, 1/d) [H][d][h],
+    W2 ~ N(0, 1/h) [H][h][d] float32.  With these fast weights the unit's
+    outputs have an rms of about 1/(2 sqrt(d)), so the scale of Wo makes the
+    gated term alpha * (O Wo) of the same order as X."""
+    rng = np.random.default_rng(seed + 104729)
+    D = n_heads * d
+    X = round_io(rng.standard_normal((n_tokens, D)), io_dtype)
+    Wqkv = round_io(rng.standard_normal((D, 3 * D)) / np.sqrt(D), io_dtype)
+    Wo = round_io(rng.standard_normal((D, D)) * np.sqrt(4.0 * d / D), io_dtype)
+    bqkv = (0.02 * rng.standard_normal(3 * D)).astype(np.float32) if bias else None
+    bo = (0.02 * rng.standard_normal(D)).astype(np.float32) if bias else None
+    alpha = rng.uniform(0.5, 1.5, D).astype(np.float32)
+    W1 = (rng.standard_normal((n_heads, d, h)) / np.sqrt(d)).astype(np.float32)
+    W2 = (rng.standard_normal((n_heads, h, d)) / np.sqrt(h)).astype(np.float32)
+    return dict(X=X, Wqkv=Wqkv, Wo=Wo, bqkv=bqkv, bo=bo, alpha=alpha, W1=W1, W2=W2)
