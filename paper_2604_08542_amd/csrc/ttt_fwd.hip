@@ -305,7 +305,16 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;
   constexpr int TPR = D / EPT;
-  constexpr int XS_LD = D + 8;
+  // Row pitches of the LDS tiles (elements).  The token-row tiles are read
+  // by 16-byte row fragments, by the transposing read and written by 4-byte
+  // and 2-byte stores; among the pitches that keep the 16-byte reads aligned
+  // (multiples of 8) the measured pass times on MI355X favour 80, 88 and 104
+  // (8-sequence batch, persistent launch: 7.44 / 7.48 / 7.51 ms against
+  // 8.26 / 8.67 / 8.31 ms at 72 / 96 / 112); outputs are bit-identical.
+  constexpr int XS_LD = D + 24;  // K rows
+  constexpr int VS_LD = XS_LD;   // V rows
+  constexpr int QS_LD = XS_LD;   // Q rows
+  constexpr int ES_LD = XS_LD;   // E rows
   constexpr int AS_LD = HH + 8;
   constexpr int DH = D * HH;
   constexpr float LOG2E = 1.4426950408889634f;
@@ -315,11 +324,11 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
   __shared__ __attribute__((aligned(16))) bf16 xs[3][TT * XS_LD];    // K rows
-  __shared__ __attribute__((aligned(16))) bf16 vs[2][TT * XS_LD];    // V rows
-  __shared__ __attribute__((aligned(16))) bf16 qs[2][TT * XS_LD];    // Q rows
+  __shared__ __attribute__((aligned(16))) bf16 vs[2][TT * VS_LD];    // V rows
+  __shared__ __attribute__((aligned(16))) bf16 qs[2][TT * QS_LD];    // Q rows
   __shared__ __attribute__((aligned(16))) bf16 as_[TT * AS_LD];      // A' = -log2(e) SiLU(K W1)
   __shared__ __attribute__((aligned(16))) bf16 aqs[TT * AS_LD];      // -log2(e) SiLU(Q W1)
-  __shared__ __attribute__((aligned(16))) bf16 es[TT * XS_LD];       // E
+  __shared__ __attribute__((aligned(16))) bf16 es[TT * ES_LD];       // E
   __shared__ float red[NW];
 
   // in a loop that calls this body (the persistent kernel) the lane index is
@@ -442,7 +451,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
     f32x16 z = {};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&X[l32 * XS_LD + 16 * m + 8 * hf]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&X[l32 * QS_LD + 16 * m + 8 * hf]);
       z = mma32(w1b[m], b, z);
     }
     return z;
@@ -458,7 +467,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
     return y;
   };
 
-  // Transposing read of a row-major bf16 tile T (pitch XS_LD): in each
+  // Transposing read of a row-major bf16 tile T (pitch ld): in each
   // group of 16 lanes, lane j receives T[t0 + q][c0 + j] for q = 0..3.  The
   // instruction hands lane j element j%4 of the 8-byte runs addressed by
   // lanes j/4 + 4q of its group, so lane i points at row t0 + i/4, columns
@@ -469,14 +478,14 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
   auto tr4 = [&](const bf16* T, int off) -> bf16x4 {
     return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(T + off)));
   };
-  const int tr_lane = (l16 >> 2) * XS_LD + 4 * (l16 & 3);
+  auto tr_lane = [&](int ld) { return (l16 >> 2) * ld + 4 * (l16 & 3); };
   // token-contraction operand of a row-major [token][d] tile: lane (d = 32 db
   // + l32, hf) holds tokens 16m + 4hf + 0..3 and 16m + 8 + 4hf + 0..3, the
   // token slots of result registers 8m .. 8m+7 of a 32x32 block
-  const int tok_lane = tr_lane + 4 * hf * XS_LD + 16 * ((l >> 4) & 1);
-  auto tok_frag = [&](const bf16* T, int m, int db) -> bf16x8 {
-    const bf16x4 lo = tr4(T, tok_lane + 16 * m * XS_LD + 32 * db);
-    const bf16x4 hi = tr4(T, tok_lane + (16 * m + 8) * XS_LD + 32 * db);
+  auto tok_frag = [&](const bf16* T, int ld, int m, int db) -> bf16x8 {
+    const int tok_lane = tr_lane(ld) + 4 * hf * ld + 16 * ((l >> 4) & 1);
+    const bf16x4 lo = tr4(T, tok_lane + 16 * m * ld + 32 * db);
+    const bf16x4 hi = tr4(T, tok_lane + (16 * m + 8) * ld + 32 * db);
     return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
   };
 
@@ -511,7 +520,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
 #pragma unroll
         for (int i = 0; i < EPT; i += 2) {
           *reinterpret_cast<uint32_t*>(&xs[b3][row * XS_LD + col0 + i]) = pack_bf16x2(fk[i], fk[i + 1]);
-          *reinterpret_cast<uint32_t*>(&vs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fv[i], fv[i + 1]);
+          *reinterpret_cast<uint32_t*>(&vs[b2][row * VS_LD + col0 + i]) = pack_bf16x2(fv[i], fv[i + 1]);
         }
       }
       if constexpr (DO_A) {
@@ -521,7 +530,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
         normalise(fq, norm_q);
 #pragma unroll
         for (int i = 0; i < EPT; i += 2)
-          *reinterpret_cast<uint32_t*>(&qs[b2][row * XS_LD + col0 + i]) = pack_bf16x2(fq[i], fq[i + 1]);
+          *reinterpret_cast<uint32_t*>(&qs[b2][row * QS_LD + col0 + i]) = pack_bf16x2(fq[i], fq[i + 1]);
       }
     };
     // z' = -log2(e) z:  sigma = 1/(1+2^z'),  A' = z' sigma = -log2(e) SiLU(z),
@@ -579,7 +588,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
           const f32x4 y = y_block(as_, tb, bi);
           const int dcol = 16 * db + l16;
           const int tok0 = 16 * tb + 4 * g4;
-          const bf16x4 vv = tr4(vs[P], tr_lane + tok0 * XS_LD + 16 * db);  // V[tok0 + r][dcol]
+          const bf16x4 vv = tr4(vs[P], tr_lane(VS_LD) + tok0 * VS_LD + 16 * db);  // V[tok0 + r][dcol]
           float ev[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -589,10 +598,10 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
           }
           const uint32_t e01 = pack_bf16x2(ev[0], ev[1]), e23 = pack_bf16x2(ev[2], ev[3]);
           uint16_t* es16 = reinterpret_cast<uint16_t*>(es);
-          es16[(tok0 + 0) * XS_LD + dcol] = (uint16_t)e01;
-          es16[(tok0 + 1) * XS_LD + dcol] = (uint16_t)(e01 >> 16);
-          es16[(tok0 + 2) * XS_LD + dcol] = (uint16_t)e23;
-          es16[(tok0 + 3) * XS_LD + dcol] = (uint16_t)(e23 >> 16);
+          es16[(tok0 + 0) * ES_LD + dcol] = (uint16_t)e01;
+          es16[(tok0 + 1) * ES_LD + dcol] = (uint16_t)(e01 >> 16);
+          es16[(tok0 + 2) * ES_LD + dcol] = (uint16_t)e23;
+          es16[(tok0 + 3) * ES_LD + dcol] = (uint16_t)(e23 >> 16);
         }
       }
       if constexpr (DO_A) {
@@ -632,7 +641,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
         f32x16 pz = {};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * XS_LD + 16 * m + 8 * hf]);
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(&es[l32 * ES_LD + 16 * m + 8 * hf]);
           pz = mma32(a, w2b[m], pz);
         }
         const bf16x8 apv[2] = {as_bf16x8(apk[P][0], apk[P][1], apk[P][2], apk[P][3]),
@@ -640,7 +649,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
 #pragma unroll
         for (int db = 0; db < 2; ++db)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) gw2[db] = mma32(apv[m], tok_frag(es, m, db), gw2[db]);
+          for (int m = 0; m < 2; ++m) gw2[db] = mma32(apv[m], tok_frag(es, ES_LD, m, db), gw2[db]);
         uint32_t dw[8];
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
@@ -651,7 +660,7 @@ __device__ __forceinline__ void fwd_body_bf(const StepCtx& p) {
 #pragma unroll
         for (int db = 0; db < 2; ++db)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) gw1[db] = mma32(tok_frag(xs[b3], m, db), dpk[m], gw1[db]);
+          for (int m = 0; m < 2; ++m) gw1[db] = mma32(tok_frag(xs[b3], XS_LD, m, db), dpk[m], gw1[db]);
       }
       if constexpr (DO_A) act_apply_t(zq);
     };

@@ -13,11 +13,11 @@ struct TunedShape {
   ttt_tile_cfg_t cfg;
 };
 inline constexpr TunedShape kTuned[] = {
-    {128, 1, 1374, 1, 0, {32, 0, 1, 0}},  // single_head_256x1374_bf16: 4.225 ms
+    {128, 1, 1374, 1, 0, {32, 0, 0, 0}},  // single_head_256x1374_bf16: 4.064 ms
     {128, 0, 1374, 1, 0, {0, 512, 1, 0}},  // single_head_4x1374: 0.122 ms
-    {256, 1, 10992, 128, 0, {16, 0, 1, 0}},  // batch8_uneven_chunk8f_bf16: 8.136 ms
+    {256, 1, 10992, 128, 0, {0, 0, 0, 0}},  // batch8_uneven_chunk8f_bf16: 7.397 ms
     {256, 1, 10992, 128, 1, {16, 0, 1, 0}},  // batch8_uneven_chunk8f_bf16: 43.296 ms
-    {256, 1, 10992, 16, 0, {16, 0, 1, 0}},  // layer16_64f_chunk8f: 0.675 ms
-    {256, 0, 10992, 16, 0, {16, 0, 1, 0}},  // layer16_64f_chunk8f: 2.862 ms
+    {256, 1, 10992, 16, 0, {16, 0, 1, 0}},  // layer16_64f_chunk8f: 0.674 ms
+    {256, 0, 10992, 16, 0, {16, 0, 1, 0}},  // layer16_64f_chunk8f: 2.867 ms
 };
 }  // namespace ttt
