@@ -83,7 +83,7 @@ ttt_status_t check_problem(const ttt_problem_t* p, Shape* s) {
 // the chunk's normalised rows and intermediate products, the FP32 masters and
 // their operand copies, the loss partials.
 struct LargeLayout {
-  size_t Kn, Qn, E, A, D, Aq, Vn, S1, W1, W2, W1op, W2op, loss_part, total;
+  size_t sync, Kn, Qn, E, A, D, Aq, Vn, S1, W1, W2, W1op, W2op, loss_part, total;
 };
 LargeLayout large_layout(const Shape& s) {
   LargeLayout L{};
@@ -95,6 +95,7 @@ LargeLayout large_layout(const Shape& s) {
     off = (off + bytes + 255) / 256 * 256;
     return o;
   };
+  L.sync = take(256);  // word 0: the device error word (no barrier here; kept clear)
   L.Kn = take(M * d * op);
   L.Qn = take(M * d * op);
   L.E = take(M * d * op);
@@ -766,6 +767,9 @@ ttt_status_t run_forward_large(const ttt_problem_t* p, const Shape& S, int B, co
   if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
   const int64_t dh = S.dh(), M = S.M;
   const size_t iob = S.io_bf16 ? 2 : 4;
+  // the error word reads 0 after a call (nothing here can give up)
+  if (cu[B] > 0 && !launched([&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
+    return TTT_EHIP;
   float* W1 = at<float>(ws, L.W1);
   float* W2 = at<float>(ws, L.W2);
   int64_t ckrow = 0;

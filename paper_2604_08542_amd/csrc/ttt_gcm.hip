@@ -29,8 +29,10 @@ struct EpProj : EpBase {
   __device__ __forceinline__ void operator()(int r, int c, float x) {
     if (r >= rows) return;
     const float y = bias ? x + bias[c] : x;
-    const int which = c / D, f = c - which * D;
-    T* dst = which == 0 ? q : which == 1 ? k : v;
+    // a 128-column tile never straddles two of the thirds (D % 128 == 0),
+    // so the selection is uniform over the tile; comparisons, no division
+    T* dst = c < D ? q : c < 2 * D ? k : v;
+    const int f = c < D ? c : c < 2 * D ? c - D : c - 2 * D;
     dst[(int64_t)r * D + f] = (T)y;
   }
 };

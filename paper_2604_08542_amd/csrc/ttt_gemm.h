@@ -65,7 +65,9 @@ struct Stage {
   static constexpr int PER = BYTES / NTH / 16;  // 16-byte loads per thread
   static constexpr int EPC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   u32x4 r[PER];
-  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int ld, int mn0, int k0) {
+  // This thread's byte offsets of its chunks for the slice at k0 = 0; a
+  // slice at k0 adds the uniform kbytes(ld) * k0.
+  __device__ __forceinline__ static void offsets(int ld, int mn0, int (&vo)[PER]) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -74,14 +76,21 @@ struct Stage {
       if constexpr (LAYOUT == KMAJ) {  // [ROWS][BK]
         constexpr int CPR = BK / EPC;
         row = mn0 + c / CPR;
-        col = k0 + (c % CPR) * EPC;
+        col = (c % CPR) * EPC;
       } else {  // [BK][ROWS]
         constexpr int CPR = ROWS / EPC;
-        row = k0 + c / CPR;
+        row = c / CPR;
         col = mn0 + (c % CPR) * EPC;
       }
-      r[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, (row * ld + col) * (int)sizeof(T), 0, 0);
+      vo[i] = (row * ld + col) * (int)sizeof(T);
     }
+  }
+  __device__ __forceinline__ static int kbytes(int ld) {
+    return LAYOUT == KMAJ ? (int)sizeof(T) : ld * (int)sizeof(T);
+  }
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, const int (&vo)[PER], int kofs) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) r[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, vo[i] + kofs, 0, 0);
   }
   __device__ __forceinline__ void store(T* lds) const {
     const int tid = threadIdx.x;
@@ -170,16 +179,22 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   // buffer, slice kt+1 waits in the other and slice kt+2 is in flight from
   // HBM into registers (two register stages, alternating), so a global load
   // has two slices of products to arrive before it is needed.
-  Stage<T, LA, BM> ga[2];
-  Stage<T, LB, BN> gb[2];
+  using SA = Stage<T, LA, BM>;
+  using SB = Stage<T, LB, BN>;
+  SA ga[2];
+  SB gb[2];
+  int voa[SA::PER], vob[SB::PER];
+  SA::offsets(lda, m0, voa);
+  SB::offsets(ldb, n0, vob);
+  const int ka = SA::kbytes(lda) * bk<T>(), kb = SB::kbytes(ldb) * bk<T>();  // bytes per slice
   constexpr int BK = bk<T>();
   const int nk = (K + BK - 1) / BK;
   f32x16 acc[MB][2] = {};
-  ga[0].load(ra, lda, m0, 0);
-  gb[0].load(rb, ldb, n0, 0);
+  ga[0].load(ra, voa, 0);
+  gb[0].load(rb, vob, 0);
   if (nk > 1) {
-    ga[1].load(ra, lda, m0, BK);
-    gb[1].load(rb, ldb, n0, BK);
+    ga[1].load(ra, voa, ka);
+    gb[1].load(rb, vob, kb);
   }
   ga[0].store(sa[0]);
   gb[0].store(sb[0]);
@@ -187,17 +202,26 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   auto body = [&](int kt, auto PC) {
     constexpr int P = decltype(PC)::value;  // kt & 1
     if (kt + 2 < nk) {  // slice kt+2 into register stage P (free: slice kt left it last iteration)
-      ga[P].load(ra, lda, m0, (kt + 2) * BK);
-      gb[P].load(rb, ldb, n0, (kt + 2) * BK);
+      ga[P].load(ra, voa, (kt + 2) * ka);
+      gb[P].load(rb, vob, (kt + 2) * kb);
+    }
+    // every operand fragment of the slice is read before the products, so
+    // the LDS latency is paid once per slice, not once per product step
+    using FT = decltype(frag<T, LB, BN>(sb[P], wn, 0));
+    FT fb[ksteps<T>()][2], fa[ksteps<T>()][MB];
+#pragma unroll
+    for (int j = 0; j < ksteps<T>(); ++j) {
+      fb[j][0] = frag<T, LB, BN>(sb[P], wn, j);
+      fb[j][1] = frag<T, LB, BN>(sb[P], wn + 32, j);
+#pragma unroll
+      for (int bm = 0; bm < MB; ++bm) fa[j][bm] = frag<T, LA, BM>(sa[P], wm + 32 * bm, j);
     }
 #pragma unroll
     for (int j = 0; j < ksteps<T>(); ++j) {
-      const auto b0 = frag<T, LB, BN>(sb[P], wn, j), b1 = frag<T, LB, BN>(sb[P], wn + 32, j);
 #pragma unroll
       for (int bm = 0; bm < MB; ++bm) {
-        const auto a = frag<T, LA, BM>(sa[P], wm + 32 * bm, j);
-        acc[bm][0] = mma32(a, b0, acc[bm][0]);
-        acc[bm][1] = mma32(a, b1, acc[bm][1]);
+        acc[bm][0] = mma32(fa[j][bm], fb[j][0], acc[bm][0]);
+        acc[bm][1] = mma32(fa[j][bm], fb[j][1], acc[bm][1]);
       }
     }
     if (kt + 1 < nk) {  // slice kt+1 (register stage P^1) into the other LDS buffer

@@ -39,9 +39,9 @@ def test_abi_under_asan_ubsan(tmp_path):
         if os.path.exists(built) and os.path.getmtime(built) >= newest:
             return built
         obj = str(tmp_path / (os.path.basename(src) + ".o"))
-        subprocess.run([cc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-w", "-Xclang",
-                        "-target-feature", "-Xclang", "-packed-fp32-ops", "-c", "-o", obj, src], check=True,
-                       capture_output=True, timeout=600)
+        from paper_2604_08542_amd.build import FLAGS
+        subprocess.run([cc] + [f for f in FLAGS if f not in ("-Wall", "-Werror")] + ["-w", "-c", "-o", obj, src],
+                       check=True, capture_output=True, timeout=600)
         return obj
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(kernel_obj, srcs))
