@@ -21,6 +21,7 @@ Every time is taken with HIP events on the stream the library launches on
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -221,6 +222,28 @@ def other_forms(forms, steps, warmup):
                 res[f"amu_fwd_bwd_{sync}_{io}"] = dict(workload=w.name, ms_per_step=ms,
                                                        tokens_per_s=w.n_tokens / (ms * 1e-3))
             del dev, O, W3, et
+        # the paper's own regime: one head of 1024, hidden 4096 (streamed-weight GEMM chunk step)
+        wp = WORKLOADS["paper_state_64f_chunk8f_bf16"]
+        for io in ("bf16", "f32"):
+            dev = make_inputs_torch(wp.n_tokens, wp.n_heads, wp.d_head, wp.d_hidden, seed=0, io_dtype=io)
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1)
+            W3 = torch.randn(dev["W1"].shape, generator=g, device="cuda") / float(wp.d_head) ** 0.5
+            et = torch.from_numpy(make_eta_tok(wp.n_tokens, wp.n_heads, wp.chunk_tokens, 100.0, 0)).cuda()
+            O = torch.empty_like(dev["Q"])
+            ws = torch.empty(ops.L.load().ttt_amu_workspace_bytes(ctypes.byref(
+                ops.problem(dev["Q"], wp.d_hidden, wp.n_tokens, wp.chunk_tokens, 0.0, ops._flags(True)))),
+                dtype=torch.uint8, device="cuda")
+            for sync in ("chain", "gcs"):
+                ms = timed(lambda: ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3,
+                                               wp.chunk_tokens, sync=sync, want_final=False, out=O, ws=ws),
+                           few if io == "bf16" else 2, 1)
+                ach = 18.0 * wp.d_head * wp.d_hidden * wp.n_tokens * wp.n_heads / (ms * 1e-3) / 1e12
+                res[f"amu_paper_state_{sync}_{io}"] = dict(
+                    workload=wp.name.replace("_bf16", ""), ms_per_step=ms, tokens_per_s=wp.n_tokens / (ms * 1e-3),
+                    roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io], unit="TFLOP/s", frac=ach / PEAK[io]))
+            del dev, O, W3, et, ws
+            torch.cuda.empty_cache()
     if "gcm" in forms:  # the layer around the memory unit: projections, unit, output projection, gate
         for name, H, d, h, frames in (("gcm_layer16_64f", 16, 64, 256, 64), ("gcm_paper_state_64f", 1, 1024, 4096, 64)):
             N, D, M = frames * 1374, H * d, 8 * 1374

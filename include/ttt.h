@@ -33,15 +33,16 @@
  *     exception crosses this boundary.  Calls from different host threads
  *     are safe; calls that share a workspace must be stream-ordered.
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
- *     chip by every entry point), and large states for ttt_chunk_fwd,
- *     ttt_batched_fwd and ttt_batched_fwd_ckpt: d a multiple of 256 up to
- *     4096 and h a multiple of 128 up to 16384 (the paper's single head of
- *     1024 with hidden 4096), where every product of a chunk step is a GEMM
- *     over weights streamed from HBM and a chunk's rows times max(d, h)
- *     elements must stay below 2^31 bytes.  Other sizes return TTT_ESHAPE;
- *     the other entry points return TTT_ENOTSUP for large states.  n_tokens may be 0: token pointers may then be NULL,
- *     the final weights (if asked for) are the initial ones and nothing
- *     else is written.
+ *     chip by every entry point), and large states for the forward entry
+ *     points ttt_chunk_fwd, ttt_batched_fwd, ttt_batched_fwd_ckpt,
+ *     ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     multiple of 128 up to 16384 (the paper's single head of 1024 with
+ *     hidden 4096), where every product of a chunk step is a GEMM over
+ *     weights streamed from HBM and a chunk's rows times max(d, h) elements
+ *     must stay below 2^31 bytes.  Other sizes return TTT_ESHAPE; the other
+ *     entry points return TTT_ENOTSUP for large states.  n_tokens may be 0:
+ *     token pointers may then be NULL, the final weights (if asked for) are
+ *     the initial ones and nothing else is written.
  */
 #ifndef TTT_H_
 #define TTT_H_
@@ -225,7 +226,11 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
  *   W3_0      [H][d][h] f32; W3_T likewise (W1_T, W2_T, W3_T all or none).
  *   ws        ws_bytes >= ttt_amu_workspace_bytes(p).
  * Q, K, V, O, normalisation flags, TTT_MMA_BF16 and strides as in
- * ttt_chunk_fwd; TTT_SAVE_CKPT / TTT_EMIT_LOSS return TTT_ENOTSUP. */
+ * ttt_chunk_fwd; TTT_SAVE_CKPT / TTT_EMIT_LOSS return TTT_ENOTSUP.  At
+ * large state sizes (the paper's d = 1024, h = 4096) every product is a GEMM
+ * over weights streamed from HBM, one head and one chunk at a time; the GCS
+ * form then subtracts the chunks' gradients at W0 from the FP32 weights one
+ * chunk after another (in chunk order) before the apply. */
 enum { TTT_SYNC_CHAIN = 0, TTT_SYNC_GCS = 1 };
 size_t ttt_amu_workspace_bytes(const ttt_problem_t* p);
 ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,

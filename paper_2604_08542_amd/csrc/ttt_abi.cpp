@@ -113,6 +113,43 @@ LargeLayout large_layout(const Shape& s) {
   return L;
 }
 
+// Workspace of the memory unit's large-state chunk step: the chunk's
+// normalised rows, E, the [rows][h] intermediates, three FP32 masters and
+// their operand copies.
+struct LargeAmuLayout {
+  size_t sync, Kn, Qn, E, Vn, Z3, Hd, G1, G3, D1, D3, W1, W2, W3, W1op, W2op, W3op, total;
+};
+LargeAmuLayout large_amu_layout(const Shape& s) {
+  LargeAmuLayout L{};
+  const size_t op = s.mma_bf16 ? 2 : 4;
+  const size_t M = (size_t)s.Mrows, d = (size_t)s.d, h = (size_t)s.h;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.sync = take(256);
+  L.Kn = take(M * d * op);
+  L.Qn = take(M * d * op);
+  L.E = take(M * d * op);
+  L.Vn = take(M * d * 4);
+  L.Z3 = take(M * h * op);
+  L.Hd = take(M * h * op);
+  L.G1 = take(M * h * op);
+  L.G3 = take(M * h * op);
+  L.D1 = take(M * h * op);
+  L.D3 = take(M * h * op);
+  L.W1 = take(d * h * 4);
+  L.W2 = take(d * h * 4);
+  L.W3 = take(d * h * 4);
+  L.W1op = take(d * h * op);
+  L.W2op = take(d * h * op);
+  L.W3op = take(d * h * op);
+  L.total = off;
+  return L;
+}
+
 struct WsLayout {
   size_t sync, partial, partial_loss, pp, adj, wlast, prep, fin, deta_seq, total;
   int64_t slot_cap;
@@ -965,6 +1002,79 @@ ttt_status_t run_amu(const ttt_problem_t* p, const Shape& S, int sync, const voi
 }
 
 
+// The memory unit at large state sizes, per head: the FP32 masters and their
+// operand copies from W0, then chain: per chunk in order, its gradient, the
+// update (masters and operand copies) and the apply of its queries; GCS:
+// every chunk's gradient at W0 subtracted from the masters in chunk order
+// (the operand copies keep W0), the operand copies of W*, then every
+// chunk's apply.
+ttt_status_t run_amu_large(const ttt_problem_t* p, const Shape& S, int sync, const void* Q, const void* K,
+                           const void* V, const float* eta_tok, const float* W1_0, const float* W2_0,
+                           const float* W3_0, void* O, float* W1_T, float* W2_T, float* W3_T, void* ws,
+                           size_t ws_bytes, hipStream_t st) {
+  const LargeAmuLayout L = large_amu_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh(), H = S.H;
+  const int64_t C = (N + M - 1) / M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  if (N > 0 && !launched([&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); }))
+    return TTT_EHIP;
+  float* Wm[3] = {at<float>(ws, L.W1), at<float>(ws, L.W2), at<float>(ws, L.W3)};
+  void* Wo[3] = {at<char>(ws, L.W1op), at<char>(ws, L.W2op), at<char>(ws, L.W3op)};
+  const float* W0[3] = {W1_0, W2_0, W3_0};
+  float* WT[3] = {W1_T, W2_T, W3_T};
+  auto copy = [&](float* dst, const float* src) {
+    return hipMemcpyAsync(dst, src, dh * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  };
+  auto cast_all = [&]() {
+    for (int m = 0; m < 3; ++m)
+      if (!launched([&] { return launch_large_cast(Wm[m], Wo[m], dh, S.mma_bf16, st); })) return false;
+    return true;
+  };
+  for (int64_t hd = 0; hd < H; ++hd) {
+    if (C > 0) {
+      for (int m = 0; m < 3; ++m)
+        if (!copy(Wm[m], W0[m] + hd * dh)) return TTT_EHIP;
+      if (!cast_all()) return TTT_EHIP;
+      auto step = [&](int64_t c, bool grad, bool write_op, bool apply) {
+        const int64_t t0 = c * M;
+        const int64_t off = (t0 * S.stride_tok + hd * S.stride_head) * (int64_t)iob;
+        LargeAmuArgs a{};
+        a.K = static_cast<const char*>(K) + off;
+        a.V = static_cast<const char*>(V) + off;
+        a.Q = static_cast<const char*>(Q) + off;
+        a.O = apply ? static_cast<char*>(O) + off : nullptr;
+        a.stride_tok = S.stride_tok;
+        a.eta = eta_tok + t0 * H + hd;
+        a.eta_stride = H;
+        a.flags = p->flags;
+        a.rows = (int32_t)std::min<int64_t>(M, N - t0); a.d = S.d; a.h = S.h;
+        a.grad = grad ? 1 : 0; a.write_op = write_op ? 1 : 0;
+        a.Kn = at<char>(ws, L.Kn); a.Qn = at<char>(ws, L.Qn); a.E = at<char>(ws, L.E); a.Vn = at<float>(ws, L.Vn);
+        a.Z3 = at<char>(ws, L.Z3); a.Hd = at<char>(ws, L.Hd); a.G1 = at<char>(ws, L.G1); a.G3 = at<char>(ws, L.G3);
+        a.D1 = at<char>(ws, L.D1); a.D3 = at<char>(ws, L.D3);
+        a.W1 = Wm[0]; a.W2 = Wm[1]; a.W3 = Wm[2];
+        a.W1op = Wo[0]; a.W2op = Wo[1]; a.W3op = Wo[2];
+        return launched([&] { return launch_large_amu_step(a, S.io_bf16, S.mma_bf16, st); });
+      };
+      if (sync == TTT_SYNC_CHAIN) {
+        for (int64_t c = 0; c < C; ++c)
+          if (!step(c, true, true, true)) return TTT_EHIP;
+      } else {
+        for (int64_t c = 0; c < C; ++c)
+          if (!step(c, true, false, false)) return TTT_EHIP;
+        if (!cast_all()) return TTT_EHIP;
+        for (int64_t c = 0; c < C; ++c)
+          if (!step(c, false, false, true)) return TTT_EHIP;
+      }
+    }
+    if (W1_T)
+      for (int m = 0; m < 3; ++m)
+        if (!copy(WT[m] + hd * dh, C > 0 ? Wm[m] : W0[m] + hd * dh)) return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
 // Reverse mode of the paper's memory unit.  Workspace: shard partials, the
 // carried adjoint Wh [H][3dh], the weights the backward needs ([C+1][H][3dh]
 // for the chain: every W_c, recomputed; [1][H][3dh] for GCS: W*), and three
@@ -1310,7 +1420,7 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
 size_t ttt_amu_workspace_bytes(const ttt_problem_t* p) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK) return 0;
-  if (S.large) return 0;
+  if (S.large) return large_amu_layout(S).total;
   return amu_ws_layout(S).total;
 }
 
@@ -1321,7 +1431,6 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
     if (!W1_0 || !W2_0 || !W3_0) return TTT_EINVAL;
@@ -1331,6 +1440,9 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
                           (const void*)W1_T, (const void*)W2_T, (const void*)W3_T})
       if (q && !aligned16(q)) return TTT_EINVAL;
     if (p->n_tokens == 0 && !W1_T) return TTT_OK;
+    if (S.large)
+      return run_amu_large(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, O, W1_T, W2_T, W3_T, ws, ws_bytes,
+                           static_cast<hipStream_t>(hip_stream));
     return run_amu(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, O, W1_T, W2_T, W3_T, ws, ws_bytes,
                    static_cast<hipStream_t>(hip_stream));
   } catch (...) {

@@ -47,6 +47,40 @@ struct LargeStepArgs {
   float* loss;       // nullable: the chunk's loss
 };
 hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// Chunk step of the paper's memory unit (SwiGLU network, dot-product loss
+// with token-wise step sizes) at large state sizes.
+struct LargeAmuArgs {
+  const void* K;  // first token of the chunk, head offset applied
+  const void* V;
+  const void* Q;
+  void* O;        // nullable: no apply
+  int64_t stride_tok;
+  const float* eta;    // step size of the chunk's first token for this head
+  int64_t eta_stride;  // between consecutive tokens (the head count)
+  uint32_t flags;
+  int32_t rows, d, h;
+  int32_t grad;      // 1: gradient of the chunk and the update of the masters
+  int32_t write_op;  // 1: the update also rewrites the operand copies
+  void* Kn;          // [rows][d] operand type
+  void* Qn;
+  void* E;
+  float* Vn;         // [rows][d] FP32
+  void* Z3;          // [rows][h] operand type: x W3
+  void* Hd;          // SiLU(x W1) * (x W3)
+  void* G1;          // Z3 * SiLU'(Z1)
+  void* G3;          // SiLU(Z1)
+  void* D1;          // hidden adjoint times G1
+  void* D3;          // hidden adjoint times G3
+  float* W1;         // FP32 masters [d][h], [h][d], [d][h], updated in place
+  float* W2;
+  float* W3;
+  void* W1op;        // operand copies of the masters
+  void* W2op;
+  void* W3op;
+};
+hipError_t launch_large_amu_step(const LargeAmuArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// Operand copy (BF16 or FP32) of n FP32 values.
+hipError_t launch_large_cast(const float* src, void* dst, int64_t n, bool mma_bf16, hipStream_t st);
 // One projection of the layer around the memory unit (token rows in the io
 // type, D = H * d features): kind 0, [Q | K | V] = X W (+ bias) with W
 // [D][3D]; kind 1, Y = alpha * (O W (+ bias)) + X with W [D][D].

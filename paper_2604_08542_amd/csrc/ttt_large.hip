@@ -13,6 +13,16 @@
 //   gW2    W2 -= eta A^T E
 //   Zq     Zq = Q W1'         -> Aq = SiLU(Zq)
 //   O      O = Aq W2'
+// The paper's memory unit (Supp. A: f_W(x) = (SiLU(x W1) * (x W3)) W2, the
+// dot-product loss with token-wise step sizes, W <- W - grad) runs the same
+// way; E = -eta_i v_i does not depend on W, so its gradient needs no
+// contraction over the hidden axis before the hidden adjoint:
+//   Z3     Z3 = K W3          (stored)
+//   Z1     Z1 = K W1          -> Hd = SiLU(Z1) Z3, G1 = Z3 SiLU'(Z1), G3 = SiLU(Z1)
+//   E      E = -eta_i Vn_i
+//   dH     dH = E W2^T        -> D1 = dH G1, D3 = dH G3
+//   gW     W1 -= K^T D1, W3 -= K^T D3, W2 -= Hd^T E
+//   apply  Zq3 = Q W3', Hq = SiLU(Q W1') Zq3, O = Hq W2'
 // The masters stay FP32; the matrix-core operands are BF16 copies (or FP32
 // with FP32 matrix cores).  Each output element of every product is owned by
 // one work-group, which sums its whole contraction in a fixed order, so the
@@ -87,7 +97,8 @@ struct EpD : EpBase {
     put(d + (int64_t)r * ld + c, p * (float)s1[(int64_t)r * ld + c]);
   }
 };
-// W -= eta * G (FP32 master), then the operand copy of the new W.
+// W -= eta * G (FP32 master), then the operand copy of the new W (nullable:
+// masters only, while a sum of several gradients is being taken).
 template <typename T>
 struct EpUpd : EpBase {
   float* w;
@@ -98,7 +109,7 @@ struct EpUpd : EpBase {
     const int64_t i = (int64_t)r * ld + c;
     const float wn = w[i] - eta * g;
     w[i] = wn;
-    put(wop + i, wn);
+    if (wop) put(wop + i, wn);
   }
 };
 // O rows of the chunk into the strided token tensor.
@@ -110,6 +121,55 @@ struct EpOut : EpBase {
   __device__ __forceinline__ void operator()(int r, int c, float y) {
     if (r >= rows) return;
     o[(int64_t)r * stride_tok + c] = (IOT)y;
+  }
+};
+
+// A product stored as it is ([rows][ld], operand type).
+template <typename T>
+struct EpStore : EpBase {
+  T* z;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float v) {
+    if (r >= rows) return;
+    put(z + (int64_t)r * ld + c, v);
+  }
+};
+// Z1 = x W1 of the memory unit with Z3 = x W3 stored: Hd = SiLU(Z1) Z3; for
+// the gradient also the factors of the hidden adjoint, G1 = Z3 SiLU'(Z1)
+// (towards W1) and G3 = SiLU(Z1) (towards W3).
+template <typename T, bool GRAD>
+struct EpSwi : EpBase {
+  const T* z3;
+  T* hd;
+  T* g1;
+  T* g3;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float z1) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    float sg;
+    const float sv = silu_sig(z1, sg);
+    const float z3v = (float)z3[i];
+    put(hd + i, sv * z3v);
+    if constexpr (GRAD) {
+      put(g1 + i, z3v * fmaf(sv, 1.0f - sg, sg));
+      put(g3 + i, sv);
+    }
+  }
+};
+// dH = E W2^T: D1 = dH G1, D3 = dH G3.
+template <typename T>
+struct EpD2 : EpBase {
+  const T* g1;
+  const T* g3;
+  T* d1;
+  T* d3;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float dh) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    put(d1 + i, dh * (float)g1[i]);
+    put(d3 + i, dh * (float)g3[i]);
   }
 };
 
@@ -167,6 +227,21 @@ __global__ void k_init_w(const float* w1, const float* w2, float* m1, float* m2,
     o1[i] = (T)a;
     o2[i] = (T)b;
   }
+}
+
+// E = -eta_i Vn_i of the memory unit's chunk, in the operand type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_amu_e(T* e, const float* vn, const float* eta, int64_t eta_stride, int rows,
+                                               int d) {
+  const int64_t n = (int64_t)rows * d;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    e[i] = (T)(-eta[(i / d) * eta_stride] * vn[i]);
+}
+
+template <typename T>
+__global__ void k_cast(const float* src, T* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (T)src[i];
 }
 
 // loss[c] = (sum of the tile partials, in tile order) / M_c
@@ -229,6 +304,63 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T, typename IOT>
+hipError_t amu_step_t(const LargeAmuArgs& a, hipStream_t st) {
+  const int M = a.rows, d = a.d, h = a.h;
+  constexpr int BMT = 128, BMW = 128;
+  const int mt = (M + BMT - 1) / BMT;
+  T* Kn = static_cast<T*>(a.Kn);
+  T* Qn = static_cast<T*>(a.Qn);
+  T* E = static_cast<T*>(a.E);
+  T* Z3 = static_cast<T*>(a.Z3);
+  T* Hd = static_cast<T*>(a.Hd);
+  T* G1 = static_cast<T*>(a.G1);
+  T* G3 = static_cast<T*>(a.G3);
+  T* D1 = static_cast<T*>(a.D1);
+  T* D3 = static_cast<T*>(a.D3);
+  T* W1o = static_cast<T*>(a.W1op);
+  T* W2o = static_cast<T*>(a.W2op);
+  T* W3o = static_cast<T*>(a.W3op);
+  LargeNormArgs na{a.K, a.V, a.Q, a.stride_tok, a.flags, M, d, a.Kn, a.Vn, a.Qn};
+  hipLaunchKernelGGL((k_norm<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, na);
+  if (a.grad) {
+    EpStore<T> e1{{}, Z3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStore<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M, W3o,
+                       h, d, d, e1);
+    EpSwi<T, true> e2{{}, Z3, Hd, G1, G3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpSwi<T, true>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M,
+                       W1o, h, d, d, e2);
+    const int64_t ne = (int64_t)M * d;
+    hipLaunchKernelGGL(k_amu_e<T>, dim3((unsigned)std::min<int64_t>((ne + 255) / 256, 4096)), dim3(256), 0, st, E,
+                       a.Vn, a.eta, a.eta_stride, M, d);
+    EpD2<T> e3{{}, G1, G3, D1, D3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpD2<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, E, d, M, W2o, d, h,
+                       d, e3);
+    // the step sizes are inside the loss: W <- W - grad
+    EpUpd<T> u1{{}, a.W1, a.write_op ? W1o : nullptr, h, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(h / BN, d / BMW), dim3(NTH), 0, st, Kn, d, M, D1,
+                       h, M, M, u1);
+    EpUpd<T> u3{{}, a.W3, a.write_op ? W3o : nullptr, h, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(h / BN, d / BMW), dim3(NTH), 0, st, Kn, d, M, D3,
+                       h, M, M, u3);
+    EpUpd<T> u2{{}, a.W2, a.write_op ? W2o : nullptr, d, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(d / BN, h / BMW), dim3(NTH), 0, st, Hd, h, M, E,
+                       d, M, M, u2);
+  }
+  if (a.O) {
+    EpStore<T> e6{{}, Z3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStore<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M, W3o,
+                       h, d, d, e6);
+    EpSwi<T, false> e7{{}, Z3, Hd, nullptr, nullptr, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpSwi<T, false>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M,
+                       W1o, h, d, d, e7);
+    EpOut<IOT> e8{{}, static_cast<IOT*>(a.O), a.stride_tok, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpOut<IOT>>), dim3(d / BN, mt), dim3(NTH), 0, st, Hd, h, M, W2o, d,
+                       h, h, e8);
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t init_t(const float* w1, const float* w2, float* m1, float* m2, void* o1, void* o2, int64_t n,
                   hipStream_t st) {
@@ -243,6 +375,21 @@ hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16
   using namespace large;
   if (mma_bf16) return io_bf16 ? step_t<bf16, bf16>(a, st) : step_t<bf16, float>(a, st);
   return step_t<float, float>(a, st);
+}
+
+hipError_t launch_large_amu_step(const LargeAmuArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  using namespace large;
+  if (mma_bf16) return io_bf16 ? amu_step_t<bf16, bf16>(a, st) : amu_step_t<bf16, float>(a, st);
+  return amu_step_t<float, float>(a, st);
+}
+
+hipError_t launch_large_cast(const float* src, void* dst, int64_t n, bool mma_bf16, hipStream_t st) {
+  using namespace large;
+  if (mma_bf16)
+    hipLaunchKernelGGL(k_cast<bf16>, dim3(1024), dim3(256), 0, st, src, static_cast<bf16*>(dst), n);
+  else
+    hipLaunchKernelGGL(k_cast<float>, dim3(1024), dim3(256), 0, st, src, static_cast<float*>(dst), n);
+  return hipGetLastError();
 }
 
 hipError_t launch_large_init(const float* w1, const float* w2, float* m1, float* m2, void* o1, void* o2, int64_t n,

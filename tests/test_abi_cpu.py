@@ -144,6 +144,12 @@ def test_amu_validation(lib):
     p = prob(n_tokens=1000, chunk_tokens=100)
     assert lib.ttt_amu_workspace_bytes(ctypes.byref(p)) >= 1024 * 3 * 64 * 256 * 4
     assert lib.ttt_amu_workspace_bytes(ctypes.byref(prob(d_hidden=96))) == 0
+    # the paper's state (one head of 1024, hidden 4096): the forward takes a
+    # workspace of the chunk's intermediates and three weight sets; the
+    # reverse mode is built for the on-chip sizes only
+    big = prob(n_heads=1, d_head=1024, d_hidden=4096, n_tokens=2748, chunk_tokens=1374)
+    assert lib.ttt_amu_workspace_bytes(ctypes.byref(big)) >= 6 * 1374 * 4096 * 4 + 3 * 1024 * 4096 * 4
+    assert lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(big), 0) == 0
     assert call(p, sync=2) == L.TTT_EINVAL
     assert call(p, eta=None) == L.TTT_EINVAL
     assert call(p, W3=None) == L.TTT_EINVAL
