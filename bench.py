@@ -145,6 +145,19 @@ def other_forms(forms, steps, warmup):
             r, _, _ = forward_form(w, io, few if io == "bf16" else 2, 1)
             res[f"paper_state_{io}"] = r
             torch.cuda.empty_cache()
+        # GCS form (Eq. 10) at the paper's state, BF16
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16")
+        O = torch.empty_like(dev["Q"])
+        ws = ops.workspace(ops.problem(dev["Q"], w.d_hidden, w.n_tokens, w.chunk_tokens, w.eta, ops._flags(True)), 1,
+                           dev["Q"].device)
+        ms = timed(lambda: ops.gcs_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                                       want_final=False, out=O, ws=ws), few, 1)
+        ach = fwd_flops(w.d_head, w.d_hidden, w.n_tokens, w.n_heads) / (ms * 1e-3) / 1e12
+        res["paper_state_gcs_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                           roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                                         unit="TFLOP/s", frac=ach / PEAK["bf16"]))
+        del dev, O, ws
+        torch.cuda.empty_cache()
     if "single_head" in forms:  # single-head chains: latency-bound
         for name, io in (("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16")):
             w = WORKLOADS[name]

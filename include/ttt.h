@@ -35,7 +35,7 @@
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
  *     chip by every entry point), and large states for the forward entry
  *     points ttt_chunk_fwd, ttt_batched_fwd, ttt_batched_fwd_ckpt,
- *     ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     ttt_gcs_fwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
  *     multiple of 128 up to 16384 (the paper's single head of 1024 with
  *     hidden 4096), where every product of a chunk step is a GEMM over
  *     weights streamed from HBM and a chunk's rows times max(d, h) elements
@@ -195,7 +195,10 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
  * shard partials share the workspace's max(H, 1024) partial slots: a stream
  * with more chunks x heads than that is summed in passes of as many chunks
  * as fit (each pass's sum added onto the running total in pass order), so
- * any chunk count runs in the workspace of ttt_workspace_bytes(p, 1). */
+ * any chunk count runs in the workspace of ttt_workspace_bytes(p, 1).  At
+ * large state sizes the chunks' steps -eta * grad L_c(W0) are subtracted
+ * from the FP32 weights one chunk after another (in chunk order), one head
+ * at a time, before the apply. */
 ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                          const float* W1_0, const float* W2_0, void* O, float* W1_T, float* W2_T,
                          float* loss, void* ws, size_t ws_bytes, void* hip_stream);

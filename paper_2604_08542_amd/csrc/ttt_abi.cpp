@@ -861,6 +861,62 @@ ttt_status_t run_forward_large(const ttt_problem_t* p, const Shape& S, int B, co
   return TTT_OK;
 }
 
+// GCS at large state sizes (Eq. 10), per head: every chunk's gradient at W0
+// (its own 1/M_c, its loss at W0) stepped into the FP32 masters in chunk
+// order while the operand copies keep W0, then the operand copies of W*, then
+// every chunk's apply.
+ttt_status_t run_gcs_forward_large(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K,
+                                   const void* V, const float* W1_0, const float* W2_0, void* O, float* W1_T,
+                                   float* W2_T, float* loss, void* ws, size_t ws_bytes, hipStream_t st) {
+  const LargeLayout L = large_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
+  float* W1 = at<float>(ws, L.W1);
+  float* W2 = at<float>(ws, L.W2);
+  for (int hd = 0; hd < S.H; ++hd) {
+    const int64_t w0 = (int64_t)hd * dh;
+    if (!launched([&] {
+          return launch_large_init(W1_0 + w0, W2_0 + w0, W1, W2, at<char>(ws, L.W1op), at<char>(ws, L.W2op), dh,
+                                   S.mma_bf16, st);
+        }))
+      return TTT_EHIP;
+    auto step = [&](int64_t c, bool grad) {
+      const int64_t t0 = c * M;
+      const int64_t off = (t0 * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob;
+      LargeStepArgs a{};
+      a.K = static_cast<const char*>(K) + off;
+      a.V = static_cast<const char*>(V) + off;
+      a.Q = static_cast<const char*>(Q) + off;
+      a.O = grad ? nullptr : static_cast<char*>(O) + off;
+      a.stride_tok = S.stride_tok;
+      a.flags = p->flags;
+      a.rows = (int32_t)std::min<int64_t>(M, N - t0); a.d = S.d; a.h = S.h;
+      a.grad = grad ? 1 : 0; a.masters_only = 1; a.eta = p->eta;
+      a.Kn = at<char>(ws, L.Kn); a.Qn = at<char>(ws, L.Qn); a.E = at<char>(ws, L.E);
+      a.A = at<char>(ws, L.A); a.D = at<char>(ws, L.D); a.Aq = at<char>(ws, L.Aq);
+      a.Vn = at<float>(ws, L.Vn); a.S1 = at<char>(ws, L.S1);
+      a.W1 = W1; a.W2 = W2; a.W1op = at<char>(ws, L.W1op); a.W2op = at<char>(ws, L.W2op);
+      a.loss_part = at<float>(ws, L.loss_part);
+      a.loss = grad && loss ? loss + (int64_t)hd * C + c : nullptr;
+      return launched([&] { return launch_large_step(a, S.io_bf16, S.mma_bf16, st); });
+    };
+    for (int64_t c = 0; c < C; ++c)
+      if (!step(c, true)) return TTT_EHIP;
+    if (!launched([&] { return launch_large_cast(W1, at<char>(ws, L.W1op), dh, S.mma_bf16, st); }) ||
+        !launched([&] { return launch_large_cast(W2, at<char>(ws, L.W2op), dh, S.mma_bf16, st); }))
+      return TTT_EHIP;
+    for (int64_t c = 0; c < C; ++c)
+      if (!step(c, false)) return TTT_EHIP;
+    if (W1_T && (hipMemcpyAsync(W1_T + w0, W1, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 hipMemcpyAsync(W2_T + w0, W2, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess))
+      return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
 ttt_status_t check_batch(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu, int32_t w0_per_seq,
                          const ttt_tile_cfg_t* tile_cfg) {
   if (n_seqs < 1 || !cu) return TTT_EINVAL;
@@ -1371,7 +1427,6 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!W1_0 || !W2_0) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !O)) return TTT_EINVAL;
     if ((W1_T == nullptr) != (W2_T == nullptr)) return TTT_EINVAL;
@@ -1389,6 +1444,9 @@ ttt_status_t ttt_gcs_fwd(const ttt_problem_t* p, const void* Q, const void* K, c
         return TTT_EHIP;
       return TTT_OK;
     }
+    if (S.large)
+      return run_gcs_forward_large(p, S, Q, K, V, W1_0, W2_0, O, W1_T, W2_T, loss, ws, ws_bytes,
+                                   static_cast<hipStream_t>(hip_stream));
     return run_gcs_forward(p, S, Q, K, V, W1_0, W2_0, O, W1_T, W2_T, loss, ws, ws_bytes,
                            static_cast<hipStream_t>(hip_stream), nullptr);
   } catch (...) {

@@ -30,6 +30,7 @@ struct LargeStepArgs {
   uint32_t flags;
   int32_t rows, d, h;
   int32_t grad;   // 1: gradient of the chunk and the update
+  int32_t masters_only;  // 1: the update leaves the operand copies (a sum of gradients at W0)
   float eta;
   void* Kn;       // [rows][d] operand type
   void* Qn;

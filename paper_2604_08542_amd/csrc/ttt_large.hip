@@ -286,10 +286,10 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpD<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, E, d, M, W2o, d, h, d,
                        e3);
     // W1 -= eta Kn^T D ; W2 -= eta A^T E (contractions over the chunk's tokens)
-    EpUpd<T> e4{{}, a.W1, W1o, h, a.eta};
+    EpUpd<T> e4{{}, a.W1, a.masters_only ? nullptr : W1o, h, a.eta};
     hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(h / BN, d / BMW), dim3(NTH), 0, st, Kn, d, M, Dd,
                        h, M, M, e4);
-    EpUpd<T> e5{{}, a.W2, W2o, d, a.eta};
+    EpUpd<T> e5{{}, a.W2, a.masters_only ? nullptr : W2o, d, a.eta};
     hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpUpd<T>>), dim3(d / BN, h / BMW), dim3(NTH), 0, st, Aa, h, M, E, d,
                        M, M, e5);
   }

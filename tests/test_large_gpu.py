@@ -103,11 +103,47 @@ def test_large_batched_and_strided(gpu):
         assert torch.equal(rb["O"], r["O"][s:e]) and torch.equal(rb["W1_T"], r["W1_T"][b])
 
 
+GCS_CASES = [
+    # N, H, d, h, M, eta, io, mma_bf16
+    (700, 2, 256, 512, 300, 4.0, "f32", False),   # ragged last chunk, two heads
+    (700, 2, 256, 512, 300, 4.0, "bf16", True),   # the step moves O well past the BF16 tolerance
+    (5496, 1, 1024, 4096, 2748, 2.0, "bf16", True),  # the paper's state
+]
+
+
+@pytest.mark.parametrize("N,H,d,h,M,eta,io,mma", GCS_CASES)
+def test_large_gcs_matches_oracle(gpu, N, H, d, h, M, eta, io, mma):
+    # Eq. 10 at large state sizes: every chunk's gradient at W0, one step, all
+    # queries mapped with W*
+    x, dv = dev_inputs(N, H, d, h, seed=N + d + 1, io=io)
+    r = ops().gcs_fwd(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], eta, M, emit_loss=True, mma_bf16=mma)
+    torch.cuda.synchronize()
+    ref = orc.ttt_forward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M)
+    ref0 = orc.ttt_forward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], 0.0, M)
+    tol = TOL["bf16" if mma or io == "bf16" else "f32"]
+    print(f"gcs N={N} H={H} d={d} h={h} M={M} eta={eta} io={io} mma_bf16={mma}")
+    O = host(r["O"])
+    check("O", O, ref["O"], tol)
+    check("dW1", host(r["W1_T"]) - x["W1"], ref["W1_T"] - x["W1"], tol, floor=storage_floor(ref["W1_T"], x["W1"]))
+    check("dW2", host(r["W2_T"]) - x["W2"], ref["W2_T"] - x["W2"], tol, floor=storage_floor(ref["W2_T"], x["W2"]))
+    check("loss", host(r["loss"]), ref["loss"], tol)
+    e_eta, e_0 = rel(O, ref["O"]), rel(O, ref0["O"])
+    print(f"  |O - O_ref(eta)| {e_eta:.2e} < |O - O_ref(0)| {e_0:.2e}")
+    assert e_eta < e_0
+
+
+def test_large_gcs_one_chunk_equals_chain(gpu):
+    x, dv = dev_inputs(300, 2, 256, 512, seed=73, io="bf16")
+    a = ops().gcs_fwd(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], 4.0, 300)
+    b = ops().chunk_fwd(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], 4.0, 300)
+    for k in ("O", "W1_T", "W2_T"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_large_shapes_rejected_where_not_built(gpu):
     from paper_2604_08542_amd import _lib
     x, dv = dev_inputs(64, 1, 256, 512, seed=72, io="f32")
-    for fn in (lambda: ops().gcs_fwd(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], 0.1, 32),
-               lambda: ops().chunk_fwd_noalloc(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], 0.1, 32)):
+    for fn in (lambda: ops().chunk_fwd_noalloc(dv["Q"], dv["K"], dv["V"], dv["W1"], dv["W2"], 0.1, 32),):
         with pytest.raises(_lib.TTTError) as e:
             fn()
         assert e.value.status == _lib.TTT_ENOTSUP
