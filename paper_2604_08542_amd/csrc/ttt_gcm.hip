@@ -26,7 +26,7 @@ struct EpProj : EpBase {
   T* v;
   const float* bias;  // nullable
   int D, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float x) {
+  __device__ __forceinline__ void operator()(int r, int c, float x, In) {
     if (r >= rows) return;
     const float y = bias ? x + bias[c] : x;
     // a 128-column tile never straddles two of the thirds (D % 128 == 0),
@@ -45,7 +45,7 @@ struct EpGate : EpBase {
   const float* bias;  // nullable
   const float* alpha;
   int D, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float g) {
+  __device__ __forceinline__ void operator()(int r, int c, float g, In) {
     if (r >= rows) return;
     const int64_t i = (int64_t)r * D + c;
     const float gg = bias ? g + bias[c] : g;

@@ -12,9 +12,15 @@
 namespace ttt {
 namespace large {
 
-// Epilogues derive from this: finish() runs once per work-group after its
+// Epilogues derive from this.  An epilogue that reads an input per element
+// (a factor, a residual target, the FP32 master) defines In and load(r, c);
+// the tile calls load for 16 elements before it calls operator() for any of
+// them, so those reads are in flight together instead of each waiting behind
+// the previous element's store.  finish() runs once per work-group after its
 // last element.
 struct EpBase {
+  struct In {};
+  __device__ __forceinline__ In load(int, int) const { return {}; }
   __device__ __forceinline__ void finish() {}
 };
 
@@ -162,7 +168,8 @@ constexpr int ksteps() {
 
 // C tile (this work-group's BM x 128) accumulated over the whole
 // contraction, then handed to the epilogue element by element:
-// ep(row, col, value); rows past the operand's end are the epilogue's to skip.
+// ep(row, col, value, ep.load(row, col)); rows past the operand's end are the
+// epilogue's to skip (in load as well).
 template <typename T, int LA, int LB, int BM, typename EP>
 __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows, int K,
                                           int m0, int n0, EP& ep) {
@@ -238,12 +245,14 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
 #pragma unroll
   for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
+    for (int bn = 0; bn < 2; ++bn) {
+      const int col = n0 + wn + 32 * bn + l32;
+      typename EP::In in[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm + 32 * bm + c32_row(r, hf), col = n0 + wn + 32 * bn + l32;
-        ep(row, col, acc[bm][bn][r]);
-      }
+      for (int r = 0; r < 16; ++r) in[r] = ep.load(m0 + wm + 32 * bm + c32_row(r, hf), col);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ep(m0 + wm + 32 * bm + c32_row(r, hf), col, acc[bm][bn][r], in[r]);
+    }
   ep.finish();
 }
 

@@ -53,7 +53,7 @@ struct EpAct : EpBase {
   T* a;
   T* s1;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float z) {
+  __device__ __forceinline__ void operator()(int r, int c, float z, In) {
     if (r >= rows) return;
     float sg;
     const float av = silu_sig(z, sg);
@@ -70,9 +70,11 @@ struct EpRes {
   int ld, rows;
   float scale;
   float acc = 0.f;
-  __device__ __forceinline__ void operator()(int r, int c, float y) {
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const { return r < rows ? v[(int64_t)r * ld + c] : 0.f; }
+  __device__ __forceinline__ void operator()(int r, int c, float y, float vv) {
     if (r >= rows) return;
-    const float R = y - v[(int64_t)r * ld + c];
+    const float R = y - vv;
     acc = fmaf(R, R, acc);
     put(e + (int64_t)r * ld + c, scale * R);
   }
@@ -92,9 +94,11 @@ struct EpD : EpBase {
   T* d;
   const T* s1;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float p) {
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? s1[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float p, T sv) {
     if (r >= rows) return;
-    put(d + (int64_t)r * ld + c, p * (float)s1[(int64_t)r * ld + c]);
+    put(d + (int64_t)r * ld + c, p * (float)sv);
   }
 };
 // W -= eta * G (FP32 master), then the operand copy of the new W (nullable:
@@ -105,9 +109,11 @@ struct EpUpd : EpBase {
   T* wop;
   int ld;
   float eta;
-  __device__ __forceinline__ void operator()(int r, int c, float g) {
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const { return w[(int64_t)r * ld + c]; }
+  __device__ __forceinline__ void operator()(int r, int c, float g, float wv) {
     const int64_t i = (int64_t)r * ld + c;
-    const float wn = w[i] - eta * g;
+    const float wn = wv - eta * g;
     w[i] = wn;
     if (wop) put(wop + i, wn);
   }
@@ -118,7 +124,7 @@ struct EpOut : EpBase {
   IOT* o;  // first token of the chunk, head offset applied
   int64_t stride_tok;
   int rows;
-  __device__ __forceinline__ void operator()(int r, int c, float y) {
+  __device__ __forceinline__ void operator()(int r, int c, float y, In) {
     if (r >= rows) return;
     o[(int64_t)r * stride_tok + c] = (IOT)y;
   }
@@ -129,7 +135,7 @@ template <typename T>
 struct EpStore : EpBase {
   T* z;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float v) {
+  __device__ __forceinline__ void operator()(int r, int c, float v, In) {
     if (r >= rows) return;
     put(z + (int64_t)r * ld + c, v);
   }
@@ -144,12 +150,14 @@ struct EpSwi : EpBase {
   T* g1;
   T* g3;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float z1) {
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float z1, T z3r) {
     if (r >= rows) return;
     const int64_t i = (int64_t)r * ld + c;
     float sg;
     const float sv = silu_sig(z1, sg);
-    const float z3v = (float)z3[i];
+    const float z3v = (float)z3r;
     put(hd + i, sv * z3v);
     if constexpr (GRAD) {
       put(g1 + i, z3v * fmaf(sv, 1.0f - sg, sg));
@@ -165,11 +173,19 @@ struct EpD2 : EpBase {
   T* d1;
   T* d3;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float dh) {
+  struct In {
+    T a, b;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {g1[i], g3[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float dh, In g) {
     if (r >= rows) return;
     const int64_t i = (int64_t)r * ld + c;
-    put(d1 + i, dh * (float)g1[i]);
-    put(d3 + i, dh * (float)g3[i]);
+    put(d1 + i, dh * (float)g.a);
+    put(d3 + i, dh * (float)g.b);
   }
 };
 
