@@ -309,9 +309,10 @@ ttt_status_t plan_persist(const Shape& S, const std::vector<int64_t>& nb, int64_
     const int64_t g_fill = std::max<int64_t>(1, T / n_chains);
     G = 1;
     while (G < std::max(g_lpt, g_fill)) G *= 2;
-    G = std::min(G, tiles_max);
   }
-  G = std::max<int64_t>(1, std::min<int64_t>(G, resident));
+  // members past a chunk's tile count would have no tokens; the stepwise
+  // schedule clamps its shards the same way, so both give the same partition
+  G = std::max<int64_t>(1, std::min<int64_t>({G, tiles_max, resident}));
   int64_t n_groups = std::max<int64_t>(1, std::min<int64_t>(n_chains, T / G));
   if (n_groups >= 8) n_groups -= n_groups % 8;
   n_groups = std::min<int64_t>({n_groups, (int64_t)MAX_GROUPS, slot_cap / G});

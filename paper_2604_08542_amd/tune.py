@@ -41,7 +41,8 @@ def lookup(h: int, io: str, chunk_tokens: int, n_chains: int, kind: str = "fwd",
 
 CANDIDATES = [dict(schedule="stepwise", target_wgs=t) for t in (128, 256, 384, 512, 768, 1024)] + \
              [dict(schedule="stepwise", wg_per_chain=g) for g in (1, 2, 4, 8, 16, 32)] + \
-             [dict(schedule="persistent")] + [dict(schedule="persistent", wg_per_chain=g) for g in (4, 8, 16, 32)]
+             [dict(schedule="persistent")] + \
+             [dict(schedule="persistent", wg_per_chain=g) for g in (4, 8, 12, 16, 20, 24, 32)]
 BWD_CANDIDATES = [dict(target_wgs=t) for t in (128, 256, 512, 1024)] + \
                  [dict(wg_per_chain=g) for g in (2, 4, 8, 16, 32)]
 HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "ttt_tuned.h")

@@ -18,7 +18,8 @@ def ops():
     return ops
 
 
-@pytest.mark.parametrize("io,h,G", [("f32", 256, 4), ("bf16", 256, 8), ("f32", 128, 3), ("bf16", 128, 16)])
+@pytest.mark.parametrize("io,h,G", [("f32", 256, 4), ("bf16", 256, 8), ("f32", 128, 3), ("bf16", 128, 16),
+                                    ("bf16", 128, 24), ("bf16", 256, 12)])
 def test_persistent_equals_stepwise(gpu, io, h, G):
     """Same shards, same fixed-order reductions: both schedules give the same
     bits; the batch mixes a long, a ragged and a one-token sequence."""
