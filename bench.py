@@ -158,6 +158,26 @@ def other_forms(forms, steps, warmup):
                                                          unit="TFLOP/s", frac=ach / PEAK["bf16"]))
         del dev, O, ws
         torch.cuda.empty_cache()
+        # forward with checkpoints + reverse mode at the paper's state, BF16
+        dev = make_inputs_torch(w.n_tokens, w.n_heads, w.d_head, w.d_hidden, seed=0, io_dtype="bf16", with_dO=True)
+        ws = ops.workspace(ops.problem(dev["Q"], w.d_hidden, w.n_tokens, w.chunk_tokens, w.eta, ops._flags(True)), 1,
+                           dev["Q"].device)
+
+        def fb():
+            f = ops.chunk_fwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens,
+                              save_ckpt=True, want_final=False, ws=ws)
+            ops.chunk_bwd(dev["Q"], dev["K"], dev["V"], dev["W1"], dev["W2"], w.eta, w.chunk_tokens, f["ckpt"],
+                          dev["dO"], ws=ws)
+        ms = timed(fb, 2, 1)
+        # forward 14 d h per token-head; reverse step 36 d h (3 recomputed products, 5 of the apply
+        # adjoint, 10 of the update adjoint)
+        ach = 50.0 * w.d_head * w.d_hidden * w.n_tokens * w.n_heads / (ms * 1e-3) / 1e12
+        res["paper_state_fwd_bwd_bf16"] = dict(workload=w.name, ms_per_step=ms, tokens_per_s=w.n_tokens / (ms * 1e-3),
+                                               pass_roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                                                  unit="TFLOP/s (50 d h per token-head, whole pass)",
+                                                                  frac=ach / PEAK["bf16"]))
+        del dev, ws
+        torch.cuda.empty_cache()
     if "single_head" in forms:  # single-head chains: latency-bound
         for name, io in (("single_head_4x1374", "f32"), ("single_head_256x1374_bf16", "bf16")):
             w = WORKLOADS[name]

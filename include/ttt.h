@@ -33,9 +33,9 @@
  *     exception crosses this boundary.  Calls from different host threads
  *     are safe; calls that share a workspace must be stream-ordered.
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
- *     chip by every entry point), and large states for the forward entry
- *     points ttt_chunk_fwd, ttt_batched_fwd, ttt_batched_fwd_ckpt,
- *     ttt_gcs_fwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     chip by every entry point), and large states for ttt_chunk_fwd,
+ *     ttt_chunk_bwd, ttt_batched_fwd, ttt_batched_fwd_ckpt, ttt_gcs_fwd,
+ *     ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
  *     multiple of 128 up to 16384 (the paper's single head of 1024 with
  *     hidden 4096), where every product of a chunk step is a GEMM over
  *     weights streamed from HBM and a chunk's rows times max(d, h) elements
@@ -138,7 +138,10 @@ ttt_status_t ttt_chunk_fwd(const ttt_problem_t* p, const void* Q, const void* K,
  *   dO            [N][H][d] io_dtype.
  *   dQ, dK, dV    [N][H][d] io_dtype, gradients w.r.t. the *raw* Q, K, V.
  *   dW1_0, dW2_0  gradients w.r.t. the initial fast weights, f32.
- *   deta          [H] f32, per-head contribution to d/d eta (sum = total). */
+ *   deta          [H] f32, per-head contribution to d/d eta (sum = total).
+ * At large state sizes every product of the reverse step is a GEMM over
+ * weights streamed from HBM, one head and one chunk at a time (the weights
+ * after the last chunk are recomputed from its checkpoint first). */
 ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K, const void* V,
                            const float* W1_0, const float* W2_0, const float* ckpt, const void* dO,
                            void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta,

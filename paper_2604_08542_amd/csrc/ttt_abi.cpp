@@ -113,6 +113,51 @@ LargeLayout large_layout(const Shape& s) {
   return L;
 }
 
+// Workspace of the reverse mode at large state sizes: the forward's layout
+// (its step recomputes the weights after the last chunk) followed by the
+// reverse step's buffers.
+struct LargeBwdLayout {
+  LargeLayout f;
+  size_t dOn, dY, dq, dk, dv, dE, S2, P, Sq1, dZq, dP, dZa, EWh, dZ, W1nop, W2nop, Wh1, Wh2, Wh1op, Wh2op, deta_part,
+      deta, total;
+};
+LargeBwdLayout large_bwd_layout(const Shape& s) {
+  LargeBwdLayout L{};
+  L.f = large_layout(s);
+  const size_t op = s.mma_bf16 ? 2 : 4;
+  const size_t M = (size_t)s.Mrows, d = (size_t)s.d, h = (size_t)s.h;
+  size_t off = L.f.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.dOn = take(M * d * op);
+  L.dY = take(M * d * op);
+  L.dq = take(M * d * 4);
+  L.dk = take(M * d * 4);
+  L.dv = take(M * d * 4);
+  L.dE = take(M * d * 4);
+  L.S2 = take(M * h * op);
+  L.P = take(M * h * op);
+  L.Sq1 = take(M * h * op);
+  L.dZq = take(M * h * op);
+  L.dP = take(M * h * op);
+  L.dZa = take(M * h * op);
+  L.EWh = take(M * h * op);
+  L.dZ = take(M * h * op);
+  L.W1nop = take(d * h * op);
+  L.W2nop = take(d * h * op);
+  L.Wh1 = take(d * h * 4);
+  L.Wh2 = take(d * h * 4);
+  L.Wh1op = take(d * h * op);
+  L.Wh2op = take(d * h * op);
+  L.deta_part = take((d / 128 + h / 128) * ((M + 127) / 128) * 4);
+  L.deta = take(4);
+  L.total = off;
+  return L;
+}
+
 // Workspace of the memory unit's large-state chunk step: the chunk's
 // normalised rows, E, the [rows][h] intermediates, three FP32 masters and
 // their operand copies.
@@ -918,6 +963,98 @@ ttt_status_t run_gcs_forward_large(const ttt_problem_t* p, const Shape& S, const
   return TTT_OK;
 }
 
+// Reverse mode at large state sizes, per head: the weights after the last
+// chunk recomputed from its checkpoint with one forward step, then for
+// c = C-1 .. 0 the reverse step of chunk c with W_c (checkpoint c) and W_{c+1}
+// (checkpoint c+1, or the recomputed weights), carrying the adjoint of the
+// weights from chunk to chunk; at the end it is the adjoint of W_0.
+ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, const float* ckpt, const void* Q,
+                                const void* K, const void* V, const void* dO, void* dQ, void* dK, void* dV,
+                                float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes, hipStream_t st) {
+  const LargeBwdLayout L = large_bwd_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.f.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
+  float* Wh1 = at<float>(ws, L.Wh1);
+  float* Wh2 = at<float>(ws, L.Wh2);
+  float* dt = at<float>(ws, L.deta);
+  auto cast = [&](const float* src, size_t off) {
+    return launched([&] { return launch_large_cast(src, at<char>(ws, off), dh, S.mma_bf16, st); });
+  };
+  auto zero = [&](float* q, int64_t n) { return launched([&] { return launch_large_zero(q, n, st); }); };
+  for (int hd = 0; hd < S.H; ++hd) {
+    if (!zero(Wh1, dh) || !zero(Wh2, dh) || !zero(dt, 1) || !cast(Wh1, L.Wh1op) || !cast(Wh2, L.Wh2op))
+      return TTT_EHIP;
+    auto row = [&](int64_t c) { return ckpt + (c * S.H + hd) * 2 * dh; };
+    auto chunk_off = [&](int64_t c) { return (c * M * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob; };
+    if (C > 0) {
+      // W_C: one forward step of the last chunk from its checkpoint
+      const int64_t c = C - 1;
+      float* W1 = at<float>(ws, L.f.W1);
+      float* W2 = at<float>(ws, L.f.W2);
+      if (!launched([&] {
+            return launch_large_init(row(c), row(c) + dh, W1, W2, at<char>(ws, L.f.W1op), at<char>(ws, L.f.W2op), dh,
+                                     S.mma_bf16, st);
+          }))
+        return TTT_EHIP;
+      LargeStepArgs a{};
+      a.K = static_cast<const char*>(K) + chunk_off(c);
+      a.V = static_cast<const char*>(V) + chunk_off(c);
+      a.Q = static_cast<const char*>(Q) + chunk_off(c);
+      a.O = nullptr;
+      a.stride_tok = S.stride_tok;
+      a.flags = p->flags;
+      a.rows = (int32_t)(N - c * M); a.d = S.d; a.h = S.h;
+      a.grad = 1; a.eta = p->eta;
+      a.Kn = at<char>(ws, L.f.Kn); a.Qn = at<char>(ws, L.f.Qn); a.E = at<char>(ws, L.f.E);
+      a.A = at<char>(ws, L.f.A); a.D = at<char>(ws, L.f.D); a.Aq = at<char>(ws, L.f.Aq);
+      a.Vn = at<float>(ws, L.f.Vn); a.S1 = at<char>(ws, L.f.S1);
+      a.W1 = W1; a.W2 = W2; a.W1op = at<char>(ws, L.f.W1op); a.W2op = at<char>(ws, L.f.W2op);
+      a.loss_part = at<float>(ws, L.f.loss_part);
+      if (!launched([&] { return launch_large_step(a, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+      if (!cast(W1, L.W1nop) || !cast(W2, L.W2nop)) return TTT_EHIP;
+    }
+    for (int64_t c = C - 1; c >= 0; --c) {
+      if (c + 1 < C && (!cast(row(c + 1), L.W1nop) || !cast(row(c + 1) + dh, L.W2nop))) return TTT_EHIP;
+      if (!cast(row(c), L.f.W1op) || !cast(row(c) + dh, L.f.W2op)) return TTT_EHIP;
+      const int64_t off = chunk_off(c);
+      LargeBwdArgs b{};
+      b.K = static_cast<const char*>(K) + off;
+      b.V = static_cast<const char*>(V) + off;
+      b.Q = static_cast<const char*>(Q) + off;
+      b.dO = static_cast<const char*>(dO) + off;
+      b.dQ = static_cast<char*>(dQ) + off;
+      b.dK = static_cast<char*>(dK) + off;
+      b.dV = static_cast<char*>(dV) + off;
+      b.stride_tok = S.stride_tok;
+      b.flags = p->flags;
+      b.rows = (int32_t)std::min<int64_t>(M, N - c * M); b.d = S.d; b.h = S.h;
+      b.eta = p->eta;
+      b.Kn = at<char>(ws, L.f.Kn); b.Qn = at<char>(ws, L.f.Qn); b.E = at<char>(ws, L.f.E);
+      b.dOn = at<char>(ws, L.dOn); b.dY = at<char>(ws, L.dY);
+      b.Vn = at<float>(ws, L.f.Vn); b.dq = at<float>(ws, L.dq); b.dk = at<float>(ws, L.dk);
+      b.dv = at<float>(ws, L.dv); b.dE = at<float>(ws, L.dE);
+      b.A = at<char>(ws, L.f.A); b.S1 = at<char>(ws, L.f.S1); b.S2 = at<char>(ws, L.S2); b.P = at<char>(ws, L.P);
+      b.D = at<char>(ws, L.f.D); b.Aq = at<char>(ws, L.f.Aq); b.Sq1 = at<char>(ws, L.Sq1);
+      b.dZq = at<char>(ws, L.dZq); b.dP = at<char>(ws, L.dP); b.dZa = at<char>(ws, L.dZa);
+      b.EWh = at<char>(ws, L.EWh); b.dZ = at<char>(ws, L.dZ);
+      b.W1op = at<char>(ws, L.f.W1op); b.W2op = at<char>(ws, L.f.W2op);
+      b.W1nop = at<char>(ws, L.W1nop); b.W2nop = at<char>(ws, L.W2nop);
+      b.Wh1 = Wh1; b.Wh2 = Wh2; b.Wh1op = at<char>(ws, L.Wh1op); b.Wh2op = at<char>(ws, L.Wh2op);
+      b.deta_part = at<float>(ws, L.deta_part);
+      b.deta = dt;
+      if (!launched([&] { return launch_large_bwd_step(b, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+    }
+    if (hipMemcpyAsync(dW1_0 + hd * dh, Wh1, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dW2_0 + hd * dh, Wh2, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(deta + hd, dt, sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
 ttt_status_t check_batch(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu, int32_t w0_per_seq,
                          const ttt_tile_cfg_t* tile_cfg) {
   if (n_seqs < 1 || !cu) return TTT_EINVAL;
@@ -1334,7 +1471,7 @@ extern "C" {
 size_t ttt_workspace_bytes(const ttt_problem_t* p, int32_t n_seqs) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK || n_seqs < 1) return 0;
-  if (S.large) return large_layout(S).total;
+  if (S.large) return large_bwd_layout(S).total;  // the reverse mode's layout contains the forward's
   return ws_layout(S, (int64_t)n_seqs * S.H).total;
 }
 
@@ -1406,13 +1543,15 @@ ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K,
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !ckpt || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
     (void)W1_0; (void)W2_0;  // the checkpoint of chunk 0 holds W_0
     for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
                           (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
+    if (S.large)
+      return run_backward_large(p, S, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+                                static_cast<hipStream_t>(hip_stream));
     const int64_t cu[2] = {0, p->n_tokens};
     return run_backward(p, S, 1, cu, 0, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, nullptr, ws, ws_bytes,
                         static_cast<hipStream_t>(hip_stream));

@@ -12,6 +12,16 @@
 namespace ttt {
 namespace large {
 
+__device__ __forceinline__ float silu_sig(float z, float& sg) {
+  sg = sigmoid(z);
+  return z * sg;
+}
+
+template <typename T>
+__device__ __forceinline__ void put(T* p, float v) {
+  *p = (T)v;
+}
+
 // Epilogues derive from this.  An epilogue that reads an input per element
 // (a factor, a residual target, the FP32 master) defines In and load(r, c);
 // the tile calls load for 16 elements before it calls operator() for any of

@@ -21,6 +21,8 @@ struct LargeNormArgs {
   float* Vn;
   void* Qn;
 };
+// Row normalisation of a large-state chunk (K, V, Q; the flags select which).
+hipError_t launch_large_norm(const LargeNormArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
 struct LargeStepArgs {
   const void* K;  // first token of the chunk, head offset applied
   const void* V;
@@ -48,6 +50,57 @@ struct LargeStepArgs {
   float* loss;       // nullable: the chunk's loss
 };
 hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// Reverse step of one chunk of the MSE unit at large state sizes (the apply
+// adjoint at W_{c+1}, then the update adjoint at W_c along the carried
+// adjoint Wh, which it replaces by the adjoint of W_c).
+struct LargeBwdArgs {
+  const void* K;  // first token of the chunk, head offset applied (io type)
+  const void* V;
+  const void* Q;
+  const void* dO;
+  void* dQ;       // written: gradients w.r.t. the raw rows (io type)
+  void* dK;
+  void* dV;
+  int64_t stride_tok;
+  uint32_t flags;
+  int32_t rows, d, h;
+  float eta;
+  void* Kn;       // [rows][d] operand type
+  void* Qn;
+  void* E;
+  void* dOn;
+  void* dY;
+  float* Vn;      // [rows][d] FP32
+  float* dq;
+  float* dk;
+  float* dv;
+  float* dE;
+  void* A;        // [rows][h] operand type
+  void* S1;
+  void* S2;
+  void* P;
+  void* D;
+  void* Aq;
+  void* Sq1;
+  void* dZq;
+  void* dP;
+  void* dZa;
+  void* EWh;
+  void* dZ;
+  const void* W1op;   // W_c
+  const void* W2op;
+  const void* W1nop;  // W_{c+1}
+  const void* W2nop;
+  float* Wh1;         // carried adjoint: FP32 masters and operand copies
+  float* Wh2;
+  void* Wh1op;
+  void* Wh2op;
+  float* deta_part;   // per-tile partials of the step-size derivative
+  float* deta;        // this head's running d/d eta (one float)
+};
+hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// Fill n floats with zero.
+hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st);
 // Chunk step of the paper's memory unit (SwiGLU network, dot-product loss
 // with token-wise step sizes) at large state sizes.
 struct LargeAmuArgs {

@@ -36,16 +36,6 @@
 namespace ttt {
 namespace large {
 
-__device__ __forceinline__ float silu_sig(float z, float& sg) {
-  sg = sigmoid(z);
-  return z * sg;
-}
-
-template <typename T>
-__device__ __forceinline__ void put(T* p, float v) {
-  *p = (T)v;
-}
-
 // ------------------------------------------------------------- epilogues
 // A = SiLU(Z), S1 = SiLU'(Z) (for the gradient) or only A (for the apply).
 template <typename T, bool GRAD>
@@ -394,6 +384,20 @@ hipError_t launch_large_step(const LargeStepArgs& a, bool io_bf16, bool mma_bf16
   using namespace large;
   if (mma_bf16) return io_bf16 ? step_t<bf16, bf16>(a, st) : step_t<bf16, float>(a, st);
   return step_t<float, float>(a, st);
+}
+
+hipError_t launch_large_norm(const LargeNormArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  using namespace large;
+  const dim3 grid((a.rows + 3) / 4);
+  if (mma_bf16) {
+    if (io_bf16)
+      hipLaunchKernelGGL((k_norm<bf16, bf16>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_norm<float, bf16>), grid, dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_norm<float, float>), grid, dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_large_amu_step(const LargeAmuArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st) {

@@ -1,0 +1,445 @@
+// Reverse mode of the chunk step at large state sizes (the MSE unit of
+// Sec. 4.2 Eq. 8 with the apply of Eq. 4, differentiated for an outer loss
+// <O, dO>; second-order terms through every inner gradient included).  As in
+// the forward at these sizes, every product is a matrix-core GEMM over
+// operands streamed from HBM with the elementwise work in its epilogue.
+//
+// One chunk, walking the chain backwards, with W = W_c, W' = W_{c+1} and the
+// carried adjoint Wh of W' (Wh is the adjoint of W_c afterwards):
+//   recompute   Z = K W1 -> A, s'(Z), s''(Z);  E = (2/M)(A W2 - V);
+//               P = E W2^T -> D = P s'(Z)
+//   apply       Zq = Q W1' -> Aq, s'(Zq);  Wh2 += Aq^T dO;
+//               dZq = (dO W2'^T) s'(Zq);  Wh1 += Q^T dZq;  dq = dZq W1'^T
+//   update      u1 = K Wh1 -> dD = -eta u1, deta -= <u1, D>,
+//                             dP = dD s'(Z), dZa = dD P s''(Z)
+//               u2 = A Wh2 -> dE = -eta u2, deta -= <u2, E>
+//               dY = (2/M)(dE + dP W2), dv = -dY
+//               dZ = dZa + (-eta E Wh2^T + dY W2^T) s'(Z)
+//               dk = -eta D Wh1^T + dZ W1^T
+//               Wh2 += dP^T E + A^T dY;  Wh1 += K^T dZ
+//   rows        dQ, dK, dV = the L2-normalisation adjoints of dq, dk, dv
+// Every output element is owned by one work-group summing its whole
+// contraction in a fixed order; the step-size derivative is summed from
+// per-tile partials in tile order.  The result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "ttt_common.h"
+#include "ttt_gemm.h"
+#include "ttt_internal.h"
+
+namespace ttt {
+namespace large {
+namespace bwd {
+
+// Sum of one value per lane over the work-group, written by thread 0 to
+// part[tile] (4 waves).
+__device__ __forceinline__ void tile_sum(float v, float* part) {
+  __shared__ float red[NTH / 64];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// A = s(Z), S1 = s'(Z), S2 = s''(Z) for s = SiLU.
+template <typename T>
+struct EpAct3 : EpBase {
+  T* a;
+  T* s1;
+  T* s2;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float z, In) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    float sg;
+    const float av = silu_sig(z, sg);
+    put(a + i, av);
+    put(s1 + i, fmaf(av, 1.0f - sg, sg));
+    put(s2 + i, sg * (1.0f - sg) * fmaf(z, 1.0f - 2.0f * sg, 2.0f));
+  }
+};
+// Aq = s(Zq), Sq1 = s'(Zq).
+template <typename T>
+struct EpAct2 : EpBase {
+  T* a;
+  T* s1;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float z, In) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    float sg;
+    const float av = silu_sig(z, sg);
+    put(a + i, av);
+    put(s1 + i, fmaf(av, 1.0f - sg, sg));
+  }
+};
+// E = scale (Y - V).
+template <typename T>
+struct EpE : EpBase {
+  T* e;
+  const float* v;
+  int ld, rows;
+  float scale;
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const { return r < rows ? v[(int64_t)r * ld + c] : 0.f; }
+  __device__ __forceinline__ void operator()(int r, int c, float y, float vv) {
+    if (r >= rows) return;
+    put(e + (int64_t)r * ld + c, scale * (y - vv));
+  }
+};
+// P stored, D = P S1.
+template <typename T>
+struct EpPD : EpBase {
+  T* p;
+  T* d;
+  const T* s1;
+  int ld, rows;
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? s1[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float pv, T sv) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    put(p + i, pv);
+    put(d + i, pv * (float)sv);
+  }
+};
+// out = value * fac.
+template <typename T>
+struct EpMul : EpBase {
+  T* out;
+  const T* fac;
+  int ld, rows;
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? fac[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float v, T f) {
+    if (r >= rows) return;
+    put(out + (int64_t)r * ld + c, v * (float)f);
+  }
+};
+// FP32 token-side result: out = scale * value (+ out when ADD).
+template <bool ADD>
+struct EpF32 : EpBase {
+  float* out;
+  int ld, rows;
+  float scale;
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const {
+    return (ADD && r < rows) ? out[(int64_t)r * ld + c] : 0.f;
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float v, float o) {
+    if (r >= rows) return;
+    out[(int64_t)r * ld + c] = ADD ? o + scale * v : scale * v;
+  }
+};
+// A product stored in the operand type.
+template <typename T>
+struct EpPut : EpBase {
+  T* out;
+  int ld, rows;
+  __device__ __forceinline__ void operator()(int r, int c, float v, In) {
+    if (r >= rows) return;
+    put(out + (int64_t)r * ld + c, v);
+  }
+};
+// Carried adjoint: Wh += G (FP32 master), then its operand copy (nullable:
+// the master only, while further terms are still to be added).
+template <typename T>
+struct EpAcc : EpBase {
+  float* w;
+  T* wop;
+  int ld;
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const { return w[(int64_t)r * ld + c]; }
+  __device__ __forceinline__ void operator()(int r, int c, float g, float wv) {
+    const int64_t i = (int64_t)r * ld + c;
+    const float wn = wv + g;
+    w[i] = wn;
+    if (wop) put(wop + i, wn);
+  }
+};
+// u1 = K Wh1: dD = -eta u1, dP = dD S1, dZa = dD P S2; -<u1, D> into the
+// step-size partials.
+template <typename T>
+struct EpU1 {
+  T* dp;
+  T* dza;
+  const T* d;
+  const T* s1;
+  const T* p;
+  const T* s2;
+  float* part;
+  int ld, rows;
+  float eta;
+  float acc = 0.f;
+  struct In {
+    T d, s1, p, s2;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {d[i], s1[i], p[i], s2[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float u, In x) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    acc = fmaf(-u, (float)x.d, acc);
+    const float dd = -eta * u;
+    put(dp + i, dd * (float)x.s1);
+    put(dza + i, dd * (float)x.p * (float)x.s2);
+  }
+  __device__ __forceinline__ void finish() { tile_sum(acc, part); }
+};
+// u2 = A Wh2: dE = -eta u2 (FP32); -<u2, E> into the step-size partials.
+template <typename T>
+struct EpU2 {
+  float* de;
+  const T* e;
+  float* part;
+  int ld, rows;
+  float eta;
+  float acc = 0.f;
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? e[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float u, T ev) {
+    if (r >= rows) return;
+    acc = fmaf(-u, (float)ev, acc);
+    de[(int64_t)r * ld + c] = -eta * u;
+  }
+  __device__ __forceinline__ void finish() { tile_sum(acc, part); }
+};
+// dP W2: dY = scale (dE + dP W2) (operand type), dv = -dY (FP32).
+template <typename T>
+struct EpDY : EpBase {
+  T* dy;
+  float* dv;
+  const float* de;
+  int ld, rows;
+  float scale;
+  typedef float In;
+  __device__ __forceinline__ float load(int r, int c) const { return r < rows ? de[(int64_t)r * ld + c] : 0.f; }
+  __device__ __forceinline__ void operator()(int r, int c, float v, float dev) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    const float y = scale * (dev + v);
+    put(dy + i, y);
+    dv[i] = -y;
+  }
+};
+// dY W2^T: dA = -eta EWh + dY W2^T, dZ = dZa + dA S1.
+template <typename T>
+struct EpDZ : EpBase {
+  T* dz;
+  const T* ewh;
+  const T* dza;
+  const T* s1;
+  int ld, rows;
+  float eta;
+  struct In {
+    T ewh, dza, s1;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {ewh[i], dza[i], s1[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float v, In x) {
+    if (r >= rows) return;
+    const float da = fmaf(-eta, (float)x.ewh, v);
+    put(dz + (int64_t)r * ld + c, fmaf(da, (float)x.s1, (float)x.dza));
+  }
+};
+
+// dO rows of the chunk in the operand type ([rows][d]; one wave per row).
+template <typename IOT, typename T>
+__global__ __launch_bounds__(256) void k_rows(const IOT* src, int64_t stride_tok, T* dst, int rows, int d) {
+  typedef IOT iov4 __attribute__((ext_vector_type(4)));
+  typedef T opv4 __attribute__((ext_vector_type(4)));
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (row >= rows) return;
+  for (int c = 4 * l; c < d; c += 256) {
+    const iov4 v = *reinterpret_cast<const iov4*>(src + (int64_t)row * stride_tok + c);
+    *reinterpret_cast<opv4*>(dst + (int64_t)row * d + c) = (opv4){(T)(float)v[0], (T)(float)v[1], (T)(float)v[2],
+                                                                  (T)(float)v[3]};
+  }
+}
+
+// Adjoint of the row normalisation x / max(||x||, eps) for the chunk's Q, K, V
+// rows: (g - xhat <xhat, g>) / ||x|| where ||x|| > eps, g / eps where the
+// floor is active, g itself for a tensor that is not normalised.  One wave per
+// token, 4 consecutive elements per lane, at most 16 passes of 256.
+template <typename IOT>
+__global__ __launch_bounds__(256) void k_norm_bwd(LargeBwdArgs p) {
+  typedef IOT iov4 __attribute__((ext_vector_type(4)));
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (row >= p.rows) return;
+  const int passes = p.d / 256;
+  for (int which = 0; which < 3; ++which) {
+    const IOT* src = static_cast<const IOT*>(which == 0 ? p.K : which == 1 ? p.V : p.Q) +
+                     (int64_t)row * p.stride_tok;
+    IOT* dst = static_cast<IOT*>(which == 0 ? p.dK : which == 1 ? p.dV : p.dQ) + (int64_t)row * p.stride_tok;
+    const float* g = (which == 0 ? p.dk : which == 1 ? p.dv : p.dq) + (int64_t)row * p.d;
+    const bool nrm = (p.flags >> (which == 0 ? 1 : which == 1 ? 2 : 0)) & 1u;
+    f32x4 x[16], gv[16];
+    float ss = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < passes) {
+        const iov4 v = *reinterpret_cast<const iov4*>(src + 256 * i + 4 * l);
+        x[i] = (f32x4){(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+        gv[i] = *reinterpret_cast<const f32x4*>(g + 256 * i + 4 * l);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ss = fmaf(x[i][e], x[i][e], ss);
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
+    const float n = sqrtf(ss);
+    const bool above = n > NORM_EPS;
+    const float inv = 1.0f / fmaxf(n, NORM_EPS);
+    float proj = 0.f;
+    if (nrm && above) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < passes)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) proj = fmaf(x[i][e] * inv, gv[i][e], proj);
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) proj += __shfl_xor(proj, m, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < passes) {
+        f32x4 y = gv[i];
+        if (nrm) {
+          if (above) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) y[e] = (gv[i][e] - x[i][e] * inv * proj) * inv;
+          } else {
+            y = gv[i] * (1.0f / NORM_EPS);
+          }
+        }
+        *reinterpret_cast<iov4*>(dst + 256 * i + 4 * l) = (iov4){(IOT)y[0], (IOT)y[1], (IOT)y[2], (IOT)y[3]};
+      }
+    }
+  }
+}
+
+// *deta += (the n step-size partials, in tile order)
+__global__ void k_deta(const float* part, int n, float* deta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *deta += s;
+  }
+}
+
+__global__ void k_zero(float* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+template <typename T, typename IOT>
+hipError_t step_t(const LargeBwdArgs& a, hipStream_t st) {
+  const int M = a.rows, d = a.d, h = a.h;
+  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;
+  const int mt = (M + BMT - 1) / BMT;
+  const float eta = a.eta, scale = 2.0f / (float)M;
+  T* Kn = static_cast<T*>(a.Kn);
+  T* Qn = static_cast<T*>(a.Qn);
+  T* E = static_cast<T*>(a.E);
+  T* dOn = static_cast<T*>(a.dOn);
+  T* dY = static_cast<T*>(a.dY);
+  T* A = static_cast<T*>(a.A);
+  T* S1 = static_cast<T*>(a.S1);
+  T* S2 = static_cast<T*>(a.S2);
+  T* P = static_cast<T*>(a.P);
+  T* D = static_cast<T*>(a.D);
+  T* Aq = static_cast<T*>(a.Aq);
+  T* Sq1 = static_cast<T*>(a.Sq1);
+  T* dZq = static_cast<T*>(a.dZq);
+  T* dP = static_cast<T*>(a.dP);
+  T* dZa = static_cast<T*>(a.dZa);
+  T* EWh = static_cast<T*>(a.EWh);
+  T* dZ = static_cast<T*>(a.dZ);
+  const T* W1 = static_cast<const T*>(a.W1op);
+  const T* W2 = static_cast<const T*>(a.W2op);
+  const T* W1n = static_cast<const T*>(a.W1nop);
+  const T* W2n = static_cast<const T*>(a.W2nop);
+  T* Wh1o = static_cast<T*>(a.Wh1op);
+  T* Wh2o = static_cast<T*>(a.Wh2op);
+  const dim3 gh(h / BN, mt), gd(d / BN, mt), nt(NTH);
+  // rows of the chunk
+  LargeNormArgs na{a.K, a.V, a.Q, a.stride_tok, a.flags, M, d, a.Kn, a.Vn, a.Qn};
+  const hipError_t en = launch_large_norm(na, std::is_same_v<IOT, bf16>, std::is_same_v<T, bf16>, st);
+  if (en != hipSuccess) return en;
+  hipLaunchKernelGGL((k_rows<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, static_cast<const IOT*>(a.dO),
+                     a.stride_tok, dOn, M, d);
+  // recompute the chunk's gradient terms at W_c
+  EpAct3<T> e1{{}, A, S1, S2, h, M};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct3<T>>), gh, nt, 0, st, Kn, d, M, W1, h, d, d, e1);
+  EpE<T> e2{{}, E, a.Vn, d, M, scale};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpE<T>>), gd, nt, 0, st, A, h, M, W2, d, h, h, e2);
+  EpPD<T> e3{{}, P, D, S1, h, M};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPD<T>>), gh, nt, 0, st, E, d, M, W2, d, h, d, e3);
+  // apply adjoint at W_{c+1}
+  EpAct2<T> e4{{}, Aq, Sq1, h, M};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct2<T>>), gh, nt, 0, st, Qn, d, M, W1n, h, d, d, e4);
+  EpAcc<T> e5{{}, a.Wh2, Wh2o, d};
+  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, Aq, h, M, dOn, d, M,
+                     M, e5);
+  EpMul<T> e6{{}, dZq, Sq1, h, M};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpMul<T>>), gh, nt, 0, st, dOn, d, M, W2n, d, h, d, e6);
+  EpAcc<T> e7{{}, a.Wh1, Wh1o, h};
+  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Qn, d, M, dZq, h, M,
+                     M, e7);
+  EpF32<false> e8{{}, a.dq, d, M, 1.0f};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, dZq, h, M, W1n, h, d, h, e8);
+  // update adjoint at W_c along Wh
+  EpU1<T> e9{dP, dZa, D, S1, P, S2, a.deta_part, h, M, eta};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, e9);
+  EpU2<T> e10{a.dE, E, a.deta_part + (h / BN) * mt, d, M, eta};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU2<T>>), gd, nt, 0, st, A, h, M, Wh2o, d, h, h, e10);
+  hipLaunchKernelGGL(k_deta, dim3(1), dim3(64), 0, st, a.deta_part, (h / BN + d / BN) * mt, a.deta);
+  EpDY<T> e11{{}, dY, a.dv, a.dE, d, M, scale};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpDY<T>>), gd, nt, 0, st, dP, h, M, W2, d, h, h, e11);
+  EpPut<T> e12{{}, EWh, h, M};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPut<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, e12);
+  EpDZ<T> e13{{}, dZ, EWh, dZa, S1, h, M, eta};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpDZ<T>>), gh, nt, 0, st, dY, d, M, W2, d, h, d, e13);
+  EpF32<false> e14{{}, a.dk, d, M, -eta};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, D, h, M, Wh1o, h, d, h, e14);
+  EpF32<true> e15{{}, a.dk, d, M, 1.0f};
+  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, dZ, h, M, W1, h, d, h, e15);
+  // the adjoint of W_c
+  EpAcc<T> e16{{}, a.Wh2, nullptr, d};
+  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, dP, h, M, E, d, M, M,
+                     e16);
+  EpAcc<T> e17{{}, a.Wh2, Wh2o, d};
+  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, A, h, M, dY, d, M, M,
+                     e17);
+  EpAcc<T> e18{{}, a.Wh1, Wh1o, h};
+  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Kn, d, M, dZ, h, M,
+                     M, e18);
+  // gradients of the raw rows
+  hipLaunchKernelGGL(k_norm_bwd<IOT>, dim3((M + 3) / 4), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace bwd
+}  // namespace large
+
+hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  using namespace large::bwd;
+  if (mma_bf16) return io_bf16 ? step_t<bf16, bf16>(a, st) : step_t<bf16, float>(a, st);
+  return step_t<float, float>(a, st);
+}
+
+hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(large::bwd::k_zero, dim3(1024), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ttt

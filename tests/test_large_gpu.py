@@ -140,6 +140,45 @@ def test_large_gcs_one_chunk_equals_chain(gpu):
         assert torch.equal(a[k], b[k]), k
 
 
+BWD_CASES = [
+    # N, H, d, h, M, eta, io, mma_bf16
+    (700, 2, 256, 512, 300, 0.5, "f32", False),   # ragged last chunk, two heads
+    (700, 2, 256, 512, 300, 0.5, "bf16", True),
+    (700, 1, 256, 512, 300, 0.5, "f32", True),    # FP32 tokens, BF16 matrix-core operands
+    (2748, 1, 1024, 4096, 1374, 0.5, "bf16", True),  # the paper's state: 2 chunks of one frame
+]
+
+
+@pytest.mark.parametrize("N,H,d,h,M,eta,io,mma", BWD_CASES)
+def test_large_backward_matches_oracle(gpu, N, H, d, h, M, eta, io, mma):
+    # reverse mode through every inner update (Sec. 4.2 Eq. 8 differentiated)
+    x = make_inputs(N, H, d, h, seed=N + d + 2, io_dtype=io, with_dO=True)
+    dv = {k: to_dev(x[k], io) for k in ("Q", "K", "V", "dO")}
+    W1, W2 = torch.from_numpy(x["W1"]).cuda(), torch.from_numpy(x["W2"]).cuda()
+    f = ops().chunk_fwd(dv["Q"], dv["K"], dv["V"], W1, W2, eta, M, save_ckpt=True, mma_bf16=mma)
+    g = ops().chunk_bwd(dv["Q"], dv["K"], dv["V"], W1, W2, eta, M, f["ckpt"], dv["dO"], mma_bf16=mma)
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M, x["dO"])
+    tol = TOL["bf16" if mma or io == "bf16" else "f32"]
+    print(f"bwd N={N} H={H} d={d} h={h} M={M} eta={eta} io={io} mma_bf16={mma}")
+    for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0"):
+        check(k, host(g[k]), ref[k], tol)
+    e = rel(host(g["deta"]), ref["deta"])
+    print(f"  deta {host(g['deta'])} ref {ref['deta']} rel {e:.2e}")
+    assert e <= tol
+
+
+def test_large_backward_deterministic(gpu):
+    x = make_inputs(700, 1, 256, 512, seed=74, io_dtype="bf16", with_dO=True)
+    dv = {k: to_dev(x[k], "bf16") for k in ("Q", "K", "V", "dO")}
+    W1, W2 = torch.from_numpy(x["W1"]).cuda(), torch.from_numpy(x["W2"]).cuda()
+    f = ops().chunk_fwd(dv["Q"], dv["K"], dv["V"], W1, W2, 0.5, 300, save_ckpt=True)
+    a = ops().chunk_bwd(dv["Q"], dv["K"], dv["V"], W1, W2, 0.5, 300, f["ckpt"], dv["dO"])
+    b = ops().chunk_bwd(dv["Q"], dv["K"], dv["V"], W1, W2, 0.5, 300, f["ckpt"], dv["dO"])
+    for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0", "deta"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_large_shapes_rejected_where_not_built(gpu):
     from paper_2604_08542_amd import _lib
     x, dv = dev_inputs(64, 1, 256, 512, seed=72, io="f32")
