@@ -34,8 +34,8 @@
  *     are safe; calls that share a workspace must be stream-ordered.
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
  *     chip by every entry point), and large states for ttt_chunk_fwd,
- *     ttt_chunk_bwd, ttt_batched_fwd, ttt_batched_fwd_ckpt, ttt_gcs_fwd,
- *     ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     ttt_chunk_bwd, ttt_batched_fwd, ttt_batched_fwd_ckpt, ttt_batched_bwd,
+ *     ttt_gcs_fwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
  *     multiple of 128 up to 16384 (the paper's single head of 1024 with
  *     hidden 4096), where every product of a chunk step is a GEMM over
  *     weights streamed from HBM and a chunk's rows times max(d, h) elements
@@ -179,7 +179,8 @@ ttt_status_t ttt_batched_fwd_ckpt(const ttt_problem_t* p, int32_t n_seqs, const 
  *                 w0_per_seq = 0: gradient of the shared W_0, [H][..]
  *                 (the sum over sequences, in sequence order).
  *   deta          [H] f32: per-head d/d eta summed over sequences.
- *   tile_cfg      as in ttt_batched_fwd (nullable).
+ *   tile_cfg      as in ttt_batched_fwd (nullable; not used at large state
+ *                 sizes, where the sequences run one after another).
  *   ws            ws_bytes >= ttt_workspace_bytes(p, n_seqs). */
 ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64_t* cu_seqlens_host,
                              const void* Q, const void* K, const void* V, const float* W1_0,

@@ -963,20 +963,21 @@ ttt_status_t run_gcs_forward_large(const ttt_problem_t* p, const Shape& S, const
   return TTT_OK;
 }
 
-// Reverse mode at large state sizes, per head: the weights after the last
-// chunk recomputed from its checkpoint with one forward step, then for
-// c = C-1 .. 0 the reverse step of chunk c with W_c (checkpoint c) and W_{c+1}
-// (checkpoint c+1, or the recomputed weights), carrying the adjoint of the
-// weights from chunk to chunk; at the end it is the adjoint of W_0.
-ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, const float* ckpt, const void* Q,
-                                const void* K, const void* V, const void* dO, void* dQ, void* dK, void* dV,
-                                float* dW1_0, float* dW2_0, float* deta, void* ws, size_t ws_bytes, hipStream_t st) {
-  const LargeBwdLayout L = large_bwd_layout(S);
-  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
-  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+// Reverse mode at large state sizes for one sequence (tokens t0 .. t0+N-1,
+// its checkpoints from ckpt on), per head: the weights after the last chunk
+// recomputed from its checkpoint with one forward step, then for c = C-1 .. 0
+// the reverse step of chunk c with W_c (checkpoint c) and W_{c+1} (checkpoint
+// c+1, or the recomputed weights), carrying the adjoint of the weights from
+// chunk to chunk; at the end it is the adjoint of W_0, written to dW1_0 /
+// dW2_0 (added to them with add_w0) and added to deta (or written, without
+// add_eta).
+ttt_status_t backward_large_seq(const ttt_problem_t* p, const Shape& S, const LargeBwdLayout& L, int64_t t0,
+                                int64_t N, const float* ckpt, const void* Q, const void* K, const void* V,
+                                const void* dO, void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta,
+                                bool add_w0, bool add_eta, void* ws, hipStream_t st) {
+  const int64_t M = S.M, dh = S.dh();
   const int64_t C = (N + M - 1) / M;
   const size_t iob = S.io_bf16 ? 2 : 4;
-  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.f.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
   float* Wh1 = at<float>(ws, L.Wh1);
   float* Wh2 = at<float>(ws, L.Wh2);
   float* dt = at<float>(ws, L.deta);
@@ -988,7 +989,9 @@ ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, const fl
     if (!zero(Wh1, dh) || !zero(Wh2, dh) || !zero(dt, 1) || !cast(Wh1, L.Wh1op) || !cast(Wh2, L.Wh2op))
       return TTT_EHIP;
     auto row = [&](int64_t c) { return ckpt + (c * S.H + hd) * 2 * dh; };
-    auto chunk_off = [&](int64_t c) { return (c * M * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob; };
+    auto chunk_off = [&](int64_t c) {
+      return ((t0 + c * M) * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob;
+    };
     if (C > 0) {
       // W_C: one forward step of the last chunk from its checkpoint
       const int64_t c = C - 1;
@@ -1047,10 +1050,43 @@ ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, const fl
       b.deta = dt;
       if (!launched([&] { return launch_large_bwd_step(b, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
     }
-    if (hipMemcpyAsync(dW1_0 + hd * dh, Wh1, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(dW2_0 + hd * dh, Wh2, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hipMemcpyAsync(deta + hd, dt, sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    if (add_w0) {
+      if (!launched([&] { return launch_large_add(Wh1, dW1_0 + hd * dh, dh, st); }) ||
+          !launched([&] { return launch_large_add(Wh2, dW2_0 + hd * dh, dh, st); }))
+        return TTT_EHIP;
+    } else if (hipMemcpyAsync(dW1_0 + hd * dh, Wh1, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+               hipMemcpyAsync(dW2_0 + hd * dh, Wh2, dh * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess) {
       return TTT_EHIP;
+    }
+    if (add_eta) {
+      if (!launched([&] { return launch_large_add(dt, deta + hd, 1, st); })) return TTT_EHIP;
+    } else if (hipMemcpyAsync(deta + hd, dt, sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      return TTT_EHIP;
+    }
+  }
+  return TTT_OK;
+}
+
+// Reverse mode at large state sizes over B sequences (B = 1: the chain call),
+// one sequence after another.  Shared W0 (w0_per_seq = 0): its adjoint is the
+// sum over sequences in sequence order; deta always is.
+ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, int B, const int64_t* cu, int w0_per_seq,
+                                const float* ckpt, const void* Q, const void* K, const void* V, const void* dO,
+                                void* dQ, void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws,
+                                size_t ws_bytes, hipStream_t st) {
+  const LargeBwdLayout L = large_bwd_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.f.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
+  const int64_t dh = S.dh();
+  int64_t ckrow = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t n = cu[b + 1] - cu[b];
+    const int64_t o = w0_per_seq ? (int64_t)b * S.H * dh : 0;
+    const ttt_status_t e =
+        backward_large_seq(p, S, L, cu[b], n, ckpt ? ckpt + ckrow * S.H * 2 * dh : nullptr, Q, K, V, dO, dQ, dK, dV,
+                           dW1_0 + o, dW2_0 + o, deta, !w0_per_seq && b > 0, b > 0, ws, st);
+    if (e != TTT_OK) return e;
+    ckrow += (n + S.M - 1) / S.M;
   }
   return TTT_OK;
 }
@@ -1520,7 +1556,6 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
     Shape S{};
     ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if ((e = check_batch(p, n_seqs, cu_seqlens_host, w0_per_seq, tile_cfg)) != TTT_OK) return e;
     if (!dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     const bool any = cu_seqlens_host[n_seqs] > 0;
@@ -1529,6 +1564,9 @@ ttt_status_t ttt_batched_bwd(const ttt_problem_t* p, int32_t n_seqs, const int64
     for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
                           (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
+    if (S.large)
+      return run_backward_large(p, S, n_seqs, cu_seqlens_host, w0_per_seq, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0,
+                                dW2_0, deta, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
     return run_backward(p, S, n_seqs, cu_seqlens_host, w0_per_seq, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0,
                         deta, tile_cfg, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
   } catch (...) {
@@ -1549,10 +1587,10 @@ ttt_status_t ttt_chunk_bwd(const ttt_problem_t* p, const void* Q, const void* K,
     for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)ckpt,
                           (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
-    if (S.large)
-      return run_backward_large(p, S, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
-                                static_cast<hipStream_t>(hip_stream));
     const int64_t cu[2] = {0, p->n_tokens};
+    if (S.large)
+      return run_backward_large(p, S, 1, cu, 0, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+                                static_cast<hipStream_t>(hip_stream));
     return run_backward(p, S, 1, cu, 0, ckpt, Q, K, V, dO, dQ, dK, dV, dW1_0, dW2_0, deta, nullptr, ws, ws_bytes,
                         static_cast<hipStream_t>(hip_stream));
   } catch (...) {

@@ -101,6 +101,8 @@ struct LargeBwdArgs {
 hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
 // Fill n floats with zero.
 hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st);
+// dst[i] += src[i] for n floats.
+hipError_t launch_large_add(const float* src, float* dst, int64_t n, hipStream_t st);
 // Chunk step of the paper's memory unit (SwiGLU network, dot-product loss
 // with token-wise step sizes) at large state sizes.
 struct LargeAmuArgs {

@@ -336,6 +336,11 @@ __global__ void k_deta(const float* part, int n, float* deta) {
   }
 }
 
+__global__ void k_add(const float* src, float* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+
 __global__ void k_zero(float* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.f;
@@ -439,6 +444,11 @@ hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_b
 
 hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(large::bwd::k_zero, dim3(1024), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_large_add(const float* src, float* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(large::bwd::k_add, dim3(1024), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

@@ -168,6 +168,33 @@ def test_large_backward_matches_oracle(gpu, N, H, d, h, M, eta, io, mma):
     assert e <= tol
 
 
+@pytest.mark.parametrize("io,w0_per_seq", [("f32", False), ("bf16", True), ("bf16", False)])
+def test_large_batched_backward_matches_oracle(gpu, io, w0_per_seq):
+    # uneven sequences (3 chunks with a ragged last one, an empty one, one
+    # chunk), each an independent chain; a shared W0 collects their sum
+    d, h, M, eta = 256, 512, 300, 0.5
+    cu = [0, 700, 700, 1000]
+    B = len(cu) - 1
+    x = make_inputs(1000, 2, d, h, seed=75, io_dtype=io, with_dO=True, n_w0=B if w0_per_seq else 1)
+    dv = {k: to_dev(x[k], io) for k in ("Q", "K", "V", "dO")}
+    W1, W2 = torch.from_numpy(x["W1"]).cuda(), torch.from_numpy(x["W2"]).cuda()
+    mma = io == "bf16"
+    f = ops().batched_fwd(dv["Q"], dv["K"], dv["V"], cu, W1, W2, eta, M, w0_per_seq=w0_per_seq, save_ckpt=True,
+                          mma_bf16=mma)
+    g = ops().batched_bwd(dv["Q"], dv["K"], dv["V"], cu, W1, W2, eta, M, f["ckpt"], dv["dO"], w0_per_seq=w0_per_seq,
+                          mma_bf16=mma)
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_batched(x["Q"], x["K"], x["V"], cu, x["W1"], x["W2"], eta, M, x["dO"],
+                                   w0_per_seq=w0_per_seq)
+    tol = TOL[io]
+    print(f"batched bwd {io} w0_per_seq={w0_per_seq}")
+    for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0"):
+        check(k, host(g[k]), ref[k], tol)
+    e = rel(host(g["deta"]), ref["deta"])
+    print(f"  deta rel {e:.2e}")
+    assert e <= tol
+
+
 def test_large_backward_deterministic(gpu):
     x = make_inputs(700, 1, 256, 512, seed=74, io_dtype="bf16", with_dO=True)
     dv = {k: to_dev(x[k], "bf16") for k in ("Q", "K", "V", "dO")}
