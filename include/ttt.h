@@ -35,7 +35,7 @@
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
  *     chip by every entry point), and large states for ttt_chunk_fwd,
  *     ttt_chunk_bwd, ttt_batched_fwd, ttt_batched_fwd_ckpt, ttt_batched_bwd,
- *     ttt_gcs_fwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     ttt_gcs_fwd, ttt_gcs_bwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
  *     multiple of 128 up to 16384 (the paper's single head of 1024 with
  *     hidden 4096), where every product of a chunk step is a GEMM over
  *     weights streamed from HBM and a chunk's rows times max(d, h) elements

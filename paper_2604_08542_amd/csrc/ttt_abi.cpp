@@ -118,8 +118,8 @@ LargeLayout large_layout(const Shape& s) {
 // reverse step's buffers.
 struct LargeBwdLayout {
   LargeLayout f;
-  size_t dOn, dY, dq, dk, dv, dE, S2, P, Sq1, dZq, dP, dZa, EWh, dZ, W1nop, W2nop, Wh1, Wh2, Wh1op, Wh2op, deta_part,
-      deta, total;
+  size_t dOn, dY, dq, dk, dv, dE, S2, P, Sq1, dZq, dP, dZa, EWh, dZ, W1nop, W2nop, Wh1, Wh2, Wh1op, Wh2op, tot1, tot2,
+      deta_part, deta, total;
 };
 LargeBwdLayout large_bwd_layout(const Shape& s) {
   LargeBwdLayout L{};
@@ -152,6 +152,8 @@ LargeBwdLayout large_bwd_layout(const Shape& s) {
   L.Wh2 = take(d * h * 4);
   L.Wh1op = take(d * h * op);
   L.Wh2op = take(d * h * op);
+  L.tot1 = take(d * h * 4);  // GCS: the adjoint of W0 (the apply adjoint plus every chunk's update terms)
+  L.tot2 = take(d * h * 4);
   L.deta_part = take((d / 128 + h / 128) * ((M + 127) / 128) * 4);
   L.deta = take(4);
   L.total = off;
@@ -963,6 +965,42 @@ ttt_status_t run_gcs_forward_large(const ttt_problem_t* p, const Shape& S, const
   return TTT_OK;
 }
 
+// Arguments of a large-state reverse step over the chunk at byte offset off
+// of the token tensors, its buffers in the workspace (W_c in the forward
+// layout's operand copies, W_{c+1} in W1nop / W2nop, the carried adjoint in
+// Wh1 / Wh2); the caller sets the parts to run, where the weight terms go and
+// the step-size output.
+LargeBwdArgs large_bwd_args(const ttt_problem_t* p, const Shape& S, const LargeBwdLayout& L, void* ws, int64_t off,
+                            int32_t rows, const void* Q, const void* K, const void* V, const void* dO, void* dQ,
+                            void* dK, void* dV) {
+  LargeBwdArgs b{};
+  b.K = static_cast<const char*>(K) + off;
+  b.V = static_cast<const char*>(V) + off;
+  b.Q = static_cast<const char*>(Q) + off;
+  b.dO = static_cast<const char*>(dO) + off;
+  b.dQ = static_cast<char*>(dQ) + off;
+  b.dK = static_cast<char*>(dK) + off;
+  b.dV = static_cast<char*>(dV) + off;
+  b.stride_tok = S.stride_tok;
+  b.flags = p->flags;
+  b.rows = rows; b.d = S.d; b.h = S.h;
+  b.eta = p->eta;
+  b.Kn = at<char>(ws, L.f.Kn); b.Qn = at<char>(ws, L.f.Qn); b.E = at<char>(ws, L.f.E);
+  b.dOn = at<char>(ws, L.dOn); b.dY = at<char>(ws, L.dY);
+  b.Vn = at<float>(ws, L.f.Vn); b.dq = at<float>(ws, L.dq); b.dk = at<float>(ws, L.dk);
+  b.dv = at<float>(ws, L.dv); b.dE = at<float>(ws, L.dE);
+  b.A = at<char>(ws, L.f.A); b.S1 = at<char>(ws, L.f.S1); b.S2 = at<char>(ws, L.S2); b.P = at<char>(ws, L.P);
+  b.D = at<char>(ws, L.f.D); b.Aq = at<char>(ws, L.f.Aq); b.Sq1 = at<char>(ws, L.Sq1);
+  b.dZq = at<char>(ws, L.dZq); b.dP = at<char>(ws, L.dP); b.dZa = at<char>(ws, L.dZa);
+  b.EWh = at<char>(ws, L.EWh); b.dZ = at<char>(ws, L.dZ);
+  b.W1op = at<char>(ws, L.f.W1op); b.W2op = at<char>(ws, L.f.W2op);
+  b.W1nop = at<char>(ws, L.W1nop); b.W2nop = at<char>(ws, L.W2nop);
+  b.Wh1 = at<float>(ws, L.Wh1); b.Wh2 = at<float>(ws, L.Wh2);
+  b.Wh1op = at<char>(ws, L.Wh1op); b.Wh2op = at<char>(ws, L.Wh2op);
+  b.deta_part = at<float>(ws, L.deta_part);
+  return b;
+}
+
 // Reverse mode at large state sizes for one sequence (tokens t0 .. t0+N-1,
 // its checkpoints from ckpt on), per head: the weights after the last chunk
 // recomputed from its checkpoint with one forward step, then for c = C-1 .. 0
@@ -1022,31 +1060,10 @@ ttt_status_t backward_large_seq(const ttt_problem_t* p, const Shape& S, const La
     for (int64_t c = C - 1; c >= 0; --c) {
       if (c + 1 < C && (!cast(row(c + 1), L.W1nop) || !cast(row(c + 1) + dh, L.W2nop))) return TTT_EHIP;
       if (!cast(row(c), L.f.W1op) || !cast(row(c) + dh, L.f.W2op)) return TTT_EHIP;
-      const int64_t off = chunk_off(c);
-      LargeBwdArgs b{};
-      b.K = static_cast<const char*>(K) + off;
-      b.V = static_cast<const char*>(V) + off;
-      b.Q = static_cast<const char*>(Q) + off;
-      b.dO = static_cast<const char*>(dO) + off;
-      b.dQ = static_cast<char*>(dQ) + off;
-      b.dK = static_cast<char*>(dK) + off;
-      b.dV = static_cast<char*>(dV) + off;
-      b.stride_tok = S.stride_tok;
-      b.flags = p->flags;
-      b.rows = (int32_t)std::min<int64_t>(M, N - c * M); b.d = S.d; b.h = S.h;
-      b.eta = p->eta;
-      b.Kn = at<char>(ws, L.f.Kn); b.Qn = at<char>(ws, L.f.Qn); b.E = at<char>(ws, L.f.E);
-      b.dOn = at<char>(ws, L.dOn); b.dY = at<char>(ws, L.dY);
-      b.Vn = at<float>(ws, L.f.Vn); b.dq = at<float>(ws, L.dq); b.dk = at<float>(ws, L.dk);
-      b.dv = at<float>(ws, L.dv); b.dE = at<float>(ws, L.dE);
-      b.A = at<char>(ws, L.f.A); b.S1 = at<char>(ws, L.f.S1); b.S2 = at<char>(ws, L.S2); b.P = at<char>(ws, L.P);
-      b.D = at<char>(ws, L.f.D); b.Aq = at<char>(ws, L.f.Aq); b.Sq1 = at<char>(ws, L.Sq1);
-      b.dZq = at<char>(ws, L.dZq); b.dP = at<char>(ws, L.dP); b.dZa = at<char>(ws, L.dZa);
-      b.EWh = at<char>(ws, L.EWh); b.dZ = at<char>(ws, L.dZ);
-      b.W1op = at<char>(ws, L.f.W1op); b.W2op = at<char>(ws, L.f.W2op);
-      b.W1nop = at<char>(ws, L.W1nop); b.W2nop = at<char>(ws, L.W2nop);
-      b.Wh1 = Wh1; b.Wh2 = Wh2; b.Wh1op = at<char>(ws, L.Wh1op); b.Wh2op = at<char>(ws, L.Wh2op);
-      b.deta_part = at<float>(ws, L.deta_part);
+      LargeBwdArgs b = large_bwd_args(p, S, L, ws, chunk_off(c), (int32_t)std::min<int64_t>(M, N - c * M), Q, K, V,
+                                      dO, dQ, dK, dV);
+      b.Acc1 = Wh1; b.Acc2 = Wh2; b.Acc1op = b.Wh1op; b.Acc2op = b.Wh2op;
+      b.apply = 1; b.update = 1;
       b.deta = dt;
       if (!launched([&] { return launch_large_bwd_step(b, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
     }
@@ -1087,6 +1104,90 @@ ttt_status_t run_backward_large(const ttt_problem_t* p, const Shape& S, int B, c
                            dW1_0 + o, dW2_0 + o, deta, !w0_per_seq && b > 0, b > 0, ws, st);
     if (e != TTT_OK) return e;
     ckrow += (n + S.M - 1) / S.M;
+  }
+  return TTT_OK;
+}
+
+// Reverse mode of the GCS form at large state sizes (Eq. 10), per head: W*
+// recomputed as in the forward; the apply adjoint of every chunk at W*
+// accumulated into Wh (dQ written); then every chunk's update adjoint at W0
+// against that fixed Wh, its weight terms added to a total that starts at Wh
+// (dK, dV and d/d eta written); the total is the adjoint of W0.
+ttt_status_t run_gcs_backward_large(const ttt_problem_t* p, const Shape& S, const void* Q, const void* K,
+                                    const void* V, const float* W1_0, const float* W2_0, const void* dO, void* dQ,
+                                    void* dK, void* dV, float* dW1_0, float* dW2_0, float* deta, void* ws,
+                                    size_t ws_bytes, hipStream_t st) {
+  const LargeBwdLayout L = large_bwd_layout(S);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh();
+  const int64_t C = (N + M - 1) / M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.f.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
+  float* W1 = at<float>(ws, L.f.W1);
+  float* W2 = at<float>(ws, L.f.W2);
+  float* Wh1 = at<float>(ws, L.Wh1);
+  float* Wh2 = at<float>(ws, L.Wh2);
+  float* tot1 = at<float>(ws, L.tot1);
+  float* tot2 = at<float>(ws, L.tot2);
+  float* dt = at<float>(ws, L.deta);
+  auto cast = [&](const float* src, size_t off) {
+    return launched([&] { return launch_large_cast(src, at<char>(ws, off), dh, S.mma_bf16, st); });
+  };
+  auto zero = [&](float* q, int64_t n) { return launched([&] { return launch_large_zero(q, n, st); }); };
+  auto copy = [&](float* dst, const float* src, int64_t n) {
+    return hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  };
+  for (int hd = 0; hd < S.H; ++hd) {
+    const int64_t w0 = (int64_t)hd * dh;
+    auto chunk_off = [&](int64_t c) {
+      return (c * M * S.stride_tok + (int64_t)hd * S.stride_head) * (int64_t)iob;
+    };
+    auto rows = [&](int64_t c) { return (int32_t)std::min<int64_t>(M, N - c * M); };
+    if (!zero(Wh1, dh) || !zero(Wh2, dh) || !zero(dt, 1) || !cast(Wh1, L.Wh1op) || !cast(Wh2, L.Wh2op))
+      return TTT_EHIP;
+    // W* = W0 - eta * sum_c grad L_c(W0), as the forward takes it
+    if (!launched([&] {
+          return launch_large_init(W1_0 + w0, W2_0 + w0, W1, W2, at<char>(ws, L.f.W1op), at<char>(ws, L.f.W2op), dh,
+                                   S.mma_bf16, st);
+        }))
+      return TTT_EHIP;
+    for (int64_t c = 0; c < C; ++c) {
+      LargeStepArgs a{};
+      a.K = static_cast<const char*>(K) + chunk_off(c);
+      a.V = static_cast<const char*>(V) + chunk_off(c);
+      a.Q = static_cast<const char*>(Q) + chunk_off(c);
+      a.stride_tok = S.stride_tok;
+      a.flags = p->flags;
+      a.rows = rows(c); a.d = S.d; a.h = S.h;
+      a.grad = 1; a.masters_only = 1; a.eta = p->eta;
+      a.Kn = at<char>(ws, L.f.Kn); a.Qn = at<char>(ws, L.f.Qn); a.E = at<char>(ws, L.f.E);
+      a.A = at<char>(ws, L.f.A); a.D = at<char>(ws, L.f.D); a.Aq = at<char>(ws, L.f.Aq);
+      a.Vn = at<float>(ws, L.f.Vn); a.S1 = at<char>(ws, L.f.S1);
+      a.W1 = W1; a.W2 = W2; a.W1op = at<char>(ws, L.f.W1op); a.W2op = at<char>(ws, L.f.W2op);
+      a.loss_part = at<float>(ws, L.f.loss_part);
+      if (!launched([&] { return launch_large_step(a, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+    }
+    if (!cast(W1, L.W1nop) || !cast(W2, L.W2nop)) return TTT_EHIP;
+    // the apply adjoint of every chunk at W*
+    for (int64_t c = 0; c < C; ++c) {
+      LargeBwdArgs b = large_bwd_args(p, S, L, ws, chunk_off(c), rows(c), Q, K, V, dO, dQ, dK, dV);
+      b.apply = 1; b.update = 0;
+      b.deta = dt;
+      if (!launched([&] { return launch_large_bwd_step(b, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+    }
+    // every chunk's update adjoint at W0 against the fixed Wh
+    if (!copy(tot1, Wh1, dh) || !copy(tot2, Wh2, dh) || !cast(W1_0 + w0, L.f.W1op) || !cast(W2_0 + w0, L.f.W2op))
+      return TTT_EHIP;
+    for (int64_t c = 0; c < C; ++c) {
+      LargeBwdArgs b = large_bwd_args(p, S, L, ws, chunk_off(c), rows(c), Q, K, V, dO, dQ, dK, dV);
+      b.apply = 0; b.update = 1;
+      b.Acc1 = tot1; b.Acc2 = tot2;  // operand copies not needed
+      b.deta = dt;
+      if (!launched([&] { return launch_large_bwd_step(b, S.io_bf16, S.mma_bf16, st); })) return TTT_EHIP;
+    }
+    if (!copy(dW1_0 + w0, C > 0 ? tot1 : Wh1, dh) || !copy(dW2_0 + w0, C > 0 ? tot2 : Wh2, dh) ||
+        !copy(deta + hd, dt, 1))
+      return TTT_EHIP;
   }
   return TTT_OK;
 }
@@ -1639,13 +1740,15 @@ ttt_status_t ttt_gcs_bwd(const ttt_problem_t* p, const void* Q, const void* K, c
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (!W1_0 || !W2_0 || !dW1_0 || !dW2_0 || !deta) return TTT_EINVAL;
     if (p->n_tokens > 0 && (!Q || !K || !V || !dO || !dQ || !dK || !dV)) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_EINVAL;
     for (const void* q : {Q, K, V, dO, (const void*)dQ, (const void*)dK, (const void*)dV, (const void*)W1_0,
                           (const void*)W2_0, (const void*)dW1_0, (const void*)dW2_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
+    if (S.large)
+      return run_gcs_backward_large(p, S, Q, K, V, W1_0, W2_0, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
+                                    static_cast<hipStream_t>(hip_stream));
     return run_gcs_backward(p, S, Q, K, V, W1_0, W2_0, dO, dQ, dK, dV, dW1_0, dW2_0, deta, ws, ws_bytes,
                             static_cast<hipStream_t>(hip_stream));
   } catch (...) {

@@ -95,6 +95,12 @@ struct LargeBwdArgs {
   float* Wh2;
   void* Wh1op;
   void* Wh2op;
+  float* Acc1;        // where the update adjoint's weight terms are added (the
+  float* Acc2;        // carried adjoint itself for the chain) and their
+  void* Acc1op;       // operand copies (nullable)
+  void* Acc2op;
+  int32_t apply;      // 1: the apply adjoint of the chunk (dQ written)
+  int32_t update;     // 1: the update adjoint of the chunk (dK, dV written)
   float* deta_part;   // per-tile partials of the step-size derivative
   float* deta;        // this head's running d/d eta (one float)
 };

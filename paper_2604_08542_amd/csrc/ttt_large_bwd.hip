@@ -18,6 +18,9 @@
 //               dk = -eta D Wh1^T + dZ W1^T
 //               Wh2 += dP^T E + A^T dY;  Wh1 += K^T dZ
 //   rows        dQ, dK, dV = the L2-normalisation adjoints of dq, dk, dv
+// The apply and update parts can run alone (the GCS form takes the apply
+// adjoint of every chunk at W* first, then every chunk's update adjoint at W0
+// against that fixed Wh, adding the weight terms to a separate total).
 // Every output element is owned by one work-group summing its whole
 // contraction in a fixed order; the step-size derivative is summed from
 // per-tile partials in tile order.  The result is deterministic.
@@ -277,6 +280,7 @@ __global__ __launch_bounds__(256) void k_norm_bwd(LargeBwdArgs p) {
   if (row >= p.rows) return;
   const int passes = p.d / 256;
   for (int which = 0; which < 3; ++which) {
+    if (which < 2 ? !p.update : !p.apply) continue;
     const IOT* src = static_cast<const IOT*>(which == 0 ? p.K : which == 1 ? p.V : p.Q) +
                      (int64_t)row * p.stride_tok;
     IOT* dst = static_cast<IOT*>(which == 0 ? p.dK : which == 1 ? p.dV : p.dQ) + (int64_t)row * p.stride_tok;
@@ -380,54 +384,61 @@ hipError_t step_t(const LargeBwdArgs& a, hipStream_t st) {
   LargeNormArgs na{a.K, a.V, a.Q, a.stride_tok, a.flags, M, d, a.Kn, a.Vn, a.Qn};
   const hipError_t en = launch_large_norm(na, std::is_same_v<IOT, bf16>, std::is_same_v<T, bf16>, st);
   if (en != hipSuccess) return en;
-  hipLaunchKernelGGL((k_rows<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, static_cast<const IOT*>(a.dO),
-                     a.stride_tok, dOn, M, d);
-  // recompute the chunk's gradient terms at W_c
-  EpAct3<T> e1{{}, A, S1, S2, h, M};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct3<T>>), gh, nt, 0, st, Kn, d, M, W1, h, d, d, e1);
-  EpE<T> e2{{}, E, a.Vn, d, M, scale};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpE<T>>), gd, nt, 0, st, A, h, M, W2, d, h, h, e2);
-  EpPD<T> e3{{}, P, D, S1, h, M};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPD<T>>), gh, nt, 0, st, E, d, M, W2, d, h, d, e3);
-  // apply adjoint at W_{c+1}
-  EpAct2<T> e4{{}, Aq, Sq1, h, M};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct2<T>>), gh, nt, 0, st, Qn, d, M, W1n, h, d, d, e4);
-  EpAcc<T> e5{{}, a.Wh2, Wh2o, d};
-  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, Aq, h, M, dOn, d, M,
-                     M, e5);
-  EpMul<T> e6{{}, dZq, Sq1, h, M};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpMul<T>>), gh, nt, 0, st, dOn, d, M, W2n, d, h, d, e6);
-  EpAcc<T> e7{{}, a.Wh1, Wh1o, h};
-  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Qn, d, M, dZq, h, M,
-                     M, e7);
-  EpF32<false> e8{{}, a.dq, d, M, 1.0f};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, dZq, h, M, W1n, h, d, h, e8);
-  // update adjoint at W_c along Wh
-  EpU1<T> e9{dP, dZa, D, S1, P, S2, a.deta_part, h, M, eta};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, e9);
-  EpU2<T> e10{a.dE, E, a.deta_part + (h / BN) * mt, d, M, eta};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU2<T>>), gd, nt, 0, st, A, h, M, Wh2o, d, h, h, e10);
-  hipLaunchKernelGGL(k_deta, dim3(1), dim3(64), 0, st, a.deta_part, (h / BN + d / BN) * mt, a.deta);
-  EpDY<T> e11{{}, dY, a.dv, a.dE, d, M, scale};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpDY<T>>), gd, nt, 0, st, dP, h, M, W2, d, h, h, e11);
-  EpPut<T> e12{{}, EWh, h, M};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPut<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, e12);
-  EpDZ<T> e13{{}, dZ, EWh, dZa, S1, h, M, eta};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpDZ<T>>), gh, nt, 0, st, dY, d, M, W2, d, h, d, e13);
-  EpF32<false> e14{{}, a.dk, d, M, -eta};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, D, h, M, Wh1o, h, d, h, e14);
-  EpF32<true> e15{{}, a.dk, d, M, 1.0f};
-  hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, dZ, h, M, W1, h, d, h, e15);
-  // the adjoint of W_c
-  EpAcc<T> e16{{}, a.Wh2, nullptr, d};
-  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, dP, h, M, E, d, M, M,
-                     e16);
-  EpAcc<T> e17{{}, a.Wh2, Wh2o, d};
-  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, A, h, M, dY, d, M, M,
-                     e17);
-  EpAcc<T> e18{{}, a.Wh1, Wh1o, h};
-  hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Kn, d, M, dZ, h, M,
-                     M, e18);
+  if (a.apply)
+    hipLaunchKernelGGL((k_rows<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, static_cast<const IOT*>(a.dO),
+                       a.stride_tok, dOn, M, d);
+  if (a.update) {
+    // recompute the chunk's gradient terms at W_c
+    EpAct3<T> e1{{}, A, S1, S2, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct3<T>>), gh, nt, 0, st, Kn, d, M, W1, h, d, d, e1);
+    EpE<T> e2{{}, E, a.Vn, d, M, scale};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpE<T>>), gd, nt, 0, st, A, h, M, W2, d, h, h, e2);
+    EpPD<T> e3{{}, P, D, S1, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPD<T>>), gh, nt, 0, st, E, d, M, W2, d, h, d, e3);
+  }
+  if (a.apply) {
+    // apply adjoint at W_{c+1}
+    EpAct2<T> e4{{}, Aq, Sq1, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpAct2<T>>), gh, nt, 0, st, Qn, d, M, W1n, h, d, d, e4);
+    EpAcc<T> e5{{}, a.Wh2, Wh2o, d};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, Aq, h, M, dOn, d, M,
+                       M, e5);
+    EpMul<T> e6{{}, dZq, Sq1, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpMul<T>>), gh, nt, 0, st, dOn, d, M, W2n, d, h, d, e6);
+    EpAcc<T> e7{{}, a.Wh1, Wh1o, h};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Qn, d, M, dZq, h, M,
+                       M, e7);
+    EpF32<false> e8{{}, a.dq, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, dZq, h, M, W1n, h, d, h, e8);
+  }
+  if (a.update) {
+    // update adjoint at W_c along Wh
+    EpU1<T> e9{dP, dZa, D, S1, P, S2, a.deta_part, h, M, eta};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, e9);
+    EpU2<T> e10{a.dE, E, a.deta_part + (h / BN) * mt, d, M, eta};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU2<T>>), gd, nt, 0, st, A, h, M, Wh2o, d, h, h, e10);
+    hipLaunchKernelGGL(k_deta, dim3(1), dim3(64), 0, st, a.deta_part, (h / BN + d / BN) * mt, a.deta);
+    EpDY<T> e11{{}, dY, a.dv, a.dE, d, M, scale};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpDY<T>>), gd, nt, 0, st, dP, h, M, W2, d, h, h, e11);
+    EpPut<T> e12{{}, EWh, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPut<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, e12);
+    EpDZ<T> e13{{}, dZ, EWh, dZa, S1, h, M, eta};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpDZ<T>>), gh, nt, 0, st, dY, d, M, W2, d, h, d, e13);
+    EpF32<false> e14{{}, a.dk, d, M, -eta};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, D, h, M, Wh1o, h, d, h, e14);
+    EpF32<true> e15{{}, a.dk, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, dZ, h, M, W1, h, d, h, e15);
+    // the weight terms of the update adjoint (the adjoint of W_c in the chain)
+    EpAcc<T> e16{{}, a.Acc2, nullptr, d};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, dP, h, M, E, d, M, M,
+                       e16);
+    EpAcc<T> e17{{}, a.Acc2, static_cast<T*>(a.Acc2op), d};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(d / BN, h / BMW), nt, 0, st, A, h, M, dY, d, M, M,
+                       e17);
+    EpAcc<T> e18{{}, a.Acc1, static_cast<T*>(a.Acc1op), h};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), dim3(h / BN, d / BMW), nt, 0, st, Kn, d, M, dZ, h, M,
+                       M, e18);
+  }
   // gradients of the raw rows
   hipLaunchKernelGGL(k_norm_bwd<IOT>, dim3((M + 3) / 4), dim3(256), 0, st, a);
   return hipGetLastError();

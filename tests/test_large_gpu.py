@@ -195,6 +195,29 @@ def test_large_batched_backward_matches_oracle(gpu, io, w0_per_seq):
     assert e <= tol
 
 
+@pytest.mark.parametrize("N,H,d,h,M,eta,io,mma", [
+    (700, 2, 256, 512, 300, 0.5, "f32", False),
+    (700, 2, 256, 512, 300, 0.5, "bf16", True),
+    (5496, 1, 1024, 4096, 2748, 0.5, "bf16", True),  # the paper's state: 2 chunks of 2 frames
+])
+def test_large_gcs_backward_matches_oracle(gpu, N, H, d, h, M, eta, io, mma):
+    # reverse mode of Eq. 10: the apply adjoint of every token at W*, every
+    # chunk's update adjoint at W0 against it
+    x = make_inputs(N, H, d, h, seed=N + d + 3, io_dtype=io, with_dO=True)
+    dv = {k: to_dev(x[k], io) for k in ("Q", "K", "V", "dO")}
+    W1, W2 = torch.from_numpy(x["W1"]).cuda(), torch.from_numpy(x["W2"]).cuda()
+    g = ops().gcs_bwd(dv["Q"], dv["K"], dv["V"], W1, W2, eta, M, dv["dO"], mma_bf16=mma)
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_gcs(x["Q"], x["K"], x["V"], x["W1"], x["W2"], eta, M, x["dO"])
+    tol = TOL["bf16" if mma or io == "bf16" else "f32"]
+    print(f"gcs bwd N={N} H={H} d={d} h={h} M={M} eta={eta} io={io} mma_bf16={mma}")
+    for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0"):
+        check(k, host(g[k]), ref[k], tol)
+    e = rel(host(g["deta"]), ref["deta"])
+    print(f"  deta rel {e:.2e}")
+    assert e <= tol
+
+
 def test_large_backward_deterministic(gpu):
     x = make_inputs(700, 1, 256, 512, seed=74, io_dtype="bf16", with_dO=True)
     dv = {k: to_dev(x[k], "bf16") for k in ("Q", "K", "V", "dO")}
