@@ -275,6 +275,21 @@ def other_forms(forms, steps, warmup):
                 res[f"amu_paper_state_{sync}_{io}"] = dict(
                     workload=wp.name.replace("_bf16", ""), ms_per_step=ms, tokens_per_s=wp.n_tokens / (ms * 1e-3),
                     roofline=dict(bound="mfma", achieved=ach, peak=PEAK[io], unit="TFLOP/s", frac=ach / PEAK[io]))
+                if io == "bf16":  # forward + reverse mode
+                    dOp = torch.randn(dev["Q"].shape, generator=g, device="cuda").to(dev["Q"].dtype)
+                    bws = torch.empty(ops.L.load().ttt_amu_bwd_workspace_bytes(ctypes.byref(
+                        ops.problem(dev["Q"], wp.d_hidden, wp.n_tokens, wp.chunk_tokens, 0.0, ops._flags(True))),
+                        {"chain": 0, "gcs": 1}[sync]), dtype=torch.uint8, device="cuda")
+
+                    def fbp():
+                        ops.amu_fwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, wp.chunk_tokens,
+                                    sync=sync, want_final=False, out=O, ws=ws)
+                        ops.amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, wp.chunk_tokens, dOp,
+                                    sync=sync, ws=bws)
+                    ms = timed(fbp, 2, 1)
+                    res[f"amu_paper_state_fwd_bwd_{sync}_bf16"] = dict(
+                        workload=wp.name.replace("_bf16", ""), ms_per_step=ms, tokens_per_s=wp.n_tokens / (ms * 1e-3))
+                    del dOp, bws
             del dev, O, W3, et, ws
             torch.cuda.empty_cache()
     if "gcm" in forms:  # the layer around the memory unit: projections, unit, output projection, gate

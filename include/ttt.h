@@ -35,7 +35,7 @@
  *   - Supported shapes: d = 64 with h in {128, 256} (fast weights held on
  *     chip by every entry point), and large states for ttt_chunk_fwd,
  *     ttt_chunk_bwd, ttt_batched_fwd, ttt_batched_fwd_ckpt, ttt_batched_bwd,
- *     ttt_gcs_fwd, ttt_gcs_bwd, ttt_amu_fwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
+ *     ttt_gcs_fwd, ttt_gcs_bwd, ttt_amu_fwd, ttt_amu_bwd and ttt_gcm_fwd: d a multiple of 256 up to 4096 and h a
  *     multiple of 128 up to 16384 (the paper's single head of 1024 with
  *     hidden 4096), where every product of a chunk step is a GEMM over
  *     weights streamed from HBM and a chunk's rows times max(d, h) elements
@@ -259,7 +259,8 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
  * and one update-adjoint pass over all tokens.  Every output is overwritten;
  * with n_tokens = 0 the weight adjoints are zero.  ws_bytes >=
  * ttt_amu_bwd_workspace_bytes(p, sync) (it grows with the chunk count for the
- * chain).  Errors as ttt_amu_fwd. */
+ * chain).  Errors as ttt_amu_fwd.  At large state sizes every product is a
+ * GEMM over weights streamed from HBM, one head and one chunk at a time. */
 size_t ttt_amu_bwd_workspace_bytes(const ttt_problem_t* p, int32_t sync);
 ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, const void* K, const void* V,
                          const float* eta_tok, const float* W1_0, const float* W2_0, const float* W3_0,

@@ -197,6 +197,45 @@ LargeAmuLayout large_amu_layout(const Shape& s) {
   return L;
 }
 
+// Workspace of the paper's unit's reverse mode at large state sizes: the
+// forward step's layout (it recomputes the weights), the reverse step's
+// buffers, and for the chain the weights before every chunk and after the
+// last ([C+1][3][d h] FP32).
+struct LargeAmuBwdLayout {
+  LargeAmuLayout f;
+  size_t dOn, Ydot, dq, dk, dv, S, S1, S2, Zd3, Sd, Hdot, T2, dHh, aZ1, aZ3, aZd1, aZd3, Wnop[3], Wh[3], Whop[3],
+      tot[3], wlist, total;
+};
+LargeAmuBwdLayout large_amu_bwd_layout(const Shape& s, int64_t n_tokens, int sync) {
+  LargeAmuBwdLayout L{};
+  L.f = large_amu_layout(s);
+  const size_t op = s.mma_bf16 ? 2 : 4;
+  const size_t M = (size_t)s.Mrows, d = (size_t)s.d, h = (size_t)s.h;
+  size_t off = L.f.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  L.dOn = take(M * d * op);
+  L.Ydot = take(M * d * 4);
+  L.dq = take(M * d * 4);
+  L.dk = take(M * d * 4);
+  L.dv = take(M * d * 4);
+  for (size_t* b : {&L.S, &L.S1, &L.S2, &L.Zd3, &L.Sd, &L.Hdot, &L.T2, &L.dHh, &L.aZ1, &L.aZ3, &L.aZd1, &L.aZd3})
+    *b = take(M * h * op);
+  for (int m = 0; m < 3; ++m) {
+    L.Wnop[m] = take(d * h * op);
+    L.Wh[m] = take(d * h * 4);
+    L.Whop[m] = take(d * h * op);
+    L.tot[m] = take(d * h * 4);
+  }
+  const int64_t C = (n_tokens + s.M - 1) / s.M;
+  L.wlist = take(sync == TTT_SYNC_CHAIN ? (size_t)(C + 1) * 3 * d * h * 4 : 0);
+  L.total = off;
+  return L;
+}
+
 struct WsLayout {
   size_t sync, partial, partial_loss, pp, adj, wlast, prep, fin, deta_seq, total;
   int64_t slot_cap;
@@ -1406,6 +1445,134 @@ ttt_status_t run_amu_large(const ttt_problem_t* p, const Shape& S, int sync, con
   return TTT_OK;
 }
 
+// The paper's unit in reverse at large state sizes, per head.  Chain: the
+// weights before every chunk recomputed with forward steps (W_0 .. W_C), then
+// for c = C-1 .. 0 the apply adjoint of chunk c at W_{c+1} and its update
+// adjoint at W_c, carrying the adjoint of the weights.  GCS: W* recomputed,
+// the apply adjoint of every chunk at W*, then every chunk's update adjoint
+// at W0 against that fixed adjoint, the weight terms added to a total that
+// starts at it.
+ttt_status_t run_amu_bwd_large(const ttt_problem_t* p, const Shape& S, int sync, const void* Q, const void* K,
+                               const void* V, const float* eta_tok, const float* W1_0, const float* W2_0,
+                               const float* W3_0, const void* dO, void* dQ, void* dK, void* dV, float* deta_tok,
+                               float* dW1_0, float* dW2_0, float* dW3_0, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t N = p->n_tokens, M = S.M, dh = S.dh(), H = S.H;
+  const LargeAmuBwdLayout L = large_amu_bwd_layout(S, N, sync);
+  if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+  const int64_t C = (N + M - 1) / M;
+  const size_t iob = S.io_bf16 ? 2 : 4;
+  if (!launched([&] { return launch_zero_words(at<uint32_t>(ws, L.f.sync) + SYNC_ERR, 1, st); })) return TTT_EHIP;
+  float* Wm[3] = {at<float>(ws, L.f.W1), at<float>(ws, L.f.W2), at<float>(ws, L.f.W3)};
+  const size_t Wo[3] = {L.f.W1op, L.f.W2op, L.f.W3op};
+  const float* W0[3] = {W1_0, W2_0, W3_0};
+  float* dW0[3] = {dW1_0, dW2_0, dW3_0};
+  float* wl = at<float>(ws, L.wlist);
+  auto cast = [&](const float* src, size_t off) {
+    return launched([&] { return launch_large_cast(src, at<char>(ws, off), dh, S.mma_bf16, st); });
+  };
+  auto copy = [&](float* dst, const float* src) {
+    return hipMemcpyAsync(dst, src, dh * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  };
+  for (int64_t hd = 0; hd < H; ++hd) {
+    auto chunk_off = [&](int64_t c) { return (c * M * S.stride_tok + hd * S.stride_head) * (int64_t)iob; };
+    auto rows = [&](int64_t c) { return (int32_t)std::min<int64_t>(M, N - c * M); };
+    // a forward step of chunk c (the gradient and the update, no apply)
+    auto fwd_step = [&](int64_t c, bool write_op) {
+      LargeAmuArgs a{};
+      a.K = static_cast<const char*>(K) + chunk_off(c);
+      a.V = static_cast<const char*>(V) + chunk_off(c);
+      a.Q = static_cast<const char*>(Q) + chunk_off(c);
+      a.O = nullptr;
+      a.stride_tok = S.stride_tok;
+      a.eta = eta_tok + c * M * H + hd;
+      a.eta_stride = H;
+      a.flags = p->flags;
+      a.rows = rows(c); a.d = S.d; a.h = S.h;
+      a.grad = 1; a.write_op = write_op ? 1 : 0;
+      a.Kn = at<char>(ws, L.f.Kn); a.Qn = at<char>(ws, L.f.Qn); a.E = at<char>(ws, L.f.E); a.Vn = at<float>(ws, L.f.Vn);
+      a.Z3 = at<char>(ws, L.f.Z3); a.Hd = at<char>(ws, L.f.Hd); a.G1 = at<char>(ws, L.f.G1); a.G3 = at<char>(ws, L.f.G3);
+      a.D1 = at<char>(ws, L.f.D1); a.D3 = at<char>(ws, L.f.D3);
+      a.W1 = Wm[0]; a.W2 = Wm[1]; a.W3 = Wm[2];
+      a.W1op = at<char>(ws, Wo[0]); a.W2op = at<char>(ws, Wo[1]); a.W3op = at<char>(ws, Wo[2]);
+      return launched([&] { return launch_large_amu_step(a, S.io_bf16, S.mma_bf16, st); });
+    };
+    // the reverse step of chunk c with W (operand copies in Wo) and W' (in Wnop)
+    auto bwd_step = [&](int64_t c, bool apply, bool update, float* const* acc, bool acc_op) {
+      const int64_t off = chunk_off(c);
+      LargeAmuBwdArgs b{};
+      b.K = static_cast<const char*>(K) + off;
+      b.V = static_cast<const char*>(V) + off;
+      b.Q = static_cast<const char*>(Q) + off;
+      b.dO = static_cast<const char*>(dO) + off;
+      b.dQ = static_cast<char*>(dQ) + off;
+      b.dK = static_cast<char*>(dK) + off;
+      b.dV = static_cast<char*>(dV) + off;
+      b.stride_tok = S.stride_tok;
+      b.eta = eta_tok + c * M * H + hd;
+      b.deta = deta_tok + c * M * H + hd;
+      b.eta_stride = H;
+      b.flags = p->flags;
+      b.rows = rows(c); b.d = S.d; b.h = S.h;
+      b.apply = apply ? 1 : 0; b.update = update ? 1 : 0;
+      b.Kn = at<char>(ws, L.f.Kn); b.Qn = at<char>(ws, L.f.Qn); b.E = at<char>(ws, L.f.E);
+      b.dOn = at<char>(ws, L.dOn);
+      b.Vn = at<float>(ws, L.f.Vn); b.Ydot = at<float>(ws, L.Ydot);
+      b.dq = at<float>(ws, L.dq); b.dk = at<float>(ws, L.dk); b.dv = at<float>(ws, L.dv);
+      b.Z3 = at<char>(ws, L.f.Z3); b.Hd = at<char>(ws, L.f.Hd);
+      b.S = at<char>(ws, L.S); b.S1 = at<char>(ws, L.S1); b.S2 = at<char>(ws, L.S2); b.Zd3 = at<char>(ws, L.Zd3);
+      b.Sd = at<char>(ws, L.Sd); b.Hdot = at<char>(ws, L.Hdot); b.T2 = at<char>(ws, L.T2); b.dHh = at<char>(ws, L.dHh);
+      b.aZ1 = at<char>(ws, L.aZ1); b.aZ3 = at<char>(ws, L.aZ3); b.aZd1 = at<char>(ws, L.aZd1);
+      b.aZd3 = at<char>(ws, L.aZd3);
+      for (int m = 0; m < 3; ++m) {
+        b.Wop[m] = at<char>(ws, Wo[m]);
+        b.Wnop[m] = at<char>(ws, L.Wnop[m]);
+        b.Wh[m] = at<float>(ws, L.Wh[m]);
+        b.Whop[m] = at<char>(ws, L.Whop[m]);
+        b.Acc[m] = acc[m];
+        b.Accop[m] = acc_op ? at<char>(ws, L.Whop[m]) : nullptr;
+      }
+      return launched([&] { return launch_large_amu_bwd_step(b, S.io_bf16, S.mma_bf16, st); });
+    };
+    float* Wh[3] = {at<float>(ws, L.Wh[0]), at<float>(ws, L.Wh[1]), at<float>(ws, L.Wh[2])};
+    float* tot[3] = {at<float>(ws, L.tot[0]), at<float>(ws, L.tot[1]), at<float>(ws, L.tot[2])};
+    for (int m = 0; m < 3; ++m)
+      if (!launched([&] { return launch_large_zero(Wh[m], dh, st); }) || !cast(Wh[m], L.Whop[m])) return TTT_EHIP;
+    for (int m = 0; m < 3; ++m)
+      if (!copy(Wm[m], W0[m] + hd * dh) || !cast(Wm[m], Wo[m])) return TTT_EHIP;
+    float* const* result = Wh;
+    if (sync == TTT_SYNC_CHAIN) {
+      auto wl_at = [&](int64_t c, int m) { return wl + (c * 3 + m) * dh; };
+      for (int m = 0; m < 3; ++m)
+        if (!copy(wl_at(0, m), Wm[m])) return TTT_EHIP;
+      for (int64_t c = 0; c < C; ++c) {
+        if (!fwd_step(c, true)) return TTT_EHIP;
+        for (int m = 0; m < 3; ++m)
+          if (!copy(wl_at(c + 1, m), Wm[m])) return TTT_EHIP;
+      }
+      for (int64_t c = C - 1; c >= 0; --c) {
+        for (int m = 0; m < 3; ++m)
+          if (!cast(wl_at(c + 1, m), L.Wnop[m]) || !cast(wl_at(c, m), Wo[m])) return TTT_EHIP;
+        if (!bwd_step(c, true, true, Wh, true)) return TTT_EHIP;
+      }
+    } else {
+      for (int64_t c = 0; c < C; ++c)
+        if (!fwd_step(c, false)) return TTT_EHIP;
+      for (int m = 0; m < 3; ++m)
+        if (!cast(Wm[m], L.Wnop[m])) return TTT_EHIP;
+      for (int64_t c = 0; c < C; ++c)
+        if (!bwd_step(c, true, false, tot, false)) return TTT_EHIP;
+      for (int m = 0; m < 3; ++m)
+        if (!copy(tot[m], Wh[m]) || !cast(W0[m] + hd * dh, Wo[m])) return TTT_EHIP;
+      for (int64_t c = 0; c < C; ++c)
+        if (!bwd_step(c, false, true, tot, false)) return TTT_EHIP;
+      if (C > 0) result = tot;
+    }
+    for (int m = 0; m < 3; ++m)
+      if (!copy(dW0[m] + hd * dh, result[m])) return TTT_EHIP;
+  }
+  return TTT_OK;
+}
+
 // Reverse mode of the paper's memory unit.  Workspace: shard partials, the
 // carried adjoint Wh [H][3dh], the weights the backward needs ([C+1][H][3dh]
 // for the chain: every W_c, recomputed; [1][H][3dh] for GCS: W*), and three
@@ -1792,7 +1959,7 @@ ttt_status_t ttt_amu_fwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
 size_t ttt_amu_bwd_workspace_bytes(const ttt_problem_t* p, int32_t sync) {
   Shape S{};
   if (check_problem(p, &S) != TTT_OK || (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS)) return 0;
-  if (S.large) return 0;
+  if (S.large) return large_amu_bwd_layout(S, p->n_tokens, sync).total;
   return amu_bwd_ws_layout(S, p->n_tokens, sync).total;
 }
 
@@ -1804,7 +1971,6 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
     Shape S{};
     const ttt_status_t e = check_problem(p, &S);
     if (e != TTT_OK) return e;
-    if (S.large) return TTT_ENOTSUP;  // large state sizes: forward only
     if (sync != TTT_SYNC_CHAIN && sync != TTT_SYNC_GCS) return TTT_EINVAL;
     if (p->flags & (TTT_SAVE_CKPT | TTT_EMIT_LOSS)) return TTT_ENOTSUP;
     if (!W1_0 || !W2_0 || !W3_0 || !dW1_0 || !dW2_0 || !dW3_0) return TTT_EINVAL;
@@ -1814,6 +1980,9 @@ ttt_status_t ttt_amu_bwd(const ttt_problem_t* p, int32_t sync, const void* Q, co
                           (const void*)W2_0, (const void*)W3_0, (const void*)dW1_0, (const void*)dW2_0,
                           (const void*)dW3_0})
       if (q && !aligned16(q)) return TTT_EINVAL;
+    if (S.large)
+      return run_amu_bwd_large(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, dO, dQ, dK, dV, deta_tok, dW1_0,
+                               dW2_0, dW3_0, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
     return run_amu_bwd(p, S, sync, Q, K, V, eta_tok, W1_0, W2_0, W3_0, dO, dQ, dK, dV, deta_tok, dW1_0, dW2_0,
                        dW3_0, ws, ws_bytes, static_cast<hipStream_t>(hip_stream));
   } catch (...) {

@@ -105,6 +105,55 @@ struct LargeBwdArgs {
   float* deta;        // this head's running d/d eta (one float)
 };
 hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
+// Reverse step of one chunk of the paper's memory unit at large state sizes
+// (apply adjoint at W' = W_{c+1} and/or update adjoint at W = W_c along the
+// adjoint Wh of W'; weight terms of the update adjoint added to Acc).
+struct LargeAmuBwdArgs {
+  const void* K;  // first token of the chunk, head offset applied (io type)
+  const void* V;
+  const void* Q;
+  const void* dO;
+  void* dQ;
+  void* dK;
+  void* dV;
+  int64_t stride_tok;
+  const float* eta;    // step size of the chunk's first token for this head
+  float* deta;         // its derivative (same layout)
+  int64_t eta_stride;  // between consecutive tokens (the head count)
+  uint32_t flags;
+  int32_t rows, d, h;
+  int32_t apply, update;
+  void* Kn;      // [rows][d] operand type
+  void* Qn;
+  void* E;
+  void* dOn;
+  float* Vn;     // [rows][d] FP32
+  float* Ydot;
+  float* dq;
+  float* dk;
+  float* dv;
+  void* Z3;      // [rows][h] operand type
+  void* S;
+  void* S1;
+  void* S2;
+  void* Hd;
+  void* Zd3;
+  void* Sd;
+  void* Hdot;
+  void* T2;
+  void* dHh;
+  void* aZ1;
+  void* aZ3;
+  void* aZd1;
+  void* aZd3;
+  const void* Wop[3];   // W (W1, W2, W3 operand copies)
+  const void* Wnop[3];  // W'
+  float* Wh[3];         // adjoint of W': FP32 masters and operand copies
+  void* Whop[3];
+  float* Acc[3];        // where the update adjoint's weight terms go, and
+  void* Accop[3];       // their operand copies (nullable)
+};
+hipError_t launch_large_amu_bwd_step(const LargeAmuBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st);
 // Fill n floats with zero.
 hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st);
 // dst[i] += src[i] for n floats.

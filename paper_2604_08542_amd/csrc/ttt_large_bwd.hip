@@ -147,18 +147,20 @@ struct EpPut : EpBase {
     put(out + (int64_t)r * ld + c, v);
   }
 };
-// Carried adjoint: Wh += G (FP32 master), then its operand copy (nullable:
-// the master only, while further terms are still to be added).
+// Carried adjoint: Wh += G (or -= G) in the FP32 master, then its operand
+// copy (nullable: the master only, while further terms are still to be
+// added).
 template <typename T>
 struct EpAcc : EpBase {
   float* w;
   T* wop;
   int ld;
+  float sign = 1.0f;  // -1: the term is subtracted
   typedef float In;
   __device__ __forceinline__ float load(int r, int c) const { return w[(int64_t)r * ld + c]; }
   __device__ __forceinline__ void operator()(int r, int c, float g, float wv) {
     const int64_t i = (int64_t)r * ld + c;
-    const float wn = wv + g;
+    const float wn = fmaf(sign, g, wv);
     w[i] = wn;
     if (wop) put(wop + i, wn);
   }
@@ -444,6 +446,273 @@ hipError_t step_t(const LargeBwdArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ the paper's unit
+// Reverse step of one chunk of the SwiGLU unit with the dot-product loss
+// (Supp. A; Sec. 4.2 Eq. 8-10).  With W = W_c, W' = W_{c+1}, the adjoint Wh
+// of W' and E_i = -eta_i v_i:
+//   apply    Zq3 = Q W3', Zq1 = Q W1' -> Hq = s(Zq1) Zq3;  dHq = dO W2'^T
+//            -> dZq1 = dHq Zq3 s'(Zq1), dZq3 = dHq s(Zq1);
+//            Wh1 += Q^T dZq1, Wh2 += Hq^T dO, Wh3 += Q^T dZq3;
+//            dq = dZq1 W1'^T + dZq3 W3'^T
+//   update   the gradient G of L = sum_i <f_W(k_i), E_i> enters W_{c+1} = W - G,
+//            so the adjoint of W gains -(dG/dW)^T Wh, the gradient of the
+//            derivative of L along Wh (tangents Zd1 = K Wh1, Zd3 = K Wh3,
+//            Sd = s'(Z1) Zd1, Hdot = Sd Z3 + s(Z1) Zd3, Ydot = Hdot W2 + Hd Wh2):
+//            dH = E W2^T, dHh = E Wh2^T;  aSd = dH Z3, aZ3 = dH Sd + dHh S,
+//            aS = dH Zd3 + dHh Z3, aZd3 = dH S, aZd1 = aSd s'(Z1),
+//            aZ1 = aSd s''(Z1) Zd1 + aS s'(Z1);
+//            W1 -= K^T aZ1, W2 -= Hdot^T E, W3 -= K^T aZ3;
+//            dk = -(aZ1 W1^T + aZ3 W3^T + aZd1 Wh1^T + aZd3 Wh3^T);
+//            dv_i = eta_i Ydot_i, deta_i = <v_i, Ydot_i>
+namespace amu {
+
+// Z1 -> S = s(Z1), S1 = s'(Z1), S2 = s''(Z1), Hd = S Z3 (Z3 loaded).
+template <typename T>
+struct EpZ1 : EpBase {
+  const T* z3;
+  T* sv;
+  T* s1;
+  T* s2;
+  T* hd;
+  int ld, rows;
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float z, T z3v) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    float sg;
+    const float a = silu_sig(z, sg);
+    put(sv + i, a);
+    put(s1 + i, fmaf(a, 1.0f - sg, sg));
+    put(s2 + i, sg * (1.0f - sg) * fmaf(z, 1.0f - 2.0f * sg, 2.0f));
+    put(hd + i, a * (float)z3v);
+  }
+};
+// Zd1 = K Wh1 -> Sd = S1 Zd1, Hdot = Sd Z3 + S Zd3, T2 = S2 Zd1.
+template <typename T>
+struct EpZd1 : EpBase {
+  const T* s1;
+  const T* z3;
+  const T* sv;
+  const T* zd3;
+  const T* s2;
+  T* sd;
+  T* hdot;
+  T* t2;
+  int ld, rows;
+  struct In {
+    T s1, z3, s, zd3, s2;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {s1[i], z3[i], sv[i], zd3[i], s2[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float zd1, In x) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    const float sdv = (float)x.s1 * zd1;
+    put(sd + i, sdv);
+    put(hdot + i, fmaf(sdv, (float)x.z3, (float)x.s * (float)x.zd3));
+    put(t2 + i, (float)x.s2 * zd1);
+  }
+};
+// dH = E W2^T with dHh = E Wh2^T loaded: the adjoints aZ1, aZ3, aZd1, aZd3.
+template <typename T>
+struct EpAdj : EpBase {
+  const T* z3;
+  const T* sd;
+  const T* sv;
+  const T* zd3;
+  const T* dhh;
+  const T* s1;
+  const T* t2;
+  T* az1;
+  T* az3;
+  T* azd1;
+  T* azd3;
+  int ld, rows;
+  struct In {
+    T z3, sd, s, zd3, dhh, s1, t2;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f), T(0.f), T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {z3[i], sd[i], sv[i], zd3[i], dhh[i], s1[i], t2[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float dh, In x) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    const float z3v = (float)x.z3, sdv = (float)x.sd, s = (float)x.s, zd3v = (float)x.zd3, dhh = (float)x.dhh,
+                s1 = (float)x.s1;
+    const float asd = dh * z3v;
+    const float as = fmaf(dh, zd3v, dhh * z3v);
+    put(az3 + i, fmaf(dh, sdv, dhh * s));
+    put(azd3 + i, dh * s);
+    put(azd1 + i, asd * s1);
+    put(az1 + i, fmaf(asd, (float)x.t2, as * s1));
+  }
+};
+// Apply: Zq1 -> Hq = s(Zq1) Zq3, F1 = Zq3 s'(Zq1), F3 = s(Zq1) (Zq3 loaded).
+template <typename T>
+struct EpQ1 : EpBase {
+  const T* z3;
+  T* hq;
+  T* f1;
+  T* f3;
+  int ld, rows;
+  typedef T In;
+  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
+  __device__ __forceinline__ void operator()(int r, int c, float z, T z3r) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    float sg;
+    const float a = silu_sig(z, sg);
+    const float z3v = (float)z3r;
+    put(hq + i, a * z3v);
+    put(f1 + i, z3v * fmaf(a, 1.0f - sg, sg));
+    put(f3 + i, a);
+  }
+};
+// dHq = dO W2'^T -> dZq1 = dHq F1, dZq3 = dHq F3.
+template <typename T>
+struct EpQ2 : EpBase {
+  const T* f1;
+  const T* f3;
+  T* d1;
+  T* d3;
+  int ld, rows;
+  struct In {
+    T a, b;
+  };
+  __device__ __forceinline__ In load(int r, int c) const {
+    if (r >= rows) return {T(0.f), T(0.f)};
+    const int64_t i = (int64_t)r * ld + c;
+    return {f1[i], f3[i]};
+  }
+  __device__ __forceinline__ void operator()(int r, int c, float v, In f) {
+    if (r >= rows) return;
+    const int64_t i = (int64_t)r * ld + c;
+    put(d1 + i, v * (float)f.a);
+    put(d3 + i, v * (float)f.b);
+  }
+};
+
+// E = -eta_i Vn_i (operand type) of the chunk's rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_e(T* e, const float* vn, const float* eta, int64_t eta_stride, int rows,
+                                           int d) {
+  const int64_t n = (int64_t)rows * d;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    e[i] = (T)(-eta[(i / d) * eta_stride] * vn[i]);
+}
+
+// Per token: dv = eta_i Ydot_i, deta_i = <v_i, Ydot_i> (one wave per token).
+__global__ __launch_bounds__(256) void k_ydot(LargeAmuBwdArgs p) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (row >= p.rows) return;
+  const float et = p.eta[(int64_t)row * p.eta_stride];
+  float s = 0.f;
+  for (int c = 4 * l; c < p.d; c += 256) {
+    const int64_t i = (int64_t)row * p.d + c;
+    const f32x4 y = *reinterpret_cast<const f32x4*>(p.Ydot + i);
+    const f32x4 v = *reinterpret_cast<const f32x4*>(p.Vn + i);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s = fmaf(v[e], y[e], s);
+    *reinterpret_cast<f32x4*>(p.dv + i) = et * y;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (l == 0) p.deta[(int64_t)row * p.eta_stride] = s;
+}
+
+template <typename T, typename IOT>
+hipError_t step_t(const LargeAmuBwdArgs& a, hipStream_t st) {
+  const int M = a.rows, d = a.d, h = a.h;
+  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;
+  const int mt = (M + BMT - 1) / BMT;
+  auto P = [](void* q) { return static_cast<T*>(q); };
+  auto C = [](const void* q) { return static_cast<const T*>(q); };
+  T* Kn = P(a.Kn);
+  T* Qn = P(a.Qn);
+  T* E = P(a.E);
+  T* dOn = P(a.dOn);
+  T *Z3 = P(a.Z3), *Sv = P(a.S), *S1 = P(a.S1), *S2 = P(a.S2), *Hd = P(a.Hd), *Zd3 = P(a.Zd3), *Sd = P(a.Sd),
+    *Hdot = P(a.Hdot), *T2 = P(a.T2), *dHh = P(a.dHh), *aZ1 = P(a.aZ1), *aZ3 = P(a.aZ3), *aZd1 = P(a.aZd1),
+    *aZd3 = P(a.aZd3);
+  const T *W1 = C(a.Wop[0]), *W2 = C(a.Wop[1]), *W3 = C(a.Wop[2]);
+  const T *W1n = C(a.Wnop[0]), *W2n = C(a.Wnop[1]), *W3n = C(a.Wnop[2]);
+  T *Wh1o = P(a.Whop[0]), *Wh2o = P(a.Whop[1]), *Wh3o = P(a.Whop[2]);
+  const dim3 gh(h / BN, mt), gd(d / BN, mt), gwh(h / BN, d / BMW), gwd(d / BN, h / BMW), nt(NTH);
+  LargeNormArgs na{a.K, a.V, a.Q, a.stride_tok, a.flags, M, d, a.Kn, a.Vn, a.Qn};
+  const hipError_t en = launch_large_norm(na, std::is_same_v<IOT, bf16>, std::is_same_v<T, bf16>, st);
+  if (en != hipSuccess) return en;
+  if (a.apply) {
+    hipLaunchKernelGGL((k_rows<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, static_cast<const IOT*>(a.dO),
+                       a.stride_tok, dOn, M, d);
+    EpPut<T> q3{{}, Z3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Qn, d, M, W3n, h, d, d, q3);
+    EpQ1<T> q1{{}, Z3, Hd, S1, Sv, h, M};  // Hq, F1, F3
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpQ1<T>>), gh, nt, 0, st, Qn, d, M, W1n, h, d, d, q1);
+    EpQ2<T> q2{{}, S1, Sv, aZ1, aZ3, h, M};  // dZq1, dZq3
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpQ2<T>>), gh, nt, 0, st, dOn, d, M, W2n, d, h, d, q2);
+    EpAcc<T> w1{{}, a.Wh[0], Wh1o, h};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwh, nt, 0, st, Qn, d, M, aZ1, h, M, M, w1);
+    EpAcc<T> w2{{}, a.Wh[1], Wh2o, d};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwd, nt, 0, st, Hd, h, M, dOn, d, M, M, w2);
+    EpAcc<T> w3{{}, a.Wh[2], Wh3o, h};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwh, nt, 0, st, Qn, d, M, aZ3, h, M, M, w3);
+    EpF32<false> g1{{}, a.dq, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, aZ1, h, M, W1n, h, d, h, g1);
+    EpF32<true> g3{{}, a.dq, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, aZ3, h, M, W3n, h, d, h, g3);
+  }
+  if (a.update) {
+    EpPut<T> u1{{}, Z3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Kn, d, M, W3, h, d, d, u1);
+    EpZ1<T> u2{{}, Z3, Sv, S1, S2, Hd, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpZ1<T>>), gh, nt, 0, st, Kn, d, M, W1, h, d, d, u2);
+    EpPut<T> u3{{}, Zd3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Kn, d, M, Wh3o, h, d, d, u3);
+    EpZd1<T> u4{{}, S1, Z3, Sv, Zd3, S2, Sd, Hdot, T2, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpZd1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, u4);
+    const int64_t ne = (int64_t)M * d;
+    hipLaunchKernelGGL(k_e<T>, dim3((unsigned)std::min<int64_t>((ne + 255) / 256, 4096)), dim3(256), 0, st, E, a.Vn,
+                       a.eta, a.eta_stride, M, d);
+    EpF32<false> y1{{}, a.Ydot, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpF32<false>>), gd, nt, 0, st, Hdot, h, M, W2, d, h, h, y1);
+    EpF32<true> y2{{}, a.Ydot, d, M, 1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpF32<true>>), gd, nt, 0, st, Hd, h, M, Wh2o, d, h, h, y2);
+    hipLaunchKernelGGL(k_ydot, dim3((M + 3) / 4), dim3(256), 0, st, a);
+    EpPut<T> u8{{}, dHh, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPut<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, u8);
+    EpAdj<T> u9{{}, Z3, Sd, Sv, Zd3, dHh, S1, T2, aZ1, aZ3, aZd1, aZd3, h, M};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpAdj<T>>), gh, nt, 0, st, E, d, M, W2, d, h, d, u9);
+    // dk (uses Wh before the weight terms below change it, in the chain)
+    EpF32<false> k1{{}, a.dk, d, M, -1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<false>>), gd, nt, 0, st, aZ1, h, M, W1, h, d, h, k1);
+    EpF32<true> k3{{}, a.dk, d, M, -1.0f};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, aZ3, h, M, W3, h, d, h, k3);
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, aZd1, h, M, Wh1o, h, d, h, k3);
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, aZd3, h, M, Wh3o, h, d, h, k3);
+    // the weight terms: W1 -= K^T aZ1, W2 -= Hdot^T E, W3 -= K^T aZ3
+    EpAcc<T> a1{{}, a.Acc[0], P(a.Accop[0]), h, -1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwh, nt, 0, st, Kn, d, M, aZ1, h, M, M, a1);
+    EpAcc<T> a2{{}, a.Acc[1], P(a.Accop[1]), d, -1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwd, nt, 0, st, Hdot, h, M, E, d, M, M, a2);
+    EpAcc<T> a3{{}, a.Acc[2], P(a.Accop[2]), h, -1.0f};
+    hipLaunchKernelGGL((k_gemm<T, MNMAJ, MNMAJ, BMW, EpAcc<T>>), gwh, nt, 0, st, Kn, d, M, aZ3, h, M, M, a3);
+  }
+  // gradients of the raw rows: only the parts that ran
+  LargeBwdArgs nb{};
+  nb.K = a.K; nb.V = a.V; nb.Q = a.Q; nb.dQ = a.dQ; nb.dK = a.dK; nb.dV = a.dV;
+  nb.stride_tok = a.stride_tok; nb.flags = a.flags; nb.rows = M; nb.d = d;
+  nb.dq = a.dq; nb.dk = a.dk; nb.dv = a.dv; nb.apply = a.apply; nb.update = a.update;
+  hipLaunchKernelGGL(k_norm_bwd<IOT>, dim3((M + 3) / 4), dim3(256), 0, st, nb);
+  return hipGetLastError();
+}
+
+}  // namespace amu
 }  // namespace bwd
 }  // namespace large
 
@@ -451,6 +720,12 @@ hipError_t launch_large_bwd_step(const LargeBwdArgs& a, bool io_bf16, bool mma_b
   using namespace large::bwd;
   if (mma_bf16) return io_bf16 ? step_t<bf16, bf16>(a, st) : step_t<bf16, float>(a, st);
   return step_t<float, float>(a, st);
+}
+
+hipError_t launch_large_amu_bwd_step(const LargeAmuBwdArgs& a, bool io_bf16, bool mma_bf16, hipStream_t st) {
+  using namespace large::bwd;
+  if (mma_bf16) return io_bf16 ? amu::step_t<bf16, bf16>(a, st) : amu::step_t<bf16, float>(a, st);
+  return amu::step_t<float, float>(a, st);
 }
 
 hipError_t launch_large_zero(float* p, int64_t n, hipStream_t st) {

@@ -96,15 +96,40 @@ def test_large_amu_deterministic(gpu):
         assert torch.equal(a[k], b[k]), k
 
 
-def test_large_amu_empty_stream_and_reverse_mode(gpu):
-    from paper_2604_08542_amd import _lib as L
+def test_large_amu_empty_stream(gpu):
     x, dev = dev_inputs(0, 1, 256, 512, 300, 100.0, seed=7, io="f32")
     r = run(dev, 300, "chain", False)
     assert r["O"].shape == (0, 1, 256)
     for k, w in (("W1_T", "W1"), ("W2_T", "W2"), ("W3_T", "W3")):
         assert torch.equal(r[k], dev[w]), k
-    # the reverse mode is built for the on-chip state sizes only
-    _, dev = dev_inputs(300, 1, 256, 512, 300, 100.0, seed=8, io="f32")
-    dO = torch.zeros_like(dev["Q"])
-    with pytest.raises(L.TTTError):
-        ops().amu_bwd(dev["Q"], dev["K"], dev["V"], dev["eta"], dev["W1"], dev["W2"], dev["W3"], 300, dO)
+
+
+BWD_CASES = [
+    # N, H, d, h, M, eta, io, mma_bf16, sync
+    (700, 2, 256, 512, 300, 100.0, "f32", False, "chain"),
+    (700, 2, 256, 512, 300, 100.0, "f32", False, "gcs"),
+    (700, 2, 256, 512, 300, 100.0, "bf16", True, "chain"),
+    (700, 2, 256, 512, 300, 100.0, "bf16", True, "gcs"),
+    (2748, 1, 1024, 4096, 1374, 100.0, "bf16", True, "chain"),  # the paper's state
+    (2748, 1, 1024, 4096, 1374, 100.0, "bf16", True, "gcs"),
+]
+
+
+@pytest.mark.parametrize("N,H,d,h,M,eta,io,mma,sync", BWD_CASES)
+def test_large_amu_backward_matches_oracle(gpu, N, H, d, h, M, eta, io, mma, sync):
+    # reverse mode through every inner update of the paper's unit, with the
+    # per-token step-size derivative
+    x, dev = dev_inputs(N, H, d, h, M, eta, seed=N + d + 11 + (sync == "gcs"), io=io)
+    dO = np.random.default_rng(N + 5).standard_normal((N, H, d)).astype(np.float32)
+    if io == "bf16":
+        dO = torch.from_numpy(dO).to(torch.bfloat16).float().numpy()
+    g = ops().amu_bwd(dev["Q"], dev["K"], dev["V"], dev["eta"], dev["W1"], dev["W2"], dev["W3"], M,
+                      to_dev(dO, io), sync=sync, mma_bf16=mma)
+    torch.cuda.synchronize()
+    ref = orc.ttt_backward_swiglu(x["Q"], x["K"], x["V"], x["W1"], x["W2"], x["W3"], x["eta"], M, dO, sync=sync)
+    tol = TOL["bf16" if mma or io == "bf16" else "f32"]
+    print(f"amu bwd N={N} H={H} d={d} h={h} M={M} eta={eta} io={io} mma_bf16={mma} {sync}")
+    for k in ("dQ", "dK", "dV", "dW1_0", "dW2_0", "dW3_0"):
+        check(k, host(g[k]), ref[k], tol)
+    # per-token step-size derivatives: normwise over the tokens of each head
+    check("deta_tok", host(g["deta_tok"]).T, ref["deta_tok"].T, tol, row_mult=1.0)
