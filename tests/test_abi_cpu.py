@@ -146,10 +146,16 @@ def test_amu_validation(lib):
     assert lib.ttt_amu_workspace_bytes(ctypes.byref(prob(d_hidden=96))) == 0
     # the paper's state (one head of 1024, hidden 4096): the forward takes a
     # workspace of the chunk's intermediates and three weight sets; the
-    # reverse mode is built for the on-chip sizes only
+    # reverse mode's chain form also keeps the weights before every chunk, so
+    # it grows with the chunk count, and its GCS form does not
     big = prob(n_heads=1, d_head=1024, d_hidden=4096, n_tokens=2748, chunk_tokens=1374)
-    assert lib.ttt_amu_workspace_bytes(ctypes.byref(big)) >= 6 * 1374 * 4096 * 4 + 3 * 1024 * 4096 * 4
-    assert lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(big), 0) == 0
+    longer = prob(n_heads=1, d_head=1024, d_hidden=4096, n_tokens=4 * 2748, chunk_tokens=1374)
+    fwd = lib.ttt_amu_workspace_bytes(ctypes.byref(big))
+    assert fwd >= 6 * 1374 * 4096 * 4 + 3 * 1024 * 4096 * 4
+    chain, gcs = (lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(big), s) for s in (0, 1))
+    assert gcs > fwd and chain >= gcs + 3 * 3 * 1024 * 4096 * 4
+    assert lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(longer), 0) - chain == 6 * 3 * 1024 * 4096 * 4
+    assert lib.ttt_amu_bwd_workspace_bytes(ctypes.byref(longer), 1) == gcs
     assert call(p, sync=2) == L.TTT_EINVAL
     assert call(p, eta=None) == L.TTT_EINVAL
     assert call(p, W3=None) == L.TTT_EINVAL
