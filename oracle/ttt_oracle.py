@@ -662,3 +662,41 @@ def gcm_layer_forward(X, Wqkv, Wo, alpha, W1_0, W2_0, eta, chunk_tokens, bqkv=No
     if bo is not None:
         G = G + np.asarray(bo, dtype=np.float64)
     return dict(Y=alpha * G + X, O=O, W1_T=r["W1_T"], W2_T=r["W2_T"])
+
+
+def gcm_layer_backward(X, Wqkv, Wo, alpha, W1_0, W2_0, eta, chunk_tokens, dY, bqkv=None, bo=None,
+                       norm=(True, True, True), act="silu"):
+    """Reverse mode of gcm_layer_forward for the outer loss sum <Y, dY>.
+
+    Taken back through Y = alpha * G + X, G = O Wo (+ bo), the memory unit
+    (ttt_backward above, with the adjoint dO of its output) and the
+    projection P = X Wqkv (+ bqkv):
+      dG = alpha * dY,  dalpha = sum_n G * dY,  dbo = sum_n dG,
+      dWo = O^T dG,  dO = dG Wo^T,
+      (dQ, dK, dV, dW1_0, dW2_0, deta) = the unit's reverse mode,
+      dP = [dQ | dK | dV],  dWqkv = X^T dP,  dbqkv = sum_n dP,
+      dX = dY + dP Wqkv^T.
+    Returns dict(dX, dWqkv, dbqkv, dWo, dbo, dalpha, dW1_0, dW2_0, deta); the
+    bias gradients are None where the bias is."""
+    X, Wqkv, Wo, alpha, dY = _as_f64(X, Wqkv, Wo, alpha, dY)
+    N, D = X.shape
+    H = W1_0.shape[0]
+    d = D // H
+    P = X @ Wqkv
+    if bqkv is not None:
+        P = P + np.asarray(bqkv, dtype=np.float64)
+    Q = P[:, :D].reshape(N, H, d)
+    K = P[:, D:2 * D].reshape(N, H, d)
+    V = P[:, 2 * D:].reshape(N, H, d)
+    r = ttt_forward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, norm, act)
+    O = r["O"].reshape(N, D)
+    G = O @ Wo
+    if bo is not None:
+        G = G + np.asarray(bo, dtype=np.float64)
+    dG = alpha * dY
+    dO = (dG @ Wo.T).reshape(N, H, d)
+    u = ttt_backward(Q, K, V, W1_0, W2_0, eta, chunk_tokens, dO, norm, act)
+    dP = np.concatenate([u["dQ"].reshape(N, D), u["dK"].reshape(N, D), u["dV"].reshape(N, D)], axis=1)
+    return dict(dX=dY + dP @ Wqkv.T, dWqkv=X.T @ dP, dbqkv=dP.sum(axis=0) if bqkv is not None else None,
+                dWo=O.T @ dG, dbo=dG.sum(axis=0) if bo is not None else None, dalpha=(G * dY).sum(axis=0),
+                dW1_0=u["dW1_0"], dW2_0=u["dW2_0"], deta=u["deta"])

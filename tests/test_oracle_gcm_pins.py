@@ -97,3 +97,61 @@ def test_one_chunk_against_autograd_inner_step():
     bsw = x["bqkv"].copy()
     bsw[D:2 * D], bsw[2 * D:] = x["bqkv"][2 * D:], x["bqkv"][D:2 * D]
     assert np.max(np.abs(layer(x, chunk_tokens=N, Wqkv=Wsw, bqkv=bsw)["Y"] - ref)) > 1e-6
+
+
+def test_layer_backward_against_central_differences():
+    # the directional derivative of <Y, dY> along a random direction in every
+    # input at once, by central differences of the forward, against the
+    # inner product of that direction with the reverse mode's gradients
+    x = make_layer_inputs(N, H, d, h, seed=5)
+    D = H * d
+    rng = np.random.default_rng(6)
+    dY = rng.standard_normal((N, D))
+    names = ("X", "Wqkv", "Wo", "alpha", "W1", "W2", "bqkv", "bo")
+    base = {k: x[k].astype(np.float64) for k in names}
+    base["eta"] = ETA
+    dirs = {k: rng.standard_normal(np.shape(base[k])) for k in names}
+    dirs["eta"] = 0.7
+
+    def objective(t):
+        a = {k: base[k] + t * dirs[k] for k in base}
+        y = orc.gcm_layer_forward(a["X"], a["Wqkv"], a["Wo"], a["alpha"], a["W1"], a["W2"], a["eta"], M,
+                                  bqkv=a["bqkv"], bo=a["bo"])["Y"]
+        return float(np.sum(y * dY))
+
+    eps = 1e-5
+    fd = (objective(eps) - objective(-eps)) / (2 * eps)
+    g = orc.gcm_layer_backward(base["X"], base["Wqkv"], base["Wo"], base["alpha"], base["W1"], base["W2"], ETA, M,
+                               dY, bqkv=base["bqkv"], bo=base["bo"])
+    pairs = (("dX", "X"), ("dWqkv", "Wqkv"), ("dWo", "Wo"), ("dalpha", "alpha"), ("dW1_0", "W1"), ("dW2_0", "W2"),
+             ("dbqkv", "bqkv"), ("dbo", "bo"))
+    an = sum(float(np.sum(g[gk] * dirs[k])) for gk, k in pairs) + float(np.sum(g["deta"])) * dirs["eta"]
+    assert abs(fd - an) <= 1e-7 * max(1.0, abs(fd)), (fd, an)
+    # and each input's share on its own (a dropped or misplaced term would
+    # cancel in the sum only by accident)
+    for gk, k in pairs:
+        one = {kk: (dirs[kk] if kk == k else np.zeros_like(np.asarray(dirs[kk], dtype=np.float64))) for kk in dirs}
+        one["eta"] = 0.0
+
+        def obj1(t):
+            a = {kk: base[kk] + t * one[kk] for kk in base}
+            y = orc.gcm_layer_forward(a["X"], a["Wqkv"], a["Wo"], a["alpha"], a["W1"], a["W2"], a["eta"], M,
+                                      bqkv=a["bqkv"], bo=a["bo"])["Y"]
+            return float(np.sum(y * dY))
+        fd1 = (obj1(eps) - obj1(-eps)) / (2 * eps)
+        an1 = float(np.sum(g[gk] * dirs[k]))
+        assert abs(fd1 - an1) <= 1e-7 * max(1.0, abs(fd1)), (gk, fd1, an1)
+
+
+def test_layer_backward_gate_off():
+    # alpha = 0: Y = X, so dX = dY and nothing else but dalpha is non-zero
+    x = make_layer_inputs(N, H, d, h, seed=8)
+    dY = np.random.default_rng(9).standard_normal((N, H * d))
+    g = orc.gcm_layer_backward(x["X"], x["Wqkv"], x["Wo"], np.zeros(H * d), x["W1"], x["W2"], ETA, M, dY,
+                               bqkv=x["bqkv"], bo=x["bo"])
+    assert np.array_equal(g["dX"], dY)
+    for k in ("dWqkv", "dbqkv", "dWo", "dbo", "dW1_0", "dW2_0", "deta"):
+        assert not np.any(g[k]), k
+    G = orc.gcm_layer_forward(x["X"], x["Wqkv"], x["Wo"], np.ones(H * d), x["W1"], x["W2"], ETA, M, bqkv=x["bqkv"],
+                              bo=x["bo"])["Y"] - x["X"]
+    assert np.allclose(g["dalpha"], np.sum(G * dY, axis=0), rtol=1e-12, atol=0)
