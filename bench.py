@@ -316,6 +316,16 @@ def other_forms(forms, steps, warmup):
                                                          frac=ach / PEAK[io],
                                                          note="unit 14 d h per token-head + projections 8 D^2 per "
                                                               "token"))
+                if io == "bf16":  # forward + reverse mode of the layer
+                    dY = torch.randn((N, D), generator=g, device="cuda").to(dt)
+
+                    def fbl():
+                        ops.gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, 0.05, M, out=Y, want_final=False)
+                        ops.gcm_bwd(X, Wqkv, Wo, alpha, W1, W2, 0.05, M, dY)
+                    ms = timed(fbl, 2, 1)
+                    res[f"{name}_fwd_bwd_{io}"] = dict(workload=f"{name}: {H}x{d}, h{h}, {N} tokens, chunk {M}, D {D}",
+                                                       ms_per_step=ms, tokens_per_s=N / (ms * 1e-3))
+                    del dY
                 del X, Wqkv, Wo, Y
                 torch.cuda.empty_cache()
     if "length_sweep" in forms:  # one sequence of F frames (the shape of the paper's length table)

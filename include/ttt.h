@@ -313,6 +313,31 @@ ttt_status_t ttt_gcm_fwd(const ttt_problem_t* p, const void* X, const void* Wqkv
                          const float* W2_0, void* Y, float* W1_T, float* W2_T, void* ws, size_t ws_bytes,
                          void* hip_stream);
 
+/* Reverse mode of ttt_gcm_fwd for the outer loss sum <Y, dY> (Sec. 4.1
+ * Eq. 5 and the projections of Sec. 4.2 taken back, with the memory unit's
+ * reverse mode of ttt_chunk_bwd in between):
+ *   dG = alpha * dY, dalpha = sum_n G * dY, dbo = sum_n dG, dWo = O^T dG,
+ *   dO = dG Wo^T -> the unit's reverse mode -> dQ, dK, dV, dW1_0, dW2_0, deta,
+ *   dP = [dQ | dK | dV], dWqkv = X^T dP, dbqkv = sum_n dP, dX = dY + dP Wqkv^T
+ * with G = O Wo (+ bo) and O the unit's output, both recomputed.
+ *   dY, dX     [N][D] io_dtype.
+ *   dWqkv      [D][3D] f32; dbqkv [3D] f32 (given iff bqkv is).
+ *   dWo        [D][D] f32; dbo [D] f32 (given iff bo is); dalpha [D] f32.
+ *   dW1_0, dW2_0, deta  as ttt_chunk_bwd.
+ *   ws         ws_bytes >= ttt_gcm_bwd_workspace_bytes(p): the projection,
+ *              the unit's output and adjoints ([N][3D] each, io_dtype), G
+ *              (FP32), the unit's checkpoints and its own workspace.
+ * Column sums (dalpha, dbo, dbqkv) add slabs of 256 rows, then the slabs in
+ * order; every product is a matrix-core GEMM summing its whole contraction
+ * in a fixed order, so the result is deterministic.  The [N][3D] tensors
+ * must stay below 2^31 bytes (TTT_ESHAPE).  Other errors as ttt_gcm_fwd. */
+size_t ttt_gcm_bwd_workspace_bytes(const ttt_problem_t* p);
+ttt_status_t ttt_gcm_bwd(const ttt_problem_t* p, const void* X, const void* Wqkv, const float* bqkv,
+                         const void* Wo, const float* bo, const float* alpha, const float* W1_0,
+                         const float* W2_0, const void* dY, void* dX, float* dWqkv, float* dbqkv, float* dWo,
+                         float* dbo, float* dalpha, float* dW1_0, float* dW2_0, float* deta, void* ws,
+                         size_t ws_bytes, void* hip_stream);
+
 /* Device-side status of the last call that used workspace `ws`: copies the
  * workspace's error word to *flags_host (bit 0: a barrier wait of the
  * persistent forward gave up, so that call's outputs are invalid; 0: no

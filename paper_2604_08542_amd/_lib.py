@@ -17,6 +17,7 @@ EXPORTED = ("ttt_workspace_bytes", "ttt_chunk_fwd", "ttt_chunk_bwd", "ttt_batche
             "ttt_batched_bwd", "ttt_gcs_fwd", "ttt_gcs_bwd", "ttt_amu_workspace_bytes", "ttt_amu_fwd",
             "ttt_amu_bwd_workspace_bytes", "ttt_amu_bwd",
             "ttt_chunk_fwd_noalloc", "ttt_workspace_status", "ttt_gcm_workspace_bytes", "ttt_gcm_fwd",
+            "ttt_gcm_bwd_workspace_bytes", "ttt_gcm_bwd",
             "ttt_status_string", "ttt_version")
 
 
@@ -101,6 +102,10 @@ def load(path: str = LIB_PATH):
     lib.ttt_gcm_workspace_bytes.restype = sz
     lib.ttt_gcm_fwd.argtypes = [P, vp, vp, fp, vp, fp, fp, fp, fp, vp, fp, fp, vp, sz, vp]
     lib.ttt_gcm_fwd.restype = st
+    lib.ttt_gcm_bwd_workspace_bytes.argtypes = [P]
+    lib.ttt_gcm_bwd_workspace_bytes.restype = sz
+    lib.ttt_gcm_bwd.argtypes = [P, vp, vp, fp, vp, fp, fp, fp, fp, vp, vp, fp, fp, fp, fp, fp, fp, fp, fp, vp, sz, vp]
+    lib.ttt_gcm_bwd.restype = st
     lib.ttt_workspace_status.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_uint32), vp]
     lib.ttt_workspace_status.restype = st
     lib.ttt_version.argtypes = []

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/ttt.h"
@@ -2049,6 +2050,121 @@ ttt_status_t ttt_gcm_fwd(const ttt_problem_t* p, const void* X, const void* Wqkv
     g.kind = 1; g.D = S.H * S.d; g.rows = p->n_tokens;
     g.x = X; g.w = Wo; g.bias = bo; g.alpha = alpha; g.o = o; g.y = Y;
     return launch_gcm_gemm(g, S.io_bf16, st) == hipSuccess ? TTT_OK : TTT_EHIP;
+  } catch (...) {
+    return TTT_EINVAL;
+  }
+}
+
+// Reverse mode of the layer: workspace regions.  The unit runs on views of
+// the projection P [N][3D] (Q, K, V at column offsets 0, D, 2D, token pitch
+// 3D), so its problem is the layer's with that pitch.
+struct GcmBwdLayout {
+  size_t P, O, dO, dP, dG, G, part, ckpt, unit, total;
+  ttt_problem_t pu;
+};
+static ttt_status_t gcm_bwd_layout(const ttt_problem_t* p, GcmBwdLayout* L) {
+  Shape S{};
+  size_t tb = 0, wb = 0;
+  const ttt_status_t e = gcm_check(p, &S, &tb, &wb);
+  if (e != TTT_OK) return e;
+  const int64_t N = p->n_tokens, D = (int64_t)S.H * S.d;
+  const size_t io = S.io_bf16 ? 2 : 4;
+  // the [N][3D] operands are addressed with 32-bit byte offsets
+  if ((size_t)N * 3 * D * io >= ((size_t)1 << 31)) return TTT_ESHAPE;
+  L->pu = *p;
+  L->pu.stride_tok = 3 * D;
+  L->pu.stride_head = S.d;
+  Shape Su{};
+  if (check_problem(&L->pu, &Su) != TTT_OK) return TTT_ESHAPE;
+  const size_t ub = ttt_workspace_bytes(&L->pu, 1);
+  if (!ub) return TTT_EINVAL;
+  const int64_t C = (N + S.M - 1) / S.M;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L->P = take((size_t)N * 3 * D * io);
+  L->O = take((size_t)N * 3 * D * io);
+  L->dO = take((size_t)N * 3 * D * io);
+  L->dP = take((size_t)N * 3 * D * io);
+  L->dG = take((size_t)N * D * io);
+  L->G = take((size_t)N * D * 4);
+  L->part = take((size_t)((N + 255) / 256) * 3 * D * 4);
+  L->ckpt = take((size_t)C * S.H * 2 * S.dh() * 4);
+  L->unit = take(ub);
+  L->total = off;
+  return TTT_OK;
+}
+
+size_t ttt_gcm_bwd_workspace_bytes(const ttt_problem_t* p) {
+  try {
+    GcmBwdLayout L{};
+    return gcm_bwd_layout(p, &L) == TTT_OK ? L.total : 0;
+  } catch (...) {
+    return 0;
+  }
+}
+
+ttt_status_t ttt_gcm_bwd(const ttt_problem_t* p, const void* X, const void* Wqkv, const float* bqkv, const void* Wo,
+                         const float* bo, const float* alpha, const float* W1_0, const float* W2_0, const void* dY,
+                         void* dX, float* dWqkv, float* dbqkv, float* dWo, float* dbo, float* dalpha, float* dW1_0,
+                         float* dW2_0, float* deta, void* ws, size_t ws_bytes, void* hip_stream) {
+  try {
+    GcmBwdLayout L{};
+    const ttt_status_t e = gcm_bwd_layout(p, &L);
+    if (e != TTT_OK) return e;
+    Shape S{};
+    check_problem(p, &S);
+    if (!Wqkv || !Wo || !alpha || !W1_0 || !W2_0 || !dWqkv || !dWo || !dalpha || !dW1_0 || !dW2_0 || !deta)
+      return TTT_EINVAL;
+    if ((bqkv == nullptr) != (dbqkv == nullptr) || (bo == nullptr) != (dbo == nullptr)) return TTT_EINVAL;
+    if (p->n_tokens > 0 && (!X || !dY || !dX)) return TTT_EINVAL;
+    for (const void* q : {X, Wqkv, Wo, dY, (const void*)dX, (const void*)W1_0, (const void*)W2_0, (const void*)dWqkv,
+                          (const void*)dWo, (const void*)dW1_0, (const void*)dW2_0})
+      if (q && !aligned16(q)) return TTT_EINVAL;
+    if (!ws || ws_bytes < L.total) return TTT_EWORKSPACE;
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t N = p->n_tokens, D = (int64_t)S.H * S.d;
+    const size_t io = S.io_bf16 ? 2 : 4;
+    if (N == 0) {  // no tokens: every gradient is zero, dW of the unit too
+      for (const std::pair<float*, int64_t>& z :
+           {std::pair<float*, int64_t>{dWqkv, 3 * D * D}, {dWo, D * D}, {dalpha, D}, {dbqkv, dbqkv ? 3 * D : 0},
+            {dbo, dbo ? D : 0}, {dW1_0, S.H * S.dh()}, {dW2_0, S.H * S.dh()}, {deta, S.H}})
+        if (z.second > 0 && !launched([&] { return launch_large_zero(z.first, z.second, st); })) return TTT_EHIP;
+      return TTT_OK;
+    }
+    char* b = static_cast<char*>(ws);
+    GcmBwdArgs a{};
+    a.D = (int32_t)D; a.rows = N;
+    a.X = X; a.Wqkv = Wqkv; a.bqkv = bqkv; a.Wo = Wo; a.bo = bo; a.alpha = alpha; a.dY = dY;
+    a.P = b + L.P; a.O = b + L.O; a.G = reinterpret_cast<float*>(b + L.G); a.dG = b + L.dG; a.dO = b + L.dO;
+    a.dP = b + L.dP; a.part = reinterpret_cast<float*>(b + L.part);
+    a.dX = dX; a.dWqkv = dWqkv; a.dbqkv = dbqkv; a.dWo = dWo; a.dbo = dbo; a.dalpha = dalpha;
+    // the projection, then the unit's forward with its checkpoints
+    a.phase = 0;
+    if (launch_gcm_bwd(a, S.io_bf16, st) != hipSuccess) return TTT_EHIP;
+    char* P = b + L.P;
+    char* dP = b + L.dP;
+    float* ckpt = reinterpret_cast<float*>(b + L.ckpt);
+    ttt_problem_t pf = L.pu;
+    pf.flags = (p->flags & ~(uint32_t)TTT_EMIT_LOSS) | TTT_SAVE_CKPT;
+    ttt_status_t eu = ttt_chunk_fwd(&pf, P, P + D * io, P + 2 * D * io, W1_0, W2_0, b + L.O, nullptr, nullptr, ckpt,
+                                    nullptr, b + L.unit, ws_bytes - L.unit, hip_stream);
+    if (eu != TTT_OK) return eu;
+    // the gate and the output projection
+    a.phase = 1;
+    if (launch_gcm_bwd(a, S.io_bf16, st) != hipSuccess) return TTT_EHIP;
+    // the unit's reverse mode, its adjoints of Q, K, V into dP
+    ttt_problem_t pb = L.pu;
+    pb.flags = p->flags & ~(uint32_t)(TTT_EMIT_LOSS | TTT_SAVE_CKPT);
+    eu = ttt_chunk_bwd(&pb, P, P + D * io, P + 2 * D * io, W1_0, W2_0, ckpt, b + L.dO, dP, dP + D * io,
+                       dP + 2 * D * io, dW1_0, dW2_0, deta, b + L.unit, ws_bytes - L.unit, hip_stream);
+    if (eu != TTT_OK) return eu;
+    // the query-key-value projection
+    a.phase = 2;
+    return launch_gcm_bwd(a, S.io_bf16, st) == hipSuccess ? TTT_OK : TTT_EHIP;
   } catch (...) {
     return TTT_EINVAL;
   }

@@ -210,6 +210,39 @@ struct GcmGemmArgs {
   void* y;         // kind 1 output [rows][D]
 };
 hipError_t launch_gcm_gemm(const GcmGemmArgs& a, bool io_bf16, hipStream_t st);
+// Reverse mode of the layer around the unit, in three phases around the
+// unit's own forward and reverse calls (N = rows, D features, token tensors
+// in the io type):
+//   phase 0  P = X Wqkv (+ bqkv)                      [N][3D], pitch 3D
+//   phase 1  G = O Wo (+ bo) (FP32), dG = alpha dY, dalpha = sum G dY,
+//            dbo = sum dG, dWo = O^T dG, dO = dG Wo^T  (O, dO pitch 3D)
+//   phase 2  dWqkv = X^T dP, dbqkv = sum dP, dX = dY + dP Wqkv^T   (dP pitch 3D)
+struct GcmBwdArgs {
+  int32_t phase;
+  int32_t D;
+  int64_t rows;
+  const void* X;
+  const void* Wqkv;
+  const float* bqkv;   // nullable
+  const void* Wo;
+  const float* bo;     // nullable
+  const float* alpha;
+  const void* dY;
+  void* P;             // [N][3D]
+  void* O;             // [N][3D], the first D columns used
+  float* G;            // [N][D]
+  void* dG;            // [N][D]
+  void* dO;            // [N][3D], the first D columns used
+  const void* dP;      // [N][3D]
+  float* part;         // column partial sums [ceil(N / 256)][3D]
+  void* dX;
+  float* dWqkv;        // [D][3D]
+  float* dbqkv;        // [3D], nullable
+  float* dWo;          // [D][D]
+  float* dbo;          // [D], nullable
+  float* dalpha;       // [D]
+};
+hipError_t launch_gcm_bwd(const GcmBwdArgs& a, bool io_bf16, hipStream_t st);
 hipError_t launch_large_init(const float* w1, const float* w2, float* m1, float* m2, void* o1, void* o2, int64_t n,
                              bool mma_bf16, hipStream_t st);
 hipError_t launch_fwd_step(const FwdStepArgs& a, int n_blocks, int h, bool io_bf16, bool mma_bf16, hipStream_t st);

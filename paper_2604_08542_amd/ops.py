@@ -122,14 +122,7 @@ def chunk_fwd(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False,
     return dict(O=O, W1_T=W1_T, W2_T=W2_T, ckpt=ckpt, loss=loss)
 
 
-def gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, *, bqkv=None, bo=None, norm=True, want_final=True,
-            out=None, ws=None):
-    """The layer around the memory unit over one sequence: [Q|K|V] = X Wqkv
-    (+ bqkv), O = chunked TTT forward of Q, K, V with H = W1.shape[0] heads,
-    Y = alpha * (O Wo (+ bo)) + X.  X: [N][D] (float32 or bfloat16), Wqkv
-    [D][3D] and Wo [D][D] in X's dtype, biases and alpha float32.  Returns
-    dict(Y, W1_T, W2_T)."""
-    lib = L.load()
+def _gcm_problem(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, bqkv, bo, norm):
     if X.dim() != 2 or not X.is_contiguous():
         raise ValueError("X must be a contiguous [N][D] tensor")
     N, D = X.shape
@@ -146,8 +139,19 @@ def gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, *, bqkv=None, bo=None
     for t, n in ((alpha, D), (bqkv, 3 * D), (bo, D)):
         if t is not None and (t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous()):
             raise ValueError("alpha and the biases are contiguous float32 vectors")
-    prob = L.Problem(n_heads=H, d_head=d, d_hidden=h, n_tokens=N, chunk_tokens=int(chunk_tokens), stride_tok=0,
+    return L.Problem(n_heads=H, d_head=d, d_hidden=h, n_tokens=N, chunk_tokens=int(chunk_tokens), stride_tok=0,
                      stride_head=0, eta=float(eta), flags=_flags(norm), io_dtype=_DT[X.dtype])
+
+
+def gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, *, bqkv=None, bo=None, norm=True, want_final=True,
+            out=None, ws=None):
+    """The layer around the memory unit over one sequence: [Q|K|V] = X Wqkv
+    (+ bqkv), O = chunked TTT forward of Q, K, V with H = W1.shape[0] heads,
+    Y = alpha * (O Wo (+ bo)) + X.  X: [N][D] (float32 or bfloat16), Wqkv
+    [D][3D] and Wo [D][D] in X's dtype, biases and alpha float32.  Returns
+    dict(Y, W1_T, W2_T)."""
+    lib = L.load()
+    prob = _gcm_problem(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, bqkv, bo, norm)
     Y = torch.empty_like(X) if out is None else out
     W1_T = torch.empty_like(W1) if want_final else None
     W2_T = torch.empty_like(W2) if want_final else None
@@ -160,6 +164,35 @@ def gcm_fwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, *, bqkv=None, bo=None
                          _ptr(W1), _ptr(W2), _ptr(Y), _ptr(W1_T), _ptr(W2_T), _ptr(ws), ws.numel(), _stream(X.device))
     L.check(st, "ttt_gcm_fwd")
     return dict(Y=Y, W1_T=W1_T, W2_T=W2_T)
+
+
+def gcm_bwd(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, dY, *, bqkv=None, bo=None, norm=True, ws=None):
+    """Reverse mode of gcm_fwd for sum <Y, dY> (same inputs): returns dX (X's
+    dtype) and float32 dWqkv, dbqkv, dWo, dbo (None where the bias is),
+    dalpha, dW1_0, dW2_0, deta [H]."""
+    lib = L.load()
+    prob = _gcm_problem(X, Wqkv, Wo, alpha, W1, W2, eta, chunk_tokens, bqkv, bo, norm)
+    if dY.shape != X.shape or dY.dtype != X.dtype or not dY.is_contiguous():
+        raise ValueError("dY must be a contiguous tensor like X")
+    D = X.shape[1]
+    dev = X.device
+    f32 = dict(dtype=torch.float32, device=dev)
+    dX = torch.empty_like(X)
+    g = dict(dWqkv=torch.empty((D, 3 * D), **f32), dbqkv=torch.empty(3 * D, **f32) if bqkv is not None else None,
+             dWo=torch.empty((D, D), **f32), dbo=torch.empty(D, **f32) if bo is not None else None,
+             dalpha=torch.empty(D, **f32), dW1_0=torch.empty_like(W1), dW2_0=torch.empty_like(W2),
+             deta=torch.empty(W1.shape[0], **f32))
+    if ws is None:
+        nbytes = lib.ttt_gcm_bwd_workspace_bytes(ctypes.byref(prob))
+        if nbytes == 0:
+            raise L.TTTError(L.TTT_ESHAPE, lib, "ttt_gcm_bwd_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = lib.ttt_gcm_bwd(ctypes.byref(prob), _ptr(X), _ptr(Wqkv), _ptr(bqkv), _ptr(Wo), _ptr(bo), _ptr(alpha),
+                         _ptr(W1), _ptr(W2), _ptr(dY), _ptr(dX), _ptr(g["dWqkv"]), _ptr(g["dbqkv"]), _ptr(g["dWo"]),
+                         _ptr(g["dbo"]), _ptr(g["dalpha"]), _ptr(g["dW1_0"]), _ptr(g["dW2_0"]), _ptr(g["deta"]),
+                         _ptr(ws), ws.numel(), _stream(dev))
+    L.check(st, "ttt_gcm_bwd")
+    return dict(dX=dX, **g)
 
 
 def chunk_fwd_noalloc(Q, K, V, W1, W2, eta, chunk_tokens, *, norm=True, save_ckpt=False, emit_loss=False,

@@ -90,3 +90,47 @@ def test_layer_empty_and_validation(gpu):
     x = make_layer_inputs(10, 1, 64, 128, seed=1)  # D = 64: not a multiple of 128
     with pytest.raises(L.TTTError):
         run(x, "f32", 0.05, 100)
+
+
+@pytest.mark.parametrize("N,H,d,h,M,eta,io,bias", [
+    (2500, 16, 64, 256, 600, 0.05, "f32", True),
+    (2500, 16, 64, 256, 600, 0.05, "bf16", True),
+    (1374 * 2, 1, 1024, 4096, 1374, 0.05, "bf16", False),
+])
+def test_layer_backward_matches_oracle(gpu, N, H, d, h, M, eta, io, bias):
+    # reverse mode of the whole layer for <Y, dY>: gate, output projection,
+    # the unit's reverse mode, query-key-value projection
+    x = make_layer_inputs(N, H, d, h, seed=N + H + 3, io_dtype=io, bias=bias)
+    dY = np.random.default_rng(N + 7).standard_normal((N, H * d)).astype(np.float32)
+    if io == "bf16":
+        dY = torch.from_numpy(dY).to(torch.bfloat16).float().numpy()
+    g = dev_inputs(x, io)
+    dYd = torch.from_numpy(dY).cuda().to(g["X"].dtype)
+    r = ops().gcm_bwd(g["X"], g["Wqkv"], g["Wo"], g["alpha"], g["W1"], g["W2"], eta, M, dYd, bqkv=g["bqkv"],
+                      bo=g["bo"])
+    torch.cuda.synchronize()
+    ref = orc.gcm_layer_backward(x["X"], x["Wqkv"], x["Wo"], x["alpha"], x["W1"], x["W2"], eta, M, dY, bqkv=x["bqkv"],
+                                 bo=x["bo"])
+    tol = TOL[io]
+    print(f"gcm layer backward N={N} H={H} d={d} h={h} {io} bias={bias}:")
+    keys = ["dX", "dWqkv", "dWo", "dalpha", "dW1_0", "dW2_0"] + (["dbqkv", "dbo"] if bias else [])
+    for k in keys:
+        check(k, host(r[k]), ref[k], tol)
+    # dX - dY is the part that went through the layer (dY itself passes
+    # straight through the residual)
+    check("dX - dY", host(r["dX"]) - dY, ref["dX"] - dY, tol)
+    e = rel(host(r["deta"]), ref["deta"])
+    print(f"  deta rel {e:.2e}")
+    assert e <= tol
+    if not bias:
+        assert r["dbqkv"] is None and r["dbo"] is None
+
+
+def test_layer_backward_empty_stream(gpu):
+    x = make_layer_inputs(0, 16, 64, 256, seed=1)
+    g = dev_inputs(x, "f32")
+    r = ops().gcm_bwd(g["X"], g["Wqkv"], g["Wo"], g["alpha"], g["W1"], g["W2"], 0.05, 100, torch.zeros_like(g["X"]),
+                      bqkv=g["bqkv"], bo=g["bo"])
+    torch.cuda.synchronize()
+    for k in ("dWqkv", "dbqkv", "dWo", "dbo", "dalpha", "dW1_0", "dW2_0", "deta"):
+        assert not torch.any(r[k]), k
