@@ -49,21 +49,23 @@ enum { KMAJ = 0, MNMAJ = 1 };
 
 // LDS tile of ROWS rows (m or n) by BK (contraction).  BF16 operands feed
 // 32x32x16 products: a lane's 8 contraction slots hold, for lane half hf and
-// product step j, k = 16j + 4hf + {0..3} and 16j + 8 + 4hf + {0..3}; both
-// operands use this order (the order of the transposing LDS read), so a
-// k-major and an mn-major operand can be mixed.  FP32 operands feed 32x32x2
-// products, lane (l32, hf) holding k = 2j + hf.
+// product step j, k = 16j + 8hf + {0..7}, so a k-major fragment is one
+// 16-byte LDS read and an mn-major one two transposing reads of four rows
+// each; both operands use this order, so a k-major and an mn-major operand
+// can be mixed.  FP32 operands feed 32x32x2 products, lane (l32, hf) holding
+// k = 2j + hf.
 //
-// Pitches (in 4-byte LDS banks): a k-major BF16 row is 34 banks, so the
-// 8-byte reads of 16 lanes from 16 consecutive rows cover the 32 banks once;
-// an mn-major BF16 row is 72 banks (8 mod 32), so the four rows of 32 bytes
-// that a 16-lane group of the transposing read touches fall on disjoint
-// banks.  FP32: 33 banks (k-major, 4-byte reads down a column), 132 (mn-major,
-// consecutive lanes on consecutive banks).
+// Pitches (in 4-byte LDS banks): a k-major BF16 row is 36 banks (16-byte
+// aligned), so the 16-byte reads of 8 lanes from 8 consecutive rows start 4
+// banks apart mod 32 and cover the banks once; an mn-major BF16 row is 72
+// banks (8 mod 32), so the four rows of 32 bytes that a 16-lane group of the
+// transposing read touches fall on disjoint banks.  FP32: 33 banks (k-major,
+// 4-byte reads down a column), 132 (mn-major, consecutive lanes on
+// consecutive banks).
 template <typename T, int ROWS>
 struct Tile {
   static constexpr int BK = bk<T>();
-  static constexpr int KLD = sizeof(T) == 2 ? BK + 4 : BK + 1;       // pitch of a k-major tile [ROWS][BK]
+  static constexpr int KLD = sizeof(T) == 2 ? BK + 8 : BK + 1;       // pitch of a k-major tile [ROWS][BK]
   static constexpr int MLD = sizeof(T) == 2 ? ROWS + 16 : ROWS + 4;  // pitch of an mn-major tile [BK][ROWS]
   static constexpr int ELEMS = ROWS * KLD > BK * MLD ? ROWS * KLD : BK * MLD;
 };
@@ -123,11 +125,8 @@ struct Stage {
       }
       if constexpr (LAYOUT == MNMAJ) {
         *reinterpret_cast<u32x4*>(lds + off) = r[i];
-      } else if constexpr (sizeof(T) == 2) {  // k-major BF16 rows are 8-byte aligned: two 8-byte stores
-        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-        const u32x4 v = r[i];
-        reinterpret_cast<u32x2*>(lds + off)[0] = (u32x2){v[0], v[1]};
-        reinterpret_cast<u32x2*>(lds + off)[1] = (u32x2){v[2], v[3]};
+      } else if constexpr (sizeof(T) == 2) {  // k-major BF16 rows are 16-byte aligned
+        *reinterpret_cast<u32x4*>(lds + off) = r[i];
       } else {  // FP32 k-major rows have an odd pitch: four 4-byte stores
         const u32x4 v = r[i];
 #pragma unroll
@@ -146,20 +145,18 @@ __device__ __forceinline__ auto frag(const T* t, int mn, int j) {
   if constexpr (sizeof(T) == 2) {
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
     if constexpr (LAYOUT == KMAJ) {
-      const bf16* row = t + (mn + l32) * TL::KLD + 16 * j + 4 * hf;
-      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row);
-      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 8);
-      return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      return *reinterpret_cast<const bf16x8*>(t + (mn + l32) * TL::KLD + 16 * j + 8 * hf);
     } else {
       // transposing read: in each 16-lane group lane i addresses row
-      // t0 + i/4, columns c0 + 4(i%4)..+3 and receives T[t0 + q][c0 + i], q < 4
+      // t0 + i/4, columns c0 + 4(i%4)..+3 and receives T[t0 + q][c0 + i], q < 4;
+      // rows 8hf..8hf+3, then 8hf+4..8hf+7
       const int l16 = l & 15;
-      const int off = (4 * hf + (l16 >> 2)) * TL::MLD + mn + 16 * ((l >> 4) & 1) + 4 * (l16 & 3);
+      const int off = (8 * hf + (l16 >> 2)) * TL::MLD + mn + 16 * ((l >> 4) & 1) + 4 * (l16 & 3);
       const bf16* p0 = t + off + 16 * j * TL::MLD;
       const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
           (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0)));
       const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
-          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0 + 8 * TL::MLD)));
+          (lds_bf16x4*)((__attribute__((address_space(3))) bf16*)(p0 + 4 * TL::MLD)));
       return (bf16x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
   } else {
@@ -207,20 +204,24 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   constexpr int BK = bk<T>();
   const int nk = (K + BK - 1) / BK;
   f32x16 acc[MB][2] = {};
+  // Every load and LDS store below is unconditional (a slice past the end
+  // reloads slice 0, which nothing reads), and the loop runs the two
+  // register stages in pairs with a separate last slice: with a branch around
+  // the loads, the compiler's load counters merge conservatively and each
+  // slice waited for the loads issued for the next one.
   ga[0].load(ra, voa, 0);
   gb[0].load(rb, vob, 0);
-  if (nk > 1) {
-    ga[1].load(ra, voa, ka);
-    gb[1].load(rb, vob, kb);
-  }
+  ga[1].load(ra, voa, nk > 1 ? ka : 0);
+  gb[1].load(rb, vob, nk > 1 ? kb : 0);
   ga[0].store(sa[0]);
   gb[0].store(sb[0]);
   __syncthreads();
   auto body = [&](int kt, auto PC) {
     constexpr int P = decltype(PC)::value;  // kt & 1
-    if (kt + 2 < nk) {  // slice kt+2 into register stage P (free: slice kt left it last iteration)
-      ga[P].load(ra, voa, (kt + 2) * ka);
-      gb[P].load(rb, vob, (kt + 2) * kb);
+    {  // slice kt+2 into register stage P (free: slice kt left it last iteration)
+      const bool more = kt + 2 < nk;
+      ga[P].load(ra, voa, more ? (kt + 2) * ka : 0);
+      gb[P].load(rb, vob, more ? (kt + 2) * kb : 0);
     }
     // every operand fragment of the slice is read before the products, so
     // the LDS latency is paid once per slice, not once per product step
@@ -241,16 +242,17 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
         acc[bm][1] = mma32(fa[j][bm], fb[j][1], acc[bm][1]);
       }
     }
-    if (kt + 1 < nk) {  // slice kt+1 (register stage P^1) into the other LDS buffer
-      ga[P ^ 1].store(sa[P ^ 1]);
-      gb[P ^ 1].store(sb[P ^ 1]);
-    }
+    // slice kt+1 (register stage P^1) into the other LDS buffer
+    ga[P ^ 1].store(sa[P ^ 1]);
+    gb[P ^ 1].store(sb[P ^ 1]);
     __syncthreads();
   };
-  for (int kt = 0; kt < nk; kt += 2) {
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
     body(kt, std::integral_constant<int, 0>{});
-    if (kt + 1 < nk) body(kt + 1, std::integral_constant<int, 1>{});
+    body(kt + 1, std::integral_constant<int, 1>{});
   }
+  if (kt < nk) body(kt, std::integral_constant<int, 0>{});
   const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
 #pragma unroll
   for (int bm = 0; bm < MB; ++bm)
