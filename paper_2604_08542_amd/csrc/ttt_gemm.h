@@ -268,6 +268,24 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   ep.finish();
 }
 
+// Sum of part[0..n) by one work-group of NTH threads in a fixed order:
+// thread t adds the run part[t c .. t c + c) in index order (c = ceil(n /
+// NTH)), then thread 0 adds the NTH run sums in thread order.  The result is
+// valid in thread 0 only.
+__device__ __forceinline__ float fixed_order_sum(const float* part, int n) {
+  __shared__ float run[NTH];
+  const int t = threadIdx.x, c = (n + NTH - 1) / NTH;
+  const int i0 = t * c, i1 = i0 + c < n ? i0 + c : n;
+  float s = 0.f;
+  for (int i = i0; i < i1; ++i) s += part[i];
+  run[t] = s;
+  __syncthreads();
+  float tot = 0.f;
+  if (t == 0)
+    for (int i = 0; i < NTH; ++i) tot += run[i];
+  return tot;
+}
+
 // One launch of one product; grid (N / 128, ceil(M / 128)).
 template <typename T, int LA, int LB, int BM, typename EP>
 __global__ __launch_bounds__(NTH) void k_gemm(const T* A, int lda, int a_rows, const T* B, int ldb, int b_rows,

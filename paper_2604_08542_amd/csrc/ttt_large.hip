@@ -250,13 +250,10 @@ __global__ void k_cast(const float* src, T* dst, int64_t n) {
     dst[i] = (T)src[i];
 }
 
-// loss[c] = (sum of the tile partials, in tile order) / M_c
-__global__ void k_loss(const float* part, int n, float inv_m, float* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    float s = 0.f;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * inv_m;
-  }
+// loss[c] = (sum of the tile partials, in a fixed order) / M_c; one work-group
+__global__ __launch_bounds__(NTH) void k_loss(const float* part, int n, float inv_m, float* out) {
+  const float s = fixed_order_sum(part, n);
+  if (threadIdx.x == 0) *out = s * inv_m;
 }
 
 template <typename T, typename IOT>
@@ -288,7 +285,7 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
     EpRes<T> e2{E, a.Vn, a.loss_part, d, M, 2.0f / (float)M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpRes<T>>), dim3(d / BN, mt), dim3(NTH), 0, st, Aa, h, M, W2o, d,
                        h, h, e2);
-    if (a.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, st, a.loss_part, (d / BN) * mt, 1.0f / (float)M,
+    if (a.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(NTH), 0, st, a.loss_part, (d / BN) * mt, 1.0f / (float)M,
                                    a.loss);
     // P = E W2^T -> D
     EpD<T> e3{{}, Dd, static_cast<const T*>(a.S1), h, M};

@@ -23,7 +23,8 @@
 // against that fixed Wh, adding the weight terms to a separate total).
 // Every output element is owned by one work-group summing its whole
 // contraction in a fixed order; the step-size derivative is summed from
-// per-tile partials in tile order.  The result is deterministic.
+// per-tile partials in a fixed order (runs of consecutive tiles, then the
+// run sums in order).  The result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -333,13 +334,10 @@ __global__ __launch_bounds__(256) void k_norm_bwd(LargeBwdArgs p) {
   }
 }
 
-// *deta += (the n step-size partials, in tile order)
-__global__ void k_deta(const float* part, int n, float* deta) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    float s = 0.f;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *deta += s;
-  }
+// *deta += (the n step-size partials, summed in a fixed order); one work-group
+__global__ __launch_bounds__(NTH) void k_deta(const float* part, int n, float* deta) {
+  const float s = fixed_order_sum(part, n);
+  if (threadIdx.x == 0) *deta += s;
 }
 
 __global__ void k_add(const float* src, float* dst, int64_t n) {
@@ -419,7 +417,7 @@ hipError_t step_t(const LargeBwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, e9);
     EpU2<T> e10{a.dE, E, a.deta_part + (h / BN) * mt, d, M, eta};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpU2<T>>), gd, nt, 0, st, A, h, M, Wh2o, d, h, h, e10);
-    hipLaunchKernelGGL(k_deta, dim3(1), dim3(64), 0, st, a.deta_part, (h / BN + d / BN) * mt, a.deta);
+    hipLaunchKernelGGL(k_deta, dim3(1), dim3(NTH), 0, st, a.deta_part, (h / BN + d / BN) * mt, a.deta);
     EpDY<T> e11{{}, dY, a.dv, a.dE, d, M, scale};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpDY<T>>), gd, nt, 0, st, dP, h, M, W2, d, h, h, e11);
     EpPut<T> e12{{}, EWh, h, M};
