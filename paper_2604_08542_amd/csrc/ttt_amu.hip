@@ -23,6 +23,11 @@
 
 namespace ttt {
 
+// Token t of a 32-token tile at slot(t) of a [d][token slot] column tile:
+// bits 2 and 3 swapped, so the 8 tokens whose values a lane holds in
+// registers 8m..8m+7 of a 32x32 result are 8 consecutive slots.
+__device__ __forceinline__ constexpr int amu_slot(int t) { return (t & ~12) | ((t & 4) << 1) | ((t & 8) >> 1); }
+
 template <typename IOT, bool BF, int NW>
 __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   constexpr int HH = NW * 32;
@@ -34,9 +39,18 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   using MT = std::conditional_t<BF, bf16, float>;
   constexpr int AS_LD = HH + (BF ? 8 : 4);
 
-  __shared__ __attribute__((aligned(16))) float xs[TT * LD];  // K or Q rows (normalised)
-  __shared__ __attribute__((aligned(16))) float es[TT * LD];  // E = -eta v rows, or O rows
+  // FP32 products read the token rows as FP32 tiles; BF16 products read each
+  // token operand from two BF16 tiles written once per tile: rows [token][d]
+  // (A operand of the 32x32 products, one 16-byte read per fragment) and
+  // columns [d][token slot] (operand of the token sums, likewise).
+  constexpr int XB = D + 8, XT = TT + 8;
+  __shared__ __attribute__((aligned(16))) float xs[BF ? 1 : TT * LD];  // K or Q rows (normalised)
+  __shared__ __attribute__((aligned(16))) float es[TT * LD];  // E = -eta v rows (FP32 products), or O rows
   __shared__ __attribute__((aligned(16))) MT sta[TT * AS_LD];  // staged Hq
+  __shared__ __attribute__((aligned(16))) bf16 xr[BF ? TT * XB : 1];
+  __shared__ __attribute__((aligned(16))) bf16 xc[BF ? D * XT : 1];
+  __shared__ __attribute__((aligned(16))) bf16 er[BF ? TT * XB : 1];
+  __shared__ __attribute__((aligned(16))) bf16 ec[BF ? D * XT : 1];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l32 = tid & 31, hf = (tid >> 5) & 1, l16 = tid & 15, g4 = (tid >> 4) & 3;
@@ -53,20 +67,30 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   const MT* W2n = W1t + AMU_W2N * DH;
   const MT* W2d = W1t + AMU_W2D * DH;
 
-  // 32x32 block C[token][hid] = X[token][:] M[hid][:]^T (M rows contiguous).
-  auto th = [&](const float* X, const MT* M) {
+  // BF16 operand fragments of M[hid][:] for this lane (M rows contiguous),
+  // loaded before the barrier that precedes their products so that their
+  // latency overlaps it.
+  struct WF {
+    bf16x8 f[4];
+  };
+  auto wload = [&](const MT* M) {
+    WF r;
+    if constexpr (BF) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) r.f[m] = *reinterpret_cast<const bf16x8*>(M + hid * D + 16 * m + 8 * hf);
+    }
+    return r;
+  };
+  // 32x32 block C[token][hid] = X[token][:] M[hid][:]^T (M rows contiguous);
+  // FP32 products read the FP32 row tile X and M, BF16 products the BF16 row
+  // tile Xb and the fragments wf of M.
+  auto th = [&](const float* X, const bf16* Xb, const MT* M, const WF& wf) {
     f32x16 c = {};
     const MT* mrow = M + hid * D;
     if constexpr (BF) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int d0 = 16 * m + 8 * hf;
-        const f32x4 x0 = *reinterpret_cast<const f32x4*>(&X[l32 * LD + d0]);
-        const f32x4 x1 = *reinterpret_cast<const f32x4*>(&X[l32 * LD + d0 + 4]);
-        const bf16x8 a = as_bf16x8(pack_bf16x2(x0[0], x0[1]), pack_bf16x2(x0[2], x0[3]),
-                                   pack_bf16x2(x1[0], x1[1]), pack_bf16x2(x1[2], x1[3]));
-        c = mma32(a, *reinterpret_cast<const bf16x8*>(mrow + d0), c);
-      }
+      for (int m = 0; m < 4; ++m)
+        c = mma32(*reinterpret_cast<const bf16x8*>(&Xb[l32 * XB + 16 * m + 8 * hf]), wf.f[m], c);
     } else {
 #pragma unroll
       for (int s4 = 0; s4 < 8; ++s4) {
@@ -104,44 +128,37 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
     }
     return c;
   };
-  // acc[db] (rows d = 32db.., cols hid) += X[:, d]^T Yw
-  auto tok_sum_dh = [&](f32x16 (&acc)[2], const float* X, const f32x16& Yw) {
+  // Column fragment (feature dd, register group m) of a [d][token slot] tile.
+  auto cfrag = [&](const bf16* Xc, int dd, int m) {
+    return *reinterpret_cast<const bf16x8*>(&Xc[dd * XT + 16 * m + 8 * hf]);
+  };
+  // Registers 8m..8m+7 of a 32x32 result as one BF16 operand fragment.
+  auto rfrag = [&](const f32x16& Yw, int m) {
+    return as_bf16x8(pack_bf16x2(Yw[8 * m], Yw[8 * m + 1]), pack_bf16x2(Yw[8 * m + 2], Yw[8 * m + 3]),
+                     pack_bf16x2(Yw[8 * m + 4], Yw[8 * m + 5]), pack_bf16x2(Yw[8 * m + 6], Yw[8 * m + 7]));
+  };
+  // acc[db] (rows d = 32db.., cols hid) += X[:, d]^T Yw (BF16: X from its column tile Xc)
+  auto tok_sum_dh = [&](f32x16 (&acc)[2], const float* X, const bf16* Xc, const f32x16& Yw) {
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
       const int dd = 32 * db + l32;
       if constexpr (BF) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          uint32_t aw[4], bw[4];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            aw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, hf) * LD + dd], X[c32_row(8 * m + e + 1, hf) * LD + dd]);
-            bw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
-          }
-          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
-        }
+        for (int m = 0; m < 2; ++m) acc[db] = mma32(cfrag(Xc, dd, m), rfrag(Yw, m), acc[db]);
       } else {
 #pragma unroll
         for (int s = 0; s < 16; ++s) acc[db] = mma32(X[c32_row(s, hf) * LD + dd], Yw[s], acc[db]);
       }
     }
   };
-  // acc[db] (rows hid, cols d = 32db..) += Yw^T X[:, d]
-  auto tok_sum_hd = [&](f32x16 (&acc)[2], const f32x16& Yw, const float* X) {
+  // acc[db] (rows hid, cols d = 32db..) += Yw^T X[:, d] (BF16: X from its column tile Xc)
+  auto tok_sum_hd = [&](f32x16 (&acc)[2], const f32x16& Yw, const float* X, const bf16* Xc) {
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
       const int dd = 32 * db + l32;
       if constexpr (BF) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          uint32_t aw[4], bw[4];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            aw[e / 2] = pack_bf16x2(Yw[8 * m + e], Yw[8 * m + e + 1]);
-            bw[e / 2] = pack_bf16x2(X[c32_row(8 * m + e, hf) * LD + dd], X[c32_row(8 * m + e + 1, hf) * LD + dd]);
-          }
-          acc[db] = mma32(as_bf16x8(aw[0], aw[1], aw[2], aw[3]), as_bf16x8(bw[0], bw[1], bw[2], bw[3]), acc[db]);
-        }
+        for (int m = 0; m < 2; ++m) acc[db] = mma32(rfrag(Yw, m), cfrag(Xc, dd, m), acc[db]);
       } else {
 #pragma unroll
         for (int s = 0; s < 16; ++s) acc[db] = mma32(Yw[s], X[c32_row(s, hf) * LD + dd], acc[db]);
@@ -166,7 +183,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
     }
     r.et = (times_eta && valid) ? p.eta_tok[(t0 + row) * p.H + head] : 0.f;
   };
-  auto stage_rows = [&](const RawRows& r, float* dst, bool do_norm, bool times_eta) {
+  // FP32 products: into the FP32 row tile dst; BF16 products: into the
+  // BF16 row tile rb and column tile cb.
+  auto stage_rows = [&](const RawRows& r, float* dst, bf16* rb, bf16* cb, bool do_norm, bool times_eta) {
     float scale = 1.f;
     if (do_norm) {
       float ss = 0.f;
@@ -176,8 +195,23 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
       scale = 1.0f / fmaxf(sqrtf(ss), NORM_EPS);
     }
     if (times_eta) scale *= -r.et;
+    if constexpr (BF) {
+      uint32_t pk[EPT / 2];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) dst[row * LD + col0 + i] = r.x[i] * scale;
+      for (int i = 0; i < EPT; i += 2) pk[i / 2] = pack_bf16x2(r.x[i] * scale, r.x[i + 1] * scale);
+      uint32_t* rw = reinterpret_cast<uint32_t*>(&rb[row * XB + col0]);
+#pragma unroll
+      for (int i = 0; i < EPT / 2; ++i) rw[i] = pk[i];
+      uint16_t* cw = reinterpret_cast<uint16_t*>(cb) + amu_slot(row);
+#pragma unroll
+      for (int i = 0; i < EPT; i += 2) {
+        cw[(col0 + i) * XT] = (uint16_t)(pk[i / 2] & 0xffffu);
+        cw[(col0 + i + 1) * XT] = (uint16_t)(pk[i / 2] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) dst[row * LD + col0 + i] = r.x[i] * scale;
+    }
   };
 
   f32x16 g1[2] = {}, g2[2] = {}, g3[2] = {};
@@ -193,13 +227,14 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   };
   if (g * TT < gl) fetch_grad(g);
   for (int t = g; t * TT < gl; t += G) {
-    stage_rows(rk, xs, norm_k, false);
-    stage_rows(rv, es, norm_v, true);
+    stage_rows(rk, xs, xr, xc, norm_k, false);
+    stage_rows(rv, es, er, ec, norm_v, true);
     if ((t + G) * TT < gl) fetch_grad(t + G);
+    const WF f1 = wload(W1t), f3 = wload(W3t), f2 = wload(W2n);
     __syncthreads();
-    const f32x16 Z1 = th(xs, W1t);
-    const f32x16 Z3 = th(xs, W3t);
-    const f32x16 dH = th(es, W2n);
+    const f32x16 Z1 = th(xs, xr, W1t, f1);
+    const f32x16 Z3 = th(xs, xr, W3t, f3);
+    const f32x16 dH = th(es, er, W2n, f2);
     f32x16 Hd, dZ1, dZ3;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -210,9 +245,9 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
       dZ3[r] = dH[r] * s;
       dZ1[r] = dH[r] * Z3[r] * fmaf(s, 1.0f - sg, sg);
     }
-    tok_sum_hd(g2, Hd, es);
-    tok_sum_dh(g3, xs, dZ3);
-    tok_sum_dh(g1, xs, dZ1);
+    tok_sum_hd(g2, Hd, es, ec);
+    tok_sum_dh(g3, xs, xc, dZ3);
+    tok_sum_dh(g1, xs, xc, dZ1);
     __syncthreads();
   }
 
@@ -226,12 +261,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   for (int t = g; t * TT < al; t += G) {
     const int64_t t0 = p.app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
-    stage_rows(rq, xs, norm_q, false);
+    stage_rows(rq, xs, xr, xc, norm_q, false);
     if ((t + G) * TT < al) fetch_app(t + G);
+    const WF f1 = wload(W1t), f3 = wload(W3t);
     __syncthreads();
     {
-      const f32x16 Zq1 = th(xs, W1t);
-      const f32x16 Zq3 = th(xs, W3t);
+      const f32x16 Zq1 = th(xs, xr, W1t, f1);
+      const f32x16 Zq3 = th(xs, xr, W3t, f3);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const float z = Zq1[r];
