@@ -24,10 +24,10 @@ __device__ __forceinline__ void put(T* p, float v) {
 
 // Epilogues derive from this.  An epilogue that reads an input per element
 // (a factor, a residual target, the FP32 master) defines In and load(r, c);
-// the tile calls load for 16 elements before it calls operator() for any of
-// them, so those reads are in flight together instead of each waiting behind
-// the previous element's store.  finish() runs once per work-group after its
-// last element.
+// the tile calls load for 16 elements (BF16 tiles with a small input: for all
+// of its elements) before it calls operator() for any of them, so those
+// reads are in flight together instead of each waiting behind the previous
+// element's store.  finish() runs once per work-group after its last element.
 struct EpBase {
   struct In {};
   __device__ __forceinline__ In load(int, int) const { return {}; }
@@ -254,17 +254,38 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   }
   if (kt < nk) body(kt, std::integral_constant<int, 0>{});
   const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
+  if constexpr (sizeof(T) == 2 && sizeof(typename EP::In) <= 4) {
+    // BF16 tiles with at most one 4-byte input per element request every
+    // input of the tile before the first element is stored (one load latency
+    // per tile, not one per 32x32 block); the registers fit beside the
+    // accumulators at two waves per SIMD
+    typename EP::In in[MB][2][16];
 #pragma unroll
-  for (int bm = 0; bm < MB; ++bm)
+    for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn) {
-      const int col = n0 + wn + 32 * bn + l32;
-      typename EP::In in[16];
+      for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) in[r] = ep.load(m0 + wm + 32 * bm + c32_row(r, hf), col);
+        for (int r = 0; r < 16; ++r) in[bm][bn][r] = ep.load(m0 + wm + 32 * bm + c32_row(r, hf), n0 + wn + 32 * bn + l32);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) ep(m0 + wm + 32 * bm + c32_row(r, hf), col, acc[bm][bn][r], in[r]);
-    }
+    for (int bm = 0; bm < MB; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          ep(m0 + wm + 32 * bm + c32_row(r, hf), n0 + wn + 32 * bn + l32, acc[bm][bn][r], in[bm][bn][r]);
+  } else {
+#pragma unroll
+    for (int bm = 0; bm < MB; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        const int col = n0 + wn + 32 * bn + l32;
+        typename EP::In in[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) in[r] = ep.load(m0 + wm + 32 * bm + c32_row(r, hf), col);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ep(m0 + wm + 32 * bm + c32_row(r, hf), col, acc[bm][bn][r], in[r]);
+      }
+  }
   ep.finish();
 }
 
