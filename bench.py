@@ -287,8 +287,14 @@ def other_forms(forms, steps, warmup):
                         ops.amu_bwd(dev["Q"], dev["K"], dev["V"], et, dev["W1"], dev["W2"], W3, wp.chunk_tokens, dOp,
                                     sync=sync, ws=bws)
                     ms = timed(fbp, 2, 1)
+                    # forward 18 d h per token-head; reverse step 46 d h (8 products of the apply adjoint,
+                    # 15 of the update adjoint); the chain's recomputed forward steps are not counted
+                    ach = 64.0 * wp.d_head * wp.d_hidden * wp.n_tokens * wp.n_heads / (ms * 1e-3) / 1e12
                     res[f"amu_paper_state_fwd_bwd_{sync}_bf16"] = dict(
-                        workload=wp.name.replace("_bf16", ""), ms_per_step=ms, tokens_per_s=wp.n_tokens / (ms * 1e-3))
+                        workload=wp.name.replace("_bf16", ""), ms_per_step=ms, tokens_per_s=wp.n_tokens / (ms * 1e-3),
+                        pass_roofline=dict(bound="mfma", achieved=ach, peak=PEAK["bf16"],
+                                           unit="TFLOP/s (64 d h per token-head, whole pass)",
+                                           frac=ach / PEAK["bf16"]))
                     del dOp, bws
             del dev, O, W3, et, ws
             torch.cuda.empty_cache()
