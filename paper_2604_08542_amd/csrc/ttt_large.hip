@@ -261,10 +261,11 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
   const int M = a.rows, d = a.d, h = a.h;
   // tile rows: 128 for the products over the chunk's tokens (two waves per
   // SIMD fit, which a 256-row tile with its 128 accumulator registers per lane
-  // does not); for the weight updates, whose d x h outputs give only 256
-  // tiles of 128 x 128, 64-row tiles with BF16 operands (twice the
-  // work-groups, two per CU: 1-2% faster per chunk, same results)
-  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;
+  // does not) and for the weight updates too, although their d x h outputs
+  // give only 256 tiles of 128 x 128, one per CU: with the contraction loop
+  // free of waits on the next slice's loads, 64-row tiles (twice the
+  // work-groups) are slower for these 10,992-token contractions
+  constexpr int BMT = 128, BMW = 128;
   const int mt = (M + BMT - 1) / BMT;
   T* Kn = static_cast<T*>(a.Kn);
   T* Qn = static_cast<T*>(a.Qn);
@@ -313,7 +314,7 @@ hipError_t step_t(const LargeStepArgs& a, hipStream_t st) {
 template <typename T, typename IOT>
 hipError_t amu_step_t(const LargeAmuArgs& a, hipStream_t st) {
   const int M = a.rows, d = a.d, h = a.h;
-  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;  // as in step_t
+  constexpr int BMT = 128, BMW = 128;  // as in step_t
   const int mt = (M + BMT - 1) / BMT;
   T* Kn = static_cast<T*>(a.Kn);
   T* Qn = static_cast<T*>(a.Qn);

@@ -353,7 +353,7 @@ __global__ void k_zero(float* p, int64_t n) {
 template <typename T, typename IOT>
 hipError_t step_t(const LargeBwdArgs& a, hipStream_t st) {
   const int M = a.rows, d = a.d, h = a.h;
-  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;
+  constexpr int BMT = 128, BMW = 128;
   const int mt = (M + BMT - 1) / BMT;
   const float eta = a.eta, scale = 2.0f / (float)M;
   T* Kn = static_cast<T*>(a.Kn);
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) void k_ydot(LargeAmuBwdArgs p) {
 template <typename T, typename IOT>
 hipError_t step_t(const LargeAmuBwdArgs& a, hipStream_t st) {
   const int M = a.rows, d = a.d, h = a.h;
-  constexpr int BMT = 128, BMW = sizeof(T) == 2 ? 64 : 128;
+  constexpr int BMT = 128, BMW = 128;
   const int mt = (M + BMT - 1) / BMT;
   auto P = [](void* q) { return static_cast<T*>(q); };
   auto C = [](const void* q) { return static_cast<const T*>(q); };
