@@ -44,13 +44,17 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   // (A operand of the 32x32 products, one 16-byte read per fragment) and
   // columns [d][token slot] (operand of the token sums, likewise).
   constexpr int XB = D + 8, XT = TT + 8;
-  __shared__ __attribute__((aligned(16))) float xs[BF ? 1 : TT * LD];  // K or Q rows (normalised)
-  __shared__ __attribute__((aligned(16))) float es[TT * LD];  // E = -eta v rows (FP32 products), or O rows
+  // The gradient loop alternates between two copies of its token tiles, so
+  // one barrier per tile suffices (a tile's tiles are rewritten two tiles
+  // later, after every wave has passed the next tile's barrier); the apply
+  // uses copy 0.
+  __shared__ __attribute__((aligned(16))) float xs[2][BF ? 1 : TT * LD];  // K or Q rows (normalised)
+  __shared__ __attribute__((aligned(16))) float es[2][TT * LD];  // E = -eta v rows (FP32 products), or O rows
   __shared__ __attribute__((aligned(16))) MT sta[TT * AS_LD];  // staged Hq
-  __shared__ __attribute__((aligned(16))) bf16 xr[BF ? TT * XB : 1];
-  __shared__ __attribute__((aligned(16))) bf16 xc[BF ? D * XT : 1];
-  __shared__ __attribute__((aligned(16))) bf16 er[BF ? TT * XB : 1];
-  __shared__ __attribute__((aligned(16))) bf16 ec[BF ? D * XT : 1];
+  __shared__ __attribute__((aligned(16))) bf16 xr[2][BF ? TT * XB : 1];
+  __shared__ __attribute__((aligned(16))) bf16 xc[2][BF ? D * XT : 1];
+  __shared__ __attribute__((aligned(16))) bf16 er[2][BF ? TT * XB : 1];
+  __shared__ __attribute__((aligned(16))) bf16 ec[2][BF ? D * XT : 1];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l32 = tid & 31, hf = (tid >> 5) & 1, l16 = tid & 15, g4 = (tid >> 4) & 3;
@@ -227,14 +231,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   };
   if (g * TT < gl) fetch_grad(g);
   for (int t = g; t * TT < gl; t += G) {
-    stage_rows(rk, xs, xr, xc, norm_k, false);
-    stage_rows(rv, es, er, ec, norm_v, true);
+    const int b = ((t - g) / G) & 1;
+    stage_rows(rk, xs[b], xr[b], xc[b], norm_k, false);
+    stage_rows(rv, es[b], er[b], ec[b], norm_v, true);
     if ((t + G) * TT < gl) fetch_grad(t + G);
     const WF f1 = wload(W1t), f3 = wload(W3t), f2 = wload(W2n);
     __syncthreads();
-    const f32x16 Z1 = th(xs, xr, W1t, f1);
-    const f32x16 Z3 = th(xs, xr, W3t, f3);
-    const f32x16 dH = th(es, er, W2n, f2);
+    const f32x16 Z1 = th(xs[b], xr[b], W1t, f1);
+    const f32x16 Z3 = th(xs[b], xr[b], W3t, f3);
+    const f32x16 dH = th(es[b], er[b], W2n, f2);
     f32x16 Hd, dZ1, dZ3;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -245,11 +250,11 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
       dZ3[r] = dH[r] * s;
       dZ1[r] = dH[r] * Z3[r] * fmaf(s, 1.0f - sg, sg);
     }
-    tok_sum_hd(g2, Hd, es, ec);
-    tok_sum_dh(g3, xs, xc, dZ3);
-    tok_sum_dh(g1, xs, xc, dZ1);
-    __syncthreads();
+    tok_sum_hd(g2, Hd, es[b], ec[b]);
+    tok_sum_dh(g3, xs[b], xc[b], dZ3);
+    tok_sum_dh(g1, xs[b], xc[b], dZ1);
   }
+  __syncthreads();  // the apply reuses copy 0
 
   // ------------------------------------------------ apply of chunk s-1
   const int al = p.app_len;
@@ -257,17 +262,23 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
   auto fetch_app = [&](int t) {
     fetch_rows(p.Q, p.app_start + (int64_t)t * TT, min(TT, al - t * TT), false, rq);
   };
-  if (g * TT < al) fetch_app(g);
-  for (int t = g; t * TT < al; t += G) {
+  // Pipelined over two copies of the row tiles: tile t+G is staged while the
+  // products of tile t are finishing, so the barrier that publishes O rows of
+  // tile t also publishes the rows of tile t+G (two barriers per tile).
+  if (g * TT < al) {
+    fetch_app(g);
+    stage_rows(rq, xs[0], xr[0], xc[0], norm_q, false);
+    if ((g + G) * TT < al) fetch_app(g + G);
+  }
+  const WF f1 = wload(W1t), f3 = wload(W3t);
+  __syncthreads();
+  for (int t = g, i = 0; t * TT < al; t += G, ++i) {
+    const int b = i & 1;
     const int64_t t0 = p.app_start + (int64_t)t * TT;
     const int nv = min(TT, al - t * TT);
-    stage_rows(rq, xs, xr, xc, norm_q, false);
-    if ((t + G) * TT < al) fetch_app(t + G);
-    const WF f1 = wload(W1t), f3 = wload(W3t);
-    __syncthreads();
     {
-      const f32x16 Zq1 = th(xs, xr, W1t, f1);
-      const f32x16 Zq3 = th(xs, xr, W3t, f3);
+      const f32x16 Zq1 = th(xs[b], xr[b], W1t, f1);
+      const f32x16 Zq3 = th(xs[b], xr[b], W3t, f3);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const float z = Zq1[r];
@@ -277,16 +288,20 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_step(AmuStepArgs p) {
     __syncthreads();
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
-      const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+      const int bk = w + NW * bi, tb = bk & 1, db = bk >> 1;
       const f32x4 o = td(tb, db, W2d);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) es[(16 * tb + 4 * g4 + r) * LD + 16 * db + l16] = o[r];
+      for (int r = 0; r < 4; ++r) es[0][(16 * tb + 4 * g4 + r) * LD + 16 * db + l16] = o[r];
+    }
+    if ((t + G) * TT < al) {  // rows of the next tile into the other copy (last read two tiles ago)
+      stage_rows(rq, xs[b ^ 1], xr[b ^ 1], xc[b ^ 1], norm_q, false);
+      if ((t + 2 * G) * TT < al) fetch_app(t + 2 * G);
     }
     __syncthreads();
     if (row < nv) {
       float v[EPT];
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) v[i] = es[row * LD + col0 + i];
+      for (int e = 0; e < EPT; ++e) v[e] = es[0][row * LD + col0 + e];
       store_vec<IOT, EPT>(static_cast<IOT*>(p.O) + (t0 + row) * p.stride_tok + hoff + col0, v);
     }
   }
