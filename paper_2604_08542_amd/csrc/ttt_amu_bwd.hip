@@ -221,12 +221,15 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_bwd_apply(AmuBwdArgs p) {
   constexpr int NT = NW * 64;
   constexpr int EPT = D * TT / NT;
 
-  __shared__ __attribute__((aligned(16))) float xs[TT * LD];    // normalised Q rows
-  __shared__ __attribute__((aligned(16))) float ys[TT * LD];    // dO rows, then dQ before its norm adjoint
+  // Two copies of the row tiles: the rows of the next tile are loaded into
+  // the other copy before the barrier that publishes this tile's dQ, so that
+  // barrier also publishes them (two barriers per tile).
+  __shared__ __attribute__((aligned(16))) float xs[2][TT * LD];    // normalised Q rows
+  __shared__ __attribute__((aligned(16))) float ys[2][TT * LD];    // dO rows, then dQ before its norm adjoint
   __shared__ __attribute__((aligned(16))) MT sa[TT * AS_LD];
   __shared__ __attribute__((aligned(16))) MT sb[TT * AS_LD];
-  __shared__ float ninv[TT];
-  __shared__ int nabove[TT];
+  __shared__ float ninv[2][TT];
+  __shared__ int nabove[2][TT];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6;
@@ -241,16 +244,22 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_bwd_apply(AmuBwdArgs p) {
   const MT* Wb = static_cast<const MT*>(p.prep_w) + (int64_t)head * 6 * DH;
 
   f32x16 g1[2] = {}, g2[2] = {}, g3[2] = {};
-  for (int tile = g; tile * TT < p.len; tile += G) {
+  auto load_tile = [&](int tile, int b) {
     const int64_t t0 = p.start + (int64_t)tile * TT;
     const int nv = min(TT, p.len - tile * TT);
-    load_rows_n<IOT, EPT>(static_cast<const IOT*>(p.X), t0, nv, p.stride_tok, hoff, xs, norm_q, ninv, nabove);
-    load_rows_n<IOT, EPT>(static_cast<const IOT*>(p.Y), t0, nv, p.stride_tok, hoff, ys, false, nullptr, nullptr);
-    __syncthreads();
+    load_rows_n<IOT, EPT>(static_cast<const IOT*>(p.X), t0, nv, p.stride_tok, hoff, xs[b], norm_q, ninv[b], nabove[b]);
+    load_rows_n<IOT, EPT>(static_cast<const IOT*>(p.Y), t0, nv, p.stride_tok, hoff, ys[b], false, nullptr, nullptr);
+  };
+  if (g * TT < p.len) load_tile(g, 0);
+  __syncthreads();
+  for (int tile = g, i = 0; tile * TT < p.len; tile += G, ++i) {
+    const int b = i & 1;
+    const int64_t t0 = p.start + (int64_t)tile * TT;
+    const int nv = min(TT, p.len - tile * TT);
     {
-      const f32x16 Z1 = t.th(xs, Wb + AMU_W1T * DH);
-      const f32x16 Z3 = t.th(xs, Wb + AMU_W3T * DH);
-      const f32x16 dH = t.th(ys, Wb + AMU_W2N * DH);
+      const f32x16 Z1 = t.th(xs[b], Wb + AMU_W1T * DH);
+      const f32x16 Z3 = t.th(xs[b], Wb + AMU_W3T * DH);
+      const f32x16 dH = t.th(ys[b], Wb + AMU_W2N * DH);
       f32x16 Hq, dZ1, dZ3;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -261,34 +270,36 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_bwd_apply(AmuBwdArgs p) {
         dZ3[r] = dH[r] * s;
         dZ1[r] = dH[r] * Z3[r] * fmaf(s, 1.0f - sg, sg);
       }
-      t.tok_sum_hd(g2, Hq, ys);
-      t.tok_sum_dh(g1, xs, dZ1);
-      t.tok_sum_dh(g3, xs, dZ3);
+      t.tok_sum_hd(g2, Hq, ys[b]);
+      t.tok_sum_dh(g1, xs[b], dZ1);
+      t.tok_sum_dh(g3, xs[b], dZ3);
       t.stage(sa, dZ1);
       t.stage(sb, dZ3);
     }
     __syncthreads();
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
-      const int b = w + NW * bi, tb = b & 1, db = b >> 1;
+      const int bk = w + NW * bi, tb = bk & 1, db = bk >> 1;
       f32x4 c = {};
       c = t.td(sa, tb, db, Wb + AMU_W1D * DH, c);
       c = t.td(sb, tb, db, Wb + AMU_W3D * DH, c);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ys[(16 * tb + 4 * t.g4 + r) * LD + 16 * db + t.l16] = c[r];
+      for (int r = 0; r < 4; ++r) ys[b][(16 * tb + 4 * t.g4 + r) * LD + 16 * db + t.l16] = c[r];
     }
+    // the other copy was last read by the previous tile's dQ stage, which
+    // every wave finished before the barrier above
+    if ((tile + G) * TT < p.len) load_tile(tile + G, b ^ 1);
     __syncthreads();
     {
       float gq[EPT], xh[EPT];
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        gq[i] = ys[row * LD + col0 + i];
-        xh[i] = xs[row * LD + col0 + i];
+      for (int e = 0; e < EPT; ++e) {
+        gq[e] = ys[b][row * LD + col0 + e];
+        xh[e] = xs[b][row * LD + col0 + e];
       }
-      norm_adjoint<EPT>(gq, xh, norm_q, ninv[row], nabove[row]);
+      norm_adjoint<EPT>(gq, xh, norm_q, ninv[b][row], nabove[b][row]);
       if (row < nv) store_vec<IOT, EPT>(static_cast<IOT*>(p.dX) + (t0 + row) * p.stride_tok + hoff + col0, gq);
     }
-    __syncthreads();
   }
   if (p.len > 0) t.write_partial(p.partial + ((int64_t)head * G + g) * (3 * DH), g1, g2, g3, w, 1.0f);
 }
@@ -308,8 +319,13 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_bwd_update(AmuBwdArgs p) {
   __shared__ __attribute__((aligned(16))) float vs[TT * LD];   // normalised V rows
   __shared__ __attribute__((aligned(16))) float es[TT * LD];   // E = -eta v, then dot Y
   __shared__ __attribute__((aligned(16))) float ks[TT * LD];   // adjoint of K (before the sign and norm)
-  __shared__ __attribute__((aligned(16))) MT sa[TT * AS_LD];
-  __shared__ __attribute__((aligned(16))) MT sb[TT * AS_LD];
+  // Staged [token][hidden] pairs: with BF16 products the three pairs of a
+  // tile (Hdot, Hd), (aZ1, aZ3), (aZd1, aZd3) get buffers of their own and are
+  // staged together behind one barrier; FP32 tiles are twice as large and
+  // reuse one pair, with a barrier before and after each restaging.
+  constexpr int NS = BF ? 3 : 1;
+  __shared__ __attribute__((aligned(16))) MT sa[NS][TT * AS_LD];
+  __shared__ __attribute__((aligned(16))) MT sb[NS][TT * AS_LD];
   __shared__ float kinv[TT], vinv[TT], etas[TT];
   __shared__ int kab[TT], vab[TT];
 
@@ -368,39 +384,50 @@ __global__ __launch_bounds__(NW * 64) void ttt_amu_bwd_update(AmuBwdArgs p) {
       t.tok_sum_hd(g2, Hdot, es);
       t.tok_sum_dh(g1, xs, aZ1);
       t.tok_sum_dh(g3, xs, aZ3);
-      t.stage(sa, Hdot);
-      t.stage(sb, Hd);
+      t.stage(sa[0], Hdot);
+      t.stage(sb[0], Hd);
+      if constexpr (NS == 3) {
+        t.stage(sa[1], aZ1);
+        t.stage(sb[1], aZ3);
+        t.stage(sa[2], aZd1);
+        t.stage(sb[2], aZd3);
+      }
     }
     __syncthreads();
+    constexpr int P1 = NS == 3 ? 1 : 0, P2 = NS == 3 ? 2 : 0;
     f32x4 yd[8 / NW], kb[8 / NW];
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
       f32x4 c = {};
-      c = t.td(sa, tb, db, Wb + AMU_W2D * DH, c);
-      yd[bi] = t.td(sb, tb, db, Ab + AMU_W2D * DH, c);
+      c = t.td(sa[0], tb, db, Wb + AMU_W2D * DH, c);
+      yd[bi] = t.td(sb[0], tb, db, Ab + AMU_W2D * DH, c);
     }
-    __syncthreads();
-    t.stage(sa, aZ1);
-    t.stage(sb, aZ3);
-    __syncthreads();
+    if constexpr (NS == 1) {
+      __syncthreads();
+      t.stage(sa[0], aZ1);
+      t.stage(sb[0], aZ3);
+      __syncthreads();
+    }
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
       f32x4 c = {};
-      c = t.td(sa, tb, db, Wb + AMU_W1D * DH, c);
-      kb[bi] = t.td(sb, tb, db, Wb + AMU_W3D * DH, c);
+      c = t.td(sa[P1], tb, db, Wb + AMU_W1D * DH, c);
+      kb[bi] = t.td(sb[P1], tb, db, Wb + AMU_W3D * DH, c);
     }
-    __syncthreads();
-    t.stage(sa, aZd1);
-    t.stage(sb, aZd3);
-    __syncthreads();
+    if constexpr (NS == 1) {
+      __syncthreads();
+      t.stage(sa[0], aZd1);
+      t.stage(sb[0], aZd3);
+      __syncthreads();
+    }
 #pragma unroll
     for (int bi = 0; bi < 8 / NW; ++bi) {
       const int b = w + NW * bi, tb = b & 1, db = b >> 1;
       f32x4 c = kb[bi];
-      c = t.td(sa, tb, db, Ab + AMU_W1D * DH, c);
-      c = t.td(sb, tb, db, Ab + AMU_W3D * DH, c);
+      c = t.td(sa[P2], tb, db, Ab + AMU_W1D * DH, c);
+      c = t.td(sb[P2], tb, db, Ab + AMU_W3D * DH, c);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = (16 * tb + 4 * t.g4 + r) * LD + 16 * db + t.l16;
