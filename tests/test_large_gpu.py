@@ -33,6 +33,8 @@ CASES = [
     (700, 2, 256, 512, 300, 0.5, "bf16", True),
     (700, 2, 256, 512, 300, 0.5, "f32", True),     # FP32 tokens, BF16 matrix-core operands
     (700, 2, 256, 512, 300, 16.0, "bf16", True),   # large step: the update moves O well past the tolerance
+    (620, 2, 256, 512, 300, 0.5, "f32", False),    # last chunk of 20 tokens: one contraction slice (FP32)
+    (640, 2, 256, 512, 300, 0.5, "bf16", True),    # last chunk of 40 tokens: one contraction slice (BF16)
     (5496, 1, 1024, 4096, 2748, 0.5, "f32", False),  # the paper's state: 2 chunks of 2 frames
     (5496, 1, 1024, 4096, 2748, 0.5, "bf16", True),
 ]
