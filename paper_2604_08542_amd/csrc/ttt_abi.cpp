@@ -104,7 +104,7 @@ LargeLayout large_layout(const Shape& s) {
   L.D = take(M * h * op);
   L.Aq = take(M * h * op);
   L.Vn = take(M * d * 4);
-  L.S1 = take(M * h * op);
+  L.S1 = take((M + 127) / 128 * 128 * h * op);  // tile-native: whole 128-row tiles
   L.W1 = take(d * h * 4);
   L.W2 = take(d * h * 4);
   L.W1op = take(d * h * op);

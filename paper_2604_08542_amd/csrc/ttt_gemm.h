@@ -7,6 +7,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ttt_common.h"
 
 namespace ttt {
@@ -28,11 +30,29 @@ __device__ __forceinline__ void put(T* p, float v) {
 // of its elements) before it calls operator() for any of them, so those
 // reads are in flight together instead of each waiting behind the previous
 // element's store.  finish() runs once per work-group after its last element.
+//
+// An epilogue with TILED = true instead takes each 32x32 block whole:
+// tload(blk) for every block of the wave first, then block(blk, row0, col,
+// acc, tin), where the lane owns rows row0 + c32_row(r, hf) of column col.
+// blk numbers the 32x32 blocks of the launch, so that an intermediate one
+// product writes and a later product of the same grid reads can be kept in
+// a tile-native layout (the 16 values of a lane contiguous, two 16-byte
+// accesses per block, 1,024 elements per block).
 struct EpBase {
   struct In {};
   __device__ __forceinline__ In load(int, int) const { return {}; }
   __device__ __forceinline__ void finish() {}
+  static constexpr bool TILED = false;
+  struct TIn {};
+  __device__ __forceinline__ TIn tload(int64_t) const { return {}; }
 };
+
+// whether an epilogue takes whole blocks (TILED = true; epilogues that do
+// not derive from EpBase have no TILED member)
+template <typename E, typename = void>
+struct is_tiled : std::false_type {};
+template <typename E>
+struct is_tiled<E, std::void_t<decltype(E::TILED)>> : std::bool_constant<E::TILED> {};
 
 constexpr int BN = 128;   // work-group tile width
 constexpr int NTH = 256;  // 4 waves, each a (BM/2) x 64 quarter of the BM x 128 tile
@@ -254,7 +274,19 @@ __device__ __forceinline__ void gemm_tile(const T* A, int lda, int a_rows, const
   }
   if (kt < nk) body(kt, std::integral_constant<int, 0>{});
   const int l = threadIdx.x & 63, l32 = l & 31, hf = l >> 5;
-  if constexpr (sizeof(T) == 2 && sizeof(typename EP::In) <= 4) {
+  if constexpr (is_tiled<EP>::value) {
+    const int64_t blk0 = ((int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6)) * (MB * 2);
+    typename EP::TIn tin[MB][2];
+#pragma unroll
+    for (int bm = 0; bm < MB; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) tin[bm][bn] = ep.tload(blk0 + 2 * bm + bn);
+#pragma unroll
+    for (int bm = 0; bm < MB; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        ep.block(blk0 + 2 * bm + bn, m0 + wm + 32 * bm, n0 + wn + 32 * bn + l32, acc[bm][bn], tin[bm][bn]);
+  } else if constexpr (sizeof(T) == 2 && sizeof(typename EP::In) <= 4) {
     // BF16 tiles with at most one 4-byte input per element request every
     // input of the tile before the first element is stored (one load latency
     // per tile, not one per 32x32 block); the registers fit beside the

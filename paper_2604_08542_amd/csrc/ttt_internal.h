@@ -41,7 +41,7 @@ struct LargeStepArgs {
   void* D;
   void* Aq;
   float* Vn;      // [rows][d] FP32
-  void* S1;       // [rows][h] operand type: SiLU'(Z)
+  void* S1;       // operand type: SiLU'(Z), tile-native (whole 128-row tiles) in the forward step
   float* W1;      // FP32 masters [d][h], [h][d], updated in place
   float* W2;
   void* W1op;     // operand copies of the masters

@@ -37,18 +37,47 @@ namespace ttt {
 namespace large {
 
 // ------------------------------------------------------------- epilogues
-// A = SiLU(Z), S1 = SiLU'(Z) (for the gradient) or only A (for the apply).
+// A lane's 16 values of one 32x32 block in the tile-native layout of S1
+// (only the two products of a chunk step that write and read it use it).
+template <typename T>
+struct Native16 {
+  static constexpr int W = (int)sizeof(T);  // 16-byte words per lane and block
+  u32x4 v[W];
+  __device__ __forceinline__ static T* at(T* base, int64_t blk) {
+    return base + blk * 1024 + (threadIdx.x & 63) * 16;
+  }
+};
+// A = SiLU(Z), S1 = SiLU'(Z) (for the gradient; S1 in the tile-native
+// layout, read back by EpD in the same grid) or only A (for the apply).
 template <typename T, bool GRAD>
 struct EpAct : EpBase {
   T* a;
   T* s1;
   int ld, rows;
+  static constexpr bool TILED = GRAD;
   __device__ __forceinline__ void operator()(int r, int c, float z, In) {
     if (r >= rows) return;
     float sg;
     const float av = silu_sig(z, sg);
     put(a + (int64_t)r * ld + c, av);
-    if constexpr (GRAD) put(s1 + (int64_t)r * ld + c, fmaf(av, 1.0f - sg, sg));
+  }
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    union {
+      T t[16];
+      Native16<T> n;
+    } sv;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float av = silu_sig(z[r], sg);
+      if (row < rows) put(a + (int64_t)row * ld + col, av);
+      sv.t[r] = (T)fmaf(av, 1.0f - sg, sg);
+    }
+    u32x4* dst = reinterpret_cast<u32x4*>(Native16<T>::at(s1, blk));
+#pragma unroll
+    for (int i = 0; i < Native16<T>::W; ++i) dst[i] = sv.n.v[i];
   }
 };
 // R = Y - V, E = scale * R; sum of R^2 of this tile into loss_part[tile].
@@ -82,13 +111,29 @@ struct EpRes {
 template <typename T>
 struct EpD : EpBase {
   T* d;
-  const T* s1;
+  const T* s1;  // tile-native layout, written by EpAct<T, true> over the same grid
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? s1[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float p, T sv) {
-    if (r >= rows) return;
-    put(d + (int64_t)r * ld + c, p * (float)sv);
+  static constexpr bool TILED = true;
+  typedef Native16<T> TIn;
+  __device__ __forceinline__ TIn tload(int64_t blk) const {
+    TIn r;
+    const u32x4* src = reinterpret_cast<const u32x4*>(Native16<T>::at(const_cast<T*>(s1), blk));
+#pragma unroll
+    for (int i = 0; i < Native16<T>::W; ++i) r.v[i] = src[i];
+    return r;
+  }
+  __device__ __forceinline__ void block(int64_t, int row0, int col, const f32x16& p, const TIn& n) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    union {
+      T t[16];
+      Native16<T> n;
+    } sv;
+    sv.n = n;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row < rows) put(d + (int64_t)row * ld + col, p[r] * (float)sv.t[r]);
+    }
   }
 };
 // W -= eta * G (FP32 master), then the operand copy of the new W (nullable:
