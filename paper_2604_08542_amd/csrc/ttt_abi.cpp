@@ -182,10 +182,11 @@ LargeAmuLayout large_amu_layout(const Shape& s) {
   L.Qn = take(M * d * op);
   L.E = take(M * d * op);
   L.Vn = take(M * d * 4);
-  L.Z3 = take(M * h * op);
+  const size_t Mt = (M + 127) / 128 * 128;  // Z3, G1, G3 tile-native in the forward step: whole 128-row tiles
+  L.Z3 = take(Mt * h * op);
   L.Hd = take(M * h * op);
-  L.G1 = take(M * h * op);
-  L.G3 = take(M * h * op);
+  L.G1 = take(Mt * h * op);
+  L.G3 = take(Mt * h * op);
   L.D1 = take(M * h * op);
   L.D3 = take(M * h * op);
   L.W1 = take(d * h * 4);

@@ -46,6 +46,18 @@ struct Native16 {
   __device__ __forceinline__ static T* at(T* base, int64_t blk) {
     return base + blk * 1024 + (threadIdx.x & 63) * 16;
   }
+  __device__ __forceinline__ static Native16 load(const T* base, int64_t blk) {
+    Native16 r;
+    const u32x4* src = reinterpret_cast<const u32x4*>(at(const_cast<T*>(base), blk));
+#pragma unroll
+    for (int i = 0; i < W; ++i) r.v[i] = src[i];
+    return r;
+  }
+  __device__ __forceinline__ static void store(T* base, int64_t blk, const Native16& n) {
+    u32x4* dst = reinterpret_cast<u32x4*>(at(base, blk));
+#pragma unroll
+    for (int i = 0; i < W; ++i) dst[i] = n.v[i];
+  }
 };
 // A = SiLU(Z), S1 = SiLU'(Z) (for the gradient; S1 in the tile-native
 // layout, read back by EpD in the same grid) or only A (for the apply).
@@ -167,17 +179,26 @@ struct EpOut : EpBase {
 
 // A product stored as it is ([rows][ld], operand type).
 template <typename T>
-struct EpStore : EpBase {
+struct EpStoreTiled : EpBase {  // the product in the tile-native layout (read by EpSwi over the same grid)
   T* z;
-  int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float v, In) {
-    if (r >= rows) return;
-    put(z + (int64_t)r * ld + c, v);
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int, int, const f32x16& v, TIn) {
+    union {
+      T t[16];
+      Native16<T> n;
+    } sv;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sv.t[r] = (T)v[r];
+    u32x4* dst = reinterpret_cast<u32x4*>(Native16<T>::at(z, blk));
+#pragma unroll
+    for (int i = 0; i < Native16<T>::W; ++i) dst[i] = sv.n.v[i];
   }
 };
 // Z1 = x W1 of the memory unit with Z3 = x W3 stored: Hd = SiLU(Z1) Z3; for
 // the gradient also the factors of the hidden adjoint, G1 = Z3 SiLU'(Z1)
 // (towards W1) and G3 = SiLU(Z1) (towards W3).
+// Z3, G1 and G3 are in the tile-native layout (written and read by products
+// of one chunk step over the same grid); Hd is an operand, row-major.
 template <typename T, bool GRAD>
 struct EpSwi : EpBase {
   const T* z3;
@@ -185,42 +206,65 @@ struct EpSwi : EpBase {
   T* g1;
   T* g3;
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float z1, T z3r) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    float sg;
-    const float sv = silu_sig(z1, sg);
-    const float z3v = (float)z3r;
-    put(hd + i, sv * z3v);
+  static constexpr bool TILED = true;
+  typedef Native16<T> TIn;
+  __device__ __forceinline__ TIn tload(int64_t blk) const { return Native16<T>::load(z3, blk); }
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z1, const TIn& z3n) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    union U {
+      T t[16];
+      Native16<T> n;
+    } z3v, gv1, gv3;
+    z3v.n = z3n;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float sv = silu_sig(z1[r], sg);
+      const float zz = (float)z3v.t[r];
+      if (row < rows) put(hd + (int64_t)row * ld + col, sv * zz);
+      if constexpr (GRAD) {
+        gv1.t[r] = (T)(zz * fmaf(sv, 1.0f - sg, sg));
+        gv3.t[r] = (T)sv;
+      }
+    }
     if constexpr (GRAD) {
-      put(g1 + i, z3v * fmaf(sv, 1.0f - sg, sg));
-      put(g3 + i, sv);
+      Native16<T>::store(g1, blk, gv1.n);
+      Native16<T>::store(g3, blk, gv3.n);
     }
   }
 };
 // dH = E W2^T: D1 = dH G1, D3 = dH G3.
 template <typename T>
 struct EpD2 : EpBase {
-  const T* g1;
+  const T* g1;  // tile-native, from EpSwi<T, true> over the same grid
   const T* g3;
   T* d1;
   T* d3;
   int ld, rows;
-  struct In {
-    T a, b;
+  static constexpr bool TILED = true;
+  struct TIn {
+    Native16<T> a, b;
   };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {g1[i], g3[i]};
+  __device__ __forceinline__ TIn tload(int64_t blk) const {
+    return {Native16<T>::load(g1, blk), Native16<T>::load(g3, blk)};
   }
-  __device__ __forceinline__ void operator()(int r, int c, float dh, In g) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    put(d1 + i, dh * (float)g.a);
-    put(d3 + i, dh * (float)g.b);
+  __device__ __forceinline__ void block(int64_t, int row0, int col, const f32x16& dh, const TIn& g) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    union U {
+      T t[16];
+      Native16<T> n;
+    } a, b;
+    a.n = g.a;
+    b.n = g.b;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row >= rows) continue;
+      const int64_t i = (int64_t)row * ld + col;
+      put(d1 + i, dh[r] * (float)a.t[r]);
+      put(d3 + i, dh[r] * (float)b.t[r]);
+    }
   }
 };
 
@@ -376,8 +420,8 @@ hipError_t amu_step_t(const LargeAmuArgs& a, hipStream_t st) {
   LargeNormArgs na{a.K, a.V, a.Q, a.stride_tok, a.flags, M, d, a.Kn, a.Vn, a.Qn};
   hipLaunchKernelGGL((k_norm<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, na);
   if (a.grad) {
-    EpStore<T> e1{{}, Z3, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStore<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M, W3o,
+    EpStoreTiled<T> e1{{}, Z3};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStoreTiled<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M, W3o,
                        h, d, d, e1);
     EpSwi<T, true> e2{{}, Z3, Hd, G1, G3, h, M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpSwi<T, true>>), dim3(h / BN, mt), dim3(NTH), 0, st, Kn, d, M,
@@ -400,8 +444,8 @@ hipError_t amu_step_t(const LargeAmuArgs& a, hipStream_t st) {
                        d, M, M, u2);
   }
   if (a.O) {
-    EpStore<T> e6{{}, Z3, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStore<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M, W3o,
+    EpStoreTiled<T> e6{{}, Z3};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpStoreTiled<T>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M, W3o,
                        h, d, d, e6);
     EpSwi<T, false> e7{{}, Z3, Hd, nullptr, nullptr, h, M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpSwi<T, false>>), dim3(h / BN, mt), dim3(NTH), 0, st, Qn, d, M,
