@@ -139,12 +139,12 @@ LargeBwdLayout large_bwd_layout(const Shape& s) {
   L.dk = take(M * d * 4);
   L.dv = take(M * d * 4);
   L.dE = take(M * d * 4);
-  L.S2 = take(M * h * op);
-  L.P = take(M * h * op);
-  L.Sq1 = take(M * h * op);
+  L.S2 = take((M + 127) / 128 * 128 * h * op);  // tile-native
+  L.P = take((M + 127) / 128 * 128 * h * op);  // tile-native
+  L.Sq1 = take((M + 127) / 128 * 128 * h * op);  // tile-native
   L.dZq = take(M * h * op);
   L.dP = take(M * h * op);
-  L.dZa = take(M * h * op);
+  L.dZa = take((M + 127) / 128 * 128 * h * op);  // tile-native
   L.EWh = take(M * h * op);
   L.dZ = take(M * h * op);
   L.W1nop = take(d * h * op);

@@ -62,6 +62,30 @@ constexpr int bk() {
   return sizeof(T) == 2 ? 64 : 32;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A lane's 16 values of one 32x32 block in the tile-native layout (see
+// EpBase): 16 * sizeof(T) contiguous bytes at base + blk * 1024 + lane * 16.
+template <typename T>
+struct Native16 {
+  static constexpr int W = (int)sizeof(T);  // 16-byte words per lane and block
+  u32x4 v[W];
+  __device__ __forceinline__ static T* at(T* base, int64_t blk) {
+    return base + blk * 1024 + (threadIdx.x & 63) * 16;
+  }
+  __device__ __forceinline__ static Native16 load(const T* base, int64_t blk) {
+    Native16 r;
+    const u32x4* src = reinterpret_cast<const u32x4*>(at(const_cast<T*>(base), blk));
+#pragma unroll
+    for (int i = 0; i < W; ++i) r.v[i] = src[i];
+    return r;
+  }
+  __device__ __forceinline__ static void store(T* base, int64_t blk, const Native16& n) {
+    u32x4* dst = reinterpret_cast<u32x4*>(at(base, blk));
+#pragma unroll
+    for (int i = 0; i < W; ++i) dst[i] = n.v[i];
+  }
+};
 // Operand layouts of C[m][n] = sum_k A(m, k) B(k, n):
 //   KMAJ  the operand is stored [m or n][k] (k contiguous), pitch ld
 //   MNMAJ the operand is stored [k][m or n] (m or n contiguous), pitch ld
@@ -90,7 +114,6 @@ struct Tile {
   static constexpr int ELEMS = ROWS * KLD > BK * MLD ? ROWS * KLD : BK * MLD;
 };
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Global -> registers -> LDS staging of one operand tile (rows mn0 .. +ROWS
 // of the m/n axis, k0 .. k0+BK of the contraction).  Loads go through a

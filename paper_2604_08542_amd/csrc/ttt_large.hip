@@ -37,28 +37,6 @@ namespace ttt {
 namespace large {
 
 // ------------------------------------------------------------- epilogues
-// A lane's 16 values of one 32x32 block in the tile-native layout of S1
-// (only the two products of a chunk step that write and read it use it).
-template <typename T>
-struct Native16 {
-  static constexpr int W = (int)sizeof(T);  // 16-byte words per lane and block
-  u32x4 v[W];
-  __device__ __forceinline__ static T* at(T* base, int64_t blk) {
-    return base + blk * 1024 + (threadIdx.x & 63) * 16;
-  }
-  __device__ __forceinline__ static Native16 load(const T* base, int64_t blk) {
-    Native16 r;
-    const u32x4* src = reinterpret_cast<const u32x4*>(at(const_cast<T*>(base), blk));
-#pragma unroll
-    for (int i = 0; i < W; ++i) r.v[i] = src[i];
-    return r;
-  }
-  __device__ __forceinline__ static void store(T* base, int64_t blk, const Native16& n) {
-    u32x4* dst = reinterpret_cast<u32x4*>(at(base, blk));
-#pragma unroll
-    for (int i = 0; i < W; ++i) dst[i] = n.v[i];
-  }
-};
 // A = SiLU(Z), S1 = SiLU'(Z) (for the gradient; S1 in the tile-native
 // layout, read back by EpD in the same grid) or only A (for the apply).
 template <typename T, bool GRAD>

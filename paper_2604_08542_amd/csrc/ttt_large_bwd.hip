@@ -48,6 +48,15 @@ __device__ __forceinline__ void tile_sum(float v, float* part) {
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The intermediates that the update part of a reverse step writes in one
+// product and reads in a later one over the same grid (S1, S2, P, dZa, and
+// Sq1 of the apply part) are kept in the tile-native layout; operands of
+// later products (A, Aq, D, dP, dZ, dZq) stay row-major.
+template <typename T>
+union Blk16 {
+  T t[16];
+  Native16<T> n;
+};
 // A = s(Z), S1 = s'(Z), S2 = s''(Z) for s = SiLU.
 template <typename T>
 struct EpAct3 : EpBase {
@@ -55,14 +64,21 @@ struct EpAct3 : EpBase {
   T* s1;
   T* s2;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float z, In) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    float sg;
-    const float av = silu_sig(z, sg);
-    put(a + i, av);
-    put(s1 + i, fmaf(av, 1.0f - sg, sg));
-    put(s2 + i, sg * (1.0f - sg) * fmaf(z, 1.0f - 2.0f * sg, 2.0f));
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> v1, v2;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float av = silu_sig(z[r], sg);
+      if (row < rows) put(a + (int64_t)row * ld + col, av);
+      v1.t[r] = (T)fmaf(av, 1.0f - sg, sg);
+      v2.t[r] = (T)(sg * (1.0f - sg) * fmaf(z[r], 1.0f - 2.0f * sg, 2.0f));
+    }
+    Native16<T>::store(s1, blk, v1.n);
+    Native16<T>::store(s2, blk, v2.n);
   }
 };
 // Aq = s(Zq), Sq1 = s'(Zq).
@@ -71,13 +87,19 @@ struct EpAct2 : EpBase {
   T* a;
   T* s1;
   int ld, rows;
-  __device__ __forceinline__ void operator()(int r, int c, float z, In) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    float sg;
-    const float av = silu_sig(z, sg);
-    put(a + i, av);
-    put(s1 + i, fmaf(av, 1.0f - sg, sg));
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> v1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float av = silu_sig(z[r], sg);
+      if (row < rows) put(a + (int64_t)row * ld + col, av);
+      v1.t[r] = (T)fmaf(av, 1.0f - sg, sg);
+    }
+    Native16<T>::store(s1, blk, v1.n);
   }
 };
 // E = scale (Y - V).
@@ -101,26 +123,40 @@ struct EpPD : EpBase {
   T* d;
   const T* s1;
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? s1[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float pv, T sv) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    put(p + i, pv);
-    put(d + i, pv * (float)sv);
+  static constexpr bool TILED = true;
+  typedef Native16<T> TIn;
+  __device__ __forceinline__ TIn tload(int64_t blk) const { return Native16<T>::load(s1, blk); }
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& pv, const TIn& sn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> sv, pp;
+    sv.n = sn;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      pp.t[r] = (T)pv[r];
+      if (row < rows) put(d + (int64_t)row * ld + col, pv[r] * (float)sv.t[r]);
+    }
+    Native16<T>::store(p, blk, pp.n);
   }
 };
 // out = value * fac.
 template <typename T>
 struct EpMul : EpBase {
   T* out;
-  const T* fac;
+  const T* fac;  // tile-native
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? fac[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float v, T f) {
-    if (r >= rows) return;
-    put(out + (int64_t)r * ld + c, v * (float)f);
+  static constexpr bool TILED = true;
+  typedef Native16<T> TIn;
+  __device__ __forceinline__ TIn tload(int64_t blk) const { return Native16<T>::load(fac, blk); }
+  __device__ __forceinline__ void block(int64_t, int row0, int col, const f32x16& v, const TIn& fn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> f;
+    f.n = fn;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row < rows) put(out + (int64_t)row * ld + col, v[r] * (float)f.t[r]);
+    }
   }
 };
 // FP32 token-side result: out = scale * value (+ out when ADD).
@@ -180,21 +216,38 @@ struct EpU1 {
   int ld, rows;
   float eta;
   float acc = 0.f;
-  struct In {
-    T d, s1, p, s2;
+  // S1, P, S2 and dZa tile-native; D (an operand of a later product) and dP
+  // row-major
+  static constexpr bool TILED = true;
+  struct TIn {
+    Native16<T> s1, p, s2;
   };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {d[i], s1[i], p[i], s2[i]};
+  __device__ __forceinline__ TIn tload(int64_t blk) const {
+    return {Native16<T>::load(s1, blk), Native16<T>::load(p, blk), Native16<T>::load(s2, blk)};
   }
-  __device__ __forceinline__ void operator()(int r, int c, float u, In x) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    acc = fmaf(-u, (float)x.d, acc);
-    const float dd = -eta * u;
-    put(dp + i, dd * (float)x.s1);
-    put(dza + i, dd * (float)x.p * (float)x.s2);
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& u, const TIn& x) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> vs1, vp, vs2, vz;
+    vs1.n = x.s1;
+    vp.n = x.p;
+    vs2.n = x.s2;
+    T dv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      dv[r] = row < rows ? d[(int64_t)row * ld + col] : T(0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      const float dd = -eta * u[r];
+      vz.t[r] = (T)(dd * (float)vp.t[r] * (float)vs2.t[r]);
+      if (row < rows) {
+        acc = fmaf(-u[r], (float)dv[r], acc);
+        put(dp + (int64_t)row * ld + col, dd * (float)vs1.t[r]);
+      }
+    }
+    Native16<T>::store(dza, blk, vz.n);
   }
   __device__ __forceinline__ void finish() { tile_sum(acc, part); }
 };
@@ -243,18 +296,32 @@ struct EpDZ : EpBase {
   const T* s1;
   int ld, rows;
   float eta;
-  struct In {
-    T ewh, dza, s1;
+  // dZa and S1 tile-native, EWh row-major
+  static constexpr bool TILED = true;
+  struct TIn {
+    Native16<T> dza, s1;
   };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {ewh[i], dza[i], s1[i]};
+  __device__ __forceinline__ TIn tload(int64_t blk) const {
+    return {Native16<T>::load(dza, blk), Native16<T>::load(s1, blk)};
   }
-  __device__ __forceinline__ void operator()(int r, int c, float v, In x) {
-    if (r >= rows) return;
-    const float da = fmaf(-eta, (float)x.ewh, v);
-    put(dz + (int64_t)r * ld + c, fmaf(da, (float)x.s1, (float)x.dza));
+  __device__ __forceinline__ void block(int64_t, int row0, int col, const f32x16& v, const TIn& x) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> vz, vs1;
+    vz.n = x.dza;
+    vs1.n = x.s1;
+    T ev[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      ev[r] = row < rows ? ewh[(int64_t)row * ld + col] : T(0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row >= rows) continue;
+      const float da = fmaf(-eta, (float)ev[r], v[r]);
+      put(dz + (int64_t)row * ld + col, fmaf(da, (float)vs1.t[r], (float)vz.t[r]));
+    }
   }
 };
 
