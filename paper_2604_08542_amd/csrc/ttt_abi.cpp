@@ -224,8 +224,9 @@ LargeAmuBwdLayout large_amu_bwd_layout(const Shape& s, int64_t n_tokens, int syn
   L.dq = take(M * d * 4);
   L.dk = take(M * d * 4);
   L.dv = take(M * d * 4);
+  // whole 128-row tiles: S, S1, S2, Zd3, Sd, T2, dHh are tile-native in the reverse step
   for (size_t* b : {&L.S, &L.S1, &L.S2, &L.Zd3, &L.Sd, &L.Hdot, &L.T2, &L.dHh, &L.aZ1, &L.aZ3, &L.aZd1, &L.aZd3})
-    *b = take(M * h * op);
+    *b = take((M + 127) / 128 * 128 * h * op);
   for (int m = 0; m < 3; ++m) {
     L.Wnop[m] = take(d * h * op);
     L.Wh[m] = take(d * h * 4);

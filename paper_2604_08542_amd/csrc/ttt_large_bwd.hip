@@ -533,29 +533,36 @@ namespace amu {
 
 // Z1 -> S = s(Z1), S1 = s'(Z1), S2 = s''(Z1), Hd = S Z3 (Z3 loaded).
 template <typename T>
-struct EpZ1 : EpBase {
+struct EpZ1 : EpBase {  // Z3, Sv, S1, S2 tile-native; Hd row-major (an operand)
   const T* z3;
   T* sv;
   T* s1;
   T* s2;
   T* hd;
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float z, T z3v) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    float sg;
-    const float a = silu_sig(z, sg);
-    put(sv + i, a);
-    put(s1 + i, fmaf(a, 1.0f - sg, sg));
-    put(s2 + i, sg * (1.0f - sg) * fmaf(z, 1.0f - 2.0f * sg, 2.0f));
-    put(hd + i, a * (float)z3v);
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> z3v, vs, v1, v2;
+    z3v.n = Native16<T>::load(z3, blk);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float a = silu_sig(z[r], sg);
+      vs.t[r] = (T)a;
+      v1.t[r] = (T)fmaf(a, 1.0f - sg, sg);
+      v2.t[r] = (T)(sg * (1.0f - sg) * fmaf(z[r], 1.0f - 2.0f * sg, 2.0f));
+      if (row < rows) put(hd + (int64_t)row * ld + col, a * (float)z3v.t[r]);
+    }
+    Native16<T>::store(sv, blk, vs.n);
+    Native16<T>::store(s1, blk, v1.n);
+    Native16<T>::store(s2, blk, v2.n);
   }
 };
 // Zd1 = K Wh1 -> Sd = S1 Zd1, Hdot = Sd Z3 + S Zd3, T2 = S2 Zd1.
 template <typename T>
-struct EpZd1 : EpBase {
+struct EpZd1 : EpBase {  // inputs and Sd, T2 tile-native; Hdot row-major (an operand)
   const T* s1;
   const T* z3;
   const T* sv;
@@ -565,26 +572,31 @@ struct EpZd1 : EpBase {
   T* hdot;
   T* t2;
   int ld, rows;
-  struct In {
-    T s1, z3, s, zd3, s2;
-  };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {s1[i], z3[i], sv[i], zd3[i], s2[i]};
-  }
-  __device__ __forceinline__ void operator()(int r, int c, float zd1, In x) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    const float sdv = (float)x.s1 * zd1;
-    put(sd + i, sdv);
-    put(hdot + i, fmaf(sdv, (float)x.z3, (float)x.s * (float)x.zd3));
-    put(t2 + i, (float)x.s2 * zd1);
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& zd1, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> x1, xz3, xs, xzd3, x2, osd, ot2;
+    x1.n = Native16<T>::load(s1, blk);
+    xz3.n = Native16<T>::load(z3, blk);
+    xs.n = Native16<T>::load(sv, blk);
+    xzd3.n = Native16<T>::load(zd3, blk);
+    x2.n = Native16<T>::load(s2, blk);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      const float sdv = (float)x1.t[r] * zd1[r];
+      osd.t[r] = (T)sdv;
+      ot2.t[r] = (T)((float)x2.t[r] * zd1[r]);
+      if (row < rows)
+        put(hdot + (int64_t)row * ld + col, fmaf(sdv, (float)xz3.t[r], (float)xs.t[r] * (float)xzd3.t[r]));
+    }
+    Native16<T>::store(sd, blk, osd.n);
+    Native16<T>::store(t2, blk, ot2.n);
   }
 };
 // dH = E W2^T with dHh = E Wh2^T loaded: the adjoints aZ1, aZ3, aZd1, aZd3.
 template <typename T>
-struct EpAdj : EpBase {
+struct EpAdj : EpBase {  // inputs tile-native; the four adjoints row-major (operands)
   const T* z3;
   const T* sd;
   const T* sv;
@@ -597,69 +609,102 @@ struct EpAdj : EpBase {
   T* azd1;
   T* azd3;
   int ld, rows;
-  struct In {
-    T z3, sd, s, zd3, dhh, s1, t2;
-  };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f), T(0.f), T(0.f), T(0.f), T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {z3[i], sd[i], sv[i], zd3[i], dhh[i], s1[i], t2[i]};
-  }
-  __device__ __forceinline__ void operator()(int r, int c, float dh, In x) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    const float z3v = (float)x.z3, sdv = (float)x.sd, s = (float)x.s, zd3v = (float)x.zd3, dhh = (float)x.dhh,
-                s1 = (float)x.s1;
-    const float asd = dh * z3v;
-    const float as = fmaf(dh, zd3v, dhh * z3v);
-    put(az3 + i, fmaf(dh, sdv, dhh * s));
-    put(azd3 + i, dh * s);
-    put(azd1 + i, asd * s1);
-    put(az1 + i, fmaf(asd, (float)x.t2, as * s1));
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& dh, TIn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> xz3, xsd, xs, xzd3, xdhh, x1, xt2;
+    xz3.n = Native16<T>::load(z3, blk);
+    xsd.n = Native16<T>::load(sd, blk);
+    xs.n = Native16<T>::load(sv, blk);
+    xzd3.n = Native16<T>::load(zd3, blk);
+    xdhh.n = Native16<T>::load(dhh, blk);
+    x1.n = Native16<T>::load(s1, blk);
+    xt2.n = Native16<T>::load(t2, blk);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row >= rows) continue;
+      const int64_t i = (int64_t)row * ld + col;
+      const float z3v = (float)xz3.t[r], sdv = (float)xsd.t[r], sa = (float)xs.t[r], zd3v = (float)xzd3.t[r],
+                  dhv = (float)xdhh.t[r], s1v = (float)x1.t[r];
+      const float asd = dh[r] * z3v;
+      const float as = fmaf(dh[r], zd3v, dhv * z3v);
+      put(az3 + i, fmaf(dh[r], sdv, dhv * sa));
+      put(azd3 + i, dh[r] * sa);
+      put(azd1 + i, asd * s1v);
+      put(az1 + i, fmaf(asd, (float)xt2.t[r], as * s1v));
+    }
   }
 };
 // Apply: Zq1 -> Hq = s(Zq1) Zq3, F1 = Zq3 s'(Zq1), F3 = s(Zq1) (Zq3 loaded).
 template <typename T>
-struct EpQ1 : EpBase {
+struct EpQ1 : EpBase {  // Zq3 in, F1, F3 out tile-native; Hq row-major (an operand)
   const T* z3;
   T* hq;
   T* f1;
   T* f3;
   int ld, rows;
-  typedef T In;
-  __device__ __forceinline__ T load(int r, int c) const { return r < rows ? z3[(int64_t)r * ld + c] : T(0.f); }
-  __device__ __forceinline__ void operator()(int r, int c, float z, T z3r) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    float sg;
-    const float a = silu_sig(z, sg);
-    const float z3v = (float)z3r;
-    put(hq + i, a * z3v);
-    put(f1 + i, z3v * fmaf(a, 1.0f - sg, sg));
-    put(f3 + i, a);
+  static constexpr bool TILED = true;
+  typedef Native16<T> TIn;
+  __device__ __forceinline__ TIn tload(int64_t blk) const { return Native16<T>::load(z3, blk); }
+  __device__ __forceinline__ void block(int64_t blk, int row0, int col, const f32x16& z, const TIn& zn) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> z3v, o1, o3;
+    z3v.n = zn;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      float sg;
+      const float a = silu_sig(z[r], sg);
+      const float zz = (float)z3v.t[r];
+      o1.t[r] = (T)(zz * fmaf(a, 1.0f - sg, sg));
+      o3.t[r] = (T)a;
+      if (row < rows) put(hq + (int64_t)row * ld + col, a * zz);
+    }
+    Native16<T>::store(f1, blk, o1.n);
+    Native16<T>::store(f3, blk, o3.n);
   }
 };
 // dHq = dO W2'^T -> dZq1 = dHq F1, dZq3 = dHq F3.
 template <typename T>
-struct EpQ2 : EpBase {
+struct EpQ2 : EpBase {  // F1, F3 tile-native; dZq1, dZq3 row-major (operands)
   const T* f1;
   const T* f3;
   T* d1;
   T* d3;
   int ld, rows;
-  struct In {
-    T a, b;
+  static constexpr bool TILED = true;
+  struct TIn {
+    Native16<T> a, b;
   };
-  __device__ __forceinline__ In load(int r, int c) const {
-    if (r >= rows) return {T(0.f), T(0.f)};
-    const int64_t i = (int64_t)r * ld + c;
-    return {f1[i], f3[i]};
+  __device__ __forceinline__ TIn tload(int64_t blk) const { return {Native16<T>::load(f1, blk), Native16<T>::load(f3, blk)}; }
+  __device__ __forceinline__ void block(int64_t, int row0, int col, const f32x16& v, const TIn& f) {
+    const int hf = (threadIdx.x >> 5) & 1;
+    Blk16<T> a, b;
+    a.n = f.a;
+    b.n = f.b;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + c32_row(r, hf);
+      if (row >= rows) continue;
+      const int64_t i = (int64_t)row * ld + col;
+      put(d1 + i, v[r] * (float)a.t[r]);
+      put(d3 + i, v[r] * (float)b.t[r]);
+    }
   }
-  __device__ __forceinline__ void operator()(int r, int c, float v, In f) {
-    if (r >= rows) return;
-    const int64_t i = (int64_t)r * ld + c;
-    put(d1 + i, v * (float)f.a);
-    put(d3 + i, v * (float)f.b);
+};
+
+// The product stored in the tile-native layout (Z3, Zd3, dHh of the paper
+// unit's reverse step, read by the epilogues above over the same grid).
+template <typename T>
+struct EpPutTiled : EpBase {
+  T* z;
+  static constexpr bool TILED = true;
+  __device__ __forceinline__ void block(int64_t blk, int, int, const f32x16& v, TIn) {
+    Blk16<T> o;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o.t[r] = (T)v[r];
+    Native16<T>::store(z, blk, o.n);
   }
 };
 
@@ -715,8 +760,8 @@ hipError_t step_t(const LargeAmuBwdArgs& a, hipStream_t st) {
   if (a.apply) {
     hipLaunchKernelGGL((k_rows<IOT, T>), dim3((M + 3) / 4), dim3(256), 0, st, static_cast<const IOT*>(a.dO),
                        a.stride_tok, dOn, M, d);
-    EpPut<T> q3{{}, Z3, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Qn, d, M, W3n, h, d, d, q3);
+    EpPutTiled<T> q3{{}, Z3};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPutTiled<T>>), gh, nt, 0, st, Qn, d, M, W3n, h, d, d, q3);
     EpQ1<T> q1{{}, Z3, Hd, S1, Sv, h, M};  // Hq, F1, F3
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpQ1<T>>), gh, nt, 0, st, Qn, d, M, W1n, h, d, d, q1);
     EpQ2<T> q2{{}, S1, Sv, aZ1, aZ3, h, M};  // dZq1, dZq3
@@ -733,12 +778,12 @@ hipError_t step_t(const LargeAmuBwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpF32<true>>), gd, nt, 0, st, aZ3, h, M, W3n, h, d, h, g3);
   }
   if (a.update) {
-    EpPut<T> u1{{}, Z3, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Kn, d, M, W3, h, d, d, u1);
+    EpPutTiled<T> u1{{}, Z3};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPutTiled<T>>), gh, nt, 0, st, Kn, d, M, W3, h, d, d, u1);
     EpZ1<T> u2{{}, Z3, Sv, S1, S2, Hd, h, M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpZ1<T>>), gh, nt, 0, st, Kn, d, M, W1, h, d, d, u2);
-    EpPut<T> u3{{}, Zd3, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPut<T>>), gh, nt, 0, st, Kn, d, M, Wh3o, h, d, d, u3);
+    EpPutTiled<T> u3{{}, Zd3};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpPutTiled<T>>), gh, nt, 0, st, Kn, d, M, Wh3o, h, d, d, u3);
     EpZd1<T> u4{{}, S1, Z3, Sv, Zd3, S2, Sd, Hdot, T2, h, M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpZd1<T>>), gh, nt, 0, st, Kn, d, M, Wh1o, h, d, d, u4);
     const int64_t ne = (int64_t)M * d;
@@ -749,8 +794,8 @@ hipError_t step_t(const LargeAmuBwdArgs& a, hipStream_t st) {
     EpF32<true> y2{{}, a.Ydot, d, M, 1.0f};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, MNMAJ, BMT, EpF32<true>>), gd, nt, 0, st, Hd, h, M, Wh2o, d, h, h, y2);
     hipLaunchKernelGGL(k_ydot, dim3((M + 3) / 4), dim3(256), 0, st, a);
-    EpPut<T> u8{{}, dHh, h, M};
-    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPut<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, u8);
+    EpPutTiled<T> u8{{}, dHh};
+    hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpPutTiled<T>>), gh, nt, 0, st, E, d, M, Wh2o, d, h, d, u8);
     EpAdj<T> u9{{}, Z3, Sd, Sv, Zd3, dHh, S1, T2, aZ1, aZ3, aZd1, aZd3, h, M};
     hipLaunchKernelGGL((k_gemm<T, KMAJ, KMAJ, BMT, EpAdj<T>>), gh, nt, 0, st, E, d, M, W2, d, h, d, u9);
     // dk (uses Wh before the weight terms below change it, in the chain)
